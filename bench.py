@@ -1,0 +1,179 @@
+"""Throughput of the SMS-MUSSELS IRLS solve on one MI355X.
+
+One step = one complete IRLS solve of one slice group (A^H y, Gram, weights,
+n_irls x (n_cg + 1) normal-operator applications with CG updates) on the
+realistic workload: 256x256, MB=3 slices, 4 interleaved shots, 32 coils,
+7x7 Hankel filter, lambda = 1e-3, 15 IRLS x 15 CG.  Inputs are synthetic
+(seeded phantom, shot phases and coil maps), resident in HBM before timing.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz
+HBM_TBS = 8.0
+
+
+def centred_fft2(u):
+    """Input synthesis only: k-space of the synthetic truth images."""
+    ax = (-2, -1)
+    return np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(u, axes=ax), norm="ortho"), axes=ax)
+
+
+def synth_inputs(torch, dev, plan, g, case):
+    """y = A x_true + noise, with A applied by the library itself."""
+    m = case["rho"].astype(np.float64)[:, None] * case["phase"].astype(np.complex128)
+    x_true = torch.from_numpy(centred_fft2(m)).to(dev)
+    clean = plan.apply_A(x_true)
+    torch.cuda.synchronize()
+    mask = torch.from_numpy(case["masks"].astype(np.float64)).to(dev)[:, None, :, None]
+    acquired = mask.expand_as(clean.real) > 0
+    rms = torch.sqrt(torch.mean(torch.abs(clean[acquired]) ** 2)).item()
+    noise = torch.from_numpy(case["noise"].astype(np.complex128)).to(dev)
+    y = clean + mask * (rms / g.snr) * noise
+    return y.to(torch.complex64).contiguous()
+
+
+def time_kernel(torch, plan, name, reps):
+    stream = torch.cuda.current_stream()
+    plan.launch_kernel(name, 2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.launch_kernel(name, reps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3   # seconds per launch
+
+
+def cpu_baseline(g, case, y_oracle):
+    """The FP64 oracle timed on the host on a bounded sample of the same solve:
+    one A^H y, one Gram per slice, one eigendecomposition weight per slice and
+    two normal-operator applications; the full solve time is extrapolated as
+    A^H + (n_irls+1) Grams + n_irls weights + n_irls (n_cg+1) normal ops."""
+    from oracle import smsm_oracle as o
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    coils = case["coils"].astype(np.complex128)
+    masks = case["masks"].astype(np.float64)
+    theta = o.caipi_phase(g.n, case["shifts"])
+    t0 = time.perf_counter()
+    b = o.adjoint(y_oracle, coils, masks, theta)
+    t_adj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Gs = [o.gram(b[l], g.filt) for l in range(g.n_slices)]
+    t_gram = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ws = [o.irls_weight(G, 1e-2 * o.lambda_max(G)) for G in Gs]
+    t_w = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(2):
+        o.normal_op(b, coils, masks, theta, Ws, g.lam, g.filt)
+    t_n = (time.perf_counter() - t0) / 2
+    solve_s = t_adj + (g.n_irls + 1) * t_gram + g.n_irls * t_w + g.n_irls * (g.n_cg + 1) * t_n
+    sample_s = t_adj + t_gram + t_w + 2 * t_n
+    return {"value": 1.0 / solve_s, "unit": "slice-groups/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"1 A^H y, {g.n_slices} Grams, {g.n_slices} eigh weights, 2 normal-operator "
+                       f"applications ({sample_s:.1f} s measured); solve time extrapolated to "
+                       f"{solve_s:.1f} s per slice group")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sg256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "independent slice groups would shard across GPUs with no exchange.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import smsm_inputs as si
+    from paper_1901_01893_amd import smsm
+
+    dev = torch.device("cuda:0")
+    g = si.WORKLOADS[args.workload]
+    case = si.make_case(g, 0, si.WORKLOAD_IDS[args.workload])
+    coils = torch.from_numpy(case["coils"]).to(dev)
+    params = smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg)
+    plan = smsm.Plan(g.n, g.n, g.n_slices, g.n_shots, g.n_coils, g.filt, coils, case["masks"],
+                     case["shifts"], params)
+    y = synth_inputs(torch, dev, plan, g, case)
+    x = torch.empty(plan.shape_x, dtype=torch.complex64, device=dev)
+    print(f"[bench] workload={args.workload} warmup={args.warmup} steps={args.steps}", file=sys.stderr,
+          flush=True)
+    for _ in range(args.warmup):
+        plan.solve(y, x)
+    torch.cuda.synchronize()
+    status = plan.status()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        plan.solve(y, x)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    print(f"[bench] timed {args.steps} solves in {wall:.3f} s (median {np.median(per):.2f} ms)",
+          file=sys.stderr, flush=True)
+
+    # dominant kernel: per-column SENSE + Hankel pass of every CG matvec
+    kern = {}
+    for name in ("col_normal", "rows_inv", "rows_fwd", "band_corr", "cg_update"):
+        t = time_kernel(torch, plan, name, args.kernel_reps)
+        f, b = plan.kernel_cost(name)
+        kern[name] = {"us": t * 1e6, "gflop": f / 1e9, "mb": b / 1e6,
+                      "tflops": f / t / 1e12, "gbs": b / t / 1e9}
+    kc = kern["col_normal"]
+    roofline = {"bound": "alu", "achieved": round(kc["tflops"], 3), "peak": FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(kc["tflops"] / FP64_VALU_TFLOPS, 4), "traffic": None,
+                "kernel": "k_col<COL_NORMAL>", "us_per_launch": round(kc["us"], 2),
+                "hbm_gbs": round(kc["gbs"], 1), "hbm_frac": round(kc["gbs"] / (HBM_TBS * 1e3), 4)}
+
+    out = {"metric": "slice-groups/sec (256^2, 32 coils, MB=3, 4 shots) @ NRMSE vs FP64 oracle",
+           "value": args.steps / wall, "unit": "slice-groups/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {g.n}x{g.n}, MB={g.n_slices}, {g.n_shots} shots, "
+                                  f"{g.n_coils} coils, {g.filt}x{g.filt} filter, lambda={g.lam}, "
+                                  f"{g.n_irls} IRLS x {g.n_cg} CG, inputs c64, arithmetic f64",
+                      "global_batch": 1},
+           "roofline": roofline,
+           "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
+           "solve_status": smsm.status_string(status)}
+
+    if not args.no_cpu_baseline and args.gpus == 1:
+        from oracle import smsm_oracle as o
+        _, y_or = o.simulate(case, g.n_slices, g.snr)
+        y_or = y_or.astype(np.complex64)
+        ref_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}_seed0.npy")
+        if os.path.exists(ref_path):
+            plan.solve(torch.from_numpy(y_or).to(dev), x)
+            out["nrmse_vs_oracle"] = o.nrmse(x.cpu().numpy(), np.load(ref_path))
+        out["cpu_baseline"] = cpu_baseline(g, case, y_or.astype(np.complex128))
+    plan.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

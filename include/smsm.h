@@ -1,0 +1,187 @@
+/*
+ * smsm.h - C ABI of the MI355X SMS-MUSSELS solver.
+ *
+ * The library reconstructs simultaneous-multislice (SMS), multi-shot
+ * diffusion k-space by minimising
+ *
+ *     || A(x) - y ||^2  +  lambda * sum_l || H_l(x_l) ||_*          (Eq. 10)
+ *
+ * (Mani et al., "SMS MUSSELS", Theory section, Eq. 10) with iteratively
+ * reweighted least squares: for k = 0 .. n_irls-1 the weights
+ * W_l = (H_l^H H_l + eps_l I)^(-1/2) are formed from the current iterate and
+ * n_cg conjugate-gradient steps are taken on
+ *
+ *     N(x) = A^H A x + (lambda/2) sum_l H_l^H(H_l(x_l) W_l) = A^H y.
+ *
+ * Operators (all conventions fixed here, the paper leaves them open):
+ *  - DFT F: centred and unitary, DC at index n/2 in both domains.
+ *  - A (Fig. 1): (A x)_{i,c} = M_i . sum_l theta_l . F(S_{l,c} . F^-1(x_{l,i}))
+ *    with theta_l[j2] = exp(-2 pi i s_l (j2 - n2/2)) (blipped CAIPI, Eq. 1
+ *    and its multi-shot form Eq. 3) and M_i the ky lines of shot i (Eq. 2).
+ *  - H_l (Eq. 8-9): rows = valid r x r patch anchors (n2-r+1)(n1-r+1),
+ *    columns = (shot, b2, b1); entry x_{l,i}[p2+b2][p1+b1].
+ *  - eps_l(k) = max(eps_frac * eps_decay^-k, eps_floor_frac) * sigma_l with
+ *    sigma_l the largest eigenvalue of H_l^H H_l at x0 = A^H y; a slice with
+ *    sigma_l = 0 is not regularised.
+ *
+ * Layouts: row-major, kx (n1) fastest.  Complex numbers are interleaved
+ * (re, im) pairs: "c64" = 2 x float, "c128" = 2 x double.
+ *   x    [L][Ns][n2][n1]   slice-unfolded k-space of every shot
+ *   y    [Ns][Nc][n2][n1]  measured k-space, zero-filled; entries of ky
+ *                          lines a shot does not acquire are ignored
+ *   S    [L][Nc][n2][n1]   coil sensitivities per slice (image domain)
+ *   G, W [L][K][K]         K = Ns r^2, row/column index (i*r + b2)*r + b1
+ *
+ * Pointers named *_dev are device pointers of the device that was current
+ * when the plan was created; host pointers are read during the call only.
+ * Every entry point that takes a stream enqueues its work on that stream
+ * (NULL = the default stream) and returns without waiting; kernel faults
+ * show at the caller's next synchronisation.  A plan is not re-entrant: use
+ * it from one stream at a time.  No entry point aborts or throws; invalid
+ * arguments are reported synchronously through the return status.
+ */
+#ifndef SMSM_H
+#define SMSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smsm_plan smsm_plan;   /* opaque */
+
+typedef enum {
+    SMSM_OK = 0,
+    SMSM_E_INVALID = -1,      /* bad pointer, size or parameter */
+    SMSM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. a sampling pattern) */
+    SMSM_E_NOMEM = -3,        /* device allocation failed in plan creation */
+    SMSM_E_DEVICE = -4,       /* a HIP runtime call failed */
+    SMSM_E_NUMERIC = -5       /* NaN/Inf met in the CG recurrences (smsm_plan_status) */
+} smsm_status;
+
+typedef struct {
+    int32_t n1;        /* kx / readout size; power of two, 16..256 */
+    int32_t n2;        /* ky / phase-encode size; power of two, 16..256 */
+    int32_t n_slices;  /* L, simultaneously excited slices, 1..4 */
+    int32_t n_shots;   /* Ns, interleaved shots, power of two 1..8, n2/Ns >= 8 */
+    int32_t n_coils;   /* Nc, receive channels, >= 1 */
+    int32_t filt;      /* r, Hankel filter support, 2 <= r, Ns r^2 <= 256, 2r-1 <= min(n1,n2)/2 */
+} smsm_geometry;
+
+typedef struct {
+    double  lambda;          /* lambda of Eq. 10, >= 0 */
+    int32_t n_irls;          /* IRLS iterations, >= 1 */
+    int32_t n_cg;            /* CG iterations per IRLS iteration, >= 0 */
+    double  eps_frac;        /* eps schedule start (fraction of sigma_l), > 0 */
+    double  eps_decay;       /* eta >= 1 */
+    double  eps_floor_frac;  /* >= 0 */
+    int32_t ns_max_iter;     /* cap on Newton-Schulz iterations for W (0 = 60) */
+    uint32_t flags;          /* SMSM_FLAG_* */
+} smsm_params;
+
+/* x written by smsm_solve is complex128 instead of complex64. */
+#define SMSM_FLAG_X_C128 0x1u
+
+/*
+ * Create a plan for one geometry.  coil_maps_dev: c64 [L][Nc][n2][n1] on
+ * the current device, copied (re-laid out) into the plan on `stream`, which
+ * the call synchronises before returning.  shot_mask: host uint8 [Ns][n2],
+ * 1 where shot i acquires ky line j2; this build supports the interleaved
+ * pattern of Eq. 2 only (j2 % Ns == i) and returns SMSM_E_UNSUPPORTED for
+ * any other.  caipi_shift: host [L] shift of each slice as a fraction of
+ * the FOV (NULL = l/L).  All device memory the plan needs is allocated here
+ * and released by smsm_plan_destroy.  On failure *out is NULL.
+ */
+smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* params,
+                             const void* coil_maps_dev, const uint8_t* shot_mask,
+                             const double* caipi_shift, void* stream, smsm_plan** out);
+
+/* Release the plan and its device memory (synchronises the device first). NULL is a no-op. */
+smsm_status smsm_plan_destroy(smsm_plan* plan);
+
+/* Bytes of device memory the plan holds. */
+size_t smsm_plan_device_bytes(const smsm_plan* plan);
+
+/* Replace the solver parameters of an existing plan (same geometry). */
+smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params);
+
+/*
+ * The IRLS solve.  y_dev: c64 [Ns][Nc][n2][n1]; x_dev: c64 (or c128 with
+ * SMSM_FLAG_X_C128) [L][Ns][n2][n1]; y and x must not overlap.  All work is
+ * asynchronous on `stream`; no device memory is allocated.
+ */
+smsm_status smsm_solve(smsm_plan* plan, const void* y_dev, void* x_dev, void* stream);
+
+/*
+ * Numeric status of the last solve: SMSM_E_NUMERIC if a CG step met a
+ * non-finite or non-positive curvature, else SMSM_OK.  Synchronises the
+ * device and clears the flag.
+ */
+smsm_status smsm_plan_status(smsm_plan* plan);
+
+/* Static description of a status code. */
+const char* smsm_status_string(smsm_status s);
+
+/* ---- operator entry points (one kernel chain each, asynchronous) ------- */
+
+/* y = A x (Fig. 1).  x_dev c128 [L][Ns][n2][n1] -> y_dev c128 [Ns][Nc][n2][n1]
+ * (lines a shot does not acquire are written as zero). */
+smsm_status smsm_apply_A(smsm_plan* plan, const void* x_dev, void* y_dev, void* stream);
+
+/* x = A^H y.  y_dev c64 [Ns][Nc][n2][n1] (as smsm_solve takes it) -> x_dev c128. */
+smsm_status smsm_apply_AH(smsm_plan* plan, const void* y_dev, void* x_dev, void* stream);
+
+/* out = A^H A x, c128 -> c128. */
+smsm_status smsm_apply_AHA(smsm_plan* plan, const void* x_dev, void* out_dev, void* stream);
+
+/* G_l = H_l(x_l)^H H_l(x_l) for every slice: x c128 -> G c128 [L][K][K] (Eq. 8-9). */
+smsm_status smsm_gram(smsm_plan* plan, const void* x_dev, void* g_dev, void* stream);
+
+/* W_l = (G_l + eps_l I)^(-1/2): G c128 [L][K][K] -> W c128 [L][K][K], by a
+ * coupled Newton-Schulz iteration run to convergence.  eps: host [L];
+ * eps_l <= 0 gives W_l = 0 (unregularised slice).  Synchronises `stream`. */
+smsm_status smsm_weights(smsm_plan* plan, const void* g_dev, const double* eps,
+                         void* w_dev, void* stream);
+
+/* Largest eigenvalue of each G_l: G c128 [L][K][K] -> lmax_dev double [L]. */
+smsm_status smsm_lambda_max(smsm_plan* plan, const void* g_dev, void* lmax_dev, void* stream);
+
+/* Load weights W c128 [L][K][K] into the plan (used by smsm_apply_reg and
+ * smsm_apply_normal until the next solve). */
+smsm_status smsm_set_weights(smsm_plan* plan, const void* w_dev, void* stream);
+
+/* out = (lambda/2) sum_l H_l^H(H_l(x_l) W_l) with the loaded weights, c128 -> c128. */
+smsm_status smsm_apply_reg(smsm_plan* plan, const void* x_dev, void* out_dev, void* stream);
+
+/* out = N(x) = A^H A x + (lambda/2) sum_l H_l^H(H_l(x_l) W_l), c128 -> c128. */
+smsm_status smsm_apply_normal(smsm_plan* plan, const void* x_dev, void* out_dev, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+
+/* Kernels of one CG iteration that smsm_launch_kernel can re-run. */
+typedef enum {
+    SMSM_KERNEL_COL_NORMAL = 0,  /* per-column SENSE coil loop + image-domain Hankel term */
+    SMSM_KERNEL_ROWS_INV = 1,    /* kx inverse DFT of p, transposed write */
+    SMSM_KERNEL_ROWS_FWD = 2,    /* kx forward DFT + band correction + <p,q> partials */
+    SMSM_KERNEL_BAND_CORR = 3,   /* Hankel band correction */
+    SMSM_KERNEL_CG_UPDATE = 4    /* x, r update and |r|^2 partials */
+} smsm_kernel_id;
+
+/*
+ * Launch one kernel of the CG iteration `reps` times back to back on the
+ * plan's internal buffers (whatever the last solve left there), for timing
+ * and profiling.  The plan's vectors are overwritten; call smsm_solve again
+ * before reading results.  Asynchronous on `stream`.
+ */
+smsm_status smsm_launch_kernel(smsm_plan* plan, int kernel_id, int reps, void* stream);
+
+/* Algorithmic cost of one launch of a kernel of smsm_launch_kernel for this
+ * plan's geometry: FP64 flops and compulsory HBM bytes (reads + writes). */
+smsm_status smsm_kernel_cost(const smsm_plan* plan, int kernel_id, double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMSM_H */

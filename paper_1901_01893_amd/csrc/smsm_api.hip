@@ -1,0 +1,679 @@
+// Host side of the SMS-MUSSELS solver: plan creation, device memory layout,
+// and the kernel sequences behind every C-ABI entry point of smsm.h.
+#include "smsm_kernels.h"
+#include "smsm.h"
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kColThreads = 512;
+constexpr int kVecBlocks = 512;      // fixed grid of the CG vector kernels
+constexpr int kNsDefaultIters = 60;  // Newton-Schulz iteration cap
+constexpr int kSqSteps = 30;         // squarings for the largest eigenvalue
+constexpr double kNsTol = 1e-10;     // ||I - Z Y||_F at which NS is converged
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct smsm_plan {
+    Geo g;
+    smsm_params prm;
+    int dev = 0;
+    int TR = 1, TRy = 1;
+    int npq = 0;             // blocks of the forward row pass (partials of <p,q>)
+    int ntile = 0;           // GEMM tiles per slice
+    size_t lds_rows = 0, lds_col = 0, lds_gram = 0;
+    bool have_weights = false;
+    void* arena = nullptr;
+    size_t bytes = 0;
+    // device buffers
+    float2* ST = nullptr;                     // coils [L][Nc][n1][n2]
+    double2 *tw1 = nullptr, *tw2 = nullptr, *twM = nullptr;
+    double2 *theta = nullptr, *tau = nullptr;
+    double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+    double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
+    double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
+    double2 *Kc = nullptr, *D = nullptr, *corr = nullptr;
+    double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
+    double *pr = nullptr, *pq = nullptr, *nspart = nullptr, *sigma = nullptr, *eps = nullptr;
+    double *wscale = nullptr, *sqscale = nullptr, *epsin = nullptr;
+    int *done = nullptr, *flags = nullptr;
+    int ns_iters = kNsDefaultIters;
+};
+
+namespace {
+
+#define LAUNCH_CHECK()                                      \
+    do {                                                    \
+        if (hipGetLastError() != hipSuccess) return SMSM_E_DEVICE; \
+    } while (0)
+
+smsm_status check_params(const smsm_params* p) {
+    if (!p) return SMSM_E_INVALID;
+    if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return SMSM_E_INVALID;
+    if (p->n_irls < 1 || p->n_cg < 0) return SMSM_E_INVALID;
+    if (!(p->eps_frac > 0.0) || !(p->eps_decay >= 1.0) || !(p->eps_floor_frac >= 0.0)) return SMSM_E_INVALID;
+    if (p->ns_max_iter < 0 || p->ns_max_iter > 200) return SMSM_E_INVALID;
+    return SMSM_OK;
+}
+
+void twiddles(int n, std::vector<double2>& out) {
+    out.resize(n);
+    for (int k = 0; k < n; ++k) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
+        out[k] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+}
+
+// Carve 256-byte aligned pieces out of one allocation.
+struct Carver {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        const size_t o = (off + 255) & ~size_t(255);
+        off = o + count * sizeof(T);
+        return o;
+    }
+};
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+dim3 vec_grid() { return dim3(kVecBlocks); }
+
+// ---- kernel chains -------------------------------------------------------
+smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
+    const Geo& g = P->g;
+    dim3 grid(g.n2 / P->TR, g.B);
+    hipLaunchKernelGGL(k_rows_inv_T<ROWS_PLAIN>, grid, dim3(kThreads), P->lds_rows, st, g, in, out,
+                       nullptr, nullptr, nullptr, nullptr, 0, P->tw1, P->TR);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+template <bool CG, bool BAND>
+smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, const double2* pvec, hipStream_t st) {
+    const Geo& g = P->g;
+    dim3 grid(g.n2 / P->TR, g.B);
+    hipLaunchKernelGGL((k_rows_fwd_T<CG, BAND>), grid, dim3(kThreads), P->lds_rows, st, g, in, out,
+                       P->corr, pvec, P->pq, P->tw1, P->TR);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+template <int MODE>
+smsm_status col(smsm_plan* P, int use_reg, hipStream_t st) {
+    const Geo& g = P->g;
+    hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, P->h1, P->h2,
+                       P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status band_corr(smsm_plan* P, const double2* vin, hipStream_t st) {
+    const Geo& g = P->g;
+    const int total = g.B * g.nband;
+    hipLaunchKernelGGL(k_band_corr, dim3((total + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g,
+                       vin, P->D, P->corr);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status band_tables(smsm_plan* P, hipStream_t st) {
+    const Geo& g = P->g;
+    const long total = (long)g.L * g.nc * g.nc * g.Ns * g.Ns * g.nc * g.nc;
+    const int blocks = (int)std::min<long>(8192, (total + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
+                       P->Kc, P->D);
+    LAUNCH_CHECK();
+    P->have_weights = true;
+    return SMSM_OK;
+}
+
+// b' = A^H y (y c64) into `out`.
+smsm_status chain_AH(smsm_plan* P, const float2* y, double2* out, hipStream_t st) {
+    const Geo& g = P->g;
+    hipLaunchKernelGGL(k_yrows_inv, dim3(g.M / P->TRy, g.Ns * g.Nc), dim3(kThreads), P->lds_rows, st, g, y,
+                       P->ytil, P->tw1, P->TRy);
+    LAUNCH_CHECK();
+    smsm_status s = col<COL_ADJ>(P, 0, st);
+    if (s) return s;
+    return rows_fwd<false, false>(P, P->h2, out, nullptr, st);
+}
+
+// out = N(v) (use_reg) or A^H A v.
+smsm_status chain_normal(smsm_plan* P, const double2* v, double2* out, bool use_reg, hipStream_t st) {
+    smsm_status s = rows_inv(P, v, P->h1, st);
+    if (s) return s;
+    if (use_reg) {
+        if ((s = col<COL_NORMAL>(P, 1, st))) return s;
+        if ((s = band_corr(P, v, st))) return s;
+        return rows_fwd<false, true>(P, P->h2, out, nullptr, st);
+    }
+    if ((s = col<COL_NORMAL>(P, 0, st))) return s;
+    return rows_fwd<false, false>(P, P->h2, out, nullptr, st);
+}
+
+smsm_status chain_gram(smsm_plan* P, const double2* v, double2* G, hipStream_t st) {
+    const Geo& g = P->g;
+    smsm_status s = rows_inv(P, v, P->h1, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_gram_col, dim3(g.n1), dim3(kThreads), P->lds_gram, st, g, P->h1, P->tw2, P->tw1,
+                       P->gpart);
+    LAUNCH_CHECK();
+    const int per = g.L * g.npairs * g.nc * g.nc;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((per + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g,
+                       P->gpart, P->gC);
+    LAUNCH_CHECK();
+    const long nb = (long)per * (2 * 2 * g.e + 4 * g.e * g.e);
+    const int blocks = (int)std::min<long>(8192, (nb + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_gram_band, dim3(blocks), dim3(kThreads), 0, st, g, v, P->grow, P->gcol, P->gcor);
+    LAUNCH_CHECK();
+    const long tot = (long)g.L * g.K * g.K;
+    hipLaunchKernelGGL(k_gram_assemble, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       g, P->gC, P->grow, P->gcol, P->gcor, G);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+dim3 gemm_grid(const Geo& g, int z) {
+    const int t = (g.K + GT - 1) / GT;
+    return dim3(t, t, z);
+}
+
+// W = (G + eps I)^(-1/2) with eps_l = mult * src[l] (device array).
+smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, double mult, hipStream_t st) {
+    const Geo& g = P->g;
+    const int nit = P->ns_iters;
+    hipLaunchKernelGGL(k_ns_init, dim3(g.L), dim3(kThreads), 0, st, g.K, g.L, G, src, mult, P->Y0, P->Z0,
+                       P->wscale, P->done, nit);
+    LAUNCH_CHECK();
+    double2* Y[2] = {P->Y0, P->Y1};
+    double2* Z[2] = {P->Z0, P->Z1};
+    for (int k = 0; k < nit; ++k) {
+        const int a = k & 1, bsel = a ^ 1;
+        hipLaunchKernelGGL(k_cgemm<EPI_NS>, gemm_grid(g, g.L), dim3(kThreads), 0, st, g.K, g.L, Z[a], Y[a],
+                           P->T, nullptr, P->done + (size_t)k * g.L, P->nspart);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_ns_update, gemm_grid(g, 2 * g.L), dim3(kThreads), 0, st, g.K, g.L, Y[a], Z[a],
+                           P->T, Y[bsel], Z[bsel], P->nspart, P->ntile, P->done + (size_t)k * g.L,
+                           P->done + (size_t)(k + 1) * g.L, kNsTol * kNsTol);
+        LAUNCH_CHECK();
+    }
+    const long tot = (long)g.L * g.K * g.K;
+    hipLaunchKernelGGL(k_ns_final, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g.K,
+                       g.L, Z[nit & 1], P->wscale, P->W);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// lmax[l] = largest eigenvalue of G_l by repeated normalised squaring.
+smsm_status chain_lmax(smsm_plan* P, const double2* G, double* lmax, hipStream_t st) {
+    const Geo& g = P->g;
+    hipLaunchKernelGGL(k_fro_inv, dim3(g.L), dim3(kThreads), 0, st, g.K, G, P->sqscale);
+    LAUNCH_CHECK();
+    const double2* cur = G;
+    double2* buf[2] = {P->Y0, P->Y1};
+    for (int k = 0; k < kSqSteps; ++k) {
+        double2* nxt = buf[k & 1];
+        hipLaunchKernelGGL(k_cgemm<EPI_NORM>, gemm_grid(g, g.L), dim3(kThreads), 0, st, g.K, g.L, cur, cur,
+                           nxt, P->sqscale, nullptr, P->nspart);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_part_inv, dim3(g.L), dim3(kThreads), 0, st, P->nspart, P->ntile, P->sqscale);
+        LAUNCH_CHECK();
+        cur = nxt;
+    }
+    hipLaunchKernelGGL(k_sq_final, dim3(g.L), dim3(kThreads), 0, st, g.K, G, cur, lmax);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* smsm_status_string(smsm_status s) {
+    switch (s) {
+        case SMSM_OK: return "ok";
+        case SMSM_E_INVALID: return "invalid argument";
+        case SMSM_E_UNSUPPORTED: return "unsupported geometry or sampling pattern";
+        case SMSM_E_NOMEM: return "device allocation failed";
+        case SMSM_E_DEVICE: return "HIP runtime error";
+        case SMSM_E_NUMERIC: return "non-finite or non-positive CG curvature";
+    }
+    return "unknown status";
+}
+
+smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* params, const void* coil_maps_dev,
+                             const uint8_t* shot_mask, const double* caipi_shift, void* stream,
+                             smsm_plan** out) {
+    if (!out) return SMSM_E_INVALID;
+    *out = nullptr;
+    if (!geom || !coil_maps_dev || !shot_mask) return SMSM_E_INVALID;
+    smsm_status ps = check_params(params);
+    if (ps) return ps;
+    const int n1 = geom->n1, n2 = geom->n2, L = geom->n_slices, Ns = geom->n_shots, Nc = geom->n_coils,
+              r = geom->filt;
+    if (n1 <= 0 || n2 <= 0 || L <= 0 || Ns <= 0 || Nc <= 0 || r <= 0) return SMSM_E_INVALID;
+    if (!is_pow2(n1) || !is_pow2(n2) || n1 < 16 || n2 < 16 || n1 > 256 || n2 > 256) return SMSM_E_UNSUPPORTED;
+    if (!is_pow2(Ns) || Ns > 8 || n2 / Ns < 8 || L > 4) return SMSM_E_UNSUPPORTED;
+    if (r < 2 || 2 * r - 1 > std::min(n1, n2) / 2 || Ns * r * r > 256) return SMSM_E_UNSUPPORTED;
+    // interleaved sampling of Eq. 2 only
+    for (int i = 0; i < Ns; ++i)
+        for (int j = 0; j < n2; ++j)
+            if ((shot_mask[i * n2 + j] != 0) != (j % Ns == i)) return SMSM_E_UNSUPPORTED;
+
+    smsm_plan* P = new (std::nothrow) smsm_plan();
+    if (!P) return SMSM_E_NOMEM;
+    if (hipGetDevice(&P->dev) != hipSuccess) { delete P; return SMSM_E_DEVICE; }
+    Geo& g = P->g;
+    g.n1 = n1; g.n2 = n2; g.L = L; g.Ns = Ns; g.Nc = Nc; g.r = r;
+    g.K = Ns * r * r; g.nc = 2 * r - 1; g.e = r - 1; g.M = n2 / Ns;
+    g.logn1 = ilog2(n1); g.logn2 = ilog2(n2); g.logM = ilog2(g.M);
+    g.B = L * Ns;
+    g.nband = 2 * g.e * n1 + 2 * g.e * (n2 - 2 * g.e);
+    g.npairs = Ns * (Ns + 1) / 2;
+    P->prm = *params;
+    P->ns_iters = params->ns_max_iter > 0 ? params->ns_max_iter : kNsDefaultIters;
+
+    P->TR = std::max(1, std::min(n2, 2048 / n1));
+    P->TRy = std::min(g.M, P->TR);
+    P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
+    P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
+    P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
+    P->npq = (n2 / P->TR) * g.B;
+    P->ntile = ((g.K + GT - 1) / GT) * ((g.K + GT - 1) / GT);
+    int max_lds = 0;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
+    if (max_lds <= 0) max_lds = 65536;
+    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds) { delete P; return SMSM_E_UNSUPPORTED; }
+
+    // device memory layout
+    const size_t nvec = (size_t)L * Ns * n2 * n1;
+    const size_t KK = (size_t)L * g.K * g.K;
+    const size_t ntab = (size_t)L * g.nc * g.nc * Ns * Ns * g.nc * g.nc;
+    const size_t nper = (size_t)L * g.npairs * g.nc * g.nc;
+    Carver cv;
+    const size_t oST = cv.take<float2>((size_t)L * Nc * n1 * n2);
+    const size_t otw1 = cv.take<double2>(n1), otw2 = cv.take<double2>(n2), otwM = cv.take<double2>(g.M);
+    const size_t oth = cv.take<double2>((size_t)L * n2), otau = cv.take<double2>((size_t)Ns * n2);
+    const size_t ox = cv.take<double2>(nvec), ob = cv.take<double2>(nvec), orr = cv.take<double2>(nvec);
+    const size_t op = cv.take<double2>(nvec), oq = cv.take<double2>(nvec);
+    const size_t oh1 = cv.take<double2>(nvec), oh2 = cv.take<double2>(nvec);
+    const size_t oyt = cv.take<double2>((size_t)Ns * Nc * n1 * g.M);
+    const size_t oG = cv.take<double2>(KK), oW = cv.take<double2>(KK);
+    const size_t oY0 = cv.take<double2>(KK), oY1 = cv.take<double2>(KK);
+    const size_t oZ0 = cv.take<double2>(KK), oZ1 = cv.take<double2>(KK), oT = cv.take<double2>(KK);
+    const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
+    const size_t oD = cv.take<double2>(ntab);
+    const size_t ocorr = cv.take<double2>((size_t)g.B * g.nband);
+    const size_t ogp = cv.take<double2>(nper * n1), ogC = cv.take<double2>(nper);
+    const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
+    const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
+    const size_t opr = cv.take<double>(3 * kVecBlocks), opq = cv.take<double>(P->npq);
+    const size_t onsp = cv.take<double>((size_t)L * P->ntile);
+    const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
+    const size_t osq = cv.take<double>(L), oei = cv.take<double>(L);
+    const size_t odone = cv.take<int>((size_t)(P->ns_iters + 1) * L), oflags = cv.take<int>(4);
+    P->bytes = cv.off;
+    if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
+    char* base = static_cast<char*>(P->arena);
+    P->ST = (float2*)(base + oST);
+    P->tw1 = (double2*)(base + otw1); P->tw2 = (double2*)(base + otw2); P->twM = (double2*)(base + otwM);
+    P->theta = (double2*)(base + oth); P->tau = (double2*)(base + otau);
+    P->x = (double2*)(base + ox); P->b = (double2*)(base + ob); P->r = (double2*)(base + orr);
+    P->p = (double2*)(base + op); P->q = (double2*)(base + oq);
+    P->h1 = (double2*)(base + oh1); P->h2 = (double2*)(base + oh2); P->ytil = (double2*)(base + oyt);
+    P->G = (double2*)(base + oG); P->W = (double2*)(base + oW);
+    P->Y0 = (double2*)(base + oY0); P->Y1 = (double2*)(base + oY1);
+    P->Z0 = (double2*)(base + oZ0); P->Z1 = (double2*)(base + oZ1); P->T = (double2*)(base + oT);
+    P->Kc = (double2*)(base + oKc); P->D = (double2*)(base + oD); P->corr = (double2*)(base + ocorr);
+    P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
+    P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);
+    P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->nspart = (double*)(base + onsp);
+    P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
+    P->sqscale = (double*)(base + osq); P->epsin = (double*)(base + oei);
+    P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
+
+    // host tables: twiddles, CAIPI phases, shot modulation
+    std::vector<double2> t1, t2, tM, th((size_t)L * n2), ta((size_t)Ns * n2);
+    twiddles(n1, t1);
+    twiddles(n2, t2);
+    twiddles(g.M, tM);
+    for (int l = 0; l < L; ++l) {
+        const double s = caipi_shift ? caipi_shift[l] : (double)l / (double)L;
+        for (int j = 0; j < n2; ++j) {
+            const long double v = (long double)s * (long double)(j - n2 / 2);
+            const long double fr = v - floorl(v);
+            const long double a = -2.0L * 3.14159265358979323846264338327950288L * fr;
+            th[(size_t)l * n2 + j] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+    }
+    for (int i = 0; i < Ns; ++i)
+        for (int n = 0; n < n2; ++n) {
+            const double2 w = t2[(size_t)(i * n) % n2];
+            const double sg = (n & 1) ? -1.0 : 1.0;
+            ta[(size_t)i * n2 + n] = make_double2(sg * w.x, sg * w.y);
+        }
+    hipStream_t st = S(stream);
+    bool ok = hipMemcpyAsync(P->tw1, t1.data(), n1 * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->tw2, t2.data(), n2 * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->twM, tM.data(), g.M * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->theta, th.data(), th.size() * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->tau, ta.data(), ta.size() * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(k_transpose_coils, dim3(2048), dim3(kThreads), 0, st, n1, n2, (long)L * Nc,
+                           (const float2*)coil_maps_dev, P->ST);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    if (ok) {
+        hipLaunchKernelGGL(k_zero_c128, dim3(512), dim3(kThreads), 0, st, (long)(L * Ns * Ns * g.nc * g.nc), P->Kc);
+        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)ntab, P->D);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kThreads), 0, st, 4L, P->flags);
+        ok = hipGetLastError() == hipSuccess;
+    }
+    // shared-memory opt-in for the large column kernels
+    if (ok) {
+        const void* fns[] = {(const void*)&k_col<COL_NORMAL>, (const void*)&k_col<COL_FWD>,
+                             (const void*)&k_col<COL_ADJ>, (const void*)&k_col<COL_REG>,
+                             (const void*)&k_gram_col};
+        for (const void* f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
+    }
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        (void)hipFree(P->arena);
+        delete P;
+        return SMSM_E_DEVICE;
+    }
+    *out = P;
+    return SMSM_OK;
+}
+
+smsm_status smsm_plan_destroy(smsm_plan* plan) {
+    if (!plan) return SMSM_OK;
+    (void)hipSetDevice(plan->dev);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(plan->arena);
+    delete plan;
+    return SMSM_OK;
+}
+
+size_t smsm_plan_device_bytes(const smsm_plan* plan) { return plan ? plan->bytes : 0; }
+
+smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params) {
+    if (!plan) return SMSM_E_INVALID;
+    smsm_status s = check_params(params);
+    if (s) return s;
+    const int nit = params->ns_max_iter > 0 ? params->ns_max_iter : kNsDefaultIters;
+    if (nit > plan->ns_iters) return SMSM_E_UNSUPPORTED;   // done-flag array sized at creation
+    plan->prm = *params;
+    plan->ns_iters = nit;
+    return SMSM_OK;
+}
+
+smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
+    if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
+    const Geo& g = P->g;
+    const size_t nvec = (size_t)g.L * g.Ns * g.n2 * g.n1;
+    const size_t ny = (size_t)g.Ns * g.Nc * g.n2 * g.n1 * sizeof(float2);
+    const bool c128 = (P->prm.flags & SMSM_FLAG_X_C128) != 0;
+    const size_t nx = nvec * (c128 ? sizeof(double2) : sizeof(float2));
+    if (overlap(y_dev, ny, x_dev, nx)) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    const smsm_params& prm = P->prm;
+    const bool reg = prm.lambda > 0.0;
+    smsm_status s;
+
+    if ((s = chain_AH(P, (const float2*)y_dev, P->b, st))) return s;
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->b, P->x);
+    LAUNCH_CHECK();
+    if (reg) {
+        if ((s = chain_gram(P, P->x, P->G, st))) return s;
+        if ((s = chain_lmax(P, P->G, P->sigma, st))) return s;
+    }
+    double* PR[3] = {P->pr, P->pr + kVecBlocks, P->pr + 2 * kVecBlocks};
+    for (int k = 0; k < prm.n_irls; ++k) {
+        if (reg) {
+            if (k > 0 && (s = chain_gram(P, P->x, P->G, st))) return s;
+            const double frac = std::max(prm.eps_frac * std::pow(prm.eps_decay, -(double)k), prm.eps_floor_frac);
+            if ((s = chain_weights(P, P->G, P->sigma, frac, st))) return s;
+            if ((s = band_tables(P, st))) return s;
+        }
+        if ((s = chain_normal(P, P->x, P->q, reg, st))) return s;
+        hipLaunchKernelGGL(k_cg_init, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->b, P->q, P->r, PR[0]);
+        LAUNCH_CHECK();
+        for (int j = 0; j < prm.n_cg; ++j) {
+            const dim3 grid(g.n2 / P->TR, g.B);
+            if (j == 0)
+                hipLaunchKernelGGL(k_rows_inv_T<ROWS_CG_FIRST>, grid, dim3(kThreads), P->lds_rows, st, g,
+                                   (const double2*)nullptr, P->h1, P->r, P->p, (const double*)nullptr,
+                                   (const double*)nullptr, kVecBlocks, P->tw1, P->TR);
+            else
+                hipLaunchKernelGGL(k_rows_inv_T<ROWS_CG_UPDATE>, grid, dim3(kThreads), P->lds_rows, st, g,
+                                   (const double2*)nullptr, P->h1, P->r, P->p, PR[j % 3], PR[(j + 2) % 3],
+                                   kVecBlocks, P->tw1, P->TR);
+            LAUNCH_CHECK();
+            if ((s = col<COL_NORMAL>(P, reg ? 1 : 0, st))) return s;
+            if (reg) {
+                if ((s = band_corr(P, P->p, st))) return s;
+                if ((s = rows_fwd<true, true>(P, P->h2, P->q, P->p, st))) return s;
+            } else {
+                if ((s = rows_fwd<true, false>(P, P->h2, P->q, P->p, st))) return s;
+            }
+            hipLaunchKernelGGL(k_cg_update, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, P->p, P->r,
+                               P->q, PR[j % 3], kVecBlocks, P->pq, P->npq, PR[(j + 1) % 3], P->flags);
+            LAUNCH_CHECK();
+        }
+    }
+    if (c128)
+        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, (double2*)x_dev);
+    else
+        hipLaunchKernelGGL(k_to_c64, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, (float2*)x_dev);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status smsm_plan_status(smsm_plan* P) {
+    if (!P) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
+    int h = 0;
+    if (hipMemcpy(&h, P->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SMSM_E_DEVICE;
+    const int zero = 0;
+    if (hipMemcpy(P->flags, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SMSM_E_DEVICE;
+    return h ? SMSM_E_NUMERIC : SMSM_OK;
+}
+
+smsm_status smsm_apply_A(smsm_plan* P, const void* x_dev, void* y_dev, void* stream) {
+    if (!P || !x_dev || !y_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const Geo& g = P->g;
+    hipStream_t st = S(stream);
+    const long ny = (long)g.Ns * g.Nc * g.n2 * g.n1;
+    hipLaunchKernelGGL(k_zero_c128, vec_grid(), dim3(kThreads), 0, st, ny, (double2*)y_dev);
+    LAUNCH_CHECK();
+    smsm_status s = rows_inv(P, (const double2*)x_dev, P->h1, st);
+    if (s) return s;
+    if ((s = col<COL_FWD>(P, 0, st))) return s;
+    hipLaunchKernelGGL(k_yrows_fwd, dim3(g.M / P->TRy, g.Ns * g.Nc), dim3(kThreads), P->lds_rows, st, g,
+                       P->ytil, (double2*)y_dev, P->tw1, P->TRy);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status smsm_apply_AH(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
+    if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return chain_AH(P, (const float2*)y_dev, (double2*)x_dev, S(stream));
+}
+
+smsm_status smsm_apply_AHA(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
+    if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, false, S(stream));
+}
+
+smsm_status smsm_gram(smsm_plan* P, const void* x_dev, void* g_dev, void* stream) {
+    if (!P || !x_dev || !g_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return chain_gram(P, (const double2*)x_dev, (double2*)g_dev, S(stream));
+}
+
+smsm_status smsm_weights(smsm_plan* P, const void* g_dev, const double* eps, void* w_dev, void* stream) {
+    if (!P || !g_dev || !eps || !w_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const Geo& g = P->g;
+    hipStream_t st = S(stream);
+    if (hipMemcpyAsync(P->epsin, eps, g.L * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+        return SMSM_E_DEVICE;
+    smsm_status s = chain_weights(P, (const double2*)g_dev, P->epsin, 1.0, st);
+    if (s) return s;
+    if (hipMemcpyAsync(w_dev, P->W, (size_t)g.L * g.K * g.K * sizeof(double2), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+        return SMSM_E_DEVICE;
+    return hipStreamSynchronize(st) == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_lambda_max(smsm_plan* P, const void* g_dev, void* lmax_dev, void* stream) {
+    if (!P || !g_dev || !lmax_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return chain_lmax(P, (const double2*)g_dev, (double*)lmax_dev, S(stream));
+}
+
+smsm_status smsm_set_weights(smsm_plan* P, const void* w_dev, void* stream) {
+    if (!P || !w_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const Geo& g = P->g;
+    hipStream_t st = S(stream);
+    if (hipMemcpyAsync(P->W, w_dev, (size_t)g.L * g.K * g.K * sizeof(double2), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+        return SMSM_E_DEVICE;
+    return band_tables(P, st);
+}
+
+smsm_status smsm_apply_reg(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
+    if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (!P->have_weights) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    smsm_status s = rows_inv(P, (const double2*)x_dev, P->h1, st);
+    if (s) return s;
+    if ((s = col<COL_REG>(P, 1, st))) return s;
+    if ((s = band_corr(P, (const double2*)x_dev, st))) return s;
+    return rows_fwd<false, true>(P, P->h2, (double2*)out_dev, nullptr, st);
+}
+
+smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
+    if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (!P->have_weights) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, true, S(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// Algorithmic FP64 flops and compulsory bytes of one launch (see smsm.h).
+void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
+    const double n1 = g.n1, n2 = g.n2, B = g.B, L = g.L, Ns = g.Ns, Nc = g.Nc, M = g.M, nc = g.nc;
+    const double vec = B * n1 * n2 * 16.0;               // one c128 vector
+    auto F = [](double n) { return 5.0 * n * std::log2(n); };
+    double f = 0.0, b = 0.0;
+    switch (id) {
+        case SMSM_KERNEL_COL_NORMAL: {
+            const double per_col =
+                2.0 * B * F(n2)                                   // ky inverse + forward DFT
+                + 6.0 * B * n2 * 2.0                              // tau modulation and final scaling
+                + Nc * (8.0 * B * n2                              // fold
+                        + 2.0 * B * F(M)                          // pruned DFT + inverse
+                        + Ns * M * L * 14.0                       // CAIPI slice sum and split
+                        + 8.0 * B * n2)                           // unfold-accumulate
+                + L * Ns * Ns * nc * nc * 8.0                     // kx taps of the Hankel kernel
+                + B * n2 * Ns * (nc * 8.0 + 14.0);                // per-pixel Hankel term
+            f = n1 * per_col;
+            b = 2.0 * vec + L * Nc * n1 * n2 * 8.0;
+            break;
+        }
+        case SMSM_KERNEL_ROWS_INV:
+            f = B * n2 * F(n1);
+            b = 2.0 * vec;
+            break;
+        case SMSM_KERNEL_ROWS_FWD:
+            f = B * n2 * F(n1) + B * n1 * n2 * 4.0;
+            b = 3.0 * vec + B * g.nband * 16.0;
+            break;
+        case SMSM_KERNEL_BAND_CORR:
+            f = B * g.nband * Ns * nc * nc * 8.0;
+            b = B * g.nband * 16.0 + L * nc * nc * Ns * Ns * nc * nc * 16.0 +
+                B * (2.0 * g.e + nc) * (n1 + n2) * 2.0 * 16.0;
+            break;
+        case SMSM_KERNEL_CG_UPDATE:
+            f = B * n1 * n2 * 14.0;
+            b = 6.0 * vec;
+            break;
+        default:
+            break;
+    }
+    *flops = f;
+    *bytes = b;
+}
+
+}  // namespace
+
+extern "C" {
+
+smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* bytes) {
+    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_CG_UPDATE) return SMSM_E_INVALID;
+    kernel_cost(P->g, id, flops, bytes);
+    return SMSM_OK;
+}
+
+smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
+    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_CG_UPDATE) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    const Geo& g = P->g;
+    const size_t nvec = (size_t)g.L * g.Ns * g.n2 * g.n1;
+    const bool reg = P->prm.lambda > 0.0 && P->have_weights;
+    for (int k = 0; k < reps; ++k) {
+        smsm_status s = SMSM_OK;
+        switch (id) {
+            case SMSM_KERNEL_COL_NORMAL: s = col<COL_NORMAL>(P, reg ? 1 : 0, st); break;
+            case SMSM_KERNEL_ROWS_INV: s = rows_inv(P, P->p, P->h1, st); break;
+            case SMSM_KERNEL_ROWS_FWD:
+                s = reg ? rows_fwd<true, true>(P, P->h2, P->q, P->p, st)
+                        : rows_fwd<true, false>(P, P->h2, P->q, P->p, st);
+                break;
+            case SMSM_KERNEL_BAND_CORR: s = band_corr(P, P->p, st); break;
+            case SMSM_KERNEL_CG_UPDATE:
+                hipLaunchKernelGGL(k_cg_update, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, P->p, P->r,
+                                   P->q, P->pr, kVecBlocks, P->pq, P->npq, P->pr + kVecBlocks, P->flags);
+                LAUNCH_CHECK();
+                break;
+        }
+        if (s) return s;
+    }
+    return SMSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Device-side helpers for the SMS-MUSSELS kernels: complex double arithmetic,
+// block reductions and a batched in-LDS radix-2 FFT.
+//
+// All arithmetic is FP64.  Complex numbers are double2 (re, im).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SMSM_DEV __device__ __forceinline__
+
+SMSM_DEV double2 cmk(double re, double im) { return make_double2(re, im); }
+SMSM_DEV double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+SMSM_DEV double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+SMSM_DEV double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+SMSM_DEV double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+SMSM_DEV double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+SMSM_DEV double2 cmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// conj(a) * b
+SMSM_DEV double2 cconjmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// acc + a * b
+SMSM_DEV double2 cfma(double2 a, double2 b, double2 acc) {
+    return make_double2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+SMSM_DEV double2 c64to128(float2 v) { return make_double2((double)v.x, (double)v.y); }
+SMSM_DEV double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// (-1)^k as a double
+SMSM_DEV double sgn_pow(int k) { return (k & 1) ? -1.0 : 1.0; }
+
+// Sum of one double over the block, in a fixed order (deterministic).
+// `scratch` must hold blockDim.x/64 doubles of shared memory.  Every thread
+// must call it; the result is valid in all threads.
+SMSM_DEV double block_sum(double v, double* scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, warp = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[warp] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += scratch[w];
+    __syncthreads();
+    return s;
+}
+
+// Sum of `n` partial values in a fixed order (each thread of the block gets
+// the same result).  Used to turn per-block partials into a scalar.
+SMSM_DEV double sum_partials(const double* __restrict__ part, int n, double* scratch) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) v += part[k];
+    return block_sum(v, scratch);
+}
+
+// Batched in-place FFT in shared memory.
+// nb sequences of length n = 2^logn; sequence b occupies buf[b*stride + j].
+// Forward computes X[k] = sum_j x[j] e^{-2 pi i jk/n}; inverse uses e^{+...}
+// (both unnormalised).  tw[k] = e^{-2 pi i k/n} for k < n/2 (global or shared).
+// All threads of the block must call it; it starts and ends with a barrier.
+SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
+                            const double2* __restrict__ tw, bool inverse) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __syncthreads();
+    if (logn == 0) return;
+    for (int idx = tid; idx < nb * n; idx += nt) {
+        const int b = idx >> logn, j = idx & (n - 1);
+        const int rj = (int)(__brev((unsigned)j) >> (32 - logn));
+        if (j < rj) {
+            double2* s = buf + b * stride;
+            const double2 t = s[j];
+            s[j] = s[rj];
+            s[rj] = t;
+        }
+    }
+    __syncthreads();
+    const int hn = n >> 1;
+    for (int s = 0; s < logn; ++s) {
+        const int half = 1 << s;
+        for (int idx = tid; idx < nb * hn; idx += nt) {
+            const int b = idx / hn, k = idx - b * hn;
+            const int pos = k & (half - 1);
+            const int i0 = ((k >> s) << (s + 1)) + pos;
+            const int i1 = i0 + half;
+            double2 w = tw[pos << (logn - 1 - s)];
+            if (inverse) w.y = -w.y;
+            double2* base = buf + b * stride;
+            const double2 a = base[i0];
+            const double2 c = cmul(base[i1], w);
+            base[i0] = cadd(a, c);
+            base[i1] = csub(a, c);
+        }
+        __syncthreads();
+    }
+}

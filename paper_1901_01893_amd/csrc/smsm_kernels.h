@@ -1,0 +1,867 @@
+// HIP kernels of the SMS-MUSSELS IRLS solve (gfx950, FP64 arithmetic).
+//
+// Data flow of one application of the normal operator
+//     N(p) = A^H A p + (lam/2) sum_l H_l^H(H_l(p_l) W_l)
+// (SMS forward model of Fig. 1, block-Hankel lift of Eq. 8-9):
+//   rows_inv_T  k-space rows -> inverse DFT along kx -> hybrid (x, ky),
+//               written transposed so every x column is contiguous in ky;
+//   col<NORMAL> one workgroup per x column: inverse DFT along ky (image),
+//               coil loop with mask-pruned ky transforms (the interleaved mask
+//               of shot i keeps ky = i mod Ns, so each coil image is folded to
+//               n2/Ns points before its DFT), CAIPI phase and slice sum, the
+//               adjoint chain, plus the circular part of the Hankel term as a
+//               per-pixel Ns x Ns multiply in the image domain, then the
+//               forward DFT along ky;
+//   band_corr   exact correction of the Hankel term on the k-space band of
+//               width r-1 where valid patch anchors end (direct taps);
+//   rows_fwd_T  forward DFT along kx back to k-space, adds the band
+//               correction and the partial <p, N p> of CG.
+// Because the mask and the CAIPI phase depend on ky only, the kx transforms
+// of A^H A cancel in the coil loop, so the coil loop needs only ky transforms.
+#pragma once
+#include "smsm_device.h"
+
+struct Geo {
+    int n1, n2, L, Ns, Nc, r, K, nc, e, M, logn1, logn2, logM, B, nband, npairs;
+};
+
+// ---------------------------------------------------------------------------
+// Band of the k-space grid where the Hankel term differs from its circular
+// version: rows/columns within e = r-1 of an edge.  Enumeration: the e top
+// rows and e bottom rows (row-major), then the 2e edge columns of the middle
+// rows (column-major, so consecutive indices share a tap class).
+// ---------------------------------------------------------------------------
+SMSM_DEV int band_index(const Geo& g, int t2, int t1) {
+    const int e = g.e;
+    if (t2 < e) return t2 * g.n1 + t1;
+    if (t2 >= g.n2 - e) return (e + t2 - (g.n2 - e)) * g.n1 + t1;
+    int cc;
+    if (t1 < e) cc = t1;
+    else if (t1 >= g.n1 - e) cc = e + t1 - (g.n1 - e);
+    else return -1;
+    return 2 * e * g.n1 + cc * (g.n2 - 2 * e) + (t2 - e);
+}
+
+SMSM_DEV void band_pos(const Geo& g, int idx, int& t2, int& t1) {
+    const int e = g.e, top = 2 * e * g.n1;
+    if (idx < top) {
+        const int row = idx / g.n1;
+        t1 = idx - row * g.n1;
+        t2 = row < e ? row : g.n2 - e + (row - e);
+    } else {
+        const int k = idx - top, h = g.n2 - 2 * e;
+        const int cc = k / h;
+        t2 = e + (k - cc * h);
+        t1 = cc < e ? cc : g.n1 - e + (cc - e);
+    }
+}
+
+// Tap class of a coordinate: 0..r-2 near the low edge, r-1 interior,
+// r..2r-2 near the high edge.
+SMSM_DEV int band_class(int t, int n, int r) {
+    if (t <= r - 2) return t;
+    if (t >= n - r + 1) return r + (t - (n - r + 1));
+    return r - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Row passes
+// ---------------------------------------------------------------------------
+enum { ROWS_PLAIN = 0, ROWS_CG_UPDATE = 1, ROWS_CG_FIRST = 2 };
+
+// out[b][x][j2] = centred inverse DFT along kx of in[b][j2][:], evaluated at x.
+// ROWS_CG_UPDATE: the transformed vector is p = r + beta p (beta = rr_j/rr_{j-1}
+// from block partials), written back to p.  ROWS_CG_FIRST: p = r.
+template <int MODE>
+__global__ void k_rows_inv_T(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
+                             const double2* __restrict__ rvec, double2* __restrict__ pvec,
+                             const double* __restrict__ pr_new, const double* __restrict__ pr_old,
+                             int npart, const double2* __restrict__ tw1, int TR) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, stride = n1 + 1;
+    double2* v = sm;
+    double* red = (double*)(sm + TR * stride);
+    const int b = blockIdx.y, j0 = blockIdx.x * TR;
+    double beta = 0.0;
+    if (MODE == ROWS_CG_UPDATE) {
+        const double rn = sum_partials(pr_new, npart, red);
+        const double ro = sum_partials(pr_old, npart, red);
+        beta = (ro > 0.0) ? rn / ro : 0.0;
+    }
+    const size_t img = (size_t)b * g.n2 * n1;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int jr = idx / n1, c = idx - jr * n1;
+        const size_t o = img + (size_t)(j0 + jr) * n1 + c;
+        double2 val;
+        if (MODE == ROWS_PLAIN) {
+            val = in[o];
+        } else if (MODE == ROWS_CG_UPDATE) {
+            val = cadd(rvec[o], cscale(pvec[o], beta));
+            pvec[o] = val;
+        } else {
+            val = rvec[o];
+            pvec[o] = val;
+        }
+        v[jr * stride + c] = cscale(val, sgn_pow(c));
+    }
+    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, true);
+    const double sc = 1.0 / sqrt((double)n1);
+    const size_t ob = (size_t)b * n1 * g.n2;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int c = idx / TR, jr = idx - c * TR;
+        out[ob + (size_t)c * g.n2 + j0 + jr] = cscale(v[jr * stride + c], sc * sgn_pow(c));
+    }
+}
+
+// out[b][j2][:] = centred forward DFT along x of in[b][:][j2] (hybrid, transposed).
+// BAND: adds corr[b][band_index] on band pixels.  CG: per-block partial of
+// Re<p, out> into pq_part[block].
+template <bool CG, bool BAND>
+__global__ void k_rows_fwd_T(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
+                             const double2* __restrict__ corr, const double2* __restrict__ pvec,
+                             double* __restrict__ pq_part, const double2* __restrict__ tw1, int TR) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, stride = n1 + 1;
+    double2* v = sm;
+    double* red = (double*)(sm + TR * stride);
+    const int b = blockIdx.y, j0 = blockIdx.x * TR;
+    const size_t ib = (size_t)b * n1 * g.n2;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int c = idx / TR, jr = idx - c * TR;
+        v[jr * stride + c] = cscale(in[ib + (size_t)c * g.n2 + j0 + jr], sgn_pow(c));
+    }
+    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, false);
+    const double sc = 1.0 / sqrt((double)n1);
+    const size_t img = (size_t)b * g.n2 * n1;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int jr = idx / n1, k = idx - jr * n1;
+        const int j2 = j0 + jr;
+        double2 val = cscale(v[jr * stride + k], sc * sgn_pow(k));
+        if (BAND) {
+            const int bi = band_index(g, j2, k);
+            if (bi >= 0) val = cadd(val, corr[(size_t)b * g.nband + bi]);
+        }
+        const size_t o = img + (size_t)j2 * n1 + k;
+        out[o] = val;
+        if (CG) {
+            const double2 pv = pvec[o];
+            acc += pv.x * val.x + pv.y * val.y;
+        }
+    }
+    if (CG) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) pq_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// ytil[i][c][x][m] = centred inverse DFT along kx of y[i][c][i + Ns m][:] at x
+// (only the lines shot i acquires).  y is complex64.
+__global__ void k_yrows_inv(Geo g, const float2* __restrict__ y, double2* __restrict__ ytil,
+                            const double2* __restrict__ tw1, int TR) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, stride = n1 + 1;
+    double2* v = sm;
+    const int ic = blockIdx.y, i = ic / g.Nc, m0 = blockIdx.x * TR;
+    const size_t ybase = (size_t)ic * g.n2 * n1;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int mr = idx / n1, c = idx - mr * n1;
+        const int j2 = i + g.Ns * (m0 + mr);
+        v[mr * stride + c] = cscale(c64to128(y[ybase + (size_t)j2 * n1 + c]), sgn_pow(c));
+    }
+    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, true);
+    const double sc = 1.0 / sqrt((double)n1);
+    const size_t ob = (size_t)ic * n1 * g.M;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int c = idx / TR, mr = idx - c * TR;
+        ytil[ob + (size_t)c * g.M + m0 + mr] = cscale(v[mr * stride + c], sc * sgn_pow(c));
+    }
+}
+
+// y[i][c][i + Ns m][:] = centred forward DFT along x of ytil[i][c][:][m]
+// (the other lines of y must be zeroed by the caller).  y is complex128.
+__global__ void k_yrows_fwd(Geo g, const double2* __restrict__ ytil, double2* __restrict__ y,
+                            const double2* __restrict__ tw1, int TR) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, stride = n1 + 1;
+    double2* v = sm;
+    const int ic = blockIdx.y, i = ic / g.Nc, m0 = blockIdx.x * TR;
+    const size_t ib = (size_t)ic * n1 * g.M;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int c = idx / TR, mr = idx - c * TR;
+        v[mr * stride + c] = cscale(ytil[ib + (size_t)c * g.M + m0 + mr], sgn_pow(c));
+    }
+    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, false);
+    const double sc = 1.0 / sqrt((double)n1);
+    const size_t yb = (size_t)ic * g.n2 * n1;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        const int mr = idx / n1, k = idx - mr * n1;
+        const int j2 = i + g.Ns * (m0 + mr);
+        y[yb + (size_t)j2 * n1 + k] = cscale(v[mr * stride + k], sc * sgn_pow(k));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: one workgroup per x column, all slices and shots.
+// ---------------------------------------------------------------------------
+enum { COL_NORMAL = 0, COL_FWD = 1, COL_ADJ = 2, COL_REG = 3 };
+
+// Shared-memory layout (offsets in double2 units) of k_col; the host sizes
+// the launch with the same function.
+struct ColLds {
+    int U, ACC, F, SC, TW2, TWM, A, red, total;
+};
+__host__ __device__ inline ColLds col_lds(const Geo& g) {
+    ColLds c;
+    c.U = 0;
+    c.ACC = c.U + g.B * g.n2;
+    c.F = c.ACC + g.B * g.n2;
+    c.SC = c.F + g.B * g.M;
+    c.TW2 = c.SC + g.L * g.n2;
+    c.TWM = c.TW2 + g.n2;
+    c.A = c.TWM + g.M;
+    c.red = c.A + g.L * g.Ns * g.Ns * g.nc;
+    c.total = c.red + 16;
+    return c;
+}
+
+// One workgroup per image column x (blockIdx.x).
+//  COL_NORMAL  h2 = F_y[ sum_c S^H F_y^-1 M theta^H theta M F_y S u + (reg) ] for
+//              u = F_y^-1 h1 (h1, h2 hybrid [B][n1][n2]);
+//  COL_REG     only the circular Hankel term;
+//  COL_FWD     ytil[i][c][x][m] = sum_l theta_l (F_y(S_{l,c} u_{l,i}))[i + Ns m];
+//  COL_ADJ     h2 = F_y[ sum_c S^H F_y^-1 M theta^H ytil ] (input ytil, not h1).
+// Mask pruning: with tau_i[n] = (-1)^n e^{-2 pi i i n/n2} and M = n2/Ns,
+//  (F_y v)[i + Ns m] = (-1)^(i + Ns m)/sqrt(n2) * DFT_M( sum_t tau_i v [m + M t] )[m]
+// and its adjoint unfolds an M-point inverse DFT back to n2 points (the
+// (-1)^(Ns m) factors cancel in the normal operator).
+template <int MODE>
+__global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
+                      const float2* __restrict__ ST, const double2* __restrict__ theta,
+                      const double2* __restrict__ tau, const double2* __restrict__ tw2,
+                      const double2* __restrict__ twM, const double2* __restrict__ tw1,
+                      const double2* __restrict__ Kc, int use_reg, double2* __restrict__ ytil) {
+    extern __shared__ double2 sm[];
+    const ColLds lay = col_lds(g);
+    const int n1 = g.n1, n2 = g.n2, B = g.B, M = g.M, Ns = g.Ns, L = g.L, Nc = g.Nc;
+    const int x1 = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double2* U = sm + lay.U;
+    double2* ACC = sm + lay.ACC;
+    double2* F = sm + lay.F;
+    double2* SC = sm + lay.SC;
+    double2* TW2 = sm + lay.TW2;
+    double2* TWM = sm + lay.TWM;
+    double2* A = sm + lay.A;
+    const double isq2 = 1.0 / sqrt((double)n2);
+
+    for (int k = tid; k < n2; k += nt) TW2[k] = tw2[k];
+    for (int k = tid; k < M; k += nt) TWM[k] = twM[k];
+
+    if (MODE != COL_ADJ) {
+        // image column u = centred inverse DFT along ky; stored as tau_i * u
+        for (int idx = tid; idx < B * n2; idx += nt) {
+            const int b = idx / n2, j = idx - b * n2;
+            U[idx] = cscale(h1[((size_t)b * n1 + x1) * n2 + j], sgn_pow(j));
+        }
+        fft_batch_lds(U, n2, g.logn2, B, n2, TW2, true);
+        for (int idx = tid; idx < B * n2; idx += nt) {
+            const int b = idx / n2, n = idx - b * n2, i = b % Ns;
+            U[idx] = cmul(tau[i * n2 + n], cscale(U[idx], isq2 * sgn_pow(n)));
+        }
+    }
+    if (MODE != COL_FWD)
+        for (int idx = tid; idx < B * n2; idx += nt) ACC[idx] = cmk(0.0, 0.0);
+    __syncthreads();
+
+    if (MODE != COL_REG) {
+        for (int c = 0; c < Nc; ++c) {
+            for (int idx = tid; idx < L * n2; idx += nt) {
+                const int l = idx / n2, n = idx - l * n2;
+                SC[idx] = c64to128(ST[(((size_t)l * Nc + c) * n1 + x1) * n2 + n]);
+            }
+            if (MODE == COL_ADJ) {
+                __syncthreads();
+                // F[(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
+                for (int idx = tid; idx < B * M; idx += nt) {
+                    const int b = idx / M, m = idx - b * M, l = b / Ns, i = b - l * Ns;
+                    const double2 yv = ytil[(((size_t)i * Nc + c) * n1 + x1) * M + m];
+                    F[idx] = cscale(cmulc(yv, theta[l * n2 + i + Ns * m]), sgn_pow(Ns * m));
+                }
+            } else {
+                __syncthreads();
+                // fold: F[(l,i)][m] = sum_t S_l[m + M t] * (tau_i u_{l,i})[m + M t]
+                for (int idx = tid; idx < B * M; idx += nt) {
+                    const int b = idx / M, m = idx - b * M, l = b / Ns;
+                    double2 f = cmk(0.0, 0.0);
+                    for (int t = 0; t < Ns; ++t) {
+                        const int n = m + M * t;
+                        f = cfma(SC[l * n2 + n], U[b * n2 + n], f);
+                    }
+                    F[idx] = f;
+                }
+                fft_batch_lds(F, M, g.logM, B, M, TWM, false);
+                if (MODE == COL_FWD) {
+                    for (int idx = tid; idx < Ns * M; idx += nt) {
+                        const int i = idx / M, m = idx - i * M, j = i + Ns * m;
+                        double2 z = cmk(0.0, 0.0);
+                        for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], F[(l * Ns + i) * M + m], z);
+                        ytil[(((size_t)i * Nc + c) * n1 + x1) * M + m] = cscale(z, isq2 * sgn_pow(i + Ns * m));
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                // slice sum with CAIPI phase, then back to every slice
+                for (int idx = tid; idx < Ns * M; idx += nt) {
+                    const int i = idx / M, m = idx - i * M, j = i + Ns * m;
+                    double2 z = cmk(0.0, 0.0);
+                    for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], F[(l * Ns + i) * M + m], z);
+                    for (int l = 0; l < L; ++l) F[(l * Ns + i) * M + m] = cmulc(z, theta[l * n2 + j]);
+                }
+            }
+            fft_batch_lds(F, M, g.logM, B, M, TWM, true);
+            // unfold and accumulate conj(S) * g[n mod M]
+            for (int idx = tid; idx < B * n2; idx += nt) {
+                const int b = idx / n2, n = idx - b * n2, l = b / Ns;
+                ACC[idx] = cadd(ACC[idx], cconjmul(SC[l * n2 + n], F[b * M + (n & (M - 1))]));
+            }
+            __syncthreads();
+        }
+        if (MODE == COL_FWD) return;
+        // normal: conj(tau_i[n]) / n2 ; adjoint: (-1)^i conj(tau_i[n]) / sqrt(n2)
+        for (int idx = tid; idx < B * n2; idx += nt) {
+            const int b = idx / n2, n = idx - b * n2, i = b % Ns;
+            const double s = (MODE == COL_ADJ) ? isq2 * sgn_pow(i) : 1.0 / (double)n2;
+            ACC[idx] = cscale(cmulc(ACC[idx], tau[i * n2 + n]), s);
+        }
+    }
+
+    if (MODE != COL_ADJ && use_reg) {
+        // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}
+        const int nc = g.nc, e = g.e, nu1 = x1 - n1 / 2;
+        for (int idx = tid; idx < L * Ns * Ns * nc; idx += nt) {
+            const double2* kr = Kc + (size_t)idx * nc;
+            double2 a = cmk(0.0, 0.0);
+            for (int d1 = 0; d1 < nc; ++d1) {
+                const int ph = ((d1 - e) * nu1) & (n1 - 1);
+                a = cfma(kr[d1], tw1[ph], a);
+            }
+            A[idx] = a;
+        }
+        __syncthreads();
+        // ACC[(l,i')][n] += sum_i sum_d2 A[l][i][i'][d2] e^{-2 pi i d2 (n - n2/2)/n2} u_{l,i}[n]
+        for (int idx = tid; idx < B * n2; idx += nt) {
+            const int b = idx / n2, n = idx - b * n2, l = b / Ns, ip = b - l * Ns;
+            const int nu2 = n - n2 / 2;
+            double2 s = cmk(0.0, 0.0);
+            for (int i = 0; i < Ns; ++i) {
+                const double2 u = cmulc(U[(l * Ns + i) * n2 + n], tau[i * n2 + n]);
+                const double2* ar = A + ((size_t)(l * Ns + i) * Ns + ip) * nc;
+                double2 kv = cmk(0.0, 0.0);
+                for (int d2 = 0; d2 < nc; ++d2) kv = cfma(ar[d2], TW2[((d2 - e) * nu2) & (n2 - 1)], kv);
+                s = cfma(kv, u, s);
+            }
+            ACC[idx] = cadd(ACC[idx], s);
+        }
+    }
+    __syncthreads();
+    // centred forward DFT along ky
+    for (int idx = tid; idx < B * n2; idx += nt) {
+        const int n = idx % n2;
+        ACC[idx] = cscale(ACC[idx], sgn_pow(n));
+    }
+    fft_batch_lds(ACC, n2, g.logn2, B, n2, TW2, false);
+    for (int idx = tid; idx < B * n2; idx += nt) {
+        const int b = idx / n2, j = idx - b * n2;
+        h2[((size_t)b * n1 + x1) * n2 + j] = cscale(ACC[idx], isq2 * sgn_pow(j));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Hankel term on the band: exact minus circular, with per-class tap tables.
+// ---------------------------------------------------------------------------
+// Tap tables from W (lam/2 folded in):
+//   Kc[l][i][i'][d2][d1]             = sum_{b'} W[(i, b'+d), (i', b')]
+//   D[l][c2][c1][i'][i][d2][d1]      = K^{(c2,c1)}[i][i'][d] - Kc[l][i][i'][d]
+// where K^{(class)} restricts b' to the anchors valid for that band class.
+__global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_lam,
+                              double2* __restrict__ Kc, double2* __restrict__ D) {
+    const int nc = g.nc, r = g.r, Ns = g.Ns, K = g.K;
+    const long total = (long)g.L * nc * nc * Ns * Ns * nc * nc;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        long t = idx;
+        const int d1 = t % nc; t /= nc;
+        const int d2 = t % nc; t /= nc;
+        const int i = t % Ns; t /= Ns;
+        const int ip = t % Ns; t /= Ns;
+        const int c1 = t % nc; t /= nc;
+        const int c2 = t % nc; t /= nc;
+        const int l = (int)t;
+        const int dd2 = d2 - (r - 1), dd1 = d1 - (r - 1);
+        // b' range of the class in each dimension
+        const int lo2 = (c2 < r) ? 0 : c2 - (r - 1), hi2 = (c2 < r) ? c2 : r - 1;
+        const int lo1 = (c1 < r) ? 0 : c1 - (r - 1), hi1 = (c1 < r) ? c1 : r - 1;
+        const double2* Wl = W + (size_t)l * K * K;
+        double2 kfull = cmk(0.0, 0.0), kcls = cmk(0.0, 0.0);
+        const int a2 = max(0, -dd2), z2 = min(r - 1, r - 1 - dd2);
+        const int a1 = max(0, -dd1), z1 = min(r - 1, r - 1 - dd1);
+        for (int bp2 = a2; bp2 <= z2; ++bp2) {
+            for (int bp1 = a1; bp1 <= z1; ++bp1) {
+                const int row = (i * r + bp2 + dd2) * r + bp1 + dd1;
+                const int col = (ip * r + bp2) * r + bp1;
+                const double2 w = Wl[(size_t)row * K + col];
+                kfull = cadd(kfull, w);
+                if (bp2 >= lo2 && bp2 <= hi2 && bp1 >= lo1 && bp1 <= hi1) kcls = cadd(kcls, w);
+            }
+        }
+        kfull = cscale(kfull, half_lam);
+        kcls = cscale(kcls, half_lam);
+        D[idx] = csub(kcls, kfull);
+        if (c2 == r - 1 && c1 == r - 1)
+            Kc[((((size_t)l * Ns + i) * Ns + ip) * nc + d2) * nc + d1] = kfull;
+    }
+}
+
+// corr[(l,i')][bidx] = sum_i sum_d D[l][class][i'][i][d] p[l][i][(t + d) mod n]
+__global__ void k_band_corr(Geo g, const double2* __restrict__ p, const double2* __restrict__ D,
+                            double2* __restrict__ corr) {
+    const int nc = g.nc, r = g.r, Ns = g.Ns, n1 = g.n1, n2 = g.n2;
+    const int total = g.B * g.nband;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int b = idx / g.nband, bi = idx - b * g.nband;
+    const int l = b / Ns, ip = b - l * Ns;
+    int t2, t1;
+    band_pos(g, bi, t2, t1);
+    const int c2 = band_class(t2, n2, r), c1 = band_class(t1, n1, r);
+    const double2* Dp = D + ((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)Ns * nc * nc;
+    double2 s = cmk(0.0, 0.0);
+    for (int i = 0; i < Ns; ++i) {
+        const double2* pi = p + ((size_t)l * Ns + i) * n2 * n1;
+        for (int d2 = 0; d2 < nc; ++d2) {
+            const int q2 = (t2 + d2 - (r - 1)) & (n2 - 1);
+            const double2* prow = pi + (size_t)q2 * n1;
+            const double2* dr = Dp + ((size_t)i * nc + d2) * nc;
+            for (int d1 = 0; d1 < nc; ++d1) {
+                const int q1 = (t1 + d1 - (r - 1)) & (n1 - 1);
+                s = cfma(dr[d1], prow[q1], s);
+            }
+        }
+    }
+    corr[idx] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Gram G_l = H_l^H H_l.  With z_d[q] = conj(x_i[q]) x_i'[(q + d) mod n],
+//   G[(i,b),(i',b+d)] = C[d] - sum_{q2 in E(b2)} Row_d[q2] - sum_{q1 in E(b1)} Col_d[q1]
+//                       + sum_{q2 in E(b2), q1 in E(b1)} z_d[q2][q1]
+// where C[d] = sum_q z_d[q] (circular correlation, evaluated in the image
+// domain as sum_nu conj(u_i) u_i' e^{-2 pi i d.nu/n}), E(b) = [0,b) U [b+n-r+1, n)
+// the r-1 coordinates a valid anchor window misses, and Row/Col the sums of
+// z_d along the band rows/columns.  Pairs i <= i' only (Hermitian).
+// ---------------------------------------------------------------------------
+// Per-column partials: part[x][l][pair][d2][d1]
+__global__ void k_gram_col(Geo g, const double2* __restrict__ h1, const double2* __restrict__ tw2,
+                           const double2* __restrict__ tw1, double2* __restrict__ part) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, n2 = g.n2, B = g.B, Ns = g.Ns, nc = g.nc, e = g.e;
+    const int x1 = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    double2* U = sm;               // [B][n2]
+    double2* TW2 = U + B * n2;     // [n2]
+    for (int k = tid; k < n2; k += nt) TW2[k] = tw2[k];
+    for (int idx = tid; idx < B * n2; idx += nt) {
+        const int b = idx / n2, j = idx - b * n2;
+        U[idx] = cscale(h1[((size_t)b * n1 + x1) * n2 + j], sgn_pow(j));
+    }
+    fft_batch_lds(U, n2, g.logn2, B, n2, TW2, true);
+    const double isq2 = 1.0 / sqrt((double)n2);
+    for (int idx = tid; idx < B * n2; idx += nt) {
+        const int n = idx % n2;
+        U[idx] = cscale(U[idx], isq2 * sgn_pow(n));
+    }
+    __syncthreads();
+    const int nu1 = x1 - n1 / 2;
+    const int nT = g.L * g.npairs * nc;
+    for (int idx = tid; idx < nT; idx += nt) {
+        const int d2 = idx % nc, lp = idx / nc, pair = lp % g.npairs, l = lp / g.npairs;
+        int i = 0, rem = pair;
+        while (rem >= Ns - i) { rem -= Ns - i; ++i; }
+        const int ip = i + rem;
+        const double2* ui = U + (l * Ns + i) * n2;
+        const double2* uj = U + (l * Ns + ip) * n2;
+        double2 t = cmk(0.0, 0.0);
+        for (int n = 0; n < n2; ++n) {
+            const int ph = ((d2 - e) * (n - n2 / 2)) & (n2 - 1);
+            t = cfma(cconjmul(ui[n], uj[n]), TW2[ph], t);
+        }
+        double2* out = part + (((size_t)x1 * g.L + l) * g.npairs + pair) * nc * nc + (size_t)d2 * nc;
+        for (int d1 = 0; d1 < nc; ++d1) {
+            const int ph = ((d1 - e) * nu1) & (n1 - 1);
+            out[d1] = cmul(t, tw1[ph]);
+        }
+    }
+}
+
+// C[l][pair][d] = sum_x part[x][l][pair][d] (fixed order)
+__global__ void k_gram_reduce(Geo g, const double2* __restrict__ part, double2* __restrict__ C) {
+    const int per = g.L * g.npairs * g.nc * g.nc;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    double2 s = cmk(0.0, 0.0);
+    for (int x = 0; x < g.n1; ++x) s = cadd(s, part[(size_t)x * per + idx]);
+    C[idx] = s;
+}
+
+// Row/column sums of z_d on the band and the band corner values.
+//   rows[l][pair][d][qi]      qi < 2e (band row qi)
+//   cols[l][pair][d][qi]
+//   cor [l][pair][d][qi2][qi1]
+__global__ void k_gram_band(Geo g, const double2* __restrict__ x, double2* __restrict__ rows,
+                            double2* __restrict__ cols, double2* __restrict__ cor) {
+    const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
+    const long nld = (long)g.L * g.npairs * nc * nc;
+    const long n_rows = nld * e2, n_cor = nld * e2 * e2;
+    const long total = 2 * n_rows + n_cor;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        int kind;  // 0 rows, 1 cols, 2 corners
+        long t;
+        if (idx < n_rows) { kind = 0; t = idx; }
+        else if (idx < 2 * n_rows) { kind = 1; t = idx - n_rows; }
+        else { kind = 2; t = idx - 2 * n_rows; }
+        int qa = 0, qb = 0;
+        if (kind == 2) { qb = t % e2; t /= e2; qa = t % e2; t /= e2; }
+        else { qa = t % e2; t /= e2; }
+        const int d1 = t % nc; t /= nc;
+        const int d2 = t % nc; t /= nc;
+        const int pair = t % g.npairs; t /= g.npairs;
+        const int l = (int)t;
+        int i = 0, rem = pair;
+        while (rem >= Ns - i) { rem -= Ns - i; ++i; }
+        const int ip = i + rem;
+        const double2* xi = x + ((size_t)l * Ns + i) * n2 * n1;
+        const double2* xj = x + ((size_t)l * Ns + ip) * n2 * n1;
+        const int dd2 = d2 - e, dd1 = d1 - e;
+        const size_t o = (((size_t)l * g.npairs + pair) * nc + d2) * nc + d1;
+        if (kind == 0) {
+            const int q2 = qa < e ? qa : n2 - e2 + qa;
+            const double2* a = xi + (size_t)q2 * n1;
+            const double2* bb = xj + (size_t)((q2 + dd2) & (n2 - 1)) * n1;
+            double2 s = cmk(0.0, 0.0);
+            for (int q1 = 0; q1 < n1; ++q1) s = cfma(cconj(a[q1]), bb[(q1 + dd1) & (n1 - 1)], s);
+            rows[o * e2 + qa] = s;
+        } else if (kind == 1) {
+            const int q1 = qa < e ? qa : n1 - e2 + qa;
+            double2 s = cmk(0.0, 0.0);
+            for (int q2 = 0; q2 < n2; ++q2)
+                s = cfma(cconj(xi[(size_t)q2 * n1 + q1]),
+                         xj[(size_t)((q2 + dd2) & (n2 - 1)) * n1 + ((q1 + dd1) & (n1 - 1))], s);
+            cols[o * e2 + qa] = s;
+        } else {
+            const int q2 = qa < e ? qa : n2 - e2 + qa;
+            const int q1 = qb < e ? qb : n1 - e2 + qb;
+            cor[(o * e2 + qa) * e2 + qb] =
+                cconjmul(xi[(size_t)q2 * n1 + q1],
+                         xj[(size_t)((q2 + dd2) & (n2 - 1)) * n1 + ((q1 + dd1) & (n1 - 1))]);
+        }
+    }
+}
+
+// G[l][row][col] for row <= col (mirrored as the conjugate).
+__global__ void k_gram_assemble(Geo g, const double2* __restrict__ C, const double2* __restrict__ rows,
+                                const double2* __restrict__ cols, const double2* __restrict__ cor,
+                                double2* __restrict__ G) {
+    const int K = g.K, r = g.r, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
+    const long total = (long)g.L * K * K;
+    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int l = (int)(idx / ((long)K * K));
+    const int rc = (int)(idx - (long)l * K * K);
+    const int row = rc / K, col = rc - row * K;
+    if (row > col) return;
+    const int rr2 = r * r;
+    const int i = row / rr2, b2 = (row % rr2) / r, b1 = row % r;
+    const int ip = col / rr2, c2 = (col % rr2) / r, c1 = col % r;
+    const int pair = i * Ns - (i * (i - 1)) / 2 + (ip - i);
+    const int d2 = c2 - b2 + e, d1 = c1 - b1 + e;
+    const size_t o = (((size_t)l * g.npairs + pair) * nc + d2) * nc + d1;
+    double2 v = C[o];
+    // band indices missed by the anchor window: [0, b) and [e + b, 2e)
+    for (int q = 0; q < e2; ++q) {
+        const bool m2 = (q < b2) || (q >= e + b2);
+        const bool m1 = (q < b1) || (q >= e + b1);
+        if (m2) v = csub(v, rows[o * e2 + q]);
+        if (m1) v = csub(v, cols[o * e2 + q]);
+    }
+    for (int qa = 0; qa < e2; ++qa) {
+        if (!((qa < b2) || (qa >= e + b2))) continue;
+        for (int qb = 0; qb < e2; ++qb) {
+            if (!((qb < b1) || (qb >= e + b1))) continue;
+            v = cadd(v, cor[(o * e2 + qa) * e2 + qb]);
+        }
+    }
+    double2* Gl = G + (size_t)l * K * K;
+    if (row == col) v.y = 0.0;
+    Gl[(size_t)row * K + col] = v;
+    if (row != col) Gl[(size_t)col * K + row] = cconj(v);
+}
+
+// ---------------------------------------------------------------------------
+// Small dense complex matrices (K x K per slice): tiled GEMM and helpers for
+// the Newton-Schulz inverse square root and the largest eigenvalue.
+// ---------------------------------------------------------------------------
+#define GT 16
+// C = alpha * A * B for slice blockIdx.z (A, B, C: [L][K][K]), alpha from
+// `scale` (per slice) or 1.  Skips slices whose `skip` flag is set.
+// Optional epilogue (EPI_NS): C <- 1.5 I - 0.5 (A B) and the partial
+// sum |I - A B|^2 of this tile into part[l][tile].
+enum { EPI_NONE = 0, EPI_NS = 1, EPI_NORM = 2 };
+template <int EPI>
+__global__ void k_cgemm(int K, int L, const double2* __restrict__ A, const double2* __restrict__ Bm,
+                        double2* __restrict__ C, const double* __restrict__ scale,
+                        const int* __restrict__ skip, double* __restrict__ part) {
+    __shared__ double2 As[GT][GT + 1];
+    __shared__ double2 Bs[GT][GT + 1];
+    __shared__ double red[16];
+    const int l = blockIdx.z;
+    if (skip && skip[l]) return;
+    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
+    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
+    const double2* Al = A + (size_t)l * K * K;
+    const double2* Bl = Bm + (size_t)l * K * K;
+    double2 acc = cmk(0.0, 0.0);
+    for (int k0 = 0; k0 < K; k0 += GT) {
+        const int ka = k0 + tx, kb = k0 + ty;
+        As[ty][tx] = (row < K && ka < K) ? Al[(size_t)row * K + ka] : cmk(0.0, 0.0);
+        Bs[ty][tx] = (kb < K && col < K) ? Bl[(size_t)kb * K + col] : cmk(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GT; ++k) acc = cfma(As[ty][k], Bs[k][tx], acc);
+        __syncthreads();
+    }
+    const double s = scale ? scale[l] : 1.0;
+    acc = cscale(acc, s);
+    double contrib = 0.0;
+    if (row < K && col < K) {
+        if (EPI == EPI_NS) {
+            const double2 dlt = cmk(row == col ? 1.0 : 0.0, 0.0);
+            const double2 res = csub(dlt, acc);
+            contrib = cabs2(res);
+            acc = cadd(cscale(dlt, 1.5), cscale(acc, -0.5));
+        } else if (EPI == EPI_NORM) {
+            contrib = cabs2(acc);
+        }
+        C[(size_t)l * K * K + (size_t)row * K + col] = acc;
+    }
+    if (EPI != EPI_NONE) {
+        const double ssum = block_sum(contrib, red);
+        if (threadIdx.x == 0) part[(size_t)l * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = ssum;
+    }
+}
+
+// Y = (G + eps I)/c, Z = I, with eps_l = mult * src[l] and c = ||G + eps I||_F;
+// one workgroup per slice.  eps_l <= 0 marks the slice as unregularised
+// (skip0[l] = 1, W_l = 0).  Also clears the convergence flags done[1..nit].
+__global__ void k_ns_init(int K, int L, const double2* __restrict__ G, const double* __restrict__ src,
+                          double mult, double2* __restrict__ Y, double2* __restrict__ Z,
+                          double* __restrict__ wscale, int* __restrict__ done, int nit) {
+    __shared__ double red[16];
+    const int l = blockIdx.x;
+    const double eps = mult * src[l];
+    const double2* Gl = G + (size_t)l * K * K;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
+        double2 v = Gl[k];
+        if (k / K == k % K) v.x += eps;
+        s += cabs2(v);
+    }
+    const double fro2 = block_sum(s, red);
+    const bool unreg = !(eps > 0.0) || !(fro2 > 0.0);
+    const double c = unreg ? 1.0 : sqrt(fro2);
+    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
+        const bool dg = (k / K == k % K);
+        double2 v = Gl[k];
+        if (dg) v.x += eps;
+        Y[(size_t)l * K * K + k] = cscale(v, 1.0 / c);
+        Z[(size_t)l * K * K + k] = cmk(dg ? 1.0 : 0.0, 0.0);
+    }
+    if (threadIdx.x == 0) {
+        wscale[l] = unreg ? 0.0 : 1.0 / sqrt(c);
+        done[l] = unreg ? 1 : 0;
+        for (int k = 1; k <= nit; ++k) done[k * L + l] = 0;
+    }
+}
+
+// One Newton-Schulz update for slice l = blockIdx.z / 2:
+//   which = 0: Yn = Y T ; which = 1: Zn = T Z   (T = 1.5 I - 0.5 Z Y, from k_cgemm<EPI_NS>)
+// Slices already converged (done_cur[l]) copy Y, Z through.  The residual
+// ||I - Z Y||_F of this iteration is summed from the k_cgemm partials and
+// done_next[l] = done_cur[l] || residual < tol.
+__global__ void k_ns_update(int K, int L, const double2* __restrict__ Y, const double2* __restrict__ Z,
+                            const double2* __restrict__ T, double2* __restrict__ Yn, double2* __restrict__ Zn,
+                            const double* __restrict__ part, int ntile, const int* __restrict__ done_cur,
+                            int* __restrict__ done_next, double tol2) {
+    __shared__ double2 As[GT][GT + 1];
+    __shared__ double2 Bs[GT][GT + 1];
+    __shared__ double red[16];
+    const int l = blockIdx.z >> 1, which = blockIdx.z & 1;
+    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
+    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
+    const size_t off = (size_t)l * K * K;
+    const int dc = done_cur[l];
+    if (dc) {
+        if (row < K && col < K) {
+            if (which == 0) Yn[off + (size_t)row * K + col] = Y[off + (size_t)row * K + col];
+            else Zn[off + (size_t)row * K + col] = Z[off + (size_t)row * K + col];
+        }
+        if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0) done_next[l] = 1;
+        return;
+    }
+    const double res2 = sum_partials(part + (size_t)l * ntile, ntile, red);
+    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0)
+        done_next[l] = (res2 < tol2) ? 1 : 0;
+    const double2* Al = (which == 0 ? Y : T) + off;
+    const double2* Bl = (which == 0 ? T : Z) + off;
+    double2 acc = cmk(0.0, 0.0);
+    for (int k0 = 0; k0 < K; k0 += GT) {
+        const int ka = k0 + tx, kb = k0 + ty;
+        As[ty][tx] = (row < K && ka < K) ? Al[(size_t)row * K + ka] : cmk(0.0, 0.0);
+        Bs[ty][tx] = (kb < K && col < K) ? Bl[(size_t)kb * K + col] : cmk(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GT; ++k) acc = cfma(As[ty][k], Bs[k][tx], acc);
+        __syncthreads();
+    }
+    if (row < K && col < K) (which == 0 ? Yn : Zn)[off + (size_t)row * K + col] = acc;
+}
+
+// W_l = wscale_l * Z_l (wscale = 0 for an unregularised slice).
+__global__ void k_ns_final(int K, int L, const double2* __restrict__ Z, const double* __restrict__ wscale,
+                           double2* __restrict__ W) {
+    const long total = (long)L * K * K;
+    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int l = (int)(idx / ((long)K * K));
+    W[idx] = cscale(Z[idx], wscale[l]);
+}
+
+// scale[l] = 1 / ||M_l||_F^2 (0 if M_l = 0); one workgroup per slice.
+__global__ void k_fro_inv(int K, const double2* __restrict__ Mx, double* __restrict__ scale) {
+    __shared__ double red[16];
+    const int l = blockIdx.x;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < K * K; k += blockDim.x) s += cabs2(Mx[(size_t)l * K * K + k]);
+    const double f = block_sum(s, red);
+    if (threadIdx.x == 0) scale[l] = f > 0.0 ? 1.0 / f : 0.0;
+}
+
+// scale[l] = 1 / sum(part[l][:]) (0 if the sum is 0); one workgroup per slice.
+__global__ void k_part_inv(const double* __restrict__ part, int ntile, double* __restrict__ scale) {
+    __shared__ double red[16];
+    const int l = blockIdx.x;
+    const double f = sum_partials(part + (size_t)l * ntile, ntile, red);
+    if (threadIdx.x == 0) scale[l] = f > 0.0 ? 1.0 / f : 0.0;
+}
+
+// lmax[l] = Re tr(G P) / Re tr(P) with P ~ G^(2^m) (Rayleigh quotient on the
+// dominant eigenspace); 0 when P = 0.  One workgroup per slice.
+__global__ void k_sq_final(int K, const double2* __restrict__ G, const double2* __restrict__ P,
+                           double* __restrict__ lmax) {
+    __shared__ double red[16];
+    const int l = blockIdx.x;
+    const double2* Gl = G + (size_t)l * K * K;
+    const double2* Pl = P + (size_t)l * K * K;
+    double num = 0.0, den = 0.0;
+    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
+        const int j = k / K, m = k - j * K;
+        const double2 gp = cmul(Gl[k], Pl[(size_t)m * K + j]);
+        num += gp.x;
+        if (j == m) den += Pl[k].x;
+    }
+    const double a = block_sum(num, red);
+    const double b = block_sum(den, red);
+    if (threadIdx.x == 0) lmax[l] = b > 0.0 ? a / b : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// CG vector kernels (fixed grid, grid-stride, per-block FP64 partials).
+// ---------------------------------------------------------------------------
+// r = b - q; partial sum |r|^2
+__global__ void k_cg_init(long n, const double2* __restrict__ b, const double2* __restrict__ q,
+                          double2* __restrict__ r, double* __restrict__ pr_part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double2 v = csub(b[k], q[k]);
+        r[k] = v;
+        s += cabs2(v);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) pr_part[blockIdx.x] = s;
+}
+
+// alpha = rr / Re<p, q>; x += alpha p; r -= alpha q; partial |r|^2.
+// rr == 0 (exact solution reached) leaves x, r unchanged; a non-finite or
+// non-positive curvature sets flags[0].
+__global__ void k_cg_update(long n, double2* __restrict__ x, const double2* __restrict__ p,
+                            double2* __restrict__ r, const double2* __restrict__ q,
+                            const double* __restrict__ pr_cur, int npr, const double* __restrict__ pq_part,
+                            int npq, double* __restrict__ pr_next, int* __restrict__ flags) {
+    __shared__ double red[16];
+    const double rr = sum_partials(pr_cur, npr, red);
+    const double pq = sum_partials(pq_part, npq, red);
+    double alpha = 0.0;
+    if (rr > 0.0) {
+        alpha = rr / pq;
+        if (!(pq > 0.0) || !isfinite(alpha)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+            alpha = 0.0;
+        }
+    }
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        x[k] = cadd(x[k], cscale(p[k], alpha));
+        const double2 v = csub(r[k], cscale(q[k], alpha));
+        r[k] = v;
+        s += cabs2(v);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) pr_next[blockIdx.x] = s;
+}
+
+__global__ void k_copy_c128(long n, const double2* __restrict__ a, double2* __restrict__ b) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) b[k] = a[k];
+}
+
+__global__ void k_to_c64(long n, const double2* __restrict__ a, float2* __restrict__ b) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        b[k] = make_float2((float)a[k].x, (float)a[k].y);
+}
+
+__global__ void k_zero_c128(long n, double2* __restrict__ a) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        a[k] = cmk(0.0, 0.0);
+}
+
+__global__ void k_zero_i32(long n, int* __restrict__ a) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) a[k] = 0;
+}
+
+// Coil maps c64 [L][Nc][n2][n1] -> plan layout [L][Nc][n1][n2] (x-major columns).
+__global__ void k_transpose_coils(int n1, int n2, long nimg, const float2* __restrict__ S,
+                                  float2* __restrict__ ST) {
+    const long total = nimg * n1 * n2;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long img = k / ((long)n1 * n2);
+        const int rem = (int)(k - img * n1 * n2);
+        const int x = rem / n2, y = rem - x * n2;
+        ST[k] = S[img * n1 * n2 + (long)y * n1 + x];
+    }
+}
+
+// eps_l = mult * sigma_l for the current IRLS step (device-side schedule).
+__global__ void k_eps(int L, const double* __restrict__ sigma, double mult, double* __restrict__ eps) {
+    const int l = threadIdx.x;
+    if (l < L) eps[l] = mult * sigma[l];
+}

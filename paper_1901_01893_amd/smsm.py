@@ -1,0 +1,337 @@
+"""Python binding of libsmsm.so (the C ABI declared in include/smsm.h).
+
+Argument marshalling only: every function hands device pointers of torch
+tensors and the current HIP stream to the library; all arithmetic runs in the
+library's HIP kernels.  There is no fallback: if the library is not built the
+first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmsm.so")
+
+SMSM_OK = 0
+SMSM_E_INVALID = -1
+SMSM_E_UNSUPPORTED = -2
+SMSM_E_NOMEM = -3
+SMSM_E_DEVICE = -4
+SMSM_E_NUMERIC = -5
+SMSM_FLAG_X_C128 = 0x1
+
+# Every entry point of include/smsm.h.
+ABI_SYMBOLS = (
+    "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_plan_set_params",
+    "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
+    "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
+    "smsm_apply_reg", "smsm_apply_normal", "smsm_launch_kernel", "smsm_kernel_cost",
+)
+KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4}
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n_slices", ctypes.c_int32),
+                ("n_shots", ctypes.c_int32), ("n_coils", ctypes.c_int32), ("filt", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("n_irls", ctypes.c_int32), ("n_cg", ctypes.c_int32),
+                ("eps_frac", ctypes.c_double), ("eps_decay", ctypes.c_double),
+                ("eps_floor_frac", ctypes.c_double), ("ns_max_iter", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class SmsmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsmsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1901_01893_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int
+        L.smsm_plan_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params), vp,
+                                       ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
+                                       vp, ctypes.POINTER(vp)]
+        L.smsm_plan_create.restype = st
+        L.smsm_plan_destroy.argtypes = [vp]
+        L.smsm_plan_destroy.restype = st
+        L.smsm_plan_device_bytes.argtypes = [vp]
+        L.smsm_plan_device_bytes.restype = ctypes.c_size_t
+        L.smsm_plan_set_params.argtypes = [vp, ctypes.POINTER(Params)]
+        L.smsm_plan_set_params.restype = st
+        L.smsm_solve.argtypes = [vp, vp, vp, vp]
+        L.smsm_solve.restype = st
+        L.smsm_plan_status.argtypes = [vp]
+        L.smsm_plan_status.restype = st
+        L.smsm_status_string.argtypes = [st]
+        L.smsm_status_string.restype = ctypes.c_char_p
+        for name in ("smsm_apply_A", "smsm_apply_AH", "smsm_apply_AHA", "smsm_gram", "smsm_lambda_max",
+                     "smsm_apply_reg", "smsm_apply_normal"):
+            f = getattr(L, name)
+            f.argtypes = [vp, vp, vp, vp]
+            f.restype = st
+        L.smsm_weights.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp]
+        L.smsm_weights.restype = st
+        L.smsm_set_weights.argtypes = [vp, vp, vp]
+        L.smsm_set_weights.restype = st
+        L.smsm_launch_kernel.argtypes = [vp, st, st, vp]
+        L.smsm_launch_kernel.restype = st
+        L.smsm_kernel_cost.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.smsm_kernel_cost.restype = st
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().smsm_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != SMSM_OK:
+        raise SmsmError(status, where)
+
+
+def _dev_ptr(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_params(lam=1e-3, n_irls=10, n_cg=10, eps_frac=0.1, eps_decay=1.5, eps_floor_frac=1e-4,
+                ns_max_iter=0, flags=0) -> Params:
+    return Params(float(lam), int(n_irls), int(n_cg), float(eps_frac), float(eps_decay),
+                  float(eps_floor_frac), int(ns_max_iter), int(flags))
+
+
+class Plan:
+    """A solver plan for one geometry (wraps smsm_plan_create / destroy)."""
+
+    def __init__(self, n1: int, n2: int, n_slices: int, n_shots: int, n_coils: int, filt: int,
+                 coils, masks: np.ndarray, shifts: Optional[Sequence[float]] = None,
+                 params: Optional[Params] = None, stream=None):
+        import torch
+        self.geom = Geometry(n1, n2, n_slices, n_shots, n_coils, filt)
+        self.params = params if params is not None else make_params()
+        self.shape_x = (n_slices, n_shots, n2, n1)
+        self.shape_y = (n_shots, n_coils, n2, n1)
+        self.K = n_shots * filt * filt
+        self.shape_g = (n_slices, self.K, self.K)
+        cptr = _dev_ptr(coils, torch.complex64, (n_slices, n_coils, n2, n1), "coils")
+        m = np.ascontiguousarray(masks, dtype=np.uint8)
+        if m.shape != (n_shots, n2):
+            raise ValueError(f"masks: expected {(n_shots, n2)}, got {m.shape}")
+        sh = None
+        if shifts is not None:
+            sh = np.ascontiguousarray(shifts, dtype=np.float64)
+            if sh.shape != (n_slices,):
+                raise ValueError("shifts: one value per slice")
+        self._masks, self._shifts = m, sh
+        out = ctypes.c_void_p()
+        st = lib().smsm_plan_create(
+            ctypes.byref(self.geom), ctypes.byref(self.params), cptr,
+            m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+            sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if sh is not None else None,
+            _stream_ptr(stream), ctypes.byref(out))
+        _check(st, "smsm_plan_create")
+        self._h = out
+
+    # -- lifecycle ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().smsm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().smsm_plan_device_bytes(self._h))
+
+    def set_params(self, params: Params):
+        _check(lib().smsm_plan_set_params(self._h, ctypes.byref(params)), "smsm_plan_set_params")
+        self.params = params
+
+    # -- solve ----------------------------------------------------------------
+    def solve(self, y, out=None, stream=None):
+        """x = IRLS solve of Eq. 10 for y (c64 [Ns][Nc][n2][n1])."""
+        import torch
+        c128 = bool(self.params.flags & SMSM_FLAG_X_C128)
+        dt = torch.complex128 if c128 else torch.complex64
+        if out is None:
+            out = torch.empty(self.shape_x, dtype=dt, device=y.device)
+        yp = _dev_ptr(y, torch.complex64, self.shape_y, "y")
+        xp = _dev_ptr(out, dt, self.shape_x, "x")
+        _check(lib().smsm_solve(self._h, yp, xp, _stream_ptr(stream)), "smsm_solve")
+        return out
+
+    def status(self) -> int:
+        return int(lib().smsm_plan_status(self._h))
+
+    # -- operators --------------------------------------------------------------
+    def _unary(self, fname, a, a_dtype, a_shape, out_shape, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(out_shape, dtype=torch.complex128, device=a.device)
+        ap = _dev_ptr(a, a_dtype, a_shape, "input")
+        op = _dev_ptr(out, torch.complex128, out_shape, "output")
+        _check(getattr(lib(), fname)(self._h, ap, op, _stream_ptr(stream)), fname)
+        return out
+
+    def apply_A(self, x, out=None, stream=None):
+        import torch
+        return self._unary("smsm_apply_A", x, torch.complex128, self.shape_x, self.shape_y, out, stream)
+
+    def apply_AH(self, y, out=None, stream=None):
+        import torch
+        return self._unary("smsm_apply_AH", y, torch.complex64, self.shape_y, self.shape_x, out, stream)
+
+    def apply_AHA(self, x, out=None, stream=None):
+        import torch
+        return self._unary("smsm_apply_AHA", x, torch.complex128, self.shape_x, self.shape_x, out, stream)
+
+    def gram(self, x, out=None, stream=None):
+        import torch
+        return self._unary("smsm_gram", x, torch.complex128, self.shape_x, self.shape_g, out, stream)
+
+    def apply_reg(self, x, out=None, stream=None):
+        import torch
+        return self._unary("smsm_apply_reg", x, torch.complex128, self.shape_x, self.shape_x, out, stream)
+
+    def apply_normal(self, x, out=None, stream=None):
+        import torch
+        return self._unary("smsm_apply_normal", x, torch.complex128, self.shape_x, self.shape_x, out, stream)
+
+    def lambda_max(self, G, stream=None):
+        import torch
+        out = torch.empty(self.geom.n_slices, dtype=torch.float64, device=G.device)
+        gp = _dev_ptr(G, torch.complex128, self.shape_g, "G")
+        _check(lib().smsm_lambda_max(self._h, gp, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "smsm_lambda_max")
+        return out
+
+    def weights(self, G, eps: Sequence[float], out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape_g, dtype=torch.complex128, device=G.device)
+        e = np.ascontiguousarray(eps, dtype=np.float64)
+        if e.shape != (self.geom.n_slices,):
+            raise ValueError("eps: one value per slice")
+        gp = _dev_ptr(G, torch.complex128, self.shape_g, "G")
+        wp = _dev_ptr(out, torch.complex128, self.shape_g, "W")
+        _check(lib().smsm_weights(self._h, gp, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), wp,
+                                  _stream_ptr(stream)), "smsm_weights")
+        return out
+
+    def set_weights(self, W, stream=None):
+        import torch
+        wp = _dev_ptr(W, torch.complex128, self.shape_g, "W")
+        _check(lib().smsm_set_weights(self._h, wp, _stream_ptr(stream)), "smsm_set_weights")
+
+
+    # -- diagnostics -------------------------------------------------------------
+    def launch_kernel(self, name: str, reps: int = 1, stream=None):
+        """Re-launch one CG-iteration kernel `reps` times on the plan's buffers."""
+        _check(lib().smsm_launch_kernel(self._h, KERNEL_IDS[name], int(reps), _stream_ptr(stream)),
+               "smsm_launch_kernel")
+
+    def kernel_cost(self, name: str):
+        """(FP64 flops, compulsory HBM bytes) of one launch of a CG-iteration kernel."""
+        f, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().smsm_kernel_cost(self._h, KERNEL_IDS[name], ctypes.byref(f), ctypes.byref(b)),
+               "smsm_kernel_cost")
+        return f.value, b.value
+
+
+# Flat names mirroring the C ABI.
+def smsm_plan_create(n1, n2, n_slices, n_shots, n_coils, filt, coils, masks, shifts=None, params=None,
+                     stream=None) -> Plan:
+    return Plan(n1, n2, n_slices, n_shots, n_coils, filt, coils, masks, shifts, params, stream)
+
+
+def smsm_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def smsm_solve(plan: Plan, y, out=None, stream=None):
+    return plan.solve(y, out, stream)
+
+
+def smsm_plan_status(plan: Plan) -> int:
+    return plan.status()
+
+
+def smsm_apply_A(plan: Plan, x, out=None, stream=None):
+    return plan.apply_A(x, out, stream)
+
+
+def smsm_apply_AH(plan: Plan, y, out=None, stream=None):
+    return plan.apply_AH(y, out, stream)
+
+
+def smsm_apply_AHA(plan: Plan, x, out=None, stream=None):
+    return plan.apply_AHA(x, out, stream)
+
+
+def smsm_gram(plan: Plan, x, out=None, stream=None):
+    return plan.gram(x, out, stream)
+
+
+def smsm_weights(plan: Plan, G, eps, out=None, stream=None):
+    return plan.weights(G, eps, out, stream)
+
+
+def smsm_lambda_max(plan: Plan, G, stream=None):
+    return plan.lambda_max(G, stream)
+
+
+def smsm_set_weights(plan: Plan, W, stream=None):
+    plan.set_weights(W, stream)
+
+
+def smsm_apply_reg(plan: Plan, x, out=None, stream=None):
+    return plan.apply_reg(x, out, stream)
+
+
+def smsm_apply_normal(plan: Plan, x, out=None, stream=None):
+    return plan.apply_normal(x, out, stream)
+
+
+def smsm_launch_kernel(plan: Plan, name: str, reps: int = 1, stream=None):
+    plan.launch_kernel(name, reps, stream)
+
+
+def smsm_kernel_cost(plan: Plan, name: str):
+    return plan.kernel_cost(name)

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/smsm.h, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1901_01893_amd as pkg
+from paper_1901_01893_amd import smsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smsm.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(smsm_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+needs_lib = pytest.mark.skipif(not os.path.exists(smsm.LIB_PATH), reason="libsmsm.so not built")
+
+
+def test_binding_lists_every_declared_symbol():
+    assert sorted(smsm.ABI_SYMBOLS) == declared_symbols()
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(smsm.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+@needs_lib
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert pkg.status_string(code)
+    assert pkg.status_string(-99) == "unknown status"
+
+
+def _create(geom, params, coil_ptr, masks, out):
+    lib = smsm.lib()
+    return lib.smsm_plan_create(
+        ctypes.byref(geom) if geom is not None else None,
+        ctypes.byref(params) if params is not None else None,
+        coil_ptr, masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if masks is not None else None,
+        None, None, out)
+
+
+@needs_lib
+def test_plan_create_rejects_bad_arguments_without_a_device():
+    geom = smsm.Geometry(64, 64, 2, 4, 8, 5)
+    params = smsm.make_params()
+    masks = np.stack([(np.arange(64) % 4 == i) for i in range(4)]).astype(np.uint8)
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: validation fails first
+    out = ctypes.c_void_p()
+    assert _create(geom, params, fake, masks, None) == pkg.SMSM_E_INVALID
+    assert _create(None, params, fake, masks, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert _create(geom, None, fake, masks, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert _create(geom, params, None, masks, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    bad = smsm.make_params(lam=-1.0)
+    assert _create(geom, bad, fake, masks, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    bad = smsm.make_params(n_irls=0)
+    assert _create(geom, bad, fake, masks, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert _create(smsm.Geometry(60, 64, 2, 4, 8, 5), params, fake, masks, ctypes.byref(out)) == \
+        pkg.SMSM_E_UNSUPPORTED                       # not a power of two
+    assert _create(smsm.Geometry(64, 64, 2, 4, 8, 40), params, fake, masks, ctypes.byref(out)) == \
+        pkg.SMSM_E_UNSUPPORTED                       # filter wider than the grid allows
+    other = masks.copy()
+    other[0, 1] = 1                                   # not the interleaved pattern
+    assert _create(geom, params, fake, other, ctypes.byref(out)) == pkg.SMSM_E_UNSUPPORTED
+    assert out.value is None
+
+
+@needs_lib
+def test_entry_points_reject_null_plan():
+    lib = smsm.lib()
+    for name in ("smsm_apply_A", "smsm_apply_AH", "smsm_apply_AHA", "smsm_gram", "smsm_lambda_max",
+                 "smsm_apply_reg", "smsm_apply_normal", "smsm_solve"):
+        assert getattr(lib, name)(None, None, None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_set_weights(None, None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_plan_destroy(None) == pkg.SMSM_OK
+    assert lib.smsm_plan_device_bytes(None) == 0
