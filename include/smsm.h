@@ -77,7 +77,7 @@ typedef struct {
     double  eps_frac;        /* eps schedule start (fraction of sigma_l), > 0 */
     double  eps_decay;       /* eta >= 1 */
     double  eps_floor_frac;  /* >= 0 */
-    int32_t ns_max_iter;     /* cap on Newton-Schulz iterations for W (0 = 60) */
+    int32_t ns_max_iter;     /* cap on Newton-Schulz iterations for W (0 = 24) */
     uint32_t flags;          /* SMSM_FLAG_* */
 } smsm_params;
 

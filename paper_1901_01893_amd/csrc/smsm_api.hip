@@ -1,6 +1,8 @@
 // Host side of the SMS-MUSSELS solver: plan creation, device memory layout,
 // and the kernel sequences behind every C-ABI entry point of smsm.h.
 #include "smsm_kernels.h"
+#include "smsm_col_fast.h"
+#include "smsm_wavefft.h"
 #include "smsm.h"
 
 #include <cmath>
@@ -14,7 +16,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kColThreads = 512;
 constexpr int kVecBlocks = 512;      // fixed grid of the CG vector kernels
-constexpr int kNsDefaultIters = 60;  // Newton-Schulz iteration cap
+constexpr int kNsDefaultIters = 24;  // Newton-Schulz iteration cap
 constexpr int kSqSteps = 30;         // squarings for the largest eigenvalue
 constexpr double kNsTol = 1e-10;     // ||I - Z Y||_F at which NS is converged
 
@@ -32,6 +34,8 @@ struct smsm_plan {
     smsm_params prm;
     int dev = 0;
     int TR = 1, TRy = 1;
+    int TRw = 8;              // rows per workgroup of the in-wave FFT row passes
+    size_t lds_roww = 0;
     int npq = 0;             // blocks of the forward row pass (partials of <p,q>)
     int ntile = 0;           // GEMM tiles per slice
     size_t lds_rows = 0, lds_col = 0, lds_gram = 0;
@@ -51,6 +55,9 @@ struct smsm_plan {
     double *wscale = nullptr, *sqscale = nullptr, *epsin = nullptr;
     int *done = nullptr, *flags = nullptr;
     int ns_iters = kNsDefaultIters;
+    int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
+    size_t lds_colfast = 0;
+    size_t lds_band = 0;
 };
 
 namespace {
@@ -93,28 +100,78 @@ inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 dim3 vec_grid() { return dim3(kVecBlocks); }
 
 // ---- kernel chains -------------------------------------------------------
-smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
+// Row pass 1 (kx inverse DFT, transposed write) for every supported n1.
+template <int MODE>
+smsm_status rows_inv_mode(smsm_plan* P, const double2* in, double2* out, const double* prn, const double* pro,
+                          hipStream_t st) {
     const Geo& g = P->g;
-    dim3 grid(g.n2 / P->TR, g.B);
-    hipLaunchKernelGGL(k_rows_inv_T<ROWS_PLAIN>, grid, dim3(kThreads), P->lds_rows, st, g, in, out,
-                       nullptr, nullptr, nullptr, nullptr, 0, P->tw1, P->TR);
+    const dim3 grid(g.n2 / P->TRw, g.B), blk(256);
+    const size_t lds = P->lds_roww;
+    switch (g.n1) {
+        case 16: hipLaunchKernelGGL((k_rows_inv_w<16, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+        case 32: hipLaunchKernelGGL((k_rows_inv_w<32, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+        case 64: hipLaunchKernelGGL((k_rows_inv_w<64, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+        case 128: hipLaunchKernelGGL((k_rows_inv_w<128, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+        default: hipLaunchKernelGGL((k_rows_inv_w<256, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+    }
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
+smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
+    return rows_inv_mode<ROWS_PLAIN>(P, in, out, nullptr, nullptr, st);
+}
+
+// Row pass 3 (kx forward DFT from the transposed hybrid layout).
 template <bool CG, bool BAND>
 smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, const double2* pvec, hipStream_t st) {
     const Geo& g = P->g;
-    dim3 grid(g.n2 / P->TR, g.B);
-    hipLaunchKernelGGL((k_rows_fwd_T<CG, BAND>), grid, dim3(kThreads), P->lds_rows, st, g, in, out,
-                       P->corr, pvec, P->pq, P->tw1, P->TR);
+    const dim3 grid(g.n2 / P->TRw, g.B), blk(256);
+    const size_t lds = P->lds_roww;
+    switch (g.n1) {
+        case 16: hipLaunchKernelGGL((k_rows_fwd_w<16, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+        case 32: hipLaunchKernelGGL((k_rows_fwd_w<32, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+        case 64: hipLaunchKernelGGL((k_rows_fwd_w<64, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+        case 128: hipLaunchKernelGGL((k_rows_fwd_w<128, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+        default: hipLaunchKernelGGL((k_rows_fwd_w<256, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+    }
     LAUNCH_CHECK();
     return SMSM_OK;
+}
+
+// Instances of the register-resident column kernel: (M, L, Ns) with two
+// coil-group waves per shot.
+struct ColFastInst {
+    int M, L, Ns;
+    const void* fn;
+};
+#define COLFAST(M_, L_) {M_, L_, 4, (const void*)&k_col_fast<M_, L_, 4, 2>}
+const ColFastInst kColFast[] = {COLFAST(16, 2), COLFAST(16, 3), COLFAST(32, 2),
+                                COLFAST(32, 3), COLFAST(64, 2), COLFAST(64, 3)};
+#undef COLFAST
+
+template <int M_, int L_>
+void launch_colfast(smsm_plan* P, int use_reg, hipStream_t st) {
+    const Geo& g = P->g;
+    hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, P->h1,
+                       P->h2, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg);
 }
 
 template <int MODE>
 smsm_status col(smsm_plan* P, int use_reg, hipStream_t st) {
     const Geo& g = P->g;
+    if (MODE == COL_NORMAL && P->col_fast >= 0) {
+        switch (P->col_fast) {
+            case 0: launch_colfast<16, 2>(P, use_reg, st); break;
+            case 1: launch_colfast<16, 3>(P, use_reg, st); break;
+            case 2: launch_colfast<32, 2>(P, use_reg, st); break;
+            case 3: launch_colfast<32, 3>(P, use_reg, st); break;
+            case 4: launch_colfast<64, 2>(P, use_reg, st); break;
+            default: launch_colfast<64, 3>(P, use_reg, st); break;
+        }
+        LAUNCH_CHECK();
+        return SMSM_OK;
+    }
     hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, P->h1, P->h2,
                        P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
     LAUNCH_CHECK();
@@ -123,9 +180,17 @@ smsm_status col(smsm_plan* P, int use_reg, hipStream_t st) {
 
 smsm_status band_corr(smsm_plan* P, const double2* vin, hipStream_t st) {
     const Geo& g = P->g;
-    const int total = g.B * g.nband;
-    hipLaunchKernelGGL(k_band_corr, dim3((total + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g,
-                       vin, P->D, P->corr);
+    const dim3 grid(band_tiles_total(g), g.L, g.Ns), block(64 * g.e);
+    switch (g.nc) {
+        case 3: hipLaunchKernelGGL(k_band_tile<3>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 5: hipLaunchKernelGGL(k_band_tile<5>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 7: hipLaunchKernelGGL(k_band_tile<7>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 9: hipLaunchKernelGGL(k_band_tile<9>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 11: hipLaunchKernelGGL(k_band_tile<11>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 13: hipLaunchKernelGGL(k_band_tile<13>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        case 15: hipLaunchKernelGGL(k_band_tile<15>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+        default: hipLaunchKernelGGL(k_band_tile<17>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
+    }
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -208,12 +273,13 @@ smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, dou
         LAUNCH_CHECK();
         hipLaunchKernelGGL(k_ns_update, gemm_grid(g, 2 * g.L), dim3(kThreads), 0, st, g.K, g.L, Y[a], Z[a],
                            P->T, Y[bsel], Z[bsel], P->nspart, P->ntile, P->done + (size_t)k * g.L,
-                           P->done + (size_t)(k + 1) * g.L, kNsTol * kNsTol);
+                           P->done + (size_t)(k + 1) * g.L, P->done + (size_t)(nit + 1) * g.L, bsel,
+                           kNsTol * kNsTol);
         LAUNCH_CHECK();
     }
     const long tot = (long)g.L * g.K * g.K;
     hipLaunchKernelGGL(k_ns_final, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g.K,
-                       g.L, Z[nit & 1], P->wscale, P->W);
+                       g.L, P->Z0, P->Z1, P->done + (size_t)(nit + 1) * g.L, P->wscale, P->W);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -274,7 +340,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     if (n1 <= 0 || n2 <= 0 || L <= 0 || Ns <= 0 || Nc <= 0 || r <= 0) return SMSM_E_INVALID;
     if (!is_pow2(n1) || !is_pow2(n2) || n1 < 16 || n2 < 16 || n1 > 256 || n2 > 256) return SMSM_E_UNSUPPORTED;
     if (!is_pow2(Ns) || Ns > 8 || n2 / Ns < 8 || L > 4) return SMSM_E_UNSUPPORTED;
-    if (r < 2 || 2 * r - 1 > std::min(n1, n2) / 2 || Ns * r * r > 256) return SMSM_E_UNSUPPORTED;
+    if (r < 2 || 2 * r - 1 > std::min(n1, n2) / 2 || Ns * r * r > 256 || 2 * r - 1 > BAND_MAX_NC)
+        return SMSM_E_UNSUPPORTED;
     // interleaved sampling of Eq. 2 only
     for (int i = 0; i < Ns; ++i)
         for (int j = 0; j < n2; ++j)
@@ -298,12 +365,23 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
-    P->npq = (n2 / P->TR) * g.B;
+    P->TRw = (n1 == 16) ? 16 : 8;
+    P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
+    P->npq = (n2 / P->TRw) * g.B;
     P->ntile = ((g.K + GT - 1) / GT) * ((g.K + GT - 1) / GT);
+    P->lds_band = band_lds_bytes(g);
+    P->lds_colfast = (size_t)colfast_lds_total(g) * sizeof(double2);
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
     if (max_lds <= 0) max_lds = 65536;
-    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds) { delete P; return SMSM_E_UNSUPPORTED; }
+    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_band > (size_t)max_lds) {
+        delete P;
+        return SMSM_E_UNSUPPORTED;
+    }
+    for (int k = 0; k < (int)(sizeof(kColFast) / sizeof(kColFast[0])); ++k)
+        if (kColFast[k].M == g.M && kColFast[k].L == L && kColFast[k].Ns == Ns &&
+            P->lds_colfast <= (size_t)max_lds)
+            P->col_fast = k;
 
     // device memory layout
     const size_t nvec = (size_t)L * Ns * n2 * n1;
@@ -331,7 +409,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t onsp = cv.take<double>((size_t)L * P->ntile);
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
     const size_t osq = cv.take<double>(L), oei = cv.take<double>(L);
-    const size_t odone = cv.take<int>((size_t)(P->ns_iters + 1) * L), oflags = cv.take<int>(4);
+    const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
     char* base = static_cast<char*>(P->arena);
@@ -396,6 +474,16 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                              (const void*)&k_gram_col};
         for (const void* f : fns)
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
+        const void* bands[] = {(const void*)&k_band_tile<3>, (const void*)&k_band_tile<5>,
+                               (const void*)&k_band_tile<7>, (const void*)&k_band_tile<9>,
+                               (const void*)&k_band_tile<11>, (const void*)&k_band_tile<13>,
+                               (const void*)&k_band_tile<15>, (const void*)&k_band_tile<17>};
+        for (const void* f : bands)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
+        if (P->col_fast >= 0 &&
+            hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+                hipSuccess)
+            ok = false;
     }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
     if (!ok) {
@@ -462,16 +550,11 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
         hipLaunchKernelGGL(k_cg_init, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->b, P->q, P->r, PR[0]);
         LAUNCH_CHECK();
         for (int j = 0; j < prm.n_cg; ++j) {
-            const dim3 grid(g.n2 / P->TR, g.B);
             if (j == 0)
-                hipLaunchKernelGGL(k_rows_inv_T<ROWS_CG_FIRST>, grid, dim3(kThreads), P->lds_rows, st, g,
-                                   (const double2*)nullptr, P->h1, P->r, P->p, (const double*)nullptr,
-                                   (const double*)nullptr, kVecBlocks, P->tw1, P->TR);
+                s = rows_inv_mode<ROWS_CG_FIRST>(P, nullptr, P->h1, nullptr, nullptr, st);
             else
-                hipLaunchKernelGGL(k_rows_inv_T<ROWS_CG_UPDATE>, grid, dim3(kThreads), P->lds_rows, st, g,
-                                   (const double2*)nullptr, P->h1, P->r, P->p, PR[j % 3], PR[(j + 2) % 3],
-                                   kVecBlocks, P->tw1, P->TR);
-            LAUNCH_CHECK();
+                s = rows_inv_mode<ROWS_CG_UPDATE>(P, nullptr, P->h1, PR[j % 3], PR[(j + 2) % 3], st);
+            if (s) return s;
             if ((s = col<COL_NORMAL>(P, reg ? 1 : 0, st))) return s;
             if (reg) {
                 if ((s = band_corr(P, P->p, st))) return s;

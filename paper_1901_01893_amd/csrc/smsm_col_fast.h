@@ -1,0 +1,315 @@
+// Register-resident column kernel for the SENSE coil loop of the normal
+// operator (one workgroup per image column x).
+//
+// Wave w handles shot i = w % NS and the coils of coil group w / NS.  Inside a
+// wave, lane l = g*M + m works on coil group member g and folded ky point m;
+// it keeps the coil-summed accumulator of every slice s and fold index t in
+// registers and reads tau_i * u_{s,i}[m + M t] from shared memory.  Per coil:
+//   fold     f_s[m]  = sum_t S_{s,c}[m + M t] (tau_i u_{s,i})[m + M t]
+//   forward  M-point DFT across the M lanes of the group (decimation in
+//            frequency: natural order in, bit-reversed order out)
+//   CAIPI    Z = sum_s theta_s Y_s ;  Y'_s = conj(theta_s) Z   (pointwise)
+//   inverse  M-point inverse DFT (decimation in time: bit-reversed in,
+//            natural order out)
+//   unfold   acc_s[t] += conj(S_{s,c}[m + M t]) g_s[m]
+// Lane exchanges use DPP for xor distances 1..8 and the gfx950 permlane
+// swaps for 16 and 32; all 64 lanes stay active through every exchange.
+#pragma once
+#include "smsm_kernels.h"
+
+template <int CTRL>
+SMSM_DEV double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// xor 16 / xor 32 with the gfx950 permlane swaps: swapping a value with a
+// copy of itself leaves, in the two results, the even and the odd 16-lane rows
+// (resp. the low and high 32-lane halves) side by side; each lane then picks
+// the copy that came from its partner row.
+SMSM_DEV unsigned xor16_u(unsigned v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (threadIdx.x & 16) ? r[0] : r[1];
+}
+SMSM_DEV unsigned xor32_u(unsigned v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+}
+SMSM_DEV double swz_xor16_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = xor16_u((unsigned)b), hi = xor16_u((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+SMSM_DEV double perm_xor32_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = xor32_u((unsigned)b), hi = xor32_u((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// value of lane (l ^ MASK)
+template <int MASK>
+SMSM_DEV double lane_xor(double v) {
+    if constexpr (MASK == 1) return dpp_d<0xB1>(v);                 // quad_perm [1,0,3,2]
+    else if constexpr (MASK == 2) return dpp_d<0x4E>(v);            // quad_perm [2,3,0,1]
+    else if constexpr (MASK == 4) return dpp_d<0x1B>(dpp_d<0x141>(v));  // half-mirror (^7), then ^3
+    else if constexpr (MASK == 8) return dpp_d<0x141>(dpp_d<0x140>(v)); // mirror (^15), then ^7
+    else if constexpr (MASK == 16) return swz_xor16_d(v);
+    else return perm_xor32_d(v);
+}
+
+template <int MASK>
+SMSM_DEV double2 lane_xor2(double2 v) {
+    return make_double2(lane_xor<MASK>(v.x), lane_xor<MASK>(v.y));
+}
+
+// One decimation-in-frequency stage of span H on NV values:
+// upper lane (bit H clear): a + b ; lower lane: (a - b) w.
+template <int H, int NV>
+SMSM_DEV void dif_stage(double2 (&v)[NV], double sgn, double2 w) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+        const double2 p = lane_xor2<H>(v[s]);
+        const double2 d = make_double2(p.x + sgn * v[s].x, p.y + sgn * v[s].y);
+        v[s] = cmul(d, w);
+    }
+}
+
+// One decimation-in-time stage of span H with conjugated twiddle:
+// upper: u + conj(w) v ; lower: u - conj(w) v.
+template <int H, int NV>
+SMSM_DEV void dit_stage(double2 (&v)[NV], double sgn, double2 w) {
+    const double2 wc = cconj(w);
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+        const double2 t = cmul(wc, v[s]);     // upper lanes: w = 1, so t = own value
+        const double2 p = lane_xor2<H>(t);
+        v[s] = make_double2(p.x + sgn * t.x, p.y + sgn * t.y);
+    }
+}
+
+template <int M, int NV>
+SMSM_DEV void fft_dif(double2 (&v)[NV], const double2 (&w)[8], const double (&sg)[8]) {
+    if constexpr (M >= 64) dif_stage<32, NV>(v, sg[5], w[5]);
+    if constexpr (M >= 32) dif_stage<16, NV>(v, sg[4], w[4]);
+    if constexpr (M >= 16) dif_stage<8, NV>(v, sg[3], w[3]);
+    if constexpr (M >= 8) dif_stage<4, NV>(v, sg[2], w[2]);
+    if constexpr (M >= 4) dif_stage<2, NV>(v, sg[1], w[1]);
+    dif_stage<1, NV>(v, sg[0], w[0]);
+}
+
+template <int M, int NV>
+SMSM_DEV void fft_dit_inv(double2 (&v)[NV], const double2 (&w)[8], const double (&sg)[8]) {
+    dit_stage<1, NV>(v, sg[0], w[0]);
+    if constexpr (M >= 4) dit_stage<2, NV>(v, sg[1], w[1]);
+    if constexpr (M >= 8) dit_stage<4, NV>(v, sg[2], w[2]);
+    if constexpr (M >= 16) dit_stage<8, NV>(v, sg[3], w[3]);
+    if constexpr (M >= 32) dit_stage<16, NV>(v, sg[4], w[4]);
+    if constexpr (M >= 64) dit_stage<32, NV>(v, sg[5], w[5]);
+}
+
+// Shared-memory layout (double2 units) of k_col_fast.
+__host__ __device__ inline int colfast_lds_A(const Geo& g) { return 2 * g.B * g.n2 + g.n2; }
+__host__ __device__ inline int colfast_lds_total(const Geo& g) {
+    return colfast_lds_A(g) + g.L * g.Ns * g.Ns * g.nc + 16;
+}
+
+template <int N> struct WaveFft;
+
+// Normal operator column pass; same input/output contract as k_col<COL_NORMAL>.
+// Template: M = n2/Ns (folded length), L slices, NS shots, CG coil groups
+// (waves per shot).  blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
+template <int M, int L, int NS, int CG>
+__global__ void __launch_bounds__(64 * NS * CG)
+k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const float2* __restrict__ ST,
+           const double2* __restrict__ theta, const double2* __restrict__ tau, const double2* __restrict__ tw2,
+           const double2* __restrict__ twM, const double2* __restrict__ tw1, const double2* __restrict__ Kc,
+           int use_reg) {
+    constexpr int T = NS;          // n2 = M * NS
+    constexpr int N2 = M * NS;
+    constexpr int G = 64 / M;      // coils processed side by side in one wave
+    constexpr int LOGM = (M == 8) ? 3 : (M == 16) ? 4 : (M == 32) ? 5 : 6;
+    constexpr int B = L * NS, NW = NS * CG;
+    using FC = WaveFft<N2>;
+    constexpr int RC = FC::R;
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, Nc = g.Nc, nc = g.nc, e = g.e;
+    const int x1 = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int i = wave % NS, cg = wave / NS;
+    const int grp = lane / M, m = lane % M;
+    double2* U = sm;
+    double2* ACC = sm + B * N2;
+    double2* TW2 = sm + 2 * B * N2;
+    double2* A = sm + colfast_lds_A(g);
+    const double isq2 = 1.0 / sqrt((double)N2);
+
+    for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
+    // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}  (Hankel kernel, kx taps)
+    if (use_reg) {
+        const int nu1 = x1 - n1 / 2;
+        for (int idx = tid; idx < L * NS * NS * nc; idx += nt) {
+            const double2* kr = Kc + (size_t)idx * nc;
+            double2 a = cmk(0.0, 0.0);
+            for (int d1 = 0; d1 < nc; ++d1) a = cfma(kr[d1], tw1[((d1 - e) * nu1) & (n1 - 1)], a);
+            A[idx] = a;
+        }
+    }
+    __syncthreads();
+
+    // ---- column image: U[b][n] = tau_i[n] u_b[n], u_b = centred inverse DFT along ky of h1 column
+    for (int b = wave; b < B; b += NW) {
+        FC fc;
+        fc.setup(TW2, lane);
+        const int ib = b % NS;
+        const double2* src = h1 + ((size_t)b * n1 + x1) * N2;
+        double2 v[RC];
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const int k = fc.m + 64 * t;
+            v[t] = cscale(src[k], sgn_pow(k));
+        }
+        fc.template run<true>(v);
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const int n = fc.out_index(t);
+            const double2 ta = cscale(TW2[(ib * n) & (N2 - 1)], sgn_pow(n));
+            U[b * N2 + n] = cmul(ta, cscale(v[t], isq2 * sgn_pow(n)));
+        }
+    }
+    __syncthreads();
+
+    // ---- per-lane constants (tau_i u stays in shared memory: U[(s,i)][m + M t])
+    double2 acc[L][T];
+#pragma unroll
+    for (int s = 0; s < L; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[s][t] = cmk(0.0, 0.0);
+    const double2* Ui = U + i * N2 + m;
+    double2 w[8];
+    double sg[8];
+#pragma unroll
+    for (int st = 0; st < LOGM; ++st) {
+        const int h = 1 << st;
+        const bool upper = (m & h) == 0;
+        sg[st] = upper ? 1.0 : -1.0;
+        w[st] = upper ? cmk(1.0, 0.0) : twM[(m & (h - 1)) * (M / (2 * h))];
+    }
+    const int kb = (int)(__brev((unsigned)m) >> (32 - LOGM));   // this lane's DFT bin after DIF
+    double2 th[L];
+#pragma unroll
+    for (int s = 0; s < L; ++s) th[s] = theta[s * N2 + i + NS * kb];
+
+    // ---- coil loop (indices past Nc are clamped and their fold is zeroed)
+    const int per_iter = CG * G;
+    const int iters = (Nc + per_iter - 1) / per_iter;
+    const int lane_off = x1 * N2 + m;
+    const int slice_stride = Nc * n1 * N2, coil_stride = n1 * N2;
+#pragma unroll 1
+    for (int it = 0; it < iters; ++it) {
+        const int c = (it * CG + cg) * G + grp;
+        const double live = (c < Nc) ? 1.0 : 0.0;
+        const int cbase = lane_off + min(c, Nc - 1) * coil_stride;
+        float2 sc[L][T];
+#pragma unroll
+        for (int s = 0; s < L; ++s)
+#pragma unroll
+            for (int t = 0; t < T; ++t) sc[s][t] = ST[cbase + s * slice_stride + M * t];
+        double2 f[L];
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            double2 a = cmk(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < T; ++t) a = cfma(c64to128(sc[s][t]), Ui[s * NS * N2 + M * t], a);
+            f[s] = cscale(a, live);
+        }
+        fft_dif<M, L>(f, w, sg);
+        double2 z = cmk(0.0, 0.0);
+#pragma unroll
+        for (int s = 0; s < L; ++s) z = cfma(th[s], f[s], z);
+#pragma unroll
+        for (int s = 0; s < L; ++s) f[s] = cmulc(z, th[s]);
+        fft_dit_inv<M, L>(f, w, sg);
+#pragma unroll
+        for (int s = 0; s < L; ++s)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[s][t] = cadd(acc[s][t], cconjmul(c64to128(sc[s][t]), f[s]));
+    }
+
+    // ---- reduce the coil-group members of the wave
+#pragma unroll
+    for (int s = 0; s < L; ++s)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            if constexpr (G >= 4) acc[s][t] = cadd(acc[s][t], lane_xor2<16>(acc[s][t]));
+            if constexpr (G >= 2) acc[s][t] = cadd(acc[s][t], lane_xor2<32>(acc[s][t]));
+        }
+    // ---- normal-operator scaling conj(tau_i[n]) / n2, then the circular Hankel
+    // term for the positions t = cg (mod CG) of this wave (output shot i):
+    //   sum_j u_{s,j}[n] sum_d2 A[s][j][i][d2] e^{-2 pi i (d2-e)(n - n2/2)/n2}
+    const bool writer = (grp == 0);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int n = m + M * t;
+        const double2 tai = cscale(TW2[(i * n) & (N2 - 1)], sgn_pow(n));
+        const bool mine = use_reg && writer && (t % CG == cg);
+#pragma unroll
+        for (int s = 0; s < L; ++s) {
+            acc[s][t] = cscale(cmulc(acc[s][t], tai), 1.0 / (double)N2);
+            if (mine) {
+                double2 kv[NS];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) kv[j] = cmk(0.0, 0.0);
+                for (int d2 = 0; d2 < nc; ++d2) {
+                    const double2 ev = TW2[((d2 - e) * (n - N2 / 2)) & (N2 - 1)];
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) kv[j] = cfma(A[((s * NS + j) * NS + i) * nc + d2], ev, kv[j]);
+                }
+                double2 rg = cmk(0.0, 0.0);
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const double2 taj = cscale(TW2[(j * n) & (N2 - 1)], sgn_pow(n));
+                    rg = cfma(kv[j], cmulc(U[(s * NS + j) * N2 + n], taj), rg);
+                }
+                acc[s][t] = cadd(acc[s][t], rg);
+            }
+        }
+    }
+    // ---- reduce the coil groups of a shot through shared memory, in order
+    for (int k = 0; k < CG; ++k) {
+        if (cg == k && writer) {
+#pragma unroll
+            for (int s = 0; s < L; ++s)
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const int o = (s * NS + i) * N2 + m + M * t;
+                    ACC[o] = (k == 0) ? acc[s][t] : cadd(ACC[o], acc[s][t]);
+                }
+        }
+        __syncthreads();
+    }
+    // ---- centred forward DFT along ky of every sequence, back into ACC, then store
+    for (int b = wave; b < B; b += NW) {
+        FC fc;
+        fc.setup(TW2, lane);
+        double2 v[RC];
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const int x = fc.m + 64 * t;
+            v[t] = cscale(ACC[b * N2 + x], sgn_pow(x));
+        }
+        fc.template run<false>(v);
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const int k = fc.out_index(t);
+            ACC[b * N2 + k] = cscale(v[t], isq2 * sgn_pow(k));
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < B * N2; idx += nt) {
+        const int b = idx / N2, j = idx - b * N2;
+        h2[((size_t)b * n1 + x1) * N2 + j] = ACC[idx];
+    }
+}

@@ -452,6 +452,130 @@ __global__ void k_band_corr(Geo g, const double2* __restrict__ p, const double2*
     corr[idx] = s;
 }
 
+// Tiled version: one workgroup per (band tile, slice l, output shot i').
+// Edge tiles cover TW = 64 pixels along one strip (top/bottom rows 0..e-1 and
+// n2-e..n2-1 between the corner blocks, left/right columns likewise) and all
+// e lines of the strip; wave k of the workgroup computes line k with one pixel
+// per lane.  Every pixel of a line shares one tap table, so the e tables of
+// the tile are staged in shared memory next to the p patch of all shots (tile
+// plus an e-wide halo, wrapped, strip direction contiguous); table reads are
+// broadcasts.  The four e x e corner blocks (one table per pixel) are tiles
+// of their own, one pixel per lane, tables read through the cache.
+#define BAND_TW 64
+__host__ __device__ inline int band_edge_tiles(int len, int e) { return (len - 2 * e + BAND_TW - 1) / BAND_TW; }
+__host__ __device__ inline int band_tiles_total(const Geo& g) {
+    return 2 * band_edge_tiles(g.n1, g.e) + 2 * band_edge_tiles(g.n2, g.e) + 4;
+}
+__host__ __device__ inline size_t band_patch_elems(const Geo& g) {
+    return (size_t)g.Ns * (3 * g.e) * (BAND_TW + 2 * g.e);
+}
+__host__ __device__ inline size_t band_lds_bytes(const Geo& g) {
+    return (band_patch_elems(g) + (size_t)g.e * g.Ns * g.nc * g.nc) * sizeof(double2);
+}
+
+#define BAND_MAX_NC 17
+template <int NC>
+__global__ void __launch_bounds__(1024)
+k_band_tile(Geo g, const double2* __restrict__ p, const double2* __restrict__ D, double2* __restrict__ corr) {
+    extern __shared__ double2 sm[];
+    constexpr int nc = NC, tab = NC * NC;
+    const int e = g.e, r = g.r, Ns = g.Ns, n1 = g.n1, n2 = g.n2;
+    const int nth = band_edge_tiles(n1, e), ntv = band_edge_tiles(n2, e);
+    const int l = blockIdx.y, ip = blockIdx.z;
+    const int tile = blockIdx.x;
+    int kind;  // 0 top, 1 bottom, 2 left, 3 right, 4 corner
+    int t2a, t1a, H, Wd;
+    if (tile < 2 * nth) {
+        kind = tile < nth ? 0 : 1;
+        const int k = tile - (kind == 1 ? nth : 0);
+        t2a = kind == 0 ? 0 : n2 - e;
+        t1a = e + k * BAND_TW;
+        H = e;
+        Wd = min(BAND_TW, n1 - e - t1a);
+    } else if (tile < 2 * nth + 2 * ntv) {
+        const int tt = tile - 2 * nth;
+        kind = tt < ntv ? 2 : 3;
+        const int k = tt - (kind == 3 ? ntv : 0);
+        t1a = kind == 2 ? 0 : n1 - e;
+        t2a = e + k * BAND_TW;
+        Wd = e;
+        H = min(BAND_TW, n2 - e - t2a);
+    } else {
+        kind = 4;
+        const int c = tile - 2 * nth - 2 * ntv;
+        t2a = (c & 1) ? n2 - e : 0;
+        t1a = (c & 2) ? n1 - e : 0;
+        H = e;
+        Wd = e;
+    }
+    // strip coordinates: "line" across the strip, "pos" along it
+    const bool horiz = kind != 2 && kind != 3;
+    const int nline = horiz ? H : Wd, npos = horiz ? Wd : H;
+    const int PL = nline + 2 * e, PP = npos + 2 * e;     // patch extent in line / pos
+    for (int idx = threadIdx.x; idx < Ns * PL * PP; idx += blockDim.x) {
+        const int i = idx / (PL * PP), rem = idx - i * PL * PP;
+        const int pl = rem / PP, pp = rem - pl * PP;
+        const int pr = horiz ? pl : pp, pc = horiz ? pp : pl;
+        const int q2 = (t2a - e + pr) & (n2 - 1), q1 = (t1a - e + pc) & (n1 - 1);
+        sm[idx] = p[(((size_t)l * Ns + i) * n2 + q2) * n1 + q1];
+    }
+    double2* Ds = sm + band_patch_elems(g);      // tap tables of the e lines (edge tiles)
+    if (kind < 4) {
+        const int per = Ns * tab;
+        for (int idx = threadIdx.x; idx < e * per; idx += blockDim.x) {
+            const int k = idx / per, rem = idx - k * per;
+            int c2 = r - 1, c1 = r - 1;
+            if (kind == 0) c2 = k;
+            else if (kind == 1) c2 = r + k;
+            else if (kind == 2) c1 = k;
+            else c1 = r + k;
+            Ds[idx] = D[((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)per + rem];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const size_t ob = ((size_t)l * Ns + ip) * g.nband;
+    if (kind < 4) {
+        if (wave >= nline) return;
+        const int ln = wave;
+        const double2* Dl = Ds + (size_t)ln * Ns * tab;   // same address in every lane: broadcast reads
+        const int pos = min(lane, npos - 1);
+        double2 s = cmk(0.0, 0.0);
+        for (int i = 0; i < Ns; ++i) {
+            const double2* Di = Dl + (size_t)i * tab;
+            const double2* Pi = sm + (size_t)i * PL * PP + ln * PP + pos;
+            for (int dl = 0; dl < nc; ++dl) {
+                const double2* Pr = Pi + dl * PP;
+#pragma unroll
+                for (int dp = 0; dp < NC; ++dp) {
+                    // table index [d2][d1]: (dl, dp) = (d2, d1) horizontally, (d1, d2) vertically
+                    const int ti = horiz ? dl * nc + dp : dp * nc + dl;
+                    s = cfma(Di[ti], Pr[dp], s);
+                }
+            }
+        }
+        if (lane < npos) {
+            const int t2 = horiz ? t2a + ln : t2a + lane, t1 = horiz ? t1a + lane : t1a + ln;
+            corr[ob + band_index(g, t2, t1)] = s;
+        }
+    } else {
+        if (wave != 0) return;
+        const int px = min(lane, e * e - 1);
+        const int rr = px / e, cc = px - rr * e;
+        const int t2 = t2a + rr, t1 = t1a + cc;
+        const int c2 = band_class(t2, n2, r), c1 = band_class(t1, n1, r);
+        const double2* Dl = D + ((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)Ns * tab;
+        double2 s = cmk(0.0, 0.0);
+        for (int i = 0; i < Ns; ++i)
+            for (int d2 = 0; d2 < nc; ++d2)
+                for (int d1 = 0; d1 < nc; ++d1)
+                    s = cfma(Dl[((size_t)i * nc + d2) * nc + d1],
+                             sm[(size_t)i * PL * PP + (rr + d2) * PP + cc + d1], s);
+        if (lane < e * e) corr[ob + band_index(g, t2, t1)] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gram G_l = H_l^H H_l.  With z_d[q] = conj(x_i[q]) x_i'[(q + d) mod n],
 //   G[(i,b),(i',b+d)] = C[d] - sum_{q2 in E(b2)} Row_d[q2] - sum_{q1 in E(b1)} Col_d[q1]
@@ -690,18 +814,20 @@ __global__ void k_ns_init(int K, int L, const double2* __restrict__ G, const dou
         wscale[l] = unreg ? 0.0 : 1.0 / sqrt(c);
         done[l] = unreg ? 1 : 0;
         for (int k = 1; k <= nit; ++k) done[k * L + l] = 0;
+        done[(nit + 1) * L + l] = 0;   // buffer parity holding the latest Z
     }
 }
 
 // One Newton-Schulz update for slice l = blockIdx.z / 2:
 //   which = 0: Yn = Y T ; which = 1: Zn = T Z   (T = 1.5 I - 0.5 Z Y, from k_cgemm<EPI_NS>)
-// Slices already converged (done_cur[l]) copy Y, Z through.  The residual
+// Slices already converged (done_cur[l]) return at once.  The residual
 // ||I - Z Y||_F of this iteration is summed from the k_cgemm partials and
-// done_next[l] = done_cur[l] || residual < tol.
+// done_next[l] = done_cur[l] || residual < tol; an iteration that updates
+// records the parity `par` of the buffers it wrote in last[l].
 __global__ void k_ns_update(int K, int L, const double2* __restrict__ Y, const double2* __restrict__ Z,
                             const double2* __restrict__ T, double2* __restrict__ Yn, double2* __restrict__ Zn,
                             const double* __restrict__ part, int ntile, const int* __restrict__ done_cur,
-                            int* __restrict__ done_next, double tol2) {
+                            int* __restrict__ done_next, int* __restrict__ last, int par, double tol2) {
     __shared__ double2 As[GT][GT + 1];
     __shared__ double2 Bs[GT][GT + 1];
     __shared__ double red[16];
@@ -711,16 +837,14 @@ __global__ void k_ns_update(int K, int L, const double2* __restrict__ Y, const d
     const size_t off = (size_t)l * K * K;
     const int dc = done_cur[l];
     if (dc) {
-        if (row < K && col < K) {
-            if (which == 0) Yn[off + (size_t)row * K + col] = Y[off + (size_t)row * K + col];
-            else Zn[off + (size_t)row * K + col] = Z[off + (size_t)row * K + col];
-        }
         if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0) done_next[l] = 1;
         return;
     }
     const double res2 = sum_partials(part + (size_t)l * ntile, ntile, red);
-    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0)
+    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0) {
         done_next[l] = (res2 < tol2) ? 1 : 0;
+        last[l] = par;
+    }
     const double2* Al = (which == 0 ? Y : T) + off;
     const double2* Bl = (which == 0 ? T : Z) + off;
     double2 acc = cmk(0.0, 0.0);
@@ -736,14 +860,16 @@ __global__ void k_ns_update(int K, int L, const double2* __restrict__ Y, const d
     if (row < K && col < K) (which == 0 ? Yn : Zn)[off + (size_t)row * K + col] = acc;
 }
 
-// W_l = wscale_l * Z_l (wscale = 0 for an unregularised slice).
-__global__ void k_ns_final(int K, int L, const double2* __restrict__ Z, const double* __restrict__ wscale,
+// W_l = wscale_l * Z_l (wscale = 0 for an unregularised slice), Z_l taken
+// from the buffer (Z0 or Z1) the last executed iteration wrote.
+__global__ void k_ns_final(int K, int L, const double2* __restrict__ Z0, const double2* __restrict__ Z1,
+                           const int* __restrict__ last, const double* __restrict__ wscale,
                            double2* __restrict__ W) {
     const long total = (long)L * K * K;
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int l = (int)(idx / ((long)K * K));
-    W[idx] = cscale(Z[idx], wscale[l]);
+    W[idx] = cscale((last[l] ? Z1 : Z0)[idx], wscale[l]);
 }
 
 // scale[l] = 1 / ||M_l||_F^2 (0 if M_l = 0); one workgroup per slice.

@@ -1,0 +1,191 @@
+// In-wave FFTs of length N = 16..256 held in registers (FP64).
+//
+// N >= 64: one wave per sequence, lane j holds x[j + 64 t] for t < R = N/64.
+// N <  64: groups of N lanes, one sequence per group, one value per lane.
+// The transform is decimation in frequency: a radix-R stage on the values of
+// a lane (with twiddles w_N^(j k1)), then log2(lanes) butterfly stages across
+// lanes.  Output: the value at register k1 of lane j is X[k1 + R * brev(j)],
+// brev over log2(lanes) bits.  `INV` selects the conjugate transform
+// (unnormalised inverse).
+#pragma once
+#include "smsm_col_fast.h"
+
+template <int N>
+struct WaveFft {
+    static constexpr int LANES = N >= 64 ? 64 : N;
+    static constexpr int R = N >= 64 ? N / 64 : 1;
+    static constexpr int LOGL = LANES == 64 ? 6 : LANES == 32 ? 5 : LANES == 16 ? 4 : LANES == 8 ? 3 : 2;
+    double2 w[6];     // per-stage butterfly twiddle (1 on upper lanes)
+    double sg[6];     // +1 upper lane, -1 lower lane
+    double2 wr[3];    // radix-R stage twiddles w_N^(j k1), k1 = 1..R-1
+    int m;            // lane index inside the sequence
+
+    // tw: table of w_N^k = exp(-2 pi i k / N), k < N
+    SMSM_DEV void setup(const double2* __restrict__ tw, int lane) {
+        m = lane & (LANES - 1);
+#pragma unroll
+        for (int st = 0; st < LOGL; ++st) {
+            const int h = 1 << st;
+            const bool upper = (m & h) == 0;
+            sg[st] = upper ? 1.0 : -1.0;
+            w[st] = upper ? cmk(1.0, 0.0) : tw[(m & (h - 1)) * (LANES / (2 * h)) * R];
+        }
+#pragma unroll
+        for (int k = 1; k < R; ++k) wr[k - 1] = tw[m * k];
+    }
+
+    // position of register k1 of this lane in the transformed sequence
+    SMSM_DEV int out_index(int k1) const {
+        const int br = (int)(__brev((unsigned)m) >> (32 - LOGL));
+        return k1 + R * br;
+    }
+
+    template <bool INV>
+    SMSM_DEV void run(double2 (&v)[R]) const {
+        if constexpr (R == 4) {
+            const double2 a = v[0], b = v[1], c = v[2], d = v[3];
+            const double2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d), d1 = csub(b, d);
+            // forward: w_4 = -i ; inverse: +i
+            const double2 jd1 = INV ? cmk(-d1.y, d1.x) : cmk(d1.y, -d1.x);
+            v[0] = cadd(s0, s1);
+            v[2] = csub(s0, s1);
+            v[1] = cadd(d0, jd1);
+            v[3] = csub(d0, jd1);
+#pragma unroll
+            for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], INV ? cconj(wr[k - 1]) : wr[k - 1]);
+        } else if constexpr (R == 2) {
+            const double2 a = v[0], b = v[1];
+            v[0] = cadd(a, b);
+            v[1] = cmul(csub(a, b), INV ? cconj(wr[0]) : wr[0]);
+        }
+        if constexpr (LANES >= 64) dif_stage<32, R>(v, sg[5], INV ? cconj(w[5]) : w[5]);
+        if constexpr (LANES >= 32) dif_stage<16, R>(v, sg[4], INV ? cconj(w[4]) : w[4]);
+        if constexpr (LANES >= 16) dif_stage<8, R>(v, sg[3], INV ? cconj(w[3]) : w[3]);
+        if constexpr (LANES >= 8) dif_stage<4, R>(v, sg[2], INV ? cconj(w[2]) : w[2]);
+        dif_stage<2, R>(v, sg[1], INV ? cconj(w[1]) : w[1]);
+        dif_stage<1, R>(v, sg[0], INV ? cconj(w[0]) : w[0]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Row passes with in-wave FFTs.  A workgroup of 4 waves handles TR rows of one
+// image b; each wave transforms whole rows in registers and parks them in a
+// shared tile, which is then read out transposed (row pass 1) or staged from a
+// transposed read (row pass 3), so global accesses stay coalesced.
+// TR must be a multiple of 4 * (64 / LANES).
+// ---------------------------------------------------------------------------
+template <int N, int MODE>
+__global__ void __launch_bounds__(256)
+k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ rvec,
+             double2* __restrict__ pvec, const double* __restrict__ pr_new, const double* __restrict__ pr_old,
+             int npart, const double2* __restrict__ tw1, int TR) {
+    using F = WaveFft<N>;
+    constexpr int R = F::R, LANES = F::LANES, G = 64 / LANES, ST = N + 1;
+    extern __shared__ double2 sm[];
+    double* red = (double*)(sm + TR * ST);
+    const int b = blockIdx.y, j0 = blockIdx.x * TR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double beta = 0.0;
+    if (MODE == ROWS_CG_UPDATE) {
+        const double rn = sum_partials(pr_new, npart, red);
+        const double ro = sum_partials(pr_old, npart, red);
+        beta = (ro > 0.0) ? rn / ro : 0.0;
+    }
+    F f;
+    f.setup(tw1, lane);
+    const int grp = lane / LANES;
+    const size_t img = (size_t)b * g.n2 * N;
+    const double sc = 1.0 / sqrt((double)N);
+    for (int rb = 0; rb < TR; rb += nw * G) {
+        const int r = rb + wave * G + grp;
+        const size_t o = img + (size_t)(j0 + r) * N;
+        double2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int k = f.m + 64 * t;
+            double2 val;
+            if (MODE == ROWS_PLAIN) {
+                val = in[o + k];
+            } else if (MODE == ROWS_CG_UPDATE) {
+                val = cadd(rvec[o + k], cscale(pvec[o + k], beta));
+                pvec[o + k] = val;
+            } else {
+                val = rvec[o + k];
+                pvec[o + k] = val;
+            }
+            v[t] = cscale(val, sgn_pow(k));
+        }
+        f.template run<true>(v);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int n = f.out_index(t);
+            sm[r * ST + n] = cscale(v[t], sc * sgn_pow(n));
+        }
+    }
+    __syncthreads();
+    const size_t ob = (size_t)b * N * g.n2;
+    for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
+        const int c = idx / TR, jr = idx - c * TR;
+        out[ob + (size_t)c * g.n2 + j0 + jr] = sm[jr * ST + c];
+    }
+}
+
+template <int N, bool CG, bool BAND>
+__global__ void __launch_bounds__(256)
+k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ corr,
+             const double2* __restrict__ pvec, double* __restrict__ pq_part, const double2* __restrict__ tw1,
+             int TR) {
+    using F = WaveFft<N>;
+    constexpr int R = F::R, LANES = F::LANES, G = 64 / LANES, ST = N + 1;
+    extern __shared__ double2 sm[];
+    double* red = (double*)(sm + TR * ST);
+    const int b = blockIdx.y, j0 = blockIdx.x * TR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const size_t ib = (size_t)b * N * g.n2;
+    for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
+        const int c = idx / TR, jr = idx - c * TR;
+        sm[jr * ST + c] = in[ib + (size_t)c * g.n2 + j0 + jr];
+    }
+    __syncthreads();
+    F f;
+    f.setup(tw1, lane);
+    const int grp = lane / LANES;
+    const double sc = 1.0 / sqrt((double)N);
+    for (int rb = 0; rb < TR; rb += nw * G) {
+        const int r = rb + wave * G + grp;
+        double2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int x = f.m + 64 * t;
+            v[t] = cscale(sm[r * ST + x], sgn_pow(x));
+        }
+        f.template run<false>(v);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int k = f.out_index(t);
+            sm[r * ST + k] = cscale(v[t], sc * sgn_pow(k));
+        }
+    }
+    __syncthreads();
+    const size_t img = (size_t)b * g.n2 * N;
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
+        const int jr = idx / N, k = idx - jr * N;
+        const int j2 = j0 + jr;
+        double2 val = sm[jr * ST + k];
+        if (BAND) {
+            const int bi = band_index(g, j2, k);
+            if (bi >= 0) val = cadd(val, corr[(size_t)b * g.nband + bi]);
+        }
+        const size_t o = img + (size_t)j2 * N + k;
+        out[o] = val;
+        if (CG) {
+            const double2 pv = pvec[o];
+            acc += pv.x * val.x + pv.y * val.y;
+        }
+    }
+    if (CG) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) pq_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
