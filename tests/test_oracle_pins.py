@@ -390,3 +390,23 @@ def test_all_zero_slice_is_unregularised():
     x = o.solve(y, coils, masks, shifts, p)
     assert np.all(x[1] == 0)
     assert np.linalg.norm(x[0]) > 0
+
+
+def test_lambda_max_closed_form_constant_shots():
+    """x_i = c_i everywhere: every Hankel row is v = [c_0 1_{r^2}, ..., c_{Ns-1} 1_{r^2}],
+    so G = P v v^H and lambda_max = P r^2 sum_i |c_i|^2."""
+    n, r = 12, 3
+    c = np.array([1.0 + 2.0j, -0.5 + 0.25j, 3.0 - 1.0j])
+    x = c[:, None, None] * np.ones((3, n, n))
+    P = (n - r + 1) ** 2
+    G = o.gram(x, r)
+    assert abs(o.lambda_max(G) - P * r * r * np.sum(np.abs(c) ** 2)) < 1e-10 * o.lambda_max(G)
+
+
+def test_objective_is_smoothed_objective_at_zero_eps():
+    """Eq. 10 equals J_eps at eps = 0 (trace of the Gram square root = nuclear norm)."""
+    rng, coils, masks, shifts, theta, y = tiny_problem(34)
+    x = crand(rng, 2, 2, 8, 8)
+    a = o.objective(x, y, coils, masks, theta, 0.3, 3)
+    b = o.smoothed_objective(x, y, coils, masks, theta, 0.3, 3, [0.0, 0.0])
+    assert abs(a - b) < 1e-10 * abs(a)
