@@ -3,6 +3,7 @@
 #include "smsm_kernels.h"
 #include "smsm_col_fast.h"
 #include "smsm_wavefft.h"
+#include "smsm_dense.h"
 #include "smsm.h"
 
 #include <cmath>
@@ -18,6 +19,7 @@ constexpr int kColThreads = 512;
 constexpr int kVecBlocks = 512;      // fixed grid of the CG vector kernels
 constexpr int kNsDefaultIters = 24;  // Newton-Schulz iteration cap
 constexpr int kSqSteps = 30;         // squarings for the largest eigenvalue
+constexpr int kPadBlocks = 32;       // blocks per slice of the dense set-up kernels
 constexpr double kNsTol = 1e-10;     // ||I - Z Y||_F at which NS is converged
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -37,7 +39,9 @@ struct smsm_plan {
     int TRw = 8;              // rows per workgroup of the in-wave FFT row passes
     size_t lds_roww = 0;
     int npq = 0;             // blocks of the forward row pass (partials of <p,q>)
-    int ntile = 0;           // GEMM tiles per slice
+    int KP = 0;              // padded stride of the Newton-Schulz matrices
+    int ntile = 0;           // 16x16 tiles per slice of the dense products
+    int npmax = 0;           // partial sums per slice (max over producers)
     size_t lds_rows = 0, lds_col = 0, lds_gram = 0;
     bool have_weights = false;
     void* arena = nullptr;
@@ -51,8 +55,8 @@ struct smsm_plan {
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
     double2 *Kc = nullptr, *D = nullptr, *corr = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
-    double *pr = nullptr, *pq = nullptr, *nspart = nullptr, *sigma = nullptr, *eps = nullptr;
-    double *wscale = nullptr, *sqscale = nullptr, *epsin = nullptr;
+    double *pr = nullptr, *pq = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
+    double *wscale = nullptr, *epsin = nullptr;
     int *done = nullptr, *flags = nullptr;
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
@@ -252,55 +256,70 @@ smsm_status chain_gram(smsm_plan* P, const double2* v, double2* G, hipStream_t s
     return SMSM_OK;
 }
 
-dim3 gemm_grid(const Geo& g, int z) {
-    const int t = (g.K + GT - 1) / GT;
-    return dim3(t, t, z);
-}
-
 // W = (G + eps I)^(-1/2) with eps_l = mult * src[l] (device array).
 smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, double mult, hipStream_t st) {
     const Geo& g = P->g;
-    const int nit = P->ns_iters;
-    hipLaunchKernelGGL(k_ns_init, dim3(g.L), dim3(kThreads), 0, st, g.K, g.L, G, src, mult, P->Y0, P->Z0,
-                       P->wscale, P->done, nit);
+    const int nit = P->ns_iters, KP = P->KP;
+    hipLaunchKernelGGL(k_dense_pad, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, g.K, KP, G, src, mult, P->Y0,
+                       P->part0);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ns_start, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, g.K, KP, g.L, src, mult,
+                       P->part0, kPadBlocks, P->Y0, P->Z0, P->wscale, P->done, nit);
     LAUNCH_CHECK();
     double2* Y[2] = {P->Y0, P->Y1};
     double2* Z[2] = {P->Z0, P->Z1};
     for (int k = 0; k < nit; ++k) {
         const int a = k & 1, bsel = a ^ 1;
-        hipLaunchKernelGGL(k_cgemm<EPI_NS>, gemm_grid(g, g.L), dim3(kThreads), 0, st, g.K, g.L, Z[a], Y[a],
-                           P->T, nullptr, P->done + (size_t)k * g.L, P->nspart);
+        HgArgs t{};
+        t.A0 = Z[a]; t.B0 = Y[a]; t.C0 = P->T;
+        t.done_cur = P->done + (size_t)k * g.L;
+        t.part_out = P->part0;
+        hipLaunchKernelGGL(k_zgemm<HG_NS>, dim3(P->ntile, 1, g.L), dim3(64 * HW), 0, st, g.K, KP, t);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_ns_update, gemm_grid(g, 2 * g.L), dim3(kThreads), 0, st, g.K, g.L, Y[a], Z[a],
-                           P->T, Y[bsel], Z[bsel], P->nspart, P->ntile, P->done + (size_t)k * g.L,
-                           P->done + (size_t)(k + 1) * g.L, P->done + (size_t)(nit + 1) * g.L, bsel,
-                           kNsTol * kNsTol);
+        HgArgs u{};
+        u.A0 = Y[a]; u.B0 = P->T; u.C0 = Y[bsel];
+        u.A1 = P->T; u.B1 = Z[a]; u.C1 = Z[bsel];
+        u.done_cur = P->done + (size_t)k * g.L;
+        u.done_next = P->done + (size_t)(k + 1) * g.L;
+        u.last = P->done + (size_t)(nit + 1) * g.L;
+        u.par = bsel;
+        u.tol2 = kNsTol * kNsTol;
+        u.part_in = P->part0;
+        u.np_in = P->ntile;
+        hipLaunchKernelGGL(k_zgemm<HG_PAIR>, dim3(P->ntile, 1, 2 * g.L), dim3(64 * HW), 0, st, g.K, KP, u);
         LAUNCH_CHECK();
     }
     const long tot = (long)g.L * g.K * g.K;
-    hipLaunchKernelGGL(k_ns_final, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g.K,
-                       g.L, P->Z0, P->Z1, P->done + (size_t)(nit + 1) * g.L, P->wscale, P->W);
+    hipLaunchKernelGGL(k_ns_finish, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g.K,
+                       KP, g.L, P->Z0, P->Z1, P->done + (size_t)(nit + 1) * g.L, P->wscale, P->W);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
-// lmax[l] = largest eigenvalue of G_l by repeated normalised squaring.
+// lmax[l] = largest eigenvalue of G_l by repeated normalised squaring
+// P <- P^2 / ||P||_F^2 and the Rayleigh quotient tr(G P) / tr(P).
 smsm_status chain_lmax(smsm_plan* P, const double2* G, double* lmax, hipStream_t st) {
     const Geo& g = P->g;
-    hipLaunchKernelGGL(k_fro_inv, dim3(g.L), dim3(kThreads), 0, st, g.K, G, P->sqscale);
+    const int KP = P->KP;
+    hipLaunchKernelGGL(k_dense_pad, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, g.K, KP, G, nullptr, 0.0, P->T,
+                       P->part0);
     LAUNCH_CHECK();
-    const double2* cur = G;
+    const double2* cur = P->T;
     double2* buf[2] = {P->Y0, P->Y1};
+    double* part[2] = {P->part0, P->part1};
     for (int k = 0; k < kSqSteps; ++k) {
-        double2* nxt = buf[k & 1];
-        hipLaunchKernelGGL(k_cgemm<EPI_NORM>, gemm_grid(g, g.L), dim3(kThreads), 0, st, g.K, g.L, cur, cur,
-                           nxt, P->sqscale, nullptr, P->nspart);
+        HgArgs a{};
+        a.A0 = cur; a.B0 = cur; a.C0 = buf[k & 1];
+        a.part_in = part[k & 1];
+        a.np_in = k == 0 ? kPadBlocks : P->ntile;
+        a.part_out = part[(k + 1) & 1];
+        hipLaunchKernelGGL(k_zgemm<HG_NORM>, dim3(P->ntile, 1, g.L), dim3(64 * HW), 0, st, g.K, KP, a);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_part_inv, dim3(g.L), dim3(kThreads), 0, st, P->nspart, P->ntile, P->sqscale);
-        LAUNCH_CHECK();
-        cur = nxt;
+        cur = buf[k & 1];
     }
-    hipLaunchKernelGGL(k_sq_final, dim3(g.L), dim3(kThreads), 0, st, g.K, G, cur, lmax);
+    hipLaunchKernelGGL(k_trace_part, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, g.K, KP, G, cur, P->part0);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_trace_final, dim3(g.L), dim3(kThreads), 0, st, g.L, P->part0, kPadBlocks, lmax);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -368,7 +387,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->TRw = (n1 == 16) ? 16 : 8;
     P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->npq = (n2 / P->TRw) * g.B;
-    P->ntile = ((g.K + GT - 1) / GT) * ((g.K + GT - 1) / GT);
+    P->KP = dense_stride(g.K);
+    P->ntile = dense_tiles(g.K);
+    P->npmax = std::max(P->ntile, 2 * kPadBlocks);
     P->lds_band = band_lds_bytes(g);
     P->lds_colfast = (size_t)colfast_lds_total(g) * sizeof(double2);
     int max_lds = 0;
@@ -386,6 +407,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     // device memory layout
     const size_t nvec = (size_t)L * Ns * n2 * n1;
     const size_t KK = (size_t)L * g.K * g.K;
+    const size_t KKP = (size_t)L * P->KP * P->KP;
     const size_t ntab = (size_t)L * g.nc * g.nc * Ns * Ns * g.nc * g.nc;
     const size_t nper = (size_t)L * g.npairs * g.nc * g.nc;
     Carver cv;
@@ -397,8 +419,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oh1 = cv.take<double2>(nvec), oh2 = cv.take<double2>(nvec);
     const size_t oyt = cv.take<double2>((size_t)Ns * Nc * n1 * g.M);
     const size_t oG = cv.take<double2>(KK), oW = cv.take<double2>(KK);
-    const size_t oY0 = cv.take<double2>(KK), oY1 = cv.take<double2>(KK);
-    const size_t oZ0 = cv.take<double2>(KK), oZ1 = cv.take<double2>(KK), oT = cv.take<double2>(KK);
+    const size_t oY0 = cv.take<double2>(KKP), oY1 = cv.take<double2>(KKP);
+    const size_t oZ0 = cv.take<double2>(KKP), oZ1 = cv.take<double2>(KKP), oT = cv.take<double2>(KKP);
     const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
     const size_t oD = cv.take<double2>(ntab);
     const size_t ocorr = cv.take<double2>((size_t)g.B * g.nband);
@@ -406,9 +428,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
     const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
     const size_t opr = cv.take<double>(3 * kVecBlocks), opq = cv.take<double>(P->npq);
-    const size_t onsp = cv.take<double>((size_t)L * P->ntile);
+    const size_t onp0 = cv.take<double>((size_t)L * P->npmax), onp1 = cv.take<double>((size_t)L * P->npmax);
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
-    const size_t osq = cv.take<double>(L), oei = cv.take<double>(L);
+    const size_t oei = cv.take<double>(L);
     const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
@@ -425,9 +447,10 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->Kc = (double2*)(base + oKc); P->D = (double2*)(base + oD); P->corr = (double2*)(base + ocorr);
     P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
     P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);
-    P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->nspart = (double*)(base + onsp);
+    P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->part0 = (double*)(base + onp0);
+    P->part1 = (double*)(base + onp1);
     P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
-    P->sqscale = (double*)(base + osq); P->epsin = (double*)(base + oei);
+    P->epsin = (double*)(base + oei);
     P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
 
     // host tables: twiddles, CAIPI phases, shot modulation

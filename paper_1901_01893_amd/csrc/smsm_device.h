@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #define SMSM_DEV __device__ __forceinline__
+#define SMSM_HD __host__ __device__
 
 SMSM_DEV double2 cmk(double re, double im) { return make_double2(re, im); }
 SMSM_DEV double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }

@@ -732,185 +732,6 @@ __global__ void k_gram_assemble(Geo g, const double2* __restrict__ C, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Small dense complex matrices (K x K per slice): tiled GEMM and helpers for
-// the Newton-Schulz inverse square root and the largest eigenvalue.
-// ---------------------------------------------------------------------------
-#define GT 16
-// C = alpha * A * B for slice blockIdx.z (A, B, C: [L][K][K]), alpha from
-// `scale` (per slice) or 1.  Skips slices whose `skip` flag is set.
-// Optional epilogue (EPI_NS): C <- 1.5 I - 0.5 (A B) and the partial
-// sum |I - A B|^2 of this tile into part[l][tile].
-enum { EPI_NONE = 0, EPI_NS = 1, EPI_NORM = 2 };
-template <int EPI>
-__global__ void k_cgemm(int K, int L, const double2* __restrict__ A, const double2* __restrict__ Bm,
-                        double2* __restrict__ C, const double* __restrict__ scale,
-                        const int* __restrict__ skip, double* __restrict__ part) {
-    __shared__ double2 As[GT][GT + 1];
-    __shared__ double2 Bs[GT][GT + 1];
-    __shared__ double red[16];
-    const int l = blockIdx.z;
-    if (skip && skip[l]) return;
-    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
-    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
-    const double2* Al = A + (size_t)l * K * K;
-    const double2* Bl = Bm + (size_t)l * K * K;
-    double2 acc = cmk(0.0, 0.0);
-    for (int k0 = 0; k0 < K; k0 += GT) {
-        const int ka = k0 + tx, kb = k0 + ty;
-        As[ty][tx] = (row < K && ka < K) ? Al[(size_t)row * K + ka] : cmk(0.0, 0.0);
-        Bs[ty][tx] = (kb < K && col < K) ? Bl[(size_t)kb * K + col] : cmk(0.0, 0.0);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < GT; ++k) acc = cfma(As[ty][k], Bs[k][tx], acc);
-        __syncthreads();
-    }
-    const double s = scale ? scale[l] : 1.0;
-    acc = cscale(acc, s);
-    double contrib = 0.0;
-    if (row < K && col < K) {
-        if (EPI == EPI_NS) {
-            const double2 dlt = cmk(row == col ? 1.0 : 0.0, 0.0);
-            const double2 res = csub(dlt, acc);
-            contrib = cabs2(res);
-            acc = cadd(cscale(dlt, 1.5), cscale(acc, -0.5));
-        } else if (EPI == EPI_NORM) {
-            contrib = cabs2(acc);
-        }
-        C[(size_t)l * K * K + (size_t)row * K + col] = acc;
-    }
-    if (EPI != EPI_NONE) {
-        const double ssum = block_sum(contrib, red);
-        if (threadIdx.x == 0) part[(size_t)l * gridDim.x * gridDim.y + blockIdx.y * gridDim.x + blockIdx.x] = ssum;
-    }
-}
-
-// Y = (G + eps I)/c, Z = I, with eps_l = mult * src[l] and c = ||G + eps I||_F;
-// one workgroup per slice.  eps_l <= 0 marks the slice as unregularised
-// (skip0[l] = 1, W_l = 0).  Also clears the convergence flags done[1..nit].
-__global__ void k_ns_init(int K, int L, const double2* __restrict__ G, const double* __restrict__ src,
-                          double mult, double2* __restrict__ Y, double2* __restrict__ Z,
-                          double* __restrict__ wscale, int* __restrict__ done, int nit) {
-    __shared__ double red[16];
-    const int l = blockIdx.x;
-    const double eps = mult * src[l];
-    const double2* Gl = G + (size_t)l * K * K;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
-        double2 v = Gl[k];
-        if (k / K == k % K) v.x += eps;
-        s += cabs2(v);
-    }
-    const double fro2 = block_sum(s, red);
-    const bool unreg = !(eps > 0.0) || !(fro2 > 0.0);
-    const double c = unreg ? 1.0 : sqrt(fro2);
-    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
-        const bool dg = (k / K == k % K);
-        double2 v = Gl[k];
-        if (dg) v.x += eps;
-        Y[(size_t)l * K * K + k] = cscale(v, 1.0 / c);
-        Z[(size_t)l * K * K + k] = cmk(dg ? 1.0 : 0.0, 0.0);
-    }
-    if (threadIdx.x == 0) {
-        wscale[l] = unreg ? 0.0 : 1.0 / sqrt(c);
-        done[l] = unreg ? 1 : 0;
-        for (int k = 1; k <= nit; ++k) done[k * L + l] = 0;
-        done[(nit + 1) * L + l] = 0;   // buffer parity holding the latest Z
-    }
-}
-
-// One Newton-Schulz update for slice l = blockIdx.z / 2:
-//   which = 0: Yn = Y T ; which = 1: Zn = T Z   (T = 1.5 I - 0.5 Z Y, from k_cgemm<EPI_NS>)
-// Slices already converged (done_cur[l]) return at once.  The residual
-// ||I - Z Y||_F of this iteration is summed from the k_cgemm partials and
-// done_next[l] = done_cur[l] || residual < tol; an iteration that updates
-// records the parity `par` of the buffers it wrote in last[l].
-__global__ void k_ns_update(int K, int L, const double2* __restrict__ Y, const double2* __restrict__ Z,
-                            const double2* __restrict__ T, double2* __restrict__ Yn, double2* __restrict__ Zn,
-                            const double* __restrict__ part, int ntile, const int* __restrict__ done_cur,
-                            int* __restrict__ done_next, int* __restrict__ last, int par, double tol2) {
-    __shared__ double2 As[GT][GT + 1];
-    __shared__ double2 Bs[GT][GT + 1];
-    __shared__ double red[16];
-    const int l = blockIdx.z >> 1, which = blockIdx.z & 1;
-    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
-    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
-    const size_t off = (size_t)l * K * K;
-    const int dc = done_cur[l];
-    if (dc) {
-        if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0) done_next[l] = 1;
-        return;
-    }
-    const double res2 = sum_partials(part + (size_t)l * ntile, ntile, red);
-    if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && which == 0) {
-        done_next[l] = (res2 < tol2) ? 1 : 0;
-        last[l] = par;
-    }
-    const double2* Al = (which == 0 ? Y : T) + off;
-    const double2* Bl = (which == 0 ? T : Z) + off;
-    double2 acc = cmk(0.0, 0.0);
-    for (int k0 = 0; k0 < K; k0 += GT) {
-        const int ka = k0 + tx, kb = k0 + ty;
-        As[ty][tx] = (row < K && ka < K) ? Al[(size_t)row * K + ka] : cmk(0.0, 0.0);
-        Bs[ty][tx] = (kb < K && col < K) ? Bl[(size_t)kb * K + col] : cmk(0.0, 0.0);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < GT; ++k) acc = cfma(As[ty][k], Bs[k][tx], acc);
-        __syncthreads();
-    }
-    if (row < K && col < K) (which == 0 ? Yn : Zn)[off + (size_t)row * K + col] = acc;
-}
-
-// W_l = wscale_l * Z_l (wscale = 0 for an unregularised slice), Z_l taken
-// from the buffer (Z0 or Z1) the last executed iteration wrote.
-__global__ void k_ns_final(int K, int L, const double2* __restrict__ Z0, const double2* __restrict__ Z1,
-                           const int* __restrict__ last, const double* __restrict__ wscale,
-                           double2* __restrict__ W) {
-    const long total = (long)L * K * K;
-    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int l = (int)(idx / ((long)K * K));
-    W[idx] = cscale((last[l] ? Z1 : Z0)[idx], wscale[l]);
-}
-
-// scale[l] = 1 / ||M_l||_F^2 (0 if M_l = 0); one workgroup per slice.
-__global__ void k_fro_inv(int K, const double2* __restrict__ Mx, double* __restrict__ scale) {
-    __shared__ double red[16];
-    const int l = blockIdx.x;
-    double s = 0.0;
-    for (int k = threadIdx.x; k < K * K; k += blockDim.x) s += cabs2(Mx[(size_t)l * K * K + k]);
-    const double f = block_sum(s, red);
-    if (threadIdx.x == 0) scale[l] = f > 0.0 ? 1.0 / f : 0.0;
-}
-
-// scale[l] = 1 / sum(part[l][:]) (0 if the sum is 0); one workgroup per slice.
-__global__ void k_part_inv(const double* __restrict__ part, int ntile, double* __restrict__ scale) {
-    __shared__ double red[16];
-    const int l = blockIdx.x;
-    const double f = sum_partials(part + (size_t)l * ntile, ntile, red);
-    if (threadIdx.x == 0) scale[l] = f > 0.0 ? 1.0 / f : 0.0;
-}
-
-// lmax[l] = Re tr(G P) / Re tr(P) with P ~ G^(2^m) (Rayleigh quotient on the
-// dominant eigenspace); 0 when P = 0.  One workgroup per slice.
-__global__ void k_sq_final(int K, const double2* __restrict__ G, const double2* __restrict__ P,
-                           double* __restrict__ lmax) {
-    __shared__ double red[16];
-    const int l = blockIdx.x;
-    const double2* Gl = G + (size_t)l * K * K;
-    const double2* Pl = P + (size_t)l * K * K;
-    double num = 0.0, den = 0.0;
-    for (int k = threadIdx.x; k < K * K; k += blockDim.x) {
-        const int j = k / K, m = k - j * K;
-        const double2 gp = cmul(Gl[k], Pl[(size_t)m * K + j]);
-        num += gp.x;
-        if (j == m) den += Pl[k].x;
-    }
-    const double a = block_sum(num, red);
-    const double b = block_sum(den, red);
-    if (threadIdx.x == 0) lmax[l] = b > 0.0 ? a / b : 0.0;
-}
-
-// ---------------------------------------------------------------------------
 // CG vector kernels (fixed grid, grid-stride, per-block FP64 partials).
 // ---------------------------------------------------------------------------
 // r = b - q; partial sum |r|^2
