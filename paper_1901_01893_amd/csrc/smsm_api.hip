@@ -37,6 +37,7 @@ struct smsm_plan {
     int dev = 0;
     int TR = 1, TRy = 1;
     int TRw = 8;              // rows per workgroup of the in-wave FFT row passes
+    int rows_blk = 256;       // threads per workgroup of the row passes
     size_t lds_roww = 0;
     int npq = 0;             // blocks of the forward row pass (partials of <p,q>)
     int KP = 0;              // padded stride of the Newton-Schulz matrices
@@ -53,7 +54,7 @@ struct smsm_plan {
     double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
-    double2 *Kc = nullptr, *D = nullptr, *corr = nullptr;
+    double2 *Kc = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
     double *pr = nullptr, *pq = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr;
@@ -62,6 +63,7 @@ struct smsm_plan {
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
     size_t lds_colfast = 0;
     size_t lds_band = 0;
+    BandFn band = nullptr;   // band-correction kernel for (2r-1, Ns)
 };
 
 namespace {
@@ -109,7 +111,7 @@ template <int MODE>
 smsm_status rows_inv_mode(smsm_plan* P, const double2* in, double2* out, const double* prn, const double* pro,
                           hipStream_t st) {
     const Geo& g = P->g;
-    const dim3 grid(g.n2 / P->TRw, g.B), blk(256);
+    const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
     switch (g.n1) {
         case 16: hipLaunchKernelGGL((k_rows_inv_w<16, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
@@ -130,14 +132,15 @@ smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t 
 template <bool CG, bool BAND>
 smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, const double2* pvec, hipStream_t st) {
     const Geo& g = P->g;
-    const dim3 grid(g.n2 / P->TRw, g.B), blk(256);
+    const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
+    const BandAdd ba{P->crow, P->ccol, P->ccorner, band_ds(g.Ns, g.nc)};
     switch (g.n1) {
-        case 16: hipLaunchKernelGGL((k_rows_fwd_w<16, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
-        case 32: hipLaunchKernelGGL((k_rows_fwd_w<32, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
-        case 64: hipLaunchKernelGGL((k_rows_fwd_w<64, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
-        case 128: hipLaunchKernelGGL((k_rows_fwd_w<128, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
-        default: hipLaunchKernelGGL((k_rows_fwd_w<256, CG, BAND>), grid, blk, lds, st, g, in, out, P->corr, pvec, P->pq, P->tw1, P->TRw); break;
+        case 16: hipLaunchKernelGGL((k_rows_fwd_w<16, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
+        case 32: hipLaunchKernelGGL((k_rows_fwd_w<32, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
+        case 64: hipLaunchKernelGGL((k_rows_fwd_w<64, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
+        case 128: hipLaunchKernelGGL((k_rows_fwd_w<128, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
+        default: hipLaunchKernelGGL((k_rows_fwd_w<256, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
     }
     LAUNCH_CHECK();
     return SMSM_OK;
@@ -184,27 +187,25 @@ smsm_status col(smsm_plan* P, int use_reg, hipStream_t st) {
 
 smsm_status band_corr(smsm_plan* P, const double2* vin, hipStream_t st) {
     const Geo& g = P->g;
-    const dim3 grid(band_tiles_total(g), g.L, g.Ns), block(64 * g.e);
-    switch (g.nc) {
-        case 3: hipLaunchKernelGGL(k_band_tile<3>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 5: hipLaunchKernelGGL(k_band_tile<5>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 7: hipLaunchKernelGGL(k_band_tile<7>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 9: hipLaunchKernelGGL(k_band_tile<9>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 11: hipLaunchKernelGGL(k_band_tile<11>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 13: hipLaunchKernelGGL(k_band_tile<13>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        case 15: hipLaunchKernelGGL(k_band_tile<15>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-        default: hipLaunchKernelGGL(k_band_tile<17>, grid, block, P->lds_band, st, g, vin, P->D, P->corr); break;
-    }
+    Geo ga = g;
+    const double2* pa = vin;
+    const double2* da = P->Dside;
+    const double2* xd = P->Dx;
+    double2 *ra = P->crow, *ca = P->ccol, *xa = P->ccorner;
+    void* args[] = {&ga, &pa, &da, &xd, &ra, &ca, &xa};
+    if (hipLaunchKernel((const void*)P->band, dim3(band_items(g), g.L), dim3(64 * g.Ns), args, P->lds_band, st) !=
+        hipSuccess)
+        return SMSM_E_DEVICE;
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
 smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     const Geo& g = P->g;
-    const long total = (long)g.L * g.nc * g.nc * g.Ns * g.Ns * g.nc * g.nc;
+    const long total = (long)g.L * (4 * g.e + 4 * g.e * g.e + 1) * g.Ns * g.Ns * g.nc * g.nc;
     const int blocks = (int)std::min<long>(8192, (total + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
-                       P->Kc, P->D);
+                       P->Kc, P->Dside, P->Dx);
     LAUNCH_CHECK();
     P->have_weights = true;
     return SMSM_OK;
@@ -384,13 +385,19 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
-    P->TRw = (n1 == 16) ? 16 : 8;
+    P->TRw = (n1 == 16) ? 16 : (n1 == 32 ? 8 : 4);
+    P->rows_blk = std::min(256, 64 * P->TRw / std::max(1, 64 / n1));
     P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->npq = (n2 / P->TRw) * g.B;
     P->KP = dense_stride(g.K);
     P->ntile = dense_tiles(g.K);
     P->npmax = std::max(P->ntile, 2 * kPadBlocks);
     P->lds_band = band_lds_bytes(g);
+    P->band = band_fn(g.nc, Ns);
+    if (!P->band) {
+        delete P;
+        return SMSM_E_UNSUPPORTED;
+    }
     P->lds_colfast = (size_t)colfast_lds_total(g) * sizeof(double2);
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
@@ -408,7 +415,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t nvec = (size_t)L * Ns * n2 * n1;
     const size_t KK = (size_t)L * g.K * g.K;
     const size_t KKP = (size_t)L * P->KP * P->KP;
-    const size_t ntab = (size_t)L * g.nc * g.nc * Ns * Ns * g.nc * g.nc;
+    const size_t ntab = (size_t)L * 4 * g.e * Ns * Ns * g.nc * g.nc;
+    const size_t nds = band_ds(Ns, g.nc);
     const size_t nper = (size_t)L * g.npairs * g.nc * g.nc;
     Carver cv;
     const size_t oST = cv.take<float2>((size_t)L * Nc * n1 * n2);
@@ -423,7 +431,10 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oZ0 = cv.take<double2>(KKP), oZ1 = cv.take<double2>(KKP), oT = cv.take<double2>(KKP);
     const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
     const size_t oD = cv.take<double2>(ntab);
-    const size_t ocorr = cv.take<double2>((size_t)g.B * g.nband);
+    const size_t oDx = cv.take<double2>(ntab * g.e);
+    const size_t ocrow = cv.take<double2>(nds * g.B * 2 * g.e * n1);
+    const size_t occol = cv.take<double2>(nds * g.B * 2 * g.e * n2);
+    const size_t ocorner = cv.take<double2>((size_t)g.B * 4 * g.e * g.e);
     const size_t ogp = cv.take<double2>(nper * n1), ogC = cv.take<double2>(nper);
     const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
     const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
@@ -444,7 +455,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->G = (double2*)(base + oG); P->W = (double2*)(base + oW);
     P->Y0 = (double2*)(base + oY0); P->Y1 = (double2*)(base + oY1);
     P->Z0 = (double2*)(base + oZ0); P->Z1 = (double2*)(base + oZ1); P->T = (double2*)(base + oT);
-    P->Kc = (double2*)(base + oKc); P->D = (double2*)(base + oD); P->corr = (double2*)(base + ocorr);
+    P->Kc = (double2*)(base + oKc); P->Dside = (double2*)(base + oD); P->Dx = (double2*)(base + oDx);
+    P->crow = (double2*)(base + ocrow); P->ccol = (double2*)(base + occol); P->ccorner = (double2*)(base + ocorner);
     P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
     P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);
     P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->part0 = (double*)(base + onp0);
@@ -486,7 +498,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     }
     if (ok) {
         hipLaunchKernelGGL(k_zero_c128, dim3(512), dim3(kThreads), 0, st, (long)(L * Ns * Ns * g.nc * g.nc), P->Kc);
-        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)ntab, P->D);
+        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)ntab, P->Dside);
+        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)(ntab * g.e), P->Dx);
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kThreads), 0, st, 4L, P->flags);
         ok = hipGetLastError() == hipSuccess;
     }
@@ -497,12 +510,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                              (const void*)&k_gram_col};
         for (const void* f : fns)
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
-        const void* bands[] = {(const void*)&k_band_tile<3>, (const void*)&k_band_tile<5>,
-                               (const void*)&k_band_tile<7>, (const void*)&k_band_tile<9>,
-                               (const void*)&k_band_tile<11>, (const void*)&k_band_tile<13>,
-                               (const void*)&k_band_tile<15>, (const void*)&k_band_tile<17>};
-        for (const void* f : bands)
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
+        if (hipFuncSetAttribute((const void*)P->band, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
+            hipSuccess)
+            ok = false;
         if (P->col_fast >= 0 &&
             hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
                 hipSuccess)
@@ -726,13 +736,16 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
             break;
         case SMSM_KERNEL_ROWS_FWD:
             f = B * n2 * F(n1) + B * n1 * n2 * 4.0;
-            b = 3.0 * vec + B * g.nband * 16.0;
+            b = 3.0 * vec + band_ds(g.Ns, g.nc) * B * 2.0 * g.e * (n1 + n2) * 16.0;
             break;
-        case SMSM_KERNEL_BAND_CORR:
-            f = B * g.nband * Ns * nc * nc * 8.0;
-            b = B * g.nband * 16.0 + L * nc * nc * Ns * Ns * nc * nc * 16.0 +
-                B * (2.0 * g.e + nc) * (n1 + n2) * 2.0 * 16.0;
+        case SMSM_KERNEL_BAND_CORR: {
+            const double e = g.e;
+            f = 8.0 * B * (2.0 * e * (n1 + n2) + 4.0 * e * e) * Ns * nc * nc;
+            b = L * (4.0 * e + 4.0 * e * e) * Ns * Ns * nc * nc * 16.0 +
+                band_ds(g.Ns, g.nc) * B * 2.0 * e * (n1 + n2) * 16.0 +
+                B * (n1 * n2 - (n1 - 4.0 * e) * (n2 - 4.0 * e)) * 16.0;
             break;
+        }
         case SMSM_KERNEL_CG_UPDATE:
             f = B * n1 * n2 * 14.0;
             b = 6.0 * vec;

@@ -26,134 +26,9 @@ struct Geo {
 };
 
 // ---------------------------------------------------------------------------
-// Band of the k-space grid where the Hankel term differs from its circular
-// version: rows/columns within e = r-1 of an edge.  Enumeration: the e top
-// rows and e bottom rows (row-major), then the 2e edge columns of the middle
-// rows (column-major, so consecutive indices share a tap class).
-// ---------------------------------------------------------------------------
-SMSM_DEV int band_index(const Geo& g, int t2, int t1) {
-    const int e = g.e;
-    if (t2 < e) return t2 * g.n1 + t1;
-    if (t2 >= g.n2 - e) return (e + t2 - (g.n2 - e)) * g.n1 + t1;
-    int cc;
-    if (t1 < e) cc = t1;
-    else if (t1 >= g.n1 - e) cc = e + t1 - (g.n1 - e);
-    else return -1;
-    return 2 * e * g.n1 + cc * (g.n2 - 2 * e) + (t2 - e);
-}
-
-SMSM_DEV void band_pos(const Geo& g, int idx, int& t2, int& t1) {
-    const int e = g.e, top = 2 * e * g.n1;
-    if (idx < top) {
-        const int row = idx / g.n1;
-        t1 = idx - row * g.n1;
-        t2 = row < e ? row : g.n2 - e + (row - e);
-    } else {
-        const int k = idx - top, h = g.n2 - 2 * e;
-        const int cc = k / h;
-        t2 = e + (k - cc * h);
-        t1 = cc < e ? cc : g.n1 - e + (cc - e);
-    }
-}
-
-// Tap class of a coordinate: 0..r-2 near the low edge, r-1 interior,
-// r..2r-2 near the high edge.
-SMSM_DEV int band_class(int t, int n, int r) {
-    if (t <= r - 2) return t;
-    if (t >= n - r + 1) return r + (t - (n - r + 1));
-    return r - 1;
-}
-
-// ---------------------------------------------------------------------------
 // Row passes
 // ---------------------------------------------------------------------------
 enum { ROWS_PLAIN = 0, ROWS_CG_UPDATE = 1, ROWS_CG_FIRST = 2 };
-
-// out[b][x][j2] = centred inverse DFT along kx of in[b][j2][:], evaluated at x.
-// ROWS_CG_UPDATE: the transformed vector is p = r + beta p (beta = rr_j/rr_{j-1}
-// from block partials), written back to p.  ROWS_CG_FIRST: p = r.
-template <int MODE>
-__global__ void k_rows_inv_T(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
-                             const double2* __restrict__ rvec, double2* __restrict__ pvec,
-                             const double* __restrict__ pr_new, const double* __restrict__ pr_old,
-                             int npart, const double2* __restrict__ tw1, int TR) {
-    extern __shared__ double2 sm[];
-    const int n1 = g.n1, stride = n1 + 1;
-    double2* v = sm;
-    double* red = (double*)(sm + TR * stride);
-    const int b = blockIdx.y, j0 = blockIdx.x * TR;
-    double beta = 0.0;
-    if (MODE == ROWS_CG_UPDATE) {
-        const double rn = sum_partials(pr_new, npart, red);
-        const double ro = sum_partials(pr_old, npart, red);
-        beta = (ro > 0.0) ? rn / ro : 0.0;
-    }
-    const size_t img = (size_t)b * g.n2 * n1;
-    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
-        const int jr = idx / n1, c = idx - jr * n1;
-        const size_t o = img + (size_t)(j0 + jr) * n1 + c;
-        double2 val;
-        if (MODE == ROWS_PLAIN) {
-            val = in[o];
-        } else if (MODE == ROWS_CG_UPDATE) {
-            val = cadd(rvec[o], cscale(pvec[o], beta));
-            pvec[o] = val;
-        } else {
-            val = rvec[o];
-            pvec[o] = val;
-        }
-        v[jr * stride + c] = cscale(val, sgn_pow(c));
-    }
-    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, true);
-    const double sc = 1.0 / sqrt((double)n1);
-    const size_t ob = (size_t)b * n1 * g.n2;
-    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
-        const int c = idx / TR, jr = idx - c * TR;
-        out[ob + (size_t)c * g.n2 + j0 + jr] = cscale(v[jr * stride + c], sc * sgn_pow(c));
-    }
-}
-
-// out[b][j2][:] = centred forward DFT along x of in[b][:][j2] (hybrid, transposed).
-// BAND: adds corr[b][band_index] on band pixels.  CG: per-block partial of
-// Re<p, out> into pq_part[block].
-template <bool CG, bool BAND>
-__global__ void k_rows_fwd_T(Geo g, const double2* __restrict__ in, double2* __restrict__ out,
-                             const double2* __restrict__ corr, const double2* __restrict__ pvec,
-                             double* __restrict__ pq_part, const double2* __restrict__ tw1, int TR) {
-    extern __shared__ double2 sm[];
-    const int n1 = g.n1, stride = n1 + 1;
-    double2* v = sm;
-    double* red = (double*)(sm + TR * stride);
-    const int b = blockIdx.y, j0 = blockIdx.x * TR;
-    const size_t ib = (size_t)b * n1 * g.n2;
-    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
-        const int c = idx / TR, jr = idx - c * TR;
-        v[jr * stride + c] = cscale(in[ib + (size_t)c * g.n2 + j0 + jr], sgn_pow(c));
-    }
-    fft_batch_lds(v, n1, g.logn1, TR, stride, tw1, false);
-    const double sc = 1.0 / sqrt((double)n1);
-    const size_t img = (size_t)b * g.n2 * n1;
-    double acc = 0.0;
-    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
-        const int jr = idx / n1, k = idx - jr * n1;
-        const int j2 = j0 + jr;
-        double2 val = cscale(v[jr * stride + k], sc * sgn_pow(k));
-        if (BAND) {
-            const int bi = band_index(g, j2, k);
-            if (bi >= 0) val = cadd(val, corr[(size_t)b * g.nband + bi]);
-        }
-        const size_t o = img + (size_t)j2 * n1 + k;
-        out[o] = val;
-        if (CG) {
-            const double2 pv = pvec[o];
-            acc += pv.x * val.x + pv.y * val.y;
-        }
-    }
-    if (CG) {
-        const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) pq_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
-    }
-}
 
 // ytil[i][c][x][m] = centred inverse DFT along kx of y[i][c][i + Ns m][:] at x
 // (only the lines shot i acquires).  y is complex64.
@@ -378,202 +253,286 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Hankel term on the band: exact minus circular, with per-class tap tables.
+// Hankel term on the band (pixels within e = r-1 of an edge): exact minus
+// circular.
+//
+// The circular term sums over every anchor a (mod n); the exact one only over
+// anchors whose r x r patch does not wrap (a2 < n2-e and a1 < n1-e).  At pixel
+// q the wrapping anchors are a = q - b' for b' in I2(q2) x [0,r) union
+// [0,r) x I1(q1), where I2(q2) (I1(q1)) holds the b2' (b1') for which q2 - b2'
+// (q1 - b1') lands in the last e rows (columns) mod n; it is empty unless q2
+// (q1) lies within e of an edge.  By inclusion-exclusion the correction is
+//   row(q) + col(q) + cross(q)
+//   row(q)   = sum_d Drow[class of q2][d] p[q + d]        (b' in I2 x [0,r))
+//   col(q)   = sum_d Dcol[class of q1][d] p[q + d]        (b' in [0,r) x I1)
+//   cross(q) = sum_d Dx[q][d] p[q + d]                    (b' in I2 x I1, lam/2 > 0)
+// The cross term only exists at the 4 e^2 corner pixels (both I2 and I1
+// non-empty).  A row table serves a whole band row and a column table a
+// whole band column, corners included; only the small cross part needs a
+// table per corner pixel.
 // ---------------------------------------------------------------------------
-// Tap tables from W (lam/2 folded in):
-//   Kc[l][i][i'][d2][d1]             = sum_{b'} W[(i, b'+d), (i', b')]
-//   D[l][c2][c1][i'][i][d2][d1]      = K^{(c2,c1)}[i][i'][d] - Kc[l][i][i'][d]
-// where K^{(class)} restricts b' to the anchors valid for that band class.
+// Side tables (side s: 0 top, 1 bottom, 2 left, 3 right; delta = distance of
+// the line from its edge, 0..e-1), output shot i' innermost:
+//   Dside[l][s e + delta][i][d2][d1][i'] = -(lam/2) sum_{b' in X, b'+d in [0,r)^2} W[(i, b'+d), (i', b')]
+//   X(top, delta)  = {b2' > delta} x [0,r)     X(bottom, delta) = {b2' <= delta} x [0,r)
+//   X(left, delta) = [0,r) x {b1' > delta}     X(right, delta)  = [0,r) x {b1' <= delta}
+// the cross tables of the corner pixels (numbered corner * e^2 + row * e +
+// column, corner bit 0 = bottom, bit 1 = right)
+//   Dx[l][corner pixel][i][d2][d1][i'] = (lam/2) sum_{b' in I2 x I1, b'+d in [0,r)^2} W[(i, b'+d), (i', b')]
+// and the taps of the circular term (used in the image domain)
+//   Kc[l][i][i'][d2][d1] = (lam/2) sum_{b'} W[(i, b'+d), (i', b')].
 __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_lam,
-                              double2* __restrict__ Kc, double2* __restrict__ D) {
-    const int nc = g.nc, r = g.r, Ns = g.Ns, K = g.K;
-    const long total = (long)g.L * nc * nc * Ns * Ns * nc * nc;
+                              double2* __restrict__ Kc, double2* __restrict__ Dside, double2* __restrict__ Dx) {
+    const int nc = g.nc, r = g.r, Ns = g.Ns, K = g.K, e = g.e, nsd = 4 * e + 4 * e * e + 1;
+    const long total = (long)g.L * nsd * Ns * Ns * nc * nc;
     for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
          idx += (long)gridDim.x * blockDim.x) {
         long t = idx;
+        const int ip = t % Ns; t /= Ns;
         const int d1 = t % nc; t /= nc;
         const int d2 = t % nc; t /= nc;
         const int i = t % Ns; t /= Ns;
-        const int ip = t % Ns; t /= Ns;
-        const int c1 = t % nc; t /= nc;
-        const int c2 = t % nc; t /= nc;
+        const int sd = t % nsd; t /= nsd;
         const int l = (int)t;
-        const int dd2 = d2 - (r - 1), dd1 = d1 - (r - 1);
-        // b' range of the class in each dimension
-        const int lo2 = (c2 < r) ? 0 : c2 - (r - 1), hi2 = (c2 < r) ? c2 : r - 1;
-        const int lo1 = (c1 < r) ? 0 : c1 - (r - 1), hi1 = (c1 < r) ? c1 : r - 1;
+        const int dd2 = d2 - e, dd1 = d1 - e;
+        int lo2 = 0, hi2 = e, lo1 = 0, hi1 = e;    // b' ranges, inclusive
+        if (sd < 4 * e) {
+            const int side = sd / e, dl = sd - side * e;
+            if (side == 0) lo2 = dl + 1;
+            else if (side == 1) hi2 = dl;
+            else if (side == 2) lo1 = dl + 1;
+            else hi1 = dl;
+        } else if (sd < 4 * e + 4 * e * e) {
+            const int cp = sd - 4 * e, corner = cp / (e * e), px = cp - corner * e * e;
+            const int rr = px / e, cc = px - rr * e;
+            if (corner & 1) hi2 = rr; else lo2 = rr + 1;
+            if (corner & 2) hi1 = cc; else lo1 = cc + 1;
+        }
+        lo2 = max(lo2, -dd2); hi2 = min(hi2, e - dd2);
+        lo1 = max(lo1, -dd1); hi1 = min(hi1, e - dd1);
         const double2* Wl = W + (size_t)l * K * K;
-        double2 kfull = cmk(0.0, 0.0), kcls = cmk(0.0, 0.0);
-        const int a2 = max(0, -dd2), z2 = min(r - 1, r - 1 - dd2);
-        const int a1 = max(0, -dd1), z1 = min(r - 1, r - 1 - dd1);
-        for (int bp2 = a2; bp2 <= z2; ++bp2) {
-            for (int bp1 = a1; bp1 <= z1; ++bp1) {
+        double2 acc = cmk(0.0, 0.0);
+        for (int bp2 = lo2; bp2 <= hi2; ++bp2)
+            for (int bp1 = lo1; bp1 <= hi1; ++bp1) {
                 const int row = (i * r + bp2 + dd2) * r + bp1 + dd1;
                 const int col = (ip * r + bp2) * r + bp1;
-                const double2 w = Wl[(size_t)row * K + col];
-                kfull = cadd(kfull, w);
-                if (bp2 >= lo2 && bp2 <= hi2 && bp1 >= lo1 && bp1 <= hi1) kcls = cadd(kcls, w);
+                acc = cadd(acc, Wl[(size_t)row * K + col]);
             }
-        }
-        kfull = cscale(kfull, half_lam);
-        kcls = cscale(kcls, half_lam);
-        D[idx] = csub(kcls, kfull);
-        if (c2 == r - 1 && c1 == r - 1)
-            Kc[((((size_t)l * Ns + i) * Ns + ip) * nc + d2) * nc + d1] = kfull;
+        if (sd == nsd - 1)
+            Kc[((((size_t)l * Ns + i) * Ns + ip) * nc + d2) * nc + d1] = cscale(acc, half_lam);
+        else if (sd < 4 * e)
+            Dside[(((((size_t)l * 4 * e + sd) * Ns + i) * nc + d2) * nc + d1) * Ns + ip] = cscale(acc, -half_lam);
+        else
+            Dx[(((((size_t)l * 4 * e * e + sd - 4 * e) * Ns + i) * nc + d2) * nc + d1) * Ns + ip] =
+                cscale(acc, half_lam);
     }
 }
 
-// corr[(l,i')][bidx] = sum_i sum_d D[l][class][i'][i][d] p[l][i][(t + d) mod n]
-__global__ void k_band_corr(Geo g, const double2* __restrict__ p, const double2* __restrict__ D,
-                            double2* __restrict__ corr) {
-    const int nc = g.nc, r = g.r, Ns = g.Ns, n1 = g.n1, n2 = g.n2;
-    const int total = g.B * g.nband;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int b = idx / g.nband, bi = idx - b * g.nband;
-    const int l = b / Ns, ip = b - l * Ns;
-    int t2, t1;
-    band_pos(g, bi, t2, t1);
-    const int c2 = band_class(t2, n2, r), c1 = band_class(t1, n1, r);
-    const double2* Dp = D + ((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)Ns * nc * nc;
-    double2 s = cmk(0.0, 0.0);
-    for (int i = 0; i < Ns; ++i) {
-        const double2* pi = p + ((size_t)l * Ns + i) * n2 * n1;
-        for (int d2 = 0; d2 < nc; ++d2) {
-            const int q2 = (t2 + d2 - (r - 1)) & (n2 - 1);
-            const double2* prow = pi + (size_t)q2 * n1;
-            const double2* dr = Dp + ((size_t)i * nc + d2) * nc;
-            for (int d1 = 0; d1 < nc; ++d1) {
-                const int q1 = (t1 + d1 - (r - 1)) & (n1 - 1);
-                s = cfma(dr[d1], prow[q1], s);
-            }
-        }
-    }
-    corr[idx] = s;
-}
-
-// Tiled version: one workgroup per (band tile, slice l, output shot i').
-// Edge tiles cover TW = 64 pixels along one strip (top/bottom rows 0..e-1 and
-// n2-e..n2-1 between the corner blocks, left/right columns likewise) and all
-// e lines of the strip; wave k of the workgroup computes line k with one pixel
-// per lane.  Every pixel of a line shares one tap table, so the e tables of
-// the tile are staged in shared memory next to the p patch of all shots (tile
-// plus an e-wide halo, wrapped, strip direction contiguous); table reads are
-// broadcasts.  The four e x e corner blocks (one table per pixel) are tiles
-// of their own, one pixel per lane, tables read through the cache.
-#define BAND_TW 64
-__host__ __device__ inline int band_edge_tiles(int len, int e) { return (len - 2 * e + BAND_TW - 1) / BAND_TW; }
-__host__ __device__ inline int band_tiles_total(const Geo& g) {
-    return 2 * band_edge_tiles(g.n1, g.e) + 2 * band_edge_tiles(g.n2, g.e) + 4;
-}
-__host__ __device__ inline size_t band_patch_elems(const Geo& g) {
-    return (size_t)g.Ns * (3 * g.e) * (BAND_TW + 2 * g.e);
-}
-__host__ __device__ inline size_t band_lds_bytes(const Geo& g) {
-    return (band_patch_elems(g) + (size_t)g.e * g.Ns * g.nc * g.nc) * sizeof(double2);
-}
-
+// Band kernel: one workgroup (64 Ns threads) per (work item, slice l = blockIdx.y).
+//
+// Line items: BAND_SEG consecutive pixels of one band row (all n1 columns) or
+// one band column (all n2 rows) and a share of the 2r-1 tap rows across the
+// line (band_ds shares; the row pass sums the shares in order).  Wave w takes
+// input shot i = w, lane = pixel, and accumulates all Ns output shots; the
+// side table is wave-uniform and read through the scalar cache; the p patch
+// (tap rows of the share x BAND_SEG+2e positions, wrapped) is staged in
+// shared memory along the line.  The Ns wave partials are summed in order.
+// Output: row[share][l Ns + i'][row line][t1], col[share][l Ns + i'][column line][t2],
+// lines numbered 0..e-1 from the low edge and e..2e-1 for the high one.
+//
+// Corner items: one corner pixel q; the Ns (2r-1)^2 taps of its cross table
+// are spread over the threads (all output shots per thread), then summed by
+// fixed-order block reductions: corner[l Ns + i'][corner pixel].
+#define BAND_SEG 64
 #define BAND_MAX_NC 17
-template <int NC>
-__global__ void __launch_bounds__(1024)
-k_band_tile(Geo g, const double2* __restrict__ p, const double2* __restrict__ D, double2* __restrict__ corr) {
-    extern __shared__ double2 sm[];
-    constexpr int nc = NC, tab = NC * NC;
-    const int e = g.e, r = g.r, Ns = g.Ns, n1 = g.n1, n2 = g.n2;
-    const int nth = band_edge_tiles(n1, e), ntv = band_edge_tiles(n2, e);
-    const int l = blockIdx.y, ip = blockIdx.z;
-    const int tile = blockIdx.x;
-    int kind;  // 0 top, 1 bottom, 2 left, 3 right, 4 corner
-    int t2a, t1a, H, Wd;
-    if (tile < 2 * nth) {
-        kind = tile < nth ? 0 : 1;
-        const int k = tile - (kind == 1 ? nth : 0);
-        t2a = kind == 0 ? 0 : n2 - e;
-        t1a = e + k * BAND_TW;
-        H = e;
-        Wd = min(BAND_TW, n1 - e - t1a);
-    } else if (tile < 2 * nth + 2 * ntv) {
-        const int tt = tile - 2 * nth;
-        kind = tt < ntv ? 2 : 3;
-        const int k = tt - (kind == 3 ? ntv : 0);
-        t1a = kind == 2 ? 0 : n1 - e;
-        t2a = e + k * BAND_TW;
-        Wd = e;
-        H = min(BAND_TW, n2 - e - t2a);
-    } else {
-        kind = 4;
-        const int c = tile - 2 * nth - 2 * ntv;
-        t2a = (c & 1) ? n2 - e : 0;
-        t1a = (c & 2) ? n1 - e : 0;
-        H = e;
-        Wd = e;
-    }
-    // strip coordinates: "line" across the strip, "pos" along it
-    const bool horiz = kind != 2 && kind != 3;
-    const int nline = horiz ? H : Wd, npos = horiz ? Wd : H;
-    const int PL = nline + 2 * e, PP = npos + 2 * e;     // patch extent in line / pos
-    for (int idx = threadIdx.x; idx < Ns * PL * PP; idx += blockDim.x) {
-        const int i = idx / (PL * PP), rem = idx - i * PL * PP;
-        const int pl = rem / PP, pp = rem - pl * PP;
-        const int pr = horiz ? pl : pp, pc = horiz ? pp : pl;
-        const int q2 = (t2a - e + pr) & (n2 - 1), q1 = (t1a - e + pc) & (n1 - 1);
-        sm[idx] = p[(((size_t)l * Ns + i) * n2 + q2) * n1 + q1];
-    }
-    double2* Ds = sm + band_patch_elems(g);      // tap tables of the e lines (edge tiles)
-    if (kind < 4) {
-        const int per = Ns * tab;
-        for (int idx = threadIdx.x; idx < e * per; idx += blockDim.x) {
-            const int k = idx / per, rem = idx - k * per;
-            int c2 = r - 1, c1 = r - 1;
-            if (kind == 0) c2 = k;
-            else if (kind == 1) c2 = r + k;
-            else if (kind == 2) c1 = k;
-            else c1 = r + k;
-            Ds[idx] = D[((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)per + rem];
+__host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
+// shares of the tap rows (more workgroups for the same work: finer balance)
+__host__ __device__ inline int band_ds(int Ns, int nc) {
+    const int d = Ns >= 8 ? 2 : 12 / Ns;
+    return d < nc ? d : nc;
+}
+__host__ __device__ inline int band_line_items(const Geo& g) {
+    return 2 * g.e * (band_segs(g.n1) + band_segs(g.n2)) * band_ds(g.Ns, g.nc);
+}
+__host__ __device__ inline int band_items(const Geo& g) { return band_line_items(g) + 4 * g.e * g.e; }
+__host__ __device__ inline size_t band_lds_bytes(const Geo& g) {
+    const int ds = band_ds(g.Ns, g.nc);
+    const size_t patch = (size_t)g.Ns * ((g.nc + ds - 1) / ds) * (BAND_SEG + 2 * g.e);
+    const size_t red = (size_t)g.Ns * g.Ns * BAND_SEG;
+    const size_t m = patch > red ? patch : red;
+    return (m > 8 ? m : 8) * sizeof(double2);
+}
+
+template <int NC, int NS, bool HORIZ>
+SMSM_DEV void band_line_sum(const double2* __restrict__ Pw, int PP, const double2* __restrict__ Dw, int dl0,
+                            int dl1, double2 (&acc)[NS]) {
+    // Pw: patch of this wave's shot at (tap row dl0, this lane's pixel);
+    // Dw: side table of this line and shot, [d2][d1][i'] (wave-uniform)
+    for (int dl = dl0; dl < dl1; ++dl) {
+        const double2* Pr = Pw + (dl - dl0) * PP;
+        double2 pv[NC];
+#pragma unroll
+        for (int dp = 0; dp < NC; ++dp) pv[dp] = Pr[dp];
+#pragma unroll
+        for (int dp = 0; dp < NC; ++dp) {
+            const int t = HORIZ ? dl * NC + dp : dp * NC + dl;   // [d2][d1]
+            const double2* dd = Dw + t * NS;
+#pragma unroll
+            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(dd[ip], pv[dp], acc[ip]);
         }
     }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const size_t ob = ((size_t)l * Ns + ip) * g.nband;
-    if (kind < 4) {
-        if (wave >= nline) return;
-        const int ln = wave;
-        const double2* Dl = Ds + (size_t)ln * Ns * tab;   // same address in every lane: broadcast reads
-        const int pos = min(lane, npos - 1);
-        double2 s = cmk(0.0, 0.0);
-        for (int i = 0; i < Ns; ++i) {
-            const double2* Di = Dl + (size_t)i * tab;
-            const double2* Pi = sm + (size_t)i * PL * PP + ln * PP + pos;
-            for (int dl = 0; dl < nc; ++dl) {
-                const double2* Pr = Pi + dl * PP;
-#pragma unroll
-                for (int dp = 0; dp < NC; ++dp) {
-                    // table index [d2][d1]: (dl, dp) = (d2, d1) horizontally, (d1, d2) vertically
-                    const int ti = horiz ? dl * nc + dp : dp * nc + dl;
-                    s = cfma(Di[ti], Pr[dp], s);
-                }
+}
+
+template <int NC, int NS>
+__global__ void __launch_bounds__(64 * NS)
+k_band_line(Geo g, const double2* __restrict__ p, const double2* __restrict__ Dside,
+            const double2* __restrict__ Dx, double2* __restrict__ crow, double2* __restrict__ ccol,
+            double2* __restrict__ ccorner) {
+    extern __shared__ double2 sm[];
+    const int e = g.e, r = g.r, n1 = g.n1, n2 = g.n2, K = g.K;
+    const int l = blockIdx.y, item = blockIdx.x;
+    const double2* pl = p + (size_t)l * NS * n2 * n1;
+    if (item < band_line_items(g)) {
+        const int ds = band_ds(NS, NC);
+        const int nsr = band_segs(n1), nrow = 2 * e * nsr * ds;
+        const bool horiz = item < nrow;
+        int it = horiz ? item : item - nrow;
+        const int nseg = horiz ? nsr : band_segs(n2);
+        const int part = it % ds;
+        it /= ds;
+        const int seg = it % nseg, line = it / nseg;          // line 0..2e-1
+        const int delta = line < e ? line : line - e;
+        const int side = (horiz ? 0 : 2) + (line < e ? 0 : 1);
+        const int len = horiz ? n1 : n2, span = horiz ? n2 : n1;
+        const int lc = line < e ? delta : span - e + delta;     // line coordinate
+        const int pos0 = seg * BAND_SEG;
+        const int npos = min(BAND_SEG, len - pos0);
+        const int dl0 = part * NC / ds, dl1 = (part + 1) * NC / ds, nr = dl1 - dl0;
+        const int PP = BAND_SEG + 2 * e;
+        // stage p: sm[i][rr][pp] = p_i at line coordinate lc - e + dl0 + rr, position pos0 - e + pp
+        const int tot = NS * nr * PP;
+        if (horiz) {
+            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+                const int i = idx / (nr * PP), rem = idx - i * nr * PP;
+                const int rr = rem / PP, pp = rem - rr * PP;
+                const int q2 = (lc - e + dl0 + rr) & (n2 - 1), q1 = (pos0 - e + pp) & (n1 - 1);
+                sm[idx] = pl[((size_t)i * n2 + q2) * n1 + q1];
+            }
+        } else {
+            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+                const int i = idx / (nr * PP), rem = idx - i * nr * PP;
+                const int pp = rem / nr, rr = rem - pp * nr;     // consecutive threads along x
+                const int q2 = (pos0 - e + pp) & (n2 - 1), q1 = (lc - e + dl0 + rr) & (n1 - 1);
+                sm[(size_t)i * nr * PP + rr * PP + pp] = pl[((size_t)i * n2 + q2) * n1 + q1];
             }
         }
-        if (lane < npos) {
-            const int t2 = horiz ? t2a + ln : t2a + lane, t1 = horiz ? t1a + lane : t1a + ln;
-            corr[ob + band_index(g, t2, t1)] = s;
+        __syncthreads();
+        const int lane = threadIdx.x & 63;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // input shot
+        const double2* Dw = Dside + (((size_t)l * 4 * e + side * e + delta) * NS + w) * NC * NC * NS;
+        const double2* Pw = sm + (size_t)w * nr * PP + min(lane, npos - 1);
+        double2 acc[NS];
+#pragma unroll
+        for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
+        if (horiz) band_line_sum<NC, NS, true>(Pw, PP, Dw, dl0, dl1, acc);
+        else band_line_sum<NC, NS, false>(Pw, PP, Dw, dl0, dl1, acc);
+        __syncthreads();
+#pragma unroll
+        for (int ip = 0; ip < NS; ++ip) sm[((size_t)w * NS + ip) * BAND_SEG + lane] = acc[ip];
+        __syncthreads();
+        double2* dst = horiz ? crow : ccol;
+        const int B = g.B;
+        for (int idx = threadIdx.x; idx < NS * BAND_SEG; idx += blockDim.x) {
+            const int ip = idx / BAND_SEG, px = idx - ip * BAND_SEG;
+            if (px >= npos) continue;
+            double2 s = cmk(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) s = cadd(s, sm[((size_t)i * NS + ip) * BAND_SEG + px]);
+            dst[(((size_t)part * B + l * NS + ip) * 2 * e + line) * len + pos0 + px] = s;
         }
     } else {
-        if (wave != 0) return;
-        const int px = min(lane, e * e - 1);
+        const int cp = item - band_line_items(g);
+        const int corner = cp / (e * e), px = cp - corner * e * e;
         const int rr = px / e, cc = px - rr * e;
-        const int t2 = t2a + rr, t1 = t1a + cc;
-        const int c2 = band_class(t2, n2, r), c1 = band_class(t1, n1, r);
-        const double2* Dl = D + ((((size_t)l * nc + c2) * nc + c1) * Ns + ip) * (size_t)Ns * tab;
-        double2 s = cmk(0.0, 0.0);
-        for (int i = 0; i < Ns; ++i)
-            for (int d2 = 0; d2 < nc; ++d2)
-                for (int d1 = 0; d1 < nc; ++d1)
-                    s = cfma(Dl[((size_t)i * nc + d2) * nc + d1],
-                             sm[(size_t)i * PL * PP + (rr + d2) * PP + cc + d1], s);
-        if (lane < e * e) corr[ob + band_index(g, t2, t1)] = s;
+        const int q2 = ((corner & 1) ? n2 - e : 0) + rr, q1 = ((corner & 2) ? n1 - e : 0) + cc;
+        const double2* Dc = Dx + ((size_t)l * 4 * e * e + cp) * NS * NC * NC * NS;
+        double2 acc[NS];
+#pragma unroll
+        for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
+        constexpr int nt = NS * NC * NC;
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+            const int i = t / (NC * NC), d = t - i * NC * NC, d2 = d / NC, d1 = d - d2 * NC;
+            const double2 pv = pl[((size_t)i * n2 + ((q2 - e + d2) & (n2 - 1))) * n1 + ((q1 - e + d1) & (n1 - 1))];
+#pragma unroll
+            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(Dc[(size_t)t * NS + ip], pv, acc[ip]);
+        }
+        double* red = (double*)sm;
+#pragma unroll
+        for (int ip = 0; ip < NS; ++ip) {
+            const double sr = block_sum(acc[ip].x, red);
+            const double si = block_sum(acc[ip].y, red);
+            if (threadIdx.x == 0) ccorner[((size_t)l * NS + ip) * 4 * e * e + cp] = cmk(sr, si);
+        }
     }
+}
+
+// Band kernel for (2r-1, Ns); null when the pair is outside what the plan
+// accepts (Ns r^2 <= 256, 2r-1 <= BAND_MAX_NC).
+typedef void (*BandFn)(Geo, const double2*, const double2*, const double2*, double2*, double2*, double2*);
+template <int NS>
+inline BandFn band_fn_ns(int nc) {
+    switch (nc) {
+        case 3: return &k_band_line<3, NS>;
+        case 5: return &k_band_line<5, NS>;
+        case 7: return &k_band_line<7, NS>;
+        case 9: return &k_band_line<9, NS>;
+        case 11: return NS <= 4 ? &k_band_line<11, (NS <= 4 ? NS : 4)> : nullptr;
+        case 13: return NS <= 4 ? &k_band_line<13, (NS <= 4 ? NS : 4)> : nullptr;
+        case 15: return NS <= 4 ? &k_band_line<15, (NS <= 4 ? NS : 4)> : nullptr;
+        case 17: return NS <= 2 ? &k_band_line<17, (NS <= 2 ? NS : 2)> : nullptr;
+        default: return nullptr;
+    }
+}
+inline BandFn band_fn(int nc, int ns) {
+    switch (ns) {
+        case 1: return band_fn_ns<1>(nc);
+        case 2: return band_fn_ns<2>(nc);
+        case 4: return band_fn_ns<4>(nc);
+        case 8: return band_fn_ns<8>(nc);
+        default: return nullptr;
+    }
+}
+
+// Outputs of the band kernel, summed into the row pass.
+struct BandAdd {
+    const double2* row;      // [ds][B][2e][n1]
+    const double2* col;      // [ds][B][2e][n2]
+    const double2* corner;   // [B][4 e^2]
+    int ds;
+};
+
+// Band correction of image b at pixel (j2, k): row and column shares, and the
+// cross term at the corners.
+SMSM_DEV double2 band_add(const Geo& g, const BandAdd& ba, int b, int j2, int k) {
+    const int e = g.e, n1 = g.n1, n2 = g.n2;
+    double2 s = cmk(0.0, 0.0);
+    const bool rb = j2 < e || j2 >= n2 - e, cb = k < e || k >= n1 - e;
+    if (rb) {
+        const int rl = j2 < e ? j2 : j2 - (n2 - 2 * e);
+        for (int part = 0; part < ba.ds; ++part)
+            s = cadd(s, ba.row[(((size_t)part * g.B + b) * 2 * e + rl) * n1 + k]);
+    }
+    if (cb) {
+        const int cl = k < e ? k : k - (n1 - 2 * e);
+        for (int part = 0; part < ba.ds; ++part)
+            s = cadd(s, ba.col[(((size_t)part * g.B + b) * 2 * e + cl) * n2 + j2]);
+    }
+    if (rb && cb) {
+        const int corner = (j2 < e ? 0 : 1) | (k < e ? 0 : 2);
+        const int rr = j2 < e ? j2 : j2 - (n2 - e), cc = k < e ? k : k - (n1 - e);
+        s = cadd(s, ba.corner[(size_t)b * 4 * e * e + corner * e * e + rr * e + cc]);
+    }
+    return s;
 }
 
 // ---------------------------------------------------------------------------

@@ -72,7 +72,7 @@ struct WaveFft {
 // image b; each wave transforms whole rows in registers and parks them in a
 // shared tile, which is then read out transposed (row pass 1) or staged from a
 // transposed read (row pass 3), so global accesses stay coalesced.
-// TR must be a multiple of 4 * (64 / LANES).
+// TR must be a multiple of (blockDim / 64) * (64 / LANES), and TR * N <= 8 * blockDim.
 // ---------------------------------------------------------------------------
 template <int N, int MODE>
 __global__ void __launch_bounds__(256)
@@ -132,7 +132,7 @@ k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
 
 template <int N, bool CG, bool BAND>
 __global__ void __launch_bounds__(256)
-k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ corr,
+k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, BandAdd ba,
              const double2* __restrict__ pvec, double* __restrict__ pq_part, const double2* __restrict__ tw1,
              int TR) {
     using F = WaveFft<N>;
@@ -142,6 +142,21 @@ k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
     const int b = blockIdx.y, j0 = blockIdx.x * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t ib = (size_t)b * N * g.n2;
+    // band terms of this thread's outputs, loaded first so their latency
+    // overlaps the transform (TR * N <= 8 * blockDim)
+    const size_t img = (size_t)b * g.n2 * N;
+    double2 bandv[8], pv[8];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = threadIdx.x + it * blockDim.x;
+        bandv[it] = cmk(0.0, 0.0);
+        pv[it] = cmk(0.0, 0.0);
+        if (idx < TR * N) {
+            const int jr = idx / N, k = idx - jr * N;
+            if (BAND) bandv[it] = band_add(g, ba, b, j0 + jr, k);
+            if (CG) pv[it] = pvec[img + (size_t)(j0 + jr) * N + k];
+        }
+    }
     for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
         const int c = idx / TR, jr = idx - c * TR;
         sm[jr * ST + c] = in[ib + (size_t)c * g.n2 + j0 + jr];
@@ -167,22 +182,18 @@ k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
         }
     }
     __syncthreads();
-    const size_t img = (size_t)b * g.n2 * N;
     double acc = 0.0;
-    for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int idx = threadIdx.x + it * blockDim.x;
+        if (idx >= TR * N) break;
         const int jr = idx / N, k = idx - jr * N;
         const int j2 = j0 + jr;
         double2 val = sm[jr * ST + k];
-        if (BAND) {
-            const int bi = band_index(g, j2, k);
-            if (bi >= 0) val = cadd(val, corr[(size_t)b * g.nband + bi]);
-        }
+        if (BAND) val = cadd(val, bandv[it]);
         const size_t o = img + (size_t)j2 * N + k;
         out[o] = val;
-        if (CG) {
-            const double2 pv = pvec[o];
-            acc += pv.x * val.x + pv.y * val.y;
-        }
+        if (CG) acc += pv[it].x * val.x + pv[it].y * val.y;
     }
     if (CG) {
         const double s = block_sum(acc, red);
