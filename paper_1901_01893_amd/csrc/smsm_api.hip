@@ -54,7 +54,7 @@ struct smsm_plan {
     double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
-    double2 *Kc = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
+    double2 *Kc = nullptr, *Khat = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
     double *pr = nullptr, *pq = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr;
@@ -161,7 +161,7 @@ template <int M_, int L_>
 void launch_colfast(smsm_plan* P, int use_reg, hipStream_t st) {
     const Geo& g = P->g;
     hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, P->h1,
-                       P->h2, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg);
+                       P->h2, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg);
 }
 
 template <int MODE>
@@ -207,6 +207,11 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
                        P->Kc, P->Dside, P->Dx);
     LAUNCH_CHECK();
+    if (P->col_fast >= 0) {
+        hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * g.Ns), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
+                           P->tw2, P->Khat);
+        LAUNCH_CHECK();
+    }
     P->have_weights = true;
     return SMSM_OK;
 }
@@ -430,6 +435,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oY0 = cv.take<double2>(KKP), oY1 = cv.take<double2>(KKP);
     const size_t oZ0 = cv.take<double2>(KKP), oZ1 = cv.take<double2>(KKP), oT = cv.take<double2>(KKP);
     const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
+    const size_t oKh = cv.take<double2>((size_t)L * Ns * Ns * n1 * n2);
     const size_t oD = cv.take<double2>(ntab);
     const size_t oDx = cv.take<double2>(ntab * g.e);
     const size_t ocrow = cv.take<double2>(nds * g.B * 2 * g.e * n1);
@@ -455,7 +461,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->G = (double2*)(base + oG); P->W = (double2*)(base + oW);
     P->Y0 = (double2*)(base + oY0); P->Y1 = (double2*)(base + oY1);
     P->Z0 = (double2*)(base + oZ0); P->Z1 = (double2*)(base + oZ1); P->T = (double2*)(base + oT);
-    P->Kc = (double2*)(base + oKc); P->Dside = (double2*)(base + oD); P->Dx = (double2*)(base + oDx);
+    P->Kc = (double2*)(base + oKc); P->Khat = (double2*)(base + oKh); P->Dside = (double2*)(base + oD); P->Dx = (double2*)(base + oDx);
     P->crow = (double2*)(base + ocrow); P->ccol = (double2*)(base + occol); P->ccorner = (double2*)(base + ocorner);
     P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
     P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);

@@ -12,8 +12,9 @@
 //   inverse  M-point inverse DFT (decimation in time: bit-reversed in,
 //            natural order out)
 //   unfold   acc_s[t] += conj(S_{s,c}[m + M t]) g_s[m]
-// Lane exchanges use DPP for xor distances 1..8 and the gfx950 permlane
-// swaps for 16 and 32; all 64 lanes stay active through every exchange.
+// Lane exchanges use DPP for xor distances 1..8 and the LDS crossbar
+// (ds_swizzle / ds_bpermute) for 16 and 32; all 64 lanes stay active through
+// every exchange.
 #pragma once
 #include "smsm_kernels.h"
 
@@ -25,27 +26,22 @@ SMSM_DEV double dpp_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// xor 16 / xor 32 with the gfx950 permlane swaps: swapping a value with a
-// copy of itself leaves, in the two results, the even and the odd 16-lane rows
-// (resp. the low and high 32-lane halves) side by side; each lane then picks
-// the copy that came from its partner row.
-SMSM_DEV unsigned xor16_u(unsigned v) {
-    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (threadIdx.x & 16) ? r[0] : r[1];
-}
-SMSM_DEV unsigned xor32_u(unsigned v) {
-    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (threadIdx.x & 32) ? r[0] : r[1];
-}
+// xor 16 and xor 32 go through the LDS crossbar (ds_swizzle in xor mode
+// within 32-lane halves, ds_bpermute across halves): they issue on the LDS
+// pipe and leave the vector ALU to the butterflies.  (A DPP pair or a
+// permlane swap plus select costs two VALU issues per dword.)
 SMSM_DEV double swz_xor16_d(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = xor16_u((unsigned)b), hi = xor16_u((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x1F | (16 << 10));
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x1F | (16 << 10));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 SMSM_DEV double perm_xor32_d(double v) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = xor32_u((unsigned)b), hi = xor32_u((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    const long long b = __double_as_longlong(v);
+    const int addr = (int)(((threadIdx.x & 63) ^ 32) << 2);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // value of lane (l ^ MASK)
@@ -109,10 +105,29 @@ SMSM_DEV void fft_dit_inv(double2 (&v)[NV], const double2 (&w)[8], const double 
     if constexpr (M >= 64) dit_stage<32, NV>(v, sg[5], w[5]);
 }
 
-// Shared-memory layout (double2 units) of k_col_fast.
-__host__ __device__ inline int colfast_lds_A(const Geo& g) { return 2 * g.B * g.n2 + g.n2; }
-__host__ __device__ inline int colfast_lds_total(const Geo& g) {
-    return colfast_lds_A(g) + g.L * g.Ns * g.Ns * g.nc + 16;
+// Shared-memory layout (double2 units) of k_col_fast: U, ACC, ky twiddles.
+__host__ __device__ inline int colfast_lds_total(const Geo& g) { return 2 * g.B * g.n2 + g.n2 + 16; }
+
+// Image-domain kernel of the circular Hankel term, one table per IRLS step:
+//   Khat[l][j][i][x][n] = sum_{d2,d1} Kc[l][j][i][d2][d1] e^{-2 pi i ((d1-e)(x-n1/2)/n1 + (d2-e)(n-n2/2)/n2)}
+// (input shot j, output shot i).  grid (n1, L Ns Ns), block 256.
+__global__ void k_hankel_image(Geo g, const double2* __restrict__ Kc, const double2* __restrict__ tw1,
+                               const double2* __restrict__ tw2, double2* __restrict__ Khat) {
+    __shared__ double2 A[BAND_MAX_NC];
+    const int x = blockIdx.x, sji = blockIdx.y, nc = g.nc, e = g.e, n1 = g.n1, n2 = g.n2;
+    const int nu1 = x - n1 / 2;
+    for (int d2 = threadIdx.x; d2 < nc; d2 += blockDim.x) {
+        const double2* kr = Kc + ((size_t)sji * nc + d2) * nc;
+        double2 a = cmk(0.0, 0.0);
+        for (int d1 = 0; d1 < nc; ++d1) a = cfma(kr[d1], tw1[((d1 - e) * nu1) & (n1 - 1)], a);
+        A[d2] = a;
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < n2; n += blockDim.x) {
+        double2 k = cmk(0.0, 0.0);
+        for (int d2 = 0; d2 < nc; ++d2) k = cfma(A[d2], tw2[((d2 - e) * (n - n2 / 2)) & (n2 - 1)], k);
+        Khat[((size_t)sji * n1 + x) * n2 + n] = k;
+    }
 }
 
 template <int N> struct WaveFft;
@@ -123,9 +138,8 @@ template <int N> struct WaveFft;
 template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const float2* __restrict__ ST,
-           const double2* __restrict__ theta, const double2* __restrict__ tau, const double2* __restrict__ tw2,
-           const double2* __restrict__ twM, const double2* __restrict__ tw1, const double2* __restrict__ Kc,
-           int use_reg) {
+           const double2* __restrict__ theta, const double2* __restrict__ tw2, const double2* __restrict__ twM,
+           const double2* __restrict__ Khat, int use_reg) {
     constexpr int T = NS;          // n2 = M * NS
     constexpr int N2 = M * NS;
     constexpr int G = 64 / M;      // coils processed side by side in one wave
@@ -134,7 +148,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     using FC = WaveFft<N2>;
     constexpr int RC = FC::R;
     extern __shared__ double2 sm[];
-    const int n1 = g.n1, Nc = g.Nc, nc = g.nc, e = g.e;
+    const int n1 = g.n1, Nc = g.Nc;
     const int x1 = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -143,20 +157,9 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     double2* U = sm;
     double2* ACC = sm + B * N2;
     double2* TW2 = sm + 2 * B * N2;
-    double2* A = sm + colfast_lds_A(g);
     const double isq2 = 1.0 / sqrt((double)N2);
 
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
-    // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}  (Hankel kernel, kx taps)
-    if (use_reg) {
-        const int nu1 = x1 - n1 / 2;
-        for (int idx = tid; idx < L * NS * NS * nc; idx += nt) {
-            const double2* kr = Kc + (size_t)idx * nc;
-            double2 a = cmk(0.0, 0.0);
-            for (int d1 = 0; d1 < nc; ++d1) a = cfma(kr[d1], tw1[((d1 - e) * nu1) & (n1 - 1)], a);
-            A[idx] = a;
-        }
-    }
     __syncthreads();
 
     // ---- column image: U[b][n] = tau_i[n] u_b[n], u_b = centred inverse DFT along ky of h1 column
@@ -248,7 +251,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         }
     // ---- normal-operator scaling conj(tau_i[n]) / n2, then the circular Hankel
     // term for the positions t = cg (mod CG) of this wave (output shot i):
-    //   sum_j u_{s,j}[n] sum_d2 A[s][j][i][d2] e^{-2 pi i (d2-e)(n - n2/2)/n2}
+    //   sum_j Khat[s][j][i][x][n] u_{s,j}[n]
     const bool writer = (grp == 0);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -259,19 +262,12 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         for (int s = 0; s < L; ++s) {
             acc[s][t] = cscale(cmulc(acc[s][t], tai), 1.0 / (double)N2);
             if (mine) {
-                double2 kv[NS];
-#pragma unroll
-                for (int j = 0; j < NS; ++j) kv[j] = cmk(0.0, 0.0);
-                for (int d2 = 0; d2 < nc; ++d2) {
-                    const double2 ev = TW2[((d2 - e) * (n - N2 / 2)) & (N2 - 1)];
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) kv[j] = cfma(A[((s * NS + j) * NS + i) * nc + d2], ev, kv[j]);
-                }
                 double2 rg = cmk(0.0, 0.0);
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
+                    const double2 kv = Khat[((size_t)((s * NS + j) * NS + i) * n1 + x1) * N2 + n];
                     const double2 taj = cscale(TW2[(j * n) & (N2 - 1)], sgn_pow(n));
-                    rg = cfma(kv[j], cmulc(U[(s * NS + j) * N2 + n], taj), rg);
+                    rg = cfma(kv, cmulc(U[(s * NS + j) * N2 + n], taj), rg);
                 }
                 acc[s][t] = cadd(acc[s][t], rg);
             }
