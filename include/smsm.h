@@ -77,7 +77,7 @@ typedef struct {
     double  eps_frac;        /* eps schedule start (fraction of sigma_l), > 0 */
     double  eps_decay;       /* eta >= 1 */
     double  eps_floor_frac;  /* >= 0 */
-    int32_t ns_max_iter;     /* cap on Newton-Schulz iterations for W (0 = 24) */
+    int32_t ns_max_iter;     /* cap on Newton-Schulz iterations for W (0 = 16) */
     uint32_t flags;          /* SMSM_FLAG_* */
 } smsm_params;
 
@@ -140,8 +140,10 @@ smsm_status smsm_apply_AHA(smsm_plan* plan, const void* x_dev, void* out_dev, vo
 smsm_status smsm_gram(smsm_plan* plan, const void* x_dev, void* g_dev, void* stream);
 
 /* W_l = (G_l + eps_l I)^(-1/2): G c128 [L][K][K] -> W c128 [L][K][K], by a
- * coupled Newton-Schulz iteration run to convergence.  eps: host [L];
- * eps_l <= 0 gives W_l = 0 (unregularised slice).  Synchronises `stream`. */
+ * scaled coupled Newton-Schulz iteration run until ||I - Z Y||_F < 1e-10 or
+ * for ns_max_iter steps (condition numbers up to about 1e8 converge within
+ * the default cap).  eps: host [L]; eps_l <= 0 gives W_l = 0 (unregularised
+ * slice).  Synchronises `stream`. */
 smsm_status smsm_weights(smsm_plan* plan, const void* g_dev, const double* eps,
                          void* w_dev, void* stream);
 

@@ -17,7 +17,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kColThreads = 512;
 constexpr int kVecBlocks = 512;      // fixed grid of the CG vector kernels
-constexpr int kNsDefaultIters = 24;  // Newton-Schulz iteration cap
+constexpr int kNsDefaultIters = 16;  // Newton-Schulz iteration cap
 constexpr int kSqSteps = 30;         // squarings for the largest eigenvalue
 constexpr int kPadBlocks = 32;       // blocks per slice of the dense set-up kernels
 constexpr double kNsTol = 1e-10;     // ||I - Z Y||_F at which NS is converged
@@ -57,7 +57,7 @@ struct smsm_plan {
     double2 *Kc = nullptr, *Khat = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
     double *pr = nullptr, *pq = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
-    double *wscale = nullptr, *epsin = nullptr;
+    double *wscale = nullptr, *epsin = nullptr, *nsmu = nullptr;
     int *done = nullptr, *flags = nullptr;
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
@@ -270,7 +270,7 @@ smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, dou
                        P->part0);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_ns_start, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, g.K, KP, g.L, src, mult,
-                       P->part0, kPadBlocks, P->Y0, P->Z0, P->wscale, P->done, nit);
+                       P->part0, kPadBlocks, P->Y0, P->Z0, P->wscale, P->done, nit, P->nsmu);
     LAUNCH_CHECK();
     double2* Y[2] = {P->Y0, P->Y1};
     double2* Z[2] = {P->Z0, P->Z1};
@@ -280,6 +280,8 @@ smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, dou
         t.A0 = Z[a]; t.B0 = Y[a]; t.C0 = P->T;
         t.done_cur = P->done + (size_t)k * g.L;
         t.part_out = P->part0;
+        t.mu = P->nsmu + (size_t)k * g.L;
+        t.mu_stride = 1;
         hipLaunchKernelGGL(k_zgemm<HG_NS>, dim3(P->ntile, 1, g.L), dim3(64 * HW), 0, st, g.K, KP, t);
         LAUNCH_CHECK();
         HgArgs u{};
@@ -447,7 +449,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t opr = cv.take<double>(3 * kVecBlocks), opq = cv.take<double>(P->npq);
     const size_t onp0 = cv.take<double>((size_t)L * P->npmax), onp1 = cv.take<double>((size_t)L * P->npmax);
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
-    const size_t oei = cv.take<double>(L);
+    const size_t oei = cv.take<double>(L), onsmu = cv.take<double>((size_t)P->ns_iters * L);
     const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
@@ -468,7 +470,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->part0 = (double*)(base + onp0);
     P->part1 = (double*)(base + onp1);
     P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
-    P->epsin = (double*)(base + oei);
+    P->epsin = (double*)(base + oei); P->nsmu = (double*)(base + onsmu);
     P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
 
     // host tables: twiddles, CAIPI phases, shot modulation
