@@ -4,6 +4,7 @@
 #include "smsm_col_fast.h"
 #include "smsm_wavefft.h"
 #include "smsm_dense.h"
+#include "smsm_gram.h"
 #include "smsm.h"
 
 #include <cmath>
@@ -244,16 +245,25 @@ smsm_status chain_gram(smsm_plan* P, const double2* v, double2* G, hipStream_t s
     const Geo& g = P->g;
     smsm_status s = rows_inv(P, v, P->h1, st);
     if (s) return s;
-    hipLaunchKernelGGL(k_gram_col, dim3(g.n1), dim3(kThreads), P->lds_gram, st, g, P->h1, P->tw2, P->tw1,
-                       P->gpart);
+    const size_t lds = P->lds_gram;
+    switch (g.n2) {
+        case 16: hipLaunchKernelGGL(k_gram_q<16>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+        case 32: hipLaunchKernelGGL(k_gram_q<32>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+        case 64: hipLaunchKernelGGL(k_gram_q<64>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+        case 128: hipLaunchKernelGGL(k_gram_q<128>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+        default: hipLaunchKernelGGL(k_gram_q<256>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+    }
     LAUNCH_CHECK();
-    const int per = g.L * g.npairs * g.nc * g.nc;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((per + kThreads - 1) / kThreads), dim3(kThreads), 0, st, g,
-                       P->gpart, P->gC);
+    const int wpb = kThreads / 64;
+    const int nwc = g.L * g.npairs * g.nc;
+    hipLaunchKernelGGL(k_gram_c, dim3((nwc + wpb - 1) / wpb), dim3(kThreads), 0, st, g, P->gpart, P->tw1, P->gC);
     LAUNCH_CHECK();
-    const long nb = (long)per * (2 * 2 * g.e + 4 * g.e * g.e);
-    const int blocks = (int)std::min<long>(8192, (nb + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_gram_band, dim3(blocks), dim3(kThreads), 0, st, g, v, P->grow, P->gcol, P->gcor);
+    const int nwl = 2 * nwc * 2 * g.e;
+    hipLaunchKernelGGL(k_gram_lines, dim3((nwl + wpb - 1) / wpb), dim3(kThreads), 0, st, g, v, P->grow, P->gcol);
+    LAUNCH_CHECK();
+    const long ncor = (long)nwc * g.nc * 4 * g.e * g.e;
+    hipLaunchKernelGGL(k_gram_corners, dim3((int)std::min<long>(4096, (ncor + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, g, v, P->gcor);
     LAUNCH_CHECK();
     const long tot = (long)g.L * g.K * g.K;
     hipLaunchKernelGGL(k_gram_assemble, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
@@ -443,7 +453,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t ocrow = cv.take<double2>(nds * g.B * 2 * g.e * n1);
     const size_t occol = cv.take<double2>(nds * g.B * 2 * g.e * n2);
     const size_t ocorner = cv.take<double2>((size_t)g.B * 4 * g.e * g.e);
-    const size_t ogp = cv.take<double2>(nper * n1), ogC = cv.take<double2>(nper);
+    const size_t ogp = cv.take<double2>((size_t)L * g.npairs * n1 * g.nc), ogC = cv.take<double2>(nper);
     const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
     const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
     const size_t opr = cv.take<double>(3 * kVecBlocks), opq = cv.take<double>(P->npq);
@@ -515,7 +525,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     if (ok) {
         const void* fns[] = {(const void*)&k_col<COL_NORMAL>, (const void*)&k_col<COL_FWD>,
                              (const void*)&k_col<COL_ADJ>, (const void*)&k_col<COL_REG>,
-                             (const void*)&k_gram_col};
+                             (const void*)&k_gram_q<16>, (const void*)&k_gram_q<32>, (const void*)&k_gram_q<64>,
+                             (const void*)&k_gram_q<128>, (const void*)&k_gram_q<256>};
         for (const void* f : fns)
             if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
         if (hipFuncSetAttribute((const void*)P->band, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=

@@ -536,161 +536,6 @@ SMSM_DEV double2 band_add(const Geo& g, const BandAdd& ba, int b, int j2, int k)
 }
 
 // ---------------------------------------------------------------------------
-// Gram G_l = H_l^H H_l.  With z_d[q] = conj(x_i[q]) x_i'[(q + d) mod n],
-//   G[(i,b),(i',b+d)] = C[d] - sum_{q2 in E(b2)} Row_d[q2] - sum_{q1 in E(b1)} Col_d[q1]
-//                       + sum_{q2 in E(b2), q1 in E(b1)} z_d[q2][q1]
-// where C[d] = sum_q z_d[q] (circular correlation, evaluated in the image
-// domain as sum_nu conj(u_i) u_i' e^{-2 pi i d.nu/n}), E(b) = [0,b) U [b+n-r+1, n)
-// the r-1 coordinates a valid anchor window misses, and Row/Col the sums of
-// z_d along the band rows/columns.  Pairs i <= i' only (Hermitian).
-// ---------------------------------------------------------------------------
-// Per-column partials: part[x][l][pair][d2][d1]
-__global__ void k_gram_col(Geo g, const double2* __restrict__ h1, const double2* __restrict__ tw2,
-                           const double2* __restrict__ tw1, double2* __restrict__ part) {
-    extern __shared__ double2 sm[];
-    const int n1 = g.n1, n2 = g.n2, B = g.B, Ns = g.Ns, nc = g.nc, e = g.e;
-    const int x1 = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    double2* U = sm;               // [B][n2]
-    double2* TW2 = U + B * n2;     // [n2]
-    for (int k = tid; k < n2; k += nt) TW2[k] = tw2[k];
-    for (int idx = tid; idx < B * n2; idx += nt) {
-        const int b = idx / n2, j = idx - b * n2;
-        U[idx] = cscale(h1[((size_t)b * n1 + x1) * n2 + j], sgn_pow(j));
-    }
-    fft_batch_lds(U, n2, g.logn2, B, n2, TW2, true);
-    const double isq2 = 1.0 / sqrt((double)n2);
-    for (int idx = tid; idx < B * n2; idx += nt) {
-        const int n = idx % n2;
-        U[idx] = cscale(U[idx], isq2 * sgn_pow(n));
-    }
-    __syncthreads();
-    const int nu1 = x1 - n1 / 2;
-    const int nT = g.L * g.npairs * nc;
-    for (int idx = tid; idx < nT; idx += nt) {
-        const int d2 = idx % nc, lp = idx / nc, pair = lp % g.npairs, l = lp / g.npairs;
-        int i = 0, rem = pair;
-        while (rem >= Ns - i) { rem -= Ns - i; ++i; }
-        const int ip = i + rem;
-        const double2* ui = U + (l * Ns + i) * n2;
-        const double2* uj = U + (l * Ns + ip) * n2;
-        double2 t = cmk(0.0, 0.0);
-        for (int n = 0; n < n2; ++n) {
-            const int ph = ((d2 - e) * (n - n2 / 2)) & (n2 - 1);
-            t = cfma(cconjmul(ui[n], uj[n]), TW2[ph], t);
-        }
-        double2* out = part + (((size_t)x1 * g.L + l) * g.npairs + pair) * nc * nc + (size_t)d2 * nc;
-        for (int d1 = 0; d1 < nc; ++d1) {
-            const int ph = ((d1 - e) * nu1) & (n1 - 1);
-            out[d1] = cmul(t, tw1[ph]);
-        }
-    }
-}
-
-// C[l][pair][d] = sum_x part[x][l][pair][d] (fixed order)
-__global__ void k_gram_reduce(Geo g, const double2* __restrict__ part, double2* __restrict__ C) {
-    const int per = g.L * g.npairs * g.nc * g.nc;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= per) return;
-    double2 s = cmk(0.0, 0.0);
-    for (int x = 0; x < g.n1; ++x) s = cadd(s, part[(size_t)x * per + idx]);
-    C[idx] = s;
-}
-
-// Row/column sums of z_d on the band and the band corner values.
-//   rows[l][pair][d][qi]      qi < 2e (band row qi)
-//   cols[l][pair][d][qi]
-//   cor [l][pair][d][qi2][qi1]
-__global__ void k_gram_band(Geo g, const double2* __restrict__ x, double2* __restrict__ rows,
-                            double2* __restrict__ cols, double2* __restrict__ cor) {
-    const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
-    const long nld = (long)g.L * g.npairs * nc * nc;
-    const long n_rows = nld * e2, n_cor = nld * e2 * e2;
-    const long total = 2 * n_rows + n_cor;
-    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * blockDim.x) {
-        int kind;  // 0 rows, 1 cols, 2 corners
-        long t;
-        if (idx < n_rows) { kind = 0; t = idx; }
-        else if (idx < 2 * n_rows) { kind = 1; t = idx - n_rows; }
-        else { kind = 2; t = idx - 2 * n_rows; }
-        int qa = 0, qb = 0;
-        if (kind == 2) { qb = t % e2; t /= e2; qa = t % e2; t /= e2; }
-        else { qa = t % e2; t /= e2; }
-        const int d1 = t % nc; t /= nc;
-        const int d2 = t % nc; t /= nc;
-        const int pair = t % g.npairs; t /= g.npairs;
-        const int l = (int)t;
-        int i = 0, rem = pair;
-        while (rem >= Ns - i) { rem -= Ns - i; ++i; }
-        const int ip = i + rem;
-        const double2* xi = x + ((size_t)l * Ns + i) * n2 * n1;
-        const double2* xj = x + ((size_t)l * Ns + ip) * n2 * n1;
-        const int dd2 = d2 - e, dd1 = d1 - e;
-        const size_t o = (((size_t)l * g.npairs + pair) * nc + d2) * nc + d1;
-        if (kind == 0) {
-            const int q2 = qa < e ? qa : n2 - e2 + qa;
-            const double2* a = xi + (size_t)q2 * n1;
-            const double2* bb = xj + (size_t)((q2 + dd2) & (n2 - 1)) * n1;
-            double2 s = cmk(0.0, 0.0);
-            for (int q1 = 0; q1 < n1; ++q1) s = cfma(cconj(a[q1]), bb[(q1 + dd1) & (n1 - 1)], s);
-            rows[o * e2 + qa] = s;
-        } else if (kind == 1) {
-            const int q1 = qa < e ? qa : n1 - e2 + qa;
-            double2 s = cmk(0.0, 0.0);
-            for (int q2 = 0; q2 < n2; ++q2)
-                s = cfma(cconj(xi[(size_t)q2 * n1 + q1]),
-                         xj[(size_t)((q2 + dd2) & (n2 - 1)) * n1 + ((q1 + dd1) & (n1 - 1))], s);
-            cols[o * e2 + qa] = s;
-        } else {
-            const int q2 = qa < e ? qa : n2 - e2 + qa;
-            const int q1 = qb < e ? qb : n1 - e2 + qb;
-            cor[(o * e2 + qa) * e2 + qb] =
-                cconjmul(xi[(size_t)q2 * n1 + q1],
-                         xj[(size_t)((q2 + dd2) & (n2 - 1)) * n1 + ((q1 + dd1) & (n1 - 1))]);
-        }
-    }
-}
-
-// G[l][row][col] for row <= col (mirrored as the conjugate).
-__global__ void k_gram_assemble(Geo g, const double2* __restrict__ C, const double2* __restrict__ rows,
-                                const double2* __restrict__ cols, const double2* __restrict__ cor,
-                                double2* __restrict__ G) {
-    const int K = g.K, r = g.r, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
-    const long total = (long)g.L * K * K;
-    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int l = (int)(idx / ((long)K * K));
-    const int rc = (int)(idx - (long)l * K * K);
-    const int row = rc / K, col = rc - row * K;
-    if (row > col) return;
-    const int rr2 = r * r;
-    const int i = row / rr2, b2 = (row % rr2) / r, b1 = row % r;
-    const int ip = col / rr2, c2 = (col % rr2) / r, c1 = col % r;
-    const int pair = i * Ns - (i * (i - 1)) / 2 + (ip - i);
-    const int d2 = c2 - b2 + e, d1 = c1 - b1 + e;
-    const size_t o = (((size_t)l * g.npairs + pair) * nc + d2) * nc + d1;
-    double2 v = C[o];
-    // band indices missed by the anchor window: [0, b) and [e + b, 2e)
-    for (int q = 0; q < e2; ++q) {
-        const bool m2 = (q < b2) || (q >= e + b2);
-        const bool m1 = (q < b1) || (q >= e + b1);
-        if (m2) v = csub(v, rows[o * e2 + q]);
-        if (m1) v = csub(v, cols[o * e2 + q]);
-    }
-    for (int qa = 0; qa < e2; ++qa) {
-        if (!((qa < b2) || (qa >= e + b2))) continue;
-        for (int qb = 0; qb < e2; ++qb) {
-            if (!((qb < b1) || (qb >= e + b1))) continue;
-            v = cadd(v, cor[(o * e2 + qa) * e2 + qb]);
-        }
-    }
-    double2* Gl = G + (size_t)l * K * K;
-    if (row == col) v.y = 0.0;
-    Gl[(size_t)row * K + col] = v;
-    if (row != col) Gl[(size_t)col * K + row] = cconj(v);
-}
-
-// ---------------------------------------------------------------------------
 // CG vector kernels (fixed grid, grid-stride, per-block FP64 partials).
 // ---------------------------------------------------------------------------
 // r = b - q; partial sum |r|^2
