@@ -347,8 +347,9 @@ __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_
 #define BAND_MAX_NC 17
 __host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
 // shares of the tap rows (more workgroups for the same work: finer balance)
+#define BAND_MAX_DS 4
 __host__ __device__ inline int band_ds(int Ns, int nc) {
-    const int d = Ns >= 8 ? 2 : 12 / Ns;
+    const int d = Ns >= 8 ? 2 : (Ns >= 4 ? 3 : BAND_MAX_DS);
     return d < nc ? d : nc;
 }
 __host__ __device__ inline int band_line_items(const Geo& g) {
@@ -517,15 +518,25 @@ SMSM_DEV double2 band_add(const Geo& g, const BandAdd& ba, int b, int j2, int k)
     const int e = g.e, n1 = g.n1, n2 = g.n2;
     double2 s = cmk(0.0, 0.0);
     const bool rb = j2 < e || j2 >= n2 - e, cb = k < e || k >= n1 - e;
+    // shares are loaded with a compile-time trip count so that the loads
+    // issue together (a runtime loop waits for each one in turn)
     if (rb) {
         const int rl = j2 < e ? j2 : j2 - (n2 - 2 * e);
-        for (int part = 0; part < ba.ds; ++part)
-            s = cadd(s, ba.row[(((size_t)part * g.B + b) * 2 * e + rl) * n1 + k]);
+        double2 v[BAND_MAX_DS];
+#pragma unroll
+        for (int part = 0; part < BAND_MAX_DS; ++part)
+            v[part] = part < ba.ds ? ba.row[(((size_t)part * g.B + b) * 2 * e + rl) * n1 + k] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int part = 0; part < BAND_MAX_DS; ++part) s = cadd(s, v[part]);
     }
     if (cb) {
         const int cl = k < e ? k : k - (n1 - 2 * e);
-        for (int part = 0; part < ba.ds; ++part)
-            s = cadd(s, ba.col[(((size_t)part * g.B + b) * 2 * e + cl) * n2 + j2]);
+        double2 v[BAND_MAX_DS];
+#pragma unroll
+        for (int part = 0; part < BAND_MAX_DS; ++part)
+            v[part] = part < ba.ds ? ba.col[(((size_t)part * g.B + b) * 2 * e + cl) * n2 + j2] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int part = 0; part < BAND_MAX_DS; ++part) s = cadd(s, v[part]);
     }
     if (rb && cb) {
         const int corner = (j2 < e ? 0 : 1) | (k < e ? 0 : 2);
