@@ -743,10 +743,11 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                         + 2.0 * B * F(M)                          // pruned DFT + inverse
                         + Ns * M * L * 14.0                       // CAIPI slice sum and split
                         + 8.0 * B * n2)                           // unfold-accumulate
-                + L * Ns * Ns * nc * nc * 8.0                     // kx taps of the Hankel kernel
-                + B * n2 * Ns * (nc * 8.0 + 14.0);                // per-pixel Hankel term
+                + B * n2 * Ns * 8.0;                              // per-pixel Hankel term (Ns taps)
             f = n1 * per_col;
-            b = 2.0 * vec + L * Nc * n1 * n2 * 8.0;
+            b = 2.0 * vec + L * Nc * n1 * n2 * 8.0                 // p in, q out, coil maps (c64)
+                + L * Ns * Ns * n1 * n2 * 16.0;                    // image-domain Hankel kernel
+            (void)nc;
             break;
         }
         case SMSM_KERNEL_ROWS_INV:
