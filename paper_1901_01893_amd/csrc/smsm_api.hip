@@ -49,7 +49,7 @@ struct smsm_plan {
     void* arena = nullptr;
     size_t bytes = 0;
     // device buffers
-    float2* ST = nullptr;                     // coils [L][Nc][n1][n2]
+    double2* ST = nullptr;                    // coils [L][Nc][n1][n2], complex128
     double2 *tw1 = nullptr, *tw2 = nullptr, *twM = nullptr;
     double2 *theta = nullptr, *tau = nullptr;
     double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
@@ -436,7 +436,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t nds = band_ds(Ns, g.nc);
     const size_t nper = (size_t)L * g.npairs * g.nc * g.nc;
     Carver cv;
-    const size_t oST = cv.take<float2>((size_t)L * Nc * n1 * n2);
+    const size_t oST = cv.take<double2>((size_t)L * Nc * n1 * n2);
     const size_t otw1 = cv.take<double2>(n1), otw2 = cv.take<double2>(n2), otwM = cv.take<double2>(g.M);
     const size_t oth = cv.take<double2>((size_t)L * n2), otau = cv.take<double2>((size_t)Ns * n2);
     const size_t ox = cv.take<double2>(nvec), ob = cv.take<double2>(nvec), orr = cv.take<double2>(nvec);
@@ -464,7 +464,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
     char* base = static_cast<char*>(P->arena);
-    P->ST = (float2*)(base + oST);
+    P->ST = (double2*)(base + oST);
     P->tw1 = (double2*)(base + otw1); P->tw2 = (double2*)(base + otw2); P->twM = (double2*)(base + otwM);
     P->theta = (double2*)(base + oth); P->tau = (double2*)(base + otau);
     P->x = (double2*)(base + ox); P->b = (double2*)(base + ob); P->r = (double2*)(base + orr);
@@ -745,7 +745,7 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                         + 8.0 * B * n2)                           // unfold-accumulate
                 + B * n2 * Ns * 8.0;                              // per-pixel Hankel term (Ns taps)
             f = n1 * per_col;
-            b = 2.0 * vec + L * Nc * n1 * n2 * 8.0                 // p in, q out, coil maps (c64)
+            b = 2.0 * vec + L * Nc * n1 * n2 * 16.0                // p in, q out, coil maps (c128)
                 + L * Ns * Ns * n1 * n2 * 16.0;                    // image-domain Hankel kernel
             (void)nc;
             break;

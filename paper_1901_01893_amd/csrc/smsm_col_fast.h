@@ -50,7 +50,7 @@ SMSM_DEV double lane_xor(double v) {
     if constexpr (MASK == 1) return dpp_d<0xB1>(v);                 // quad_perm [1,0,3,2]
     else if constexpr (MASK == 2) return dpp_d<0x4E>(v);            // quad_perm [2,3,0,1]
     else if constexpr (MASK == 4) return dpp_d<0x1B>(dpp_d<0x141>(v));  // half-mirror (^7), then ^3
-    else if constexpr (MASK == 8) return dpp_d<0x141>(dpp_d<0x140>(v)); // mirror (^15), then ^7
+    else if constexpr (MASK == 8) return dpp_d<0x128>(v);           // row_ror:8 (within 16 lanes: ^8)
     else if constexpr (MASK == 16) return swz_xor16_d(v);
     else return perm_xor32_d(v);
 }
@@ -61,25 +61,26 @@ SMSM_DEV double2 lane_xor2(double2 v) {
 }
 
 // One decimation-in-frequency stage of span H on NV values:
-// upper lane (bit H clear): a + b ; lower lane: (a - b) w.
+// upper lane (bit H clear): a + b ; lower lane: (a - b) w.  At span 1 every
+// twiddle is 1 and the multiply is skipped.
 template <int H, int NV>
 SMSM_DEV void dif_stage(double2 (&v)[NV], double sgn, double2 w) {
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
         const double2 p = lane_xor2<H>(v[s]);
         const double2 d = make_double2(p.x + sgn * v[s].x, p.y + sgn * v[s].y);
-        v[s] = cmul(d, w);
+        v[s] = H == 1 ? d : cmul(d, w);
     }
 }
 
 // One decimation-in-time stage of span H with conjugated twiddle:
-// upper: u + conj(w) v ; lower: u - conj(w) v.
+// upper: u + conj(w) v ; lower: u - conj(w) v (twiddle 1 at span 1).
 template <int H, int NV>
 SMSM_DEV void dit_stage(double2 (&v)[NV], double sgn, double2 w) {
     const double2 wc = cconj(w);
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
-        const double2 t = cmul(wc, v[s]);     // upper lanes: w = 1, so t = own value
+        const double2 t = H == 1 ? v[s] : cmul(wc, v[s]);   // upper lanes: w = 1, so t = own value
         const double2 p = lane_xor2<H>(t);
         v[s] = make_double2(p.x + sgn * t.x, p.y + sgn * t.y);
     }
@@ -137,7 +138,7 @@ template <int N> struct WaveFft;
 // (waves per shot).  blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
 template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
-k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const float2* __restrict__ ST,
+k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
            const double2* __restrict__ theta, const double2* __restrict__ tw2, const double2* __restrict__ twM,
            const double2* __restrict__ Khat, int use_reg) {
     constexpr int T = NS;          // n2 = M * NS
@@ -215,7 +216,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         const int c = (it * CG + cg) * G + grp;
         const double live = (c < Nc) ? 1.0 : 0.0;
         const int cbase = lane_off + min(c, Nc - 1) * coil_stride;
-        float2 sc[L][T];
+        double2 sc[L][T];
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
@@ -225,7 +226,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         for (int s = 0; s < L; ++s) {
             double2 a = cmk(0.0, 0.0);
 #pragma unroll
-            for (int t = 0; t < T; ++t) a = cfma(c64to128(sc[s][t]), Ui[s * NS * N2 + M * t], a);
+            for (int t = 0; t < T; ++t) a = cfma(sc[s][t], Ui[s * NS * N2 + M * t], a);
             f[s] = cscale(a, live);
         }
         fft_dif<M, L>(f, w, sg);
@@ -238,7 +239,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < T; ++t) acc[s][t] = cadd(acc[s][t], cconjmul(c64to128(sc[s][t]), f[s]));
+            for (int t = 0; t < T; ++t) acc[s][t] = cadd(acc[s][t], cconjmul(sc[s][t], f[s]));
     }
 
     // ---- reduce the coil-group members of the wave

@@ -112,7 +112,7 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
 // (-1)^(Ns m) factors cancel in the normal operator).
 template <int MODE>
 __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
-                      const float2* __restrict__ ST, const double2* __restrict__ theta,
+                      const double2* __restrict__ ST, const double2* __restrict__ theta,
                       const double2* __restrict__ tau, const double2* __restrict__ tw2,
                       const double2* __restrict__ twM, const double2* __restrict__ tw1,
                       const double2* __restrict__ Kc, int use_reg, double2* __restrict__ ytil) {
@@ -153,7 +153,7 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
         for (int c = 0; c < Nc; ++c) {
             for (int idx = tid; idx < L * n2; idx += nt) {
                 const int l = idx / n2, n = idx - l * n2;
-                SC[idx] = c64to128(ST[(((size_t)l * Nc + c) * n1 + x1) * n2 + n]);
+                SC[idx] = ST[(((size_t)l * Nc + c) * n1 + x1) * n2 + n];
             }
             if (MODE == COL_ADJ) {
                 __syncthreads();
@@ -610,15 +610,15 @@ __global__ void k_zero_i32(long n, int* __restrict__ a) {
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) a[k] = 0;
 }
 
-// Coil maps c64 [L][Nc][n2][n1] -> plan layout [L][Nc][n1][n2] (x-major columns).
+// Coil maps c64 [L][Nc][n2][n1] -> plan layout c128 [L][Nc][n1][n2] (x-major columns; widened once).
 __global__ void k_transpose_coils(int n1, int n2, long nimg, const float2* __restrict__ S,
-                                  float2* __restrict__ ST) {
+                                  double2* __restrict__ ST) {
     const long total = nimg * n1 * n2;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
         const long img = k / ((long)n1 * n2);
         const int rem = (int)(k - img * n1 * n2);
         const int x = rem / n2, y = rem - x * n2;
-        ST[k] = S[img * n1 * n2 + (long)y * n1 + x];
+        ST[k] = c64to128(S[img * n1 * n2 + (long)y * n1 + x]);
     }
 }
 
