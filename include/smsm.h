@@ -162,13 +162,18 @@ smsm_status smsm_apply_normal(smsm_plan* plan, const void* x_dev, void* out_dev,
 
 /* ---- diagnostics ------------------------------------------------------- */
 
-/* Kernels of one CG iteration that smsm_launch_kernel can re-run. */
+/* Kernels that smsm_launch_kernel can re-run.  CG runs on the hybrid layout
+ * (image x, k-space ky; the kx transform is unitary): one CG iteration is
+ * COL_NORMAL, BAND_EXTRACT, BAND_CORR and CG_UPDATE (the last three only
+ * when lambda > 0 adds the band). */
 typedef enum {
-    SMSM_KERNEL_COL_NORMAL = 0,  /* per-column SENSE coil loop + image-domain Hankel term */
-    SMSM_KERNEL_ROWS_INV = 1,    /* kx inverse DFT of p, transposed write */
-    SMSM_KERNEL_ROWS_FWD = 2,    /* kx forward DFT + band correction + <p,q> partials */
-    SMSM_KERNEL_BAND_CORR = 3,   /* Hankel band correction */
-    SMSM_KERNEL_CG_UPDATE = 4    /* x, r update and |r|^2 partials */
+    SMSM_KERNEL_COL_NORMAL = 0,  /* p = r + beta p, then per column: SENSE coil loop, image-domain
+                                    Hankel term, Re <p, q> partials */
+    SMSM_KERNEL_ROWS_INV = 1,    /* kx inverse DFT, natural -> hybrid (Gram and operator entry points) */
+    SMSM_KERNEL_ROWS_FWD = 2,    /* kx forward DFT, hybrid -> natural (Gram and the solve's output) */
+    SMSM_KERNEL_BAND_CORR = 3,   /* Hankel band correction (rows hybrid, columns and corners natural) */
+    SMSM_KERNEL_CG_UPDATE = 4,   /* band injection, x and r update, |r|^2 partials */
+    SMSM_KERNEL_BAND_EXTRACT = 5 /* natural kx columns of p within 2(r-1) of the kx edges */
 } smsm_kernel_id;
 
 /*

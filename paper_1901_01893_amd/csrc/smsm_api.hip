@@ -5,6 +5,7 @@
 #include "smsm_wavefft.h"
 #include "smsm_dense.h"
 #include "smsm_gram.h"
+#include "smsm_hyb.h"
 #include "smsm.h"
 
 #include <cmath>
@@ -40,7 +41,11 @@ struct smsm_plan {
     int TRw = 8;              // rows per workgroup of the in-wave FFT row passes
     int rows_blk = 256;       // threads per workgroup of the row passes
     size_t lds_roww = 0;
-    int npq = 0;             // blocks of the forward row pass (partials of <p,q>)
+    int npc = 0;             // partials of Re <p, column pass> (one per column workgroup, or kVecBlocks)
+    int npr = 0;             // partials of |r|^2 (blocks of the hybrid vector pass)
+    int hyb_xw = 1;          // x steps per wave of the hybrid vector pass
+    dim3 hyb_grid;
+    int np_band = 0;         // padded width of the band-column extraction table
     int KP = 0;              // padded stride of the Newton-Schulz matrices
     int ntile = 0;           // 16x16 tiles per slice of the dense products
     int npmax = 0;           // partial sums per slice (max over producers)
@@ -56,10 +61,12 @@ struct smsm_plan {
     double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
     double2 *Kc = nullptr, *Khat = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
+    double2 *Dhat = nullptr, *pcol = nullptr, *prow = nullptr, *fx = nullptr, *finv = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
-    double *pr = nullptr, *pq = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
+    double *pr = nullptr, *pq = nullptr, *bpart = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr, *nsmu = nullptr;
     int *done = nullptr, *flags = nullptr;
+
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
     size_t lds_colfast = 0;
@@ -107,41 +114,33 @@ inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 dim3 vec_grid() { return dim3(kVecBlocks); }
 
 // ---- kernel chains -------------------------------------------------------
-// Row pass 1 (kx inverse DFT, transposed write) for every supported n1.
-template <int MODE>
-smsm_status rows_inv_mode(smsm_plan* P, const double2* in, double2* out, const double* prn, const double* pro,
-                          hipStream_t st) {
+// kx inverse DFT, natural [B][n2][n1] -> hybrid [B][n1][n2].
+smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
     const Geo& g = P->g;
     const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
     switch (g.n1) {
-        case 16: hipLaunchKernelGGL((k_rows_inv_w<16, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
-        case 32: hipLaunchKernelGGL((k_rows_inv_w<32, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
-        case 64: hipLaunchKernelGGL((k_rows_inv_w<64, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
-        case 128: hipLaunchKernelGGL((k_rows_inv_w<128, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
-        default: hipLaunchKernelGGL((k_rows_inv_w<256, MODE>), grid, blk, lds, st, g, in, out, P->r, P->p, prn, pro, kVecBlocks, P->tw1, P->TRw); break;
+        case 16: hipLaunchKernelGGL(k_rows_inv_w<16>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 32: hipLaunchKernelGGL(k_rows_inv_w<32>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 64: hipLaunchKernelGGL(k_rows_inv_w<64>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 128: hipLaunchKernelGGL(k_rows_inv_w<128>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        default: hipLaunchKernelGGL(k_rows_inv_w<256>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
     }
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
-smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
-    return rows_inv_mode<ROWS_PLAIN>(P, in, out, nullptr, nullptr, st);
-}
-
-// Row pass 3 (kx forward DFT from the transposed hybrid layout).
-template <bool CG, bool BAND>
-smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, const double2* pvec, hipStream_t st) {
+// kx forward DFT, hybrid -> natural.
+smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
     const Geo& g = P->g;
     const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
-    const BandAdd ba{P->crow, P->ccol, P->ccorner, band_ds(g.Ns, g.nc)};
     switch (g.n1) {
-        case 16: hipLaunchKernelGGL((k_rows_fwd_w<16, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
-        case 32: hipLaunchKernelGGL((k_rows_fwd_w<32, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
-        case 64: hipLaunchKernelGGL((k_rows_fwd_w<64, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
-        case 128: hipLaunchKernelGGL((k_rows_fwd_w<128, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
-        default: hipLaunchKernelGGL((k_rows_fwd_w<256, CG, BAND>), grid, blk, lds, st, g, in, out, ba, pvec, P->pq, P->tw1, P->TRw); break;
+        case 16: hipLaunchKernelGGL(k_rows_fwd_w<16>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 32: hipLaunchKernelGGL(k_rows_fwd_w<32>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 64: hipLaunchKernelGGL(k_rows_fwd_w<64>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        case 128: hipLaunchKernelGGL(k_rows_fwd_w<128>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
+        default: hipLaunchKernelGGL(k_rows_fwd_w<256>, grid, blk, lds, st, g, in, out, P->tw1, P->TRw); break;
     }
     LAUNCH_CHECK();
     return SMSM_OK;
@@ -159,46 +158,135 @@ const ColFastInst kColFast[] = {COLFAST(16, 2), COLFAST(16, 3), COLFAST(32, 2),
 #undef COLFAST
 
 template <int M_, int L_>
-void launch_colfast(smsm_plan* P, int use_reg, hipStream_t st) {
+void launch_colfast(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
-    hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, P->h1,
-                       P->h2, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg);
+    hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in, out,
+                       P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
 }
 
+// Column pass (hybrid in -> hybrid out).  For MODE == COL_NORMAL, `pc` may
+// ask for the fused CG direction update: the input is then pc.p, rebuilt from
+// pc.r, and Re <p, out> partials go to pc.pq (P->npc of them).
 template <int MODE>
-smsm_status col(smsm_plan* P, int use_reg, hipStream_t st) {
+smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
     if (MODE == COL_NORMAL && P->col_fast >= 0) {
         switch (P->col_fast) {
-            case 0: launch_colfast<16, 2>(P, use_reg, st); break;
-            case 1: launch_colfast<16, 3>(P, use_reg, st); break;
-            case 2: launch_colfast<32, 2>(P, use_reg, st); break;
-            case 3: launch_colfast<32, 3>(P, use_reg, st); break;
-            case 4: launch_colfast<64, 2>(P, use_reg, st); break;
-            default: launch_colfast<64, 3>(P, use_reg, st); break;
+            case 0: launch_colfast<16, 2>(P, in, out, use_reg, pc, st); break;
+            case 1: launch_colfast<16, 3>(P, in, out, use_reg, pc, st); break;
+            case 2: launch_colfast<32, 2>(P, in, out, use_reg, pc, st); break;
+            case 3: launch_colfast<32, 3>(P, in, out, use_reg, pc, st); break;
+            case 4: launch_colfast<64, 2>(P, in, out, use_reg, pc, st); break;
+            default: launch_colfast<64, 3>(P, in, out, use_reg, pc, st); break;
         }
         LAUNCH_CHECK();
         return SMSM_OK;
     }
-    hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, P->h1, P->h2,
+    const long nvec = (long)g.B * g.n1 * g.n2;
+    if (pc.mode != 0) {
+        hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p, pc.rr_new, pc.rr_old,
+                           pc.nrr, pc.mode == 1 ? 1 : 0);
+        LAUNCH_CHECK();
+        in = pc.p;
+    }
+    hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, in, out,
                        P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
+    LAUNCH_CHECK();
+    if (pc.mode != 0) {
+        hipLaunchKernelGGL(k_hyb_dot, vec_grid(), dim3(kThreads), 0, st, nvec, pc.p, out, pc.pq);
+        LAUNCH_CHECK();
+    }
+    return SMSM_OK;
+}
+
+ColCg no_cg() {
+    ColCg c{};
+    c.mode = 0;
+    return c;
+}
+
+// Natural band columns of the hybrid vector `in` (pcol), and its transposed
+// band rows (prow) unless the fast column pass already wrote them.
+smsm_status band_extract(smsm_plan* P, const double2* in, bool write_prow, hipStream_t st) {
+    const Geo& g = P->g;
+    hipLaunchKernelGGL(k_band_extract, dim3((g.n2 / 16) * (P->np_band / 16), g.B), dim3(kThreads), 0, st, g.n1,
+                       g.n2, g.e, P->np_band, in, P->fx, P->pcol, P->prow, write_prow ? 1 : 0);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
-smsm_status band_corr(smsm_plan* P, const double2* vin, hipStream_t st) {
+// Band corrections of the vector whose band copies band_extract made last;
+// Re <p, correction> partials to P->bpart.
+smsm_status band_corr(smsm_plan* P, hipStream_t st) {
     const Geo& g = P->g;
-    Geo ga = g;
-    const double2* pa = vin;
-    const double2* da = P->Dside;
-    const double2* xd = P->Dx;
-    double2 *ra = P->crow, *ca = P->ccol, *xa = P->ccorner;
-    void* args[] = {&ga, &pa, &da, &xd, &ra, &ca, &xa};
+    BandArgs a{};
+    a.g = g;
+    a.pcol = P->pcol;
+    a.prow = P->prow;
+    a.Dside = P->Dside;
+    a.Dhat = P->Dhat;
+    a.Dx = P->Dx;
+    a.crow = P->crow;
+    a.ccol = P->ccol;
+    a.ccorner = P->ccorner;
+    a.part = P->bpart;
+    void* args[] = {&a};
     if (hipLaunchKernel((const void*)P->band, dim3(band_items(g), g.L), dim3(64 * g.Ns), args, P->lds_band, st) !=
         hipSuccess)
         return SMSM_E_DEVICE;
     LAUNCH_CHECK();
     return SMSM_OK;
+}
+
+template <int MODE, bool WU, bool BAND>
+const void* hyb_update_fn_x(int xw) {
+    switch (xw) {
+        case 1: return (const void*)&k_hyb_update<MODE, 1, WU, BAND>;
+        case 2: return (const void*)&k_hyb_update<MODE, 2, WU, BAND>;
+        case 4: return (const void*)&k_hyb_update<MODE, 4, WU, BAND>;
+        default: return nullptr;
+    }
+}
+template <int MODE>
+const void* hyb_update_fn_m(int xw, bool wu, bool band) {
+    if (wu) return band ? hyb_update_fn_x<MODE, true, true>(xw) : hyb_update_fn_x<MODE, true, false>(xw);
+    return band ? hyb_update_fn_x<MODE, false, true>(xw) : hyb_update_fn_x<MODE, false, false>(xw);
+}
+const void* hyb_update_fn(int mode, int xw, bool wu, bool band) {
+    switch (mode) {
+        case 0: return hyb_update_fn_m<0>(xw, wu, band);
+        case 1: return hyb_update_fn_m<1>(xw, wu, band);
+        default: return hyb_update_fn_m<2>(xw, wu, band);
+    }
+}
+
+// Hybrid vector pass (see k_hyb_update).
+smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
+    a.g = P->g;
+    a.bi = BandInj{P->crow, P->ccol, P->ccorner, P->finv, band_ds(P->g.Ns, P->g.nc)};
+    a.nrr = P->npr;
+    a.pq = P->pq;
+    a.npq = P->npc + (a.use_band ? band_items(P->g) * P->g.L : 0);
+    const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
+    void* args[] = {&a};
+    if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(kThreads), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// Hybrid q = column pass + band correction of the hybrid vector `in`, then the
+// vector pass `a` (mode 0 or 1).
+smsm_status hyb_apply(smsm_plan* P, const double2* in, int mode_col, bool reg, HybArgs a, hipStream_t st) {
+    smsm_status s = mode_col == COL_REG ? col<COL_REG>(P, in, P->h2, 1, no_cg(), st)
+                                        : col<COL_NORMAL>(P, in, P->h2, reg ? 1 : 0, no_cg(), st);
+    if (s) return s;
+    if (reg) {
+        if ((s = band_extract(P, in, !(mode_col == COL_NORMAL && P->col_fast >= 0), st))) return s;
+        if ((s = band_corr(P, st))) return s;
+    }
+    a.h2 = P->h2;
+    a.use_band = reg ? 1 : 0;
+    return hyb_update(P, a, st);
 }
 
 smsm_status band_tables(smsm_plan* P, hipStream_t st) {
@@ -207,6 +295,10 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     const int blocks = (int)std::min<long>(8192, (total + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
                        P->Kc, P->Dside, P->Dx);
+    LAUNCH_CHECK();
+    const long nhat = (long)g.L * 2 * g.e * g.Ns * g.nc * g.Ns * g.n1;
+    hipLaunchKernelGGL(k_band_rowhat, dim3((int)std::min<long>(4096, (nhat + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, st, g, P->Dside, P->tw1, P->Dhat);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * g.Ns), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
@@ -217,41 +309,42 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     return SMSM_OK;
 }
 
-// b' = A^H y (y c64) into `out`.
-smsm_status chain_AH(smsm_plan* P, const float2* y, double2* out, hipStream_t st) {
+// A^H y (y c64) in the hybrid layout into `out`.
+smsm_status chain_AH_hyb(smsm_plan* P, const float2* y, double2* out, hipStream_t st) {
     const Geo& g = P->g;
     hipLaunchKernelGGL(k_yrows_inv, dim3(g.M / P->TRy, g.Ns * g.Nc), dim3(kThreads), P->lds_rows, st, g, y,
                        P->ytil, P->tw1, P->TRy);
     LAUNCH_CHECK();
-    smsm_status s = col<COL_ADJ>(P, 0, st);
-    if (s) return s;
-    return rows_fwd<false, false>(P, P->h2, out, nullptr, st);
+    return col<COL_ADJ>(P, nullptr, out, 0, no_cg(), st);
 }
 
-// out = N(v) (use_reg) or A^H A v.
-smsm_status chain_normal(smsm_plan* P, const double2* v, double2* out, bool use_reg, hipStream_t st) {
+// out = N(v) (mode_col COL_NORMAL, reg), (lambda/2) sum H^H(H W) (COL_REG) or
+// A^H A v (COL_NORMAL, !reg); natural in and out.
+smsm_status chain_normal(smsm_plan* P, const double2* v, double2* out, int mode_col, bool reg, hipStream_t st) {
     smsm_status s = rows_inv(P, v, P->h1, st);
     if (s) return s;
-    if (use_reg) {
-        if ((s = col<COL_NORMAL>(P, 1, st))) return s;
-        if ((s = band_corr(P, v, st))) return s;
-        return rows_fwd<false, true>(P, P->h2, out, nullptr, st);
-    }
-    if ((s = col<COL_NORMAL>(P, 0, st))) return s;
-    return rows_fwd<false, false>(P, P->h2, out, nullptr, st);
+    HybArgs a{};
+    a.mode = 0;
+    a.out = P->q;
+    if ((s = hyb_apply(P, P->h1, mode_col, reg, a, st))) return s;
+    return rows_fwd(P, P->q, out, st);
 }
 
-smsm_status chain_gram(smsm_plan* P, const double2* v, double2* G, hipStream_t st) {
+// G = Gram of the natural vector v; vh is its hybrid form, or null to compute it.
+smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double2* G, hipStream_t st) {
     const Geo& g = P->g;
-    smsm_status s = rows_inv(P, v, P->h1, st);
-    if (s) return s;
+    if (!vh) {
+        smsm_status s = rows_inv(P, v, P->h1, st);
+        if (s) return s;
+        vh = P->h1;
+    }
     const size_t lds = P->lds_gram;
     switch (g.n2) {
-        case 16: hipLaunchKernelGGL(k_gram_q<16>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
-        case 32: hipLaunchKernelGGL(k_gram_q<32>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
-        case 64: hipLaunchKernelGGL(k_gram_q<64>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
-        case 128: hipLaunchKernelGGL(k_gram_q<128>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
-        default: hipLaunchKernelGGL(k_gram_q<256>, dim3(g.n1), dim3(kThreads), lds, st, g, P->h1, P->tw2, P->gpart); break;
+        case 16: hipLaunchKernelGGL(k_gram_q<16>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
+        case 32: hipLaunchKernelGGL(k_gram_q<32>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
+        case 64: hipLaunchKernelGGL(k_gram_q<64>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
+        case 128: hipLaunchKernelGGL(k_gram_q<128>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
+        default: hipLaunchKernelGGL(k_gram_q<256>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
     }
     LAUNCH_CHECK();
     const int wpb = kThreads / 64;
@@ -405,7 +498,13 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->TRw = (n1 == 16) ? 16 : (n1 == 32 ? 8 : 4);
     P->rows_blk = std::min(256, 64 * P->TRw / std::max(1, 64 / n1));
     P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
-    P->npq = (n2 / P->TRw) * g.B;
+    {
+        const int LY = std::min(64, n2), XPS = 64 / LY;
+        P->hyb_xw = std::min(4, n1 / (4 * XPS));
+        P->hyb_grid = dim3((n2 / LY) * (n1 / (4 * P->hyb_xw * XPS)), g.B);
+        P->npr = (int)(P->hyb_grid.x * P->hyb_grid.y);
+    }
+    P->np_band = 16 * ((4 * g.e + 15) / 16);
     P->KP = dense_stride(g.K);
     P->ntile = dense_tiles(g.K);
     P->npmax = std::max(P->ntile, 2 * kPadBlocks);
@@ -419,7 +518,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
     if (max_lds <= 0) max_lds = 65536;
-    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_band > (size_t)max_lds) {
+    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_band + 16 * sizeof(double) > (size_t)max_lds) {
         delete P;
         return SMSM_E_UNSUPPORTED;
     }
@@ -450,17 +549,25 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oKh = cv.take<double2>((size_t)L * Ns * Ns * n1 * n2);
     const size_t oD = cv.take<double2>(ntab);
     const size_t oDx = cv.take<double2>(ntab * g.e);
-    const size_t ocrow = cv.take<double2>(nds * g.B * 2 * g.e * n1);
+    const size_t ocrow = cv.take<double2>((size_t)g.B * 2 * g.e * n1);
     const size_t occol = cv.take<double2>(nds * g.B * 2 * g.e * n2);
     const size_t ocorner = cv.take<double2>((size_t)g.B * 4 * g.e * g.e);
+    const size_t oDhat = cv.take<double2>((size_t)L * 2 * g.e * Ns * g.nc * Ns * n1);
+    const size_t opcol = cv.take<double2>((size_t)g.B * 4 * g.e * n2);
+    const size_t oprow = cv.take<double2>((size_t)g.B * 4 * g.e * n1);
+    const size_t ofx = cv.take<double2>((size_t)n1 * P->np_band), ofinv = cv.take<double2>((size_t)n1 * HYB_MAX_E2);
     const size_t ogp = cv.take<double2>((size_t)L * g.npairs * n1 * g.nc), ogC = cv.take<double2>(nper);
     const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
     const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
-    const size_t opr = cv.take<double>(3 * kVecBlocks), opq = cv.take<double>(P->npq);
+    P->npc = P->col_fast >= 0 ? n1 : kVecBlocks;
+    // partial sums: |r|^2 ring [3][npr]; Re <p, N p> [npc column pass | band]
+    const size_t opr = cv.take<double>(3 * (size_t)P->npr);
+    const size_t opq = cv.take<double>((size_t)P->npc + (size_t)band_items(g) * L);
     const size_t onp0 = cv.take<double>((size_t)L * P->npmax), onp1 = cv.take<double>((size_t)L * P->npmax);
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
     const size_t oei = cv.take<double>(L), onsmu = cv.take<double>((size_t)P->ns_iters * L);
     const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
+
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
     char* base = static_cast<char*>(P->arena);
@@ -475,13 +582,24 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->Z0 = (double2*)(base + oZ0); P->Z1 = (double2*)(base + oZ1); P->T = (double2*)(base + oT);
     P->Kc = (double2*)(base + oKc); P->Khat = (double2*)(base + oKh); P->Dside = (double2*)(base + oD); P->Dx = (double2*)(base + oDx);
     P->crow = (double2*)(base + ocrow); P->ccol = (double2*)(base + occol); P->ccorner = (double2*)(base + ocorner);
+    P->Dhat = (double2*)(base + oDhat); P->pcol = (double2*)(base + opcol); P->prow = (double2*)(base + oprow);
+    P->fx = (double2*)(base + ofx); P->finv = (double2*)(base + ofinv);
     P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
     P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);
     P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->part0 = (double*)(base + onp0);
+    P->bpart = P->pq + P->npc;   // band partials follow the column-pass partials
     P->part1 = (double*)(base + onp1);
     P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
     P->epsin = (double*)(base + oei); P->nsmu = (double*)(base + onsmu);
     P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
+    {   // every carved pointer must be set before any launch
+        const void* carved[] = {P->ST, P->tw1, P->tw2, P->twM, P->theta, P->tau, P->x, P->b, P->r, P->p, P->q,
+                                P->h1, P->h2, P->ytil, P->G, P->W, P->Kc, P->Khat, P->Dside, P->Dx, P->Dhat,
+                                P->crow, P->ccol, P->ccorner, P->pcol, P->prow, P->fx, P->finv, P->pr, P->pq,
+                                P->bpart, P->part0, P->part1};
+        for (const void* c : carved)
+            if (!c) { (void)hipFree(P->arena); delete P; return SMSM_E_DEVICE; }
+    }
 
     // host tables: twiddles, CAIPI phases, shot modulation
     std::vector<double2> t1, t2, tM, th((size_t)L * n2), ta((size_t)Ns * n2);
@@ -503,8 +621,30 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
             const double sg = (n & 1) ? -1.0 : 1.0;
             ta[(size_t)i * n2 + n] = make_double2(sg * w.x, sg * w.y);
         }
+    // kx transforms restricted to the band columns (see k_band_extract, BandInj)
+    const int e2 = 2 * g.e, npb = P->np_band;
+    std::vector<double2> fxh((size_t)n1 * npb, make_double2(0.0, 0.0)), fih((size_t)n1 * HYB_MAX_E2, make_double2(0.0, 0.0));
+    {
+        const long double pi2 = 2.0L * 3.14159265358979323846264338327950288L;
+        const long double isq = 1.0L / sqrtl((long double)n1);
+        auto phase = [&](int kx, int x) {   // e^{-2 pi i (kx - n1/2)(x - n1/2)/n1}, argument reduced exactly
+            const long long t = (long long)(kx - n1 / 2) * (long long)(x - n1 / 2);
+            const long long m = ((t % n1) + n1) % n1;
+            const long double a = -pi2 * (long double)m / (long double)n1;
+            return make_double2((double)(cosl(a) * isq), (double)(sinl(a) * isq));
+        };
+        for (int x = 0; x < n1; ++x) {
+            for (int c = 0; c < 2 * e2; ++c) fxh[(size_t)x * npb + c] = phase(c < e2 ? c : n1 - 2 * e2 + c, x);
+            for (int c = 0; c < e2; ++c) {
+                const double2 v = phase(c < g.e ? c : n1 - e2 + c, x);
+                fih[(size_t)x * HYB_MAX_E2 + c] = make_double2(v.x, -v.y);
+            }
+        }
+    }
     hipStream_t st = S(stream);
-    bool ok = hipMemcpyAsync(P->tw1, t1.data(), n1 * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    bool ok = hipMemcpyAsync(P->fx, fxh.data(), fxh.size() * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->finv, fih.data(), fih.size() * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->tw1, t1.data(), n1 * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(P->tw2, t2.data(), n2 * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(P->twM, tM.data(), g.M * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
     ok = ok && hipMemcpyAsync(P->theta, th.data(), th.size() * sizeof(double2), hipMemcpyHostToDevice, st) == hipSuccess;
@@ -519,22 +659,23 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)ntab, P->Dside);
         hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)(ntab * g.e), P->Dx);
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kThreads), 0, st, 4L, P->flags);
+
         ok = hipGetLastError() == hipSuccess;
     }
-    // shared-memory opt-in for the large column kernels
+    // shared-memory opt-in: each kernel's cap is the dynamic size it is launched
+    // with (static shared memory counts against the same per-block limit)
     if (ok) {
-        const void* fns[] = {(const void*)&k_col<COL_NORMAL>, (const void*)&k_col<COL_FWD>,
-                             (const void*)&k_col<COL_ADJ>, (const void*)&k_col<COL_REG>,
-                             (const void*)&k_gram_q<16>, (const void*)&k_gram_q<32>, (const void*)&k_gram_q<64>,
-                             (const void*)&k_gram_q<128>, (const void*)&k_gram_q<256>};
-        for (const void* f : fns)
-            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess) ok = false;
-        if (hipFuncSetAttribute((const void*)P->band, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
-            hipSuccess)
-            ok = false;
-        if (P->col_fast >= 0 &&
-            hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) !=
-                hipSuccess)
+        struct Opt { const void* f; size_t bytes; };
+        const Opt opts[] = {{(const void*)&k_col<COL_NORMAL>, P->lds_col}, {(const void*)&k_col<COL_FWD>, P->lds_col},
+                            {(const void*)&k_col<COL_ADJ>, P->lds_col}, {(const void*)&k_col<COL_REG>, P->lds_col},
+                            {(const void*)&k_gram_q<16>, P->lds_gram}, {(const void*)&k_gram_q<32>, P->lds_gram},
+                            {(const void*)&k_gram_q<64>, P->lds_gram}, {(const void*)&k_gram_q<128>, P->lds_gram},
+                            {(const void*)&k_gram_q<256>, P->lds_gram}, {(const void*)P->band, P->lds_band}};
+        for (const Opt& o : opts)
+            if (hipFuncSetAttribute(o.f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)o.bytes) != hipSuccess)
+                ok = false;
+        if (P->col_fast >= 0 && hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                    (int)P->lds_colfast) != hipSuccess)
             ok = false;
     }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
@@ -583,46 +724,62 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
     const bool reg = prm.lambda > 0.0;
     smsm_status s;
 
-    if ((s = chain_AH(P, (const float2*)y_dev, P->b, st))) return s;
-    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->b, P->x);
+    // CG runs on the hybrid layout (x image, ky k-space); the kx transform is
+    // unitary, so iterates, inner products and step lengths are those of the
+    // natural-domain CG.
+    const long nvec_l = (long)nvec;
+    if ((s = chain_AH_hyb(P, (const float2*)y_dev, P->b, st))) return s;
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, nvec_l, P->b, P->x);
     LAUNCH_CHECK();
-    if (reg) {
-        if ((s = chain_gram(P, P->x, P->G, st))) return s;
-        if ((s = chain_lmax(P, P->G, P->sigma, st))) return s;
-    }
-    double* PR[3] = {P->pr, P->pr + kVecBlocks, P->pr + 2 * kVecBlocks};
+    double* RR[3] = {P->pr, P->pr + P->npr, P->pr + 2 * P->npr};   // |r|^2 partials of the last three residuals
     for (int k = 0; k < prm.n_irls; ++k) {
         if (reg) {
-            if (k > 0 && (s = chain_gram(P, P->x, P->G, st))) return s;
+            // Gram of the natural iterate (the hybrid one feeds its column pass)
+            if ((s = rows_fwd(P, P->x, P->q, st))) return s;
+            if ((s = chain_gram(P, P->q, P->x, P->G, st))) return s;
+            if (k == 0 && (s = chain_lmax(P, P->G, P->sigma, st))) return s;
             const double frac = std::max(prm.eps_frac * std::pow(prm.eps_decay, -(double)k), prm.eps_floor_frac);
             if ((s = chain_weights(P, P->G, P->sigma, frac, st))) return s;
             if ((s = band_tables(P, st))) return s;
         }
-        if ((s = chain_normal(P, P->x, P->q, reg, st))) return s;
-        hipLaunchKernelGGL(k_cg_init, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->b, P->q, P->r, PR[0]);
-        LAUNCH_CHECK();
+        HybArgs a0{};
+        a0.mode = 1;
+        a0.bvec = P->b;
+        a0.out = P->r;
+        a0.part = RR[0];
+        if ((s = hyb_apply(P, P->x, COL_NORMAL, reg, a0, st))) return s;
         for (int j = 0; j < prm.n_cg; ++j) {
-            if (j == 0)
-                s = rows_inv_mode<ROWS_CG_FIRST>(P, nullptr, P->h1, nullptr, nullptr, st);
-            else
-                s = rows_inv_mode<ROWS_CG_UPDATE>(P, nullptr, P->h1, PR[j % 3], PR[(j + 2) % 3], st);
-            if (s) return s;
-            if ((s = col<COL_NORMAL>(P, reg ? 1 : 0, st))) return s;
+            ColCg pc{};
+            pc.r = P->r;
+            pc.p = P->p;
+            pc.rr_new = RR[j % 3];
+            pc.rr_old = RR[(j + 2) % 3];
+            pc.nrr = P->npr;
+            pc.mode = j == 0 ? 1 : 2;
+            pc.pq = P->pq;
+            if ((s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st))) return s;
             if (reg) {
-                if ((s = band_corr(P, P->p, st))) return s;
-                if ((s = rows_fwd<true, true>(P, P->h2, P->q, P->p, st))) return s;
-            } else {
-                if ((s = rows_fwd<true, false>(P, P->h2, P->q, P->p, st))) return s;
+                if ((s = band_extract(P, P->p, P->col_fast < 0, st))) return s;
+                if ((s = band_corr(P, st))) return s;
             }
-            hipLaunchKernelGGL(k_cg_update, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, P->p, P->r,
-                               P->q, PR[j % 3], kVecBlocks, P->pq, P->npq, PR[(j + 1) % 3], P->flags);
-            LAUNCH_CHECK();
+            HybArgs a{};
+            a.mode = 2;
+            a.use_band = reg ? 1 : 0;
+            a.h2 = P->h2;
+            a.x = P->x;
+            a.p = P->p;
+            a.r = P->r;
+            a.rr_cur = RR[j % 3];
+            a.part = RR[(j + 1) % 3];
+            a.flags = P->flags;
+            if ((s = hyb_update(P, a, st))) return s;
         }
     }
+    if ((s = rows_fwd(P, P->x, P->q, st))) return s;
     if (c128)
-        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, (double2*)x_dev);
+        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, nvec_l, P->q, (double2*)x_dev);
     else
-        hipLaunchKernelGGL(k_to_c64, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, (float2*)x_dev);
+        hipLaunchKernelGGL(k_to_c64, vec_grid(), dim3(kThreads), 0, st, nvec_l, P->q, (float2*)x_dev);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -648,7 +805,7 @@ smsm_status smsm_apply_A(smsm_plan* P, const void* x_dev, void* y_dev, void* str
     LAUNCH_CHECK();
     smsm_status s = rows_inv(P, (const double2*)x_dev, P->h1, st);
     if (s) return s;
-    if ((s = col<COL_FWD>(P, 0, st))) return s;
+    if ((s = col<COL_FWD>(P, P->h1, P->h2, 0, no_cg(), st))) return s;
     hipLaunchKernelGGL(k_yrows_fwd, dim3(g.M / P->TRy, g.Ns * g.Nc), dim3(kThreads), P->lds_rows, st, g,
                        P->ytil, (double2*)y_dev, P->tw1, P->TRy);
     LAUNCH_CHECK();
@@ -658,19 +815,22 @@ smsm_status smsm_apply_A(smsm_plan* P, const void* x_dev, void* y_dev, void* str
 smsm_status smsm_apply_AH(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
     if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
-    return chain_AH(P, (const float2*)y_dev, (double2*)x_dev, S(stream));
+    hipStream_t st = S(stream);
+    smsm_status s = chain_AH_hyb(P, (const float2*)y_dev, P->h2, st);
+    if (s) return s;
+    return rows_fwd(P, P->h2, (double2*)x_dev, st);
 }
 
 smsm_status smsm_apply_AHA(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
-    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, false, S(stream));
+    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, false, S(stream));
 }
 
 smsm_status smsm_gram(smsm_plan* P, const void* x_dev, void* g_dev, void* stream) {
     if (!P || !x_dev || !g_dev) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
-    return chain_gram(P, (const double2*)x_dev, (double2*)g_dev, S(stream));
+    return chain_gram(P, (const double2*)x_dev, nullptr, (double2*)g_dev, S(stream));
 }
 
 smsm_status smsm_weights(smsm_plan* P, const void* g_dev, const double* eps, void* w_dev, void* stream) {
@@ -709,19 +869,14 @@ smsm_status smsm_apply_reg(smsm_plan* P, const void* x_dev, void* out_dev, void*
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
-    hipStream_t st = S(stream);
-    smsm_status s = rows_inv(P, (const double2*)x_dev, P->h1, st);
-    if (s) return s;
-    if ((s = col<COL_REG>(P, 1, st))) return s;
-    if ((s = band_corr(P, (const double2*)x_dev, st))) return s;
-    return rows_fwd<false, true>(P, P->h2, (double2*)out_dev, nullptr, st);
+    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_REG, true, S(stream));
 }
 
 smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
-    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, true, S(stream));
+    return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, true, S(stream));
 }
 
 }  // extern "C"
@@ -730,8 +885,9 @@ namespace {
 
 // Algorithmic FP64 flops and compulsory bytes of one launch (see smsm.h).
 void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
-    const double n1 = g.n1, n2 = g.n2, B = g.B, L = g.L, Ns = g.Ns, Nc = g.Nc, M = g.M, nc = g.nc;
+    const double n1 = g.n1, n2 = g.n2, B = g.B, L = g.L, Ns = g.Ns, Nc = g.Nc, M = g.M, nc = g.nc, e = g.e;
     const double vec = B * n1 * n2 * 16.0;               // one c128 vector
+    const double ds = band_ds(g.Ns, g.nc);
     auto F = [](double n) { return 5.0 * n * std::log2(n); };
     double f = 0.0, b = 0.0;
     switch (id) {
@@ -743,36 +899,38 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                         + 2.0 * B * F(M)                          // pruned DFT + inverse
                         + Ns * M * L * 14.0                       // CAIPI slice sum and split
                         + 8.0 * B * n2)                           // unfold-accumulate
-                + B * n2 * Ns * 8.0;                              // per-pixel Hankel term (Ns taps)
+                + B * n2 * Ns * 8.0                               // per-pixel Hankel term (Ns taps)
+                + B * n2 * 8.0;                                   // p = r + beta p and Re <p, q>
             f = n1 * per_col;
-            b = 2.0 * vec + L * Nc * n1 * n2 * 16.0                // p in, q out, coil maps (c128)
+            b = 4.0 * vec + L * Nc * n1 * n2 * 16.0                // r, p in; p, q out; coil maps (c128)
                 + L * Ns * Ns * n1 * n2 * 16.0;                    // image-domain Hankel kernel
-            (void)nc;
             break;
         }
         case SMSM_KERNEL_ROWS_INV:
+        case SMSM_KERNEL_ROWS_FWD:
             f = B * n2 * F(n1);
             b = 2.0 * vec;
             break;
-        case SMSM_KERNEL_ROWS_FWD:
-            f = B * n2 * F(n1) + B * n1 * n2 * 4.0;
-            b = 3.0 * vec + band_ds(g.Ns, g.nc) * B * 2.0 * g.e * (n1 + n2) * 16.0;
-            break;
         case SMSM_KERNEL_BAND_CORR: {
-            const double e = g.e;
-            f = 8.0 * B * (2.0 * e * (n1 + n2) + 4.0 * e * e) * Ns * nc * nc;
-            b = L * (4.0 * e + 4.0 * e * e) * Ns * Ns * nc * nc * 16.0 +
-                band_ds(g.Ns, g.nc) * B * 2.0 * e * (n1 + n2) * 16.0 +
-                B * (n1 * n2 - (n1 - 4.0 * e) * (n2 - 4.0 * e)) * 16.0;
+            f = 8.0 * B * (2.0 * e * n2 * nc * nc + 2.0 * e * n1 * nc + 4.0 * e * e * nc * nc) * Ns;
+            b = L * (2.0 * e + 4.0 * e * e) * Ns * Ns * nc * nc * 16.0     // column-side and corner tables
+                + L * 2.0 * e * Ns * nc * Ns * n1 * 16.0                    // transformed row tables
+                + B * 4.0 * e * n2 * 16.0 + B * 2.0 * e * nc * n1 * 16.0    // band columns, rows of p
+                + B * (ds * 2.0 * e * n2 + 2.0 * e * n1 + 4.0 * e * e) * 16.0;   // corrections out
             break;
         }
         case SMSM_KERNEL_CG_UPDATE:
-            f = B * n1 * n2 * 14.0;
-            b = 6.0 * vec;
+            f = B * n1 * n2 * (14.0 + 8.0 * 2.0 * e);
+            b = 6.0 * vec + B * (ds * 2.0 * e * n2 + 2.0 * e * n1 + 4.0 * e * e) * 16.0;
+            break;
+        case SMSM_KERNEL_BAND_EXTRACT:
+            f = 8.0 * B * n1 * n2 * 4.0 * e;
+            b = vec + B * 4.0 * e * n2 * 16.0;
             break;
         default:
             break;
     }
+    (void)nc;
     *flops = f;
     *bytes = b;
 }
@@ -782,33 +940,49 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
 extern "C" {
 
 smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* bytes) {
-    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_CG_UPDATE) return SMSM_E_INVALID;
+    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
     kernel_cost(P->g, id, flops, bytes);
     return SMSM_OK;
 }
 
 smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
-    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_CG_UPDATE) return SMSM_E_INVALID;
+    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
-    const Geo& g = P->g;
-    const size_t nvec = (size_t)g.L * g.Ns * g.n2 * g.n1;
     const bool reg = P->prm.lambda > 0.0 && P->have_weights;
     for (int k = 0; k < reps; ++k) {
         smsm_status s = SMSM_OK;
         switch (id) {
-            case SMSM_KERNEL_COL_NORMAL: s = col<COL_NORMAL>(P, reg ? 1 : 0, st); break;
-            case SMSM_KERNEL_ROWS_INV: s = rows_inv(P, P->p, P->h1, st); break;
-            case SMSM_KERNEL_ROWS_FWD:
-                s = reg ? rows_fwd<true, true>(P, P->h2, P->q, P->p, st)
-                        : rows_fwd<true, false>(P, P->h2, P->q, P->p, st);
+            case SMSM_KERNEL_COL_NORMAL: {
+                ColCg pc{};
+                pc.r = P->r;
+                pc.p = P->p;
+                pc.rr_new = P->pr + P->npr;
+                pc.rr_old = P->pr;
+                pc.nrr = P->npr;
+                pc.mode = 2;
+                pc.pq = P->pq;
+                s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st);
                 break;
-            case SMSM_KERNEL_BAND_CORR: s = band_corr(P, P->p, st); break;
-            case SMSM_KERNEL_CG_UPDATE:
-                hipLaunchKernelGGL(k_cg_update, vec_grid(), dim3(kThreads), 0, st, (long)nvec, P->x, P->p, P->r,
-                                   P->q, P->pr, kVecBlocks, P->pq, P->npq, P->pr + kVecBlocks, P->flags);
-                LAUNCH_CHECK();
+            }
+            case SMSM_KERNEL_ROWS_INV: s = rows_inv(P, P->q, P->h1, st); break;
+            case SMSM_KERNEL_ROWS_FWD: s = rows_fwd(P, P->x, P->q, st); break;
+            case SMSM_KERNEL_BAND_CORR: s = band_corr(P, st); break;
+            case SMSM_KERNEL_BAND_EXTRACT: s = band_extract(P, P->p, P->col_fast < 0, st); break;
+            case SMSM_KERNEL_CG_UPDATE: {
+                HybArgs a{};
+                a.mode = 2;
+                a.use_band = reg ? 1 : 0;
+                a.h2 = P->h2;
+                a.x = P->x;
+                a.p = P->p;
+                a.r = P->r;
+                a.rr_cur = P->pr;
+                a.part = P->pr + 2 * P->npr;
+                a.flags = P->flags;
+                s = hyb_update(P, a, st);
                 break;
+            }
         }
         if (s) return s;
     }

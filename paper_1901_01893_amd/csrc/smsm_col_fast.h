@@ -133,14 +133,32 @@ __global__ void k_hankel_image(Geo g, const double2* __restrict__ Kc, const doub
 
 template <int N> struct WaveFft;
 
+// Optional CG direction update fused into the column pass (hybrid layout):
+// mode 0: the input is h1; mode 1: p = r; mode 2: p = r + beta p with
+// beta = sum(rr_new[0..nrr)) / sum(rr_old[0..nrr)) (0 when the old sum is 0).
+// In modes 1 and 2 the new p is written back and the input is p; each
+// workgroup also stores Re <p, output> of its column in pq[blockIdx.x],
+// evaluated in the image domain (the ky transforms are unitary).
+struct ColCg {
+    const double2* r;
+    double2* p;
+    const double* rr_new;
+    const double* rr_old;
+    int nrr;
+    int mode;
+    double* pq;
+};
+
 // Normal operator column pass; same input/output contract as k_col<COL_NORMAL>.
+// Also writes prow[b][j][x] (the input's rows within 2e of the ky edges, j as
+// in k_band_extract) for the band kernel.
 // Template: M = n2/Ns (folded length), L slices, NS shots, CG coil groups
 // (waves per shot).  blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
 template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
            const double2* __restrict__ theta, const double2* __restrict__ tw2, const double2* __restrict__ twM,
-           const double2* __restrict__ Khat, int use_reg) {
+           const double2* __restrict__ Khat, int use_reg, ColCg pc, double2* __restrict__ prow) {
     constexpr int T = NS;          // n2 = M * NS
     constexpr int N2 = M * NS;
     constexpr int G = 64 / M;      // coils processed side by side in one wave
@@ -161,6 +179,12 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     const double isq2 = 1.0 / sqrt((double)N2);
 
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
+    double beta = 0.0;
+    if (pc.mode == 2) {
+        double rn, ro;
+        sum_partials2(pc.rr_new, pc.nrr, pc.rr_old, pc.nrr, rn, ro, (double*)ACC);
+        beta = ro > 0.0 ? rn / ro : 0.0;
+    }
     __syncthreads();
 
     // ---- column image: U[b][n] = tau_i[n] u_b[n], u_b = centred inverse DFT along ky of h1 column
@@ -168,12 +192,23 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         FC fc;
         fc.setup(TW2, lane);
         const int ib = b % NS;
-        const double2* src = h1 + ((size_t)b * n1 + x1) * N2;
+        const size_t col0 = ((size_t)b * n1 + x1) * N2;
         double2 v[RC];
 #pragma unroll
         for (int t = 0; t < RC; ++t) {
             const int k = fc.m + 64 * t;
-            v[t] = cscale(src[k], sgn_pow(k));
+            double2 val;
+            if (pc.mode == 0) {
+                val = h1[col0 + k];
+            } else {
+                val = pc.r[col0 + k];
+                if (pc.mode == 2) val = cadd(val, cscale(pc.p[col0 + k], beta));
+                pc.p[col0 + k] = val;
+            }
+            v[t] = cscale(val, sgn_pow(k));
+            // transposed copy of the input rows within 2e of the ky edges
+            if (k < 2 * g.e || k >= N2 - 2 * g.e)
+                prow[((size_t)b * 4 * g.e + (k < 2 * g.e ? k : k - (N2 - 4 * g.e))) * n1 + x1] = val;
         }
         fc.template run<true>(v);
 #pragma unroll
@@ -286,6 +321,20 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
                 }
         }
         __syncthreads();
+    }
+    // ---- Re <p, output> in the image domain: sum conj(u) acc with u = conj(tau') U
+    if (pc.mode != 0) {
+        double dot = 0.0;
+        for (int idx = tid; idx < B * N2; idx += nt) {
+            const int b = idx / N2, n = idx - b * N2;
+            const double2 ta = cscale(TW2[((b % NS) * n) & (N2 - 1)], sgn_pow(n));
+            const double2 cu = cmul(ta, cconj(U[idx]));   // conj(u)
+            const double2 a = ACC[idx];
+            dot += cu.x * a.x - cu.y * a.y;
+        }
+        double* red = (double*)(sm + colfast_lds_total(g) - 16);
+        dot = block_sum(dot, red);
+        if (tid == 0) pc.pq[blockIdx.x] = dot;
     }
     // ---- centred forward DFT along ky of every sequence, back into ACC, then store
     for (int b = wave; b < B; b += NW) {

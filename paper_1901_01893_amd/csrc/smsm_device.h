@@ -57,6 +57,49 @@ SMSM_DEV double sum_partials(const double* __restrict__ part, int n, double* scr
     return block_sum(v, scratch);
 }
 
+// Sums of two ranges of per-block partials, a[0..na) and b[0..nb), each in
+// a fixed order (deterministic), with every load of a thread issued before the
+// first add (8 slots per range per pass).  Every thread must call it; the
+// results are valid in all threads.  scratch: 2 * blockDim.x/64 doubles.
+SMSM_DEV void sum_partials2(const double* __restrict__ a, int na, const double* __restrict__ b, int nb,
+                            double& sa, double& sb, double* scratch) {
+    const int nt = blockDim.x, n = na > nb ? na : nb;
+    double ta = 0.0, tb = 0.0;
+    for (int base = threadIdx.x; base < n; base += 8 * nt) {
+        double va[8], vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = base + u * nt;
+            va[u] = a[k < na ? k : na - 1];
+            vb[u] = b[k < nb ? k : nb - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = base + u * nt;
+            ta += k < na ? va[u] : 0.0;
+            tb += k < nb ? vb[u] : 0.0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ta += __shfl_xor(ta, off);
+        tb += __shfl_xor(tb, off);
+    }
+    const int lane = threadIdx.x & 63, warp = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        scratch[warp] = ta;
+        scratch[nw + warp] = tb;
+    }
+    __syncthreads();
+    sa = 0.0;
+    sb = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        sa += scratch[w];
+        sb += scratch[nw + w];
+    }
+    __syncthreads();
+}
+
 // Batched in-place FFT in shared memory.
 // nb sequences of length n = 2^logn; sequence b occupies buf[b*stride + j].
 // Forward computes X[k] = sum_j x[j] e^{-2 pi i jk/n}; inverse uses e^{+...}

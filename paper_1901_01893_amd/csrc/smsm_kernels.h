@@ -28,7 +28,6 @@ struct Geo {
 // ---------------------------------------------------------------------------
 // Row passes
 // ---------------------------------------------------------------------------
-enum { ROWS_PLAIN = 0, ROWS_CG_UPDATE = 1, ROWS_CG_FIRST = 2 };
 
 // ytil[i][c][x][m] = centred inverse DFT along kx of y[i][c][i + Ns m][:] at x
 // (only the lines shot i acquires).  y is complex64.
@@ -328,56 +327,93 @@ __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_
     }
 }
 
-// Band kernel: one workgroup (64 Ns threads) per (work item, slice l = blockIdx.y).
+// Band kernel, working on p in the hybrid layout (x image, ky k-space):
+// one workgroup (64 Ns threads) per (work item, slice l = blockIdx.y).
 //
-// Line items: BAND_SEG consecutive pixels of one band row (all n1 columns) or
-// one band column (all n2 rows) and a share of the 2r-1 tap rows across the
-// line (band_ds shares; the row pass sums the shares in order).  Wave w takes
-// input shot i = w, lane = pixel, and accumulates all Ns output shots; the
-// side table is wave-uniform and read through the scalar cache; the p patch
-// (tap rows of the share x BAND_SEG+2e positions, wrapped) is staged in
-// shared memory along the line.  The Ns wave partials are summed in order.
-// Output: row[share][l Ns + i'][row line][t1], col[share][l Ns + i'][column line][t2],
-// lines numbered 0..e-1 from the low edge and e..2e-1 for the high one.
+// Row items (2e band rows x chunks of 64 x): along kx a band-row correction
+// is a circular convolution of rows of p, which the kx inverse transform
+// turns into a product: with Dhat[l][row][i][d2][i'][x] the x-transform of
+// the row side table over d1 (built once per IRLS step),
+//   crow[l Ns + i'][row][x] = sum_{i,d2} Dhat[..][x] p_i[x][ky_row + d2 - e],
+// the correction of that band row already in the hybrid layout, with p read
+// from its transposed band-row copy prow (contiguous x).  Thread = (output
+// shot i' = wave, x = lane).
+//
+// Column items: BAND_SEG consecutive ky of one band column (all n2 rows) and
+// a share of the 2r-1 tap columns (band_ds shares, summed where the
+// correction is injected).  The natural columns of p within 2e of the kx
+// edges (pcol, from k_band_extract) are staged in shared memory; wave w
+// takes input shot i = w, lane = pixel, and accumulates all Ns output
+// shots, with the column side table wave-uniform through the scalar cache.
+//   ccol[share][l Ns + i'][column line][ky]   (natural, band column)
 //
 // Corner items: one corner pixel q; the Ns (2r-1)^2 taps of its cross table
 // are spread over the threads (all output shots per thread), then summed by
-// fixed-order block reductions: corner[l Ns + i'][corner pixel].
+// fixed-order block reductions: ccorner[l Ns + i'][corner pixel] (natural).
+//
+// Every workgroup also writes its share of Re <p, correction> (the band part
+// of Re <p, N p>) to part[blockIdx.y * gridDim.x + blockIdx.x].
 #define BAND_SEG 64
 #define BAND_MAX_NC 17
-__host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
-// shares of the tap rows (more workgroups for the same work: finer balance)
 #define BAND_MAX_DS 4
+#define BAND_STAGE 8      // staged patch entries per thread and pass
+__host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
+// shares of the tap columns (more workgroups for the same work: finer balance)
 __host__ __device__ inline int band_ds(int Ns, int nc) {
     const int d = Ns >= 8 ? 2 : (Ns >= 4 ? 3 : BAND_MAX_DS);
     return d < nc ? d : nc;
 }
-__host__ __device__ inline int band_line_items(const Geo& g) {
-    return 2 * g.e * (band_segs(g.n1) + band_segs(g.n2)) * band_ds(g.Ns, g.nc);
+__host__ __device__ inline int band_col_items(const Geo& g) {
+    return 2 * g.e * band_segs(g.n2) * band_ds(g.Ns, g.nc);
 }
-__host__ __device__ inline int band_items(const Geo& g) { return band_line_items(g) + 4 * g.e * g.e; }
+__host__ __device__ inline int band_row_items(const Geo& g) { return 2 * g.e * ((g.n1 + 63) / 64); }
+__host__ __device__ inline int band_items(const Geo& g) {
+    return band_col_items(g) + band_row_items(g) + 4 * g.e * g.e;
+}
+// shared memory of a column item: the p patch, then the share's side-table
+// slice (reused for the cross-shot reduction afterwards)
+__host__ __device__ inline size_t band_patch_len(const Geo& g) {
+    const int ds = band_ds(g.Ns, g.nc);
+    return (size_t)g.Ns * ((g.nc + ds - 1) / ds) * (BAND_SEG + 2 * g.e);
+}
 __host__ __device__ inline size_t band_lds_bytes(const Geo& g) {
     const int ds = band_ds(g.Ns, g.nc);
-    const size_t patch = (size_t)g.Ns * ((g.nc + ds - 1) / ds) * (BAND_SEG + 2 * g.e);
+    const size_t tab = (size_t)g.Ns * g.nc * ((g.nc + ds - 1) / ds) * g.Ns;
     const size_t red = (size_t)g.Ns * g.Ns * BAND_SEG;
-    const size_t m = patch > red ? patch : red;
+    const size_t m = band_patch_len(g) + tab > red ? band_patch_len(g) + tab : red;
     return (m > 8 ? m : 8) * sizeof(double2);
 }
+// slot of line k (within 2e of an edge of a length-n axis) in the band copies
+// pcol (natural kx columns) and prow (hybrid ky rows)
+SMSM_HD inline int band_pcol(int k, int n, int e) { return k < 2 * e ? k : k - (n - 4 * e); }
 
-template <int NC, int NS, bool HORIZ>
-SMSM_DEV void band_line_sum(const double2* __restrict__ Pw, int PP, const double2* __restrict__ Dw, int dl0,
-                            int dl1, double2 (&acc)[NS]) {
-    // Pw: patch of this wave's shot at (tap row dl0, this lane's pixel);
-    // Dw: side table of this line and shot, [d2][d1][i'] (wave-uniform)
-    for (int dl = dl0; dl < dl1; ++dl) {
-        const double2* Pr = Pw + (dl - dl0) * PP;
+struct BandArgs {
+    Geo g;
+    const double2* pcol;    // natural columns of p within 2e of the kx edges [B][4e][n2]
+    const double2* prow;    // hybrid rows of p within 2e of the ky edges, transposed [B][4e][n1]
+    const double2* Dside;   // side tables (the column sides 2, 3 are used here)
+    const double2* Dhat;    // row tables transformed along x [L][2e][Ns][nc][Ns][n1]
+    const double2* Dx;      // corner cross tables
+    double2* crow;          // [B][2e][n1], hybrid
+    double2* ccol;          // [ds][B][2e][n2], natural
+    double2* ccorner;       // [B][4e^2], natural
+    double* part;           // Re <p, correction> per workgroup
+};
+
+template <int NC, int NS>
+SMSM_DEV void band_col_sum(const double2* __restrict__ Pw, int PP, const double2* __restrict__ Dl, int nr,
+                           double2 (&acc)[NS]) {
+    // Pw: patch of this wave's shot at (first tap column of the share, this
+    // lane's pixel); Dl: the share's side-table slice of this wave's shot in
+    // shared memory, [d2][d1 - dl0][i'] (wave-uniform reads)
+    for (int rr = 0; rr < nr; ++rr) {
+        const double2* Pr = Pw + rr * PP;
         double2 pv[NC];
 #pragma unroll
         for (int dp = 0; dp < NC; ++dp) pv[dp] = Pr[dp];
 #pragma unroll
         for (int dp = 0; dp < NC; ++dp) {
-            const int t = HORIZ ? dl * NC + dp : dp * NC + dl;   // [d2][d1]
-            const double2* dd = Dw + t * NS;
+            const double2* dd = Dl + (dp * nr + rr) * NS;
 #pragma unroll
             for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(dd[ip], pv[dp], acc[ip]);
         }
@@ -385,112 +421,165 @@ SMSM_DEV void band_line_sum(const double2* __restrict__ Pw, int PP, const double
 }
 
 template <int NC, int NS>
-__global__ void __launch_bounds__(64 * NS)
-k_band_line(Geo g, const double2* __restrict__ p, const double2* __restrict__ Dside,
-            const double2* __restrict__ Dx, double2* __restrict__ crow, double2* __restrict__ ccol,
-            double2* __restrict__ ccorner) {
+__global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
     extern __shared__ double2 sm[];
-    const int e = g.e, r = g.r, n1 = g.n1, n2 = g.n2, K = g.K;
+    __shared__ double red[16];
+    const Geo& g = a.g;
+    const int e = g.e, r = g.r, n1 = g.n1, n2 = g.n2, B = g.B;
     const int l = blockIdx.y, item = blockIdx.x;
-    const double2* pl = p + (size_t)l * NS * n2 * n1;
-    if (item < band_line_items(g)) {
+    const int ncol = band_col_items(g), nrow = band_row_items(g);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double contrib = 0.0;
+    if (item < ncol) {
         const int ds = band_ds(NS, NC);
-        const int nsr = band_segs(n1), nrow = 2 * e * nsr * ds;
-        const bool horiz = item < nrow;
-        int it = horiz ? item : item - nrow;
-        const int nseg = horiz ? nsr : band_segs(n2);
+        const int nseg = band_segs(n2);
+        int it = item;
         const int part = it % ds;
         it /= ds;
-        const int seg = it % nseg, line = it / nseg;          // line 0..2e-1
+        const int seg = it % nseg, line = it / nseg;          // column line 0..2e-1
         const int delta = line < e ? line : line - e;
-        const int side = (horiz ? 0 : 2) + (line < e ? 0 : 1);
-        const int len = horiz ? n1 : n2, span = horiz ? n2 : n1;
-        const int lc = line < e ? delta : span - e + delta;     // line coordinate
+        const int side = 2 + (line < e ? 0 : 1);
+        const int lc = line < e ? delta : n1 - e + delta;     // kx of the line
         const int pos0 = seg * BAND_SEG;
-        const int npos = min(BAND_SEG, len - pos0);
+        const int npos = min(BAND_SEG, n2 - pos0);
         const int dl0 = part * NC / ds, dl1 = (part + 1) * NC / ds, nr = dl1 - dl0;
         const int PP = BAND_SEG + 2 * e;
-        // stage p: sm[i][rr][pp] = p_i at line coordinate lc - e + dl0 + rr, position pos0 - e + pp
+        // p at this thread's output (output shot = wave, pixel = lane), for Re <p, correction>
+        const double2 pout = a.pcol[((size_t)(l * NS + w) * 4 * e + band_pcol(lc, n1, e)) * n2 + pos0 +
+                                    min(lane, npos - 1)];
+        // stage sm[i][rr][pp] = p_i at kx = lc - e + dl0 + rr, ky = pos0 - e + pp
+        // (wrapped); at most BAND_STAGE entries per thread, all loads issued
+        // together (threads past the end reload the last entry)
         const int tot = NS * nr * PP;
-        if (horiz) {
-            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+        for (int base = threadIdx.x; base < tot; base += BAND_STAGE * blockDim.x) {
+            double2 v[BAND_STAGE];
+#pragma unroll
+            for (int u = 0; u < BAND_STAGE; ++u) {
+                const int i0 = base + u * blockDim.x, idx = i0 < tot ? i0 : tot - 1;
                 const int i = idx / (nr * PP), rem = idx - i * nr * PP;
                 const int rr = rem / PP, pp = rem - rr * PP;
-                const int q2 = (lc - e + dl0 + rr) & (n2 - 1), q1 = (pos0 - e + pp) & (n1 - 1);
-                sm[idx] = pl[((size_t)i * n2 + q2) * n1 + q1];
+                const int kx = (lc - e + dl0 + rr) & (n1 - 1), ky = (pos0 - e + pp) & (n2 - 1);
+                v[u] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
             }
-        } else {
-            for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-                const int i = idx / (nr * PP), rem = idx - i * nr * PP;
-                const int pp = rem / nr, rr = rem - pp * nr;     // consecutive threads along x
-                const int q2 = (pos0 - e + pp) & (n2 - 1), q1 = (lc - e + dl0 + rr) & (n1 - 1);
-                sm[(size_t)i * nr * PP + rr * PP + pp] = pl[((size_t)i * n2 + q2) * n1 + q1];
+#pragma unroll
+            for (int u = 0; u < BAND_STAGE; ++u) {
+                const int i0 = base + u * blockDim.x;
+                sm[i0 < tot ? i0 : tot - 1] = v[u];
+            }
+        }
+        // the share's side-table slice: Ds[i][d2][d1 - dl0][i'] (contiguous in
+        // d1, i' for each i, d2)
+        double2* Ds = sm + band_patch_len(g);
+        const double2* Dsrc = a.Dside + ((size_t)l * 4 * e + side * e + delta) * NS * NC * NC * NS;
+        const int ndt = NS * NC * nr * NS, run = nr * NS;
+        for (int base = threadIdx.x; base < ndt; base += BAND_STAGE * blockDim.x) {
+            double2 v[BAND_STAGE];
+#pragma unroll
+            for (int u = 0; u < BAND_STAGE; ++u) {
+                const int i0 = base + u * blockDim.x, idx = i0 < ndt ? i0 : ndt - 1;
+                const int idp = idx / run, k = idx - idp * run;   // idp = i * NC + d2
+                v[u] = Dsrc[((size_t)idp * NC + dl0) * NS + k];
+            }
+#pragma unroll
+            for (int u = 0; u < BAND_STAGE; ++u) {
+                const int i0 = base + u * blockDim.x;
+                Ds[i0 < ndt ? i0 : ndt - 1] = v[u];
             }
         }
         __syncthreads();
-        const int lane = threadIdx.x & 63;
-        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // input shot
-        const double2* Dw = Dside + (((size_t)l * 4 * e + side * e + delta) * NS + w) * NC * NC * NS;
         const double2* Pw = sm + (size_t)w * nr * PP + min(lane, npos - 1);
         double2 acc[NS];
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
-        if (horiz) band_line_sum<NC, NS, true>(Pw, PP, Dw, dl0, dl1, acc);
-        else band_line_sum<NC, NS, false>(Pw, PP, Dw, dl0, dl1, acc);
+        band_col_sum<NC, NS>(Pw, PP, Ds + (size_t)w * NC * run, nr, acc);
         __syncthreads();
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) sm[((size_t)w * NS + ip) * BAND_SEG + lane] = acc[ip];
         __syncthreads();
-        double2* dst = horiz ? crow : ccol;
-        const int B = g.B;
-        for (int idx = threadIdx.x; idx < NS * BAND_SEG; idx += blockDim.x) {
-            const int ip = idx / BAND_SEG, px = idx - ip * BAND_SEG;
-            if (px >= npos) continue;
-            double2 s = cmk(0.0, 0.0);
+        {   // one output per thread: shot ip = wave, pixel px = lane
+            const int ip = w, px = lane;
+            const size_t o = (((size_t)l * NS + ip) * 2 * e + line) * n2 + pos0 + px, pstride = (size_t)B * 2 * e * n2;
+            if (px < npos) {
+                double2 s = cmk(0.0, 0.0);
 #pragma unroll
-            for (int i = 0; i < NS; ++i) s = cadd(s, sm[((size_t)i * NS + ip) * BAND_SEG + px]);
-            dst[(((size_t)part * B + l * NS + ip) * 2 * e + line) * len + pos0 + px] = s;
+                for (int i = 0; i < NS; ++i) s = cadd(s, sm[((size_t)i * NS + ip) * BAND_SEG + px]);
+                a.ccol[part * pstride + o] = s;
+                contrib = pout.x * s.x + pout.y * s.y;
+            }
+        }
+    } else if (item < ncol + nrow) {
+        const int ri = item - ncol, nxc = (n1 + 63) / 64;
+        const int line = ri / nxc, x = (ri - line * nxc) * 64 + lane;
+        const int ky = line < e ? line : n2 - 2 * e + line;
+        const int ip = w;
+        if (x < n1) {
+            const double2 pout = a.prow[((size_t)(l * NS + ip) * 4 * e + band_pcol(ky, n2, e)) * n1 + x];
+            const double2* dh = a.Dhat + ((size_t)(l * 2 * e + line) * NS * NC * NS) * n1 + x;
+            double2 s = cmk(0.0, 0.0);
+            for (int i = 0; i < NS; ++i) {
+                const double2* pri = a.prow + (size_t)(l * NS + i) * 4 * e * n1 + x;
+                double2 dv[NC], pv[NC];
+#pragma unroll
+                for (int d2 = 0; d2 < NC; ++d2) {
+                    dv[d2] = dh[(((size_t)i * NC + d2) * NS + ip) * n1];
+                    pv[d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
+                }
+#pragma unroll
+                for (int d2 = 0; d2 < NC; ++d2) s = cfma(dv[d2], pv[d2], s);
+            }
+            a.crow[((size_t)(l * NS + ip) * 2 * e + line) * n1 + x] = s;
+            contrib = pout.x * s.x + pout.y * s.y;
         }
     } else {
-        const int cp = item - band_line_items(g);
+        const int cp = item - ncol - nrow;
         const int corner = cp / (e * e), px = cp - corner * e * e;
         const int rr = px / e, cc = px - rr * e;
         const int q2 = ((corner & 1) ? n2 - e : 0) + rr, q1 = ((corner & 2) ? n1 - e : 0) + cc;
-        const double2* Dc = Dx + ((size_t)l * 4 * e * e + cp) * NS * NC * NC * NS;
+        const double2* Dc = a.Dx + ((size_t)l * 4 * e * e + cp) * NS * NC * NC * NS;
+        const int cq = band_pcol(q1, n1, e);
+        double2 pq[NS];
+#pragma unroll
+        for (int ip = 0; ip < NS; ++ip) pq[ip] = a.pcol[((size_t)(l * NS + ip) * 4 * e + cq) * n2 + q2];
         double2 acc[NS];
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
         constexpr int nt = NS * NC * NC;
         for (int t = threadIdx.x; t < nt; t += blockDim.x) {
             const int i = t / (NC * NC), d = t - i * NC * NC, d2 = d / NC, d1 = d - d2 * NC;
-            const double2 pv = pl[((size_t)i * n2 + ((q2 - e + d2) & (n2 - 1))) * n1 + ((q1 - e + d1) & (n1 - 1))];
+            const int kx = (q1 - e + d1) & (n1 - 1), ky = (q2 - e + d2) & (n2 - 1);
+            const double2 pv = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
 #pragma unroll
             for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(Dc[(size_t)t * NS + ip], pv, acc[ip]);
         }
-        double* red = (double*)sm;
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) {
             const double sr = block_sum(acc[ip].x, red);
             const double si = block_sum(acc[ip].y, red);
-            if (threadIdx.x == 0) ccorner[((size_t)l * NS + ip) * 4 * e * e + cp] = cmk(sr, si);
+            if (threadIdx.x == 0) {
+                a.ccorner[((size_t)l * NS + ip) * 4 * e * e + cp] = cmk(sr, si);
+                contrib += pq[ip].x * sr + pq[ip].y * si;
+            }
         }
     }
+    contrib = block_sum(contrib, red);
+    if (threadIdx.x == 0) a.part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = contrib;
 }
 
 // Band kernel for (2r-1, Ns); null when the pair is outside what the plan
 // accepts (Ns r^2 <= 256, 2r-1 <= BAND_MAX_NC).
-typedef void (*BandFn)(Geo, const double2*, const double2*, const double2*, double2*, double2*, double2*);
+typedef void (*BandFn)(BandArgs);
 template <int NS>
 inline BandFn band_fn_ns(int nc) {
     switch (nc) {
-        case 3: return &k_band_line<3, NS>;
-        case 5: return &k_band_line<5, NS>;
-        case 7: return &k_band_line<7, NS>;
-        case 9: return &k_band_line<9, NS>;
-        case 11: return NS <= 4 ? &k_band_line<11, (NS <= 4 ? NS : 4)> : nullptr;
-        case 13: return NS <= 4 ? &k_band_line<13, (NS <= 4 ? NS : 4)> : nullptr;
-        case 15: return NS <= 4 ? &k_band_line<15, (NS <= 4 ? NS : 4)> : nullptr;
-        case 17: return NS <= 2 ? &k_band_line<17, (NS <= 2 ? NS : 2)> : nullptr;
+        case 3: return &k_band_hyb<3, NS>;
+        case 5: return &k_band_hyb<5, NS>;
+        case 7: return &k_band_hyb<7, NS>;
+        case 9: return &k_band_hyb<9, NS>;
+        case 11: return NS <= 4 ? &k_band_hyb<11, (NS <= 4 ? NS : 4)> : nullptr;
+        case 13: return NS <= 4 ? &k_band_hyb<13, (NS <= 4 ? NS : 4)> : nullptr;
+        case 15: return NS <= 4 ? &k_band_hyb<15, (NS <= 4 ? NS : 4)> : nullptr;
+        case 17: return NS <= 2 ? &k_band_hyb<17, (NS <= 2 ? NS : 2)> : nullptr;
         default: return nullptr;
     }
 }
@@ -504,94 +593,46 @@ inline BandFn band_fn(int nc, int ns) {
     }
 }
 
-// Outputs of the band kernel, summed into the row pass.
-struct BandAdd {
-    const double2* row;      // [ds][B][2e][n1]
-    const double2* col;      // [ds][B][2e][n2]
-    const double2* corner;   // [B][4 e^2]
+// Row tables along x: Dhat[l][row][i][d2][i'][x] = sum_d1 Drow[l][row][i][d2][d1][i']
+// e^{-2 pi i (d1 - e)(x - n1/2)/n1}, rows 0..e-1 top and e..2e-1 bottom
+// (side tables 0 and 1).  One thread per output.
+__global__ void k_band_rowhat(Geo g, const double2* __restrict__ Dside, const double2* __restrict__ tw1,
+                              double2* __restrict__ Dhat) {
+    const int n1 = g.n1, Ns = g.Ns, nc = g.nc, e = g.e;
+    const long total = (long)g.L * 2 * e * Ns * nc * Ns * n1;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long)gridDim.x * blockDim.x) {
+        long t = idx;
+        const int x = t % n1; t /= n1;
+        const int ip = t % Ns; t /= Ns;
+        const int d2 = t % nc; t /= nc;
+        const int i = t % Ns; t /= Ns;
+        const int row = t % (2 * e);
+        const int l = (int)(t / (2 * e));
+        // rows 0..2e-1 are the side tables 0 (top) and 1 (bottom), in that order
+        const double2* dr = Dside + ((((size_t)l * 4 * e + row) * Ns + i) * nc + d2) * nc * Ns + ip;
+        double2 s = cmk(0.0, 0.0);
+        for (int d1 = 0; d1 < nc; ++d1) s = cfma(dr[(size_t)d1 * Ns], tw1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
+        Dhat[idx] = s;
+    }
+}
+
+// Band corrections as the hybrid-layout vector pass takes them: the row
+// corrections (already transformed along kx), the natural corrections on the
+// 2e band columns in ds shares, the corner cross terms, and
+// finv[x][cl] = e^{+2 pi i (kx_cl - n1/2)(x - n1/2)/n1} / sqrt(n1), the kx
+// inverse transform restricted to the band columns kx_cl (cl < e: cl, else
+// n1 - 2e + cl); rows are 16 entries wide, zero past 2e.
+struct BandInj {
+    const double2* crow;
+    const double2* ccol;
+    const double2* ccorner;
+    const double2* finv;
     int ds;
 };
-
-// Band correction of image b at pixel (j2, k): row and column shares, and the
-// cross term at the corners.
-SMSM_DEV double2 band_add(const Geo& g, const BandAdd& ba, int b, int j2, int k) {
-    const int e = g.e, n1 = g.n1, n2 = g.n2;
-    double2 s = cmk(0.0, 0.0);
-    const bool rb = j2 < e || j2 >= n2 - e, cb = k < e || k >= n1 - e;
-    // shares are loaded with a compile-time trip count so that the loads
-    // issue together (a runtime loop waits for each one in turn)
-    if (rb) {
-        const int rl = j2 < e ? j2 : j2 - (n2 - 2 * e);
-        double2 v[BAND_MAX_DS];
-#pragma unroll
-        for (int part = 0; part < BAND_MAX_DS; ++part)
-            v[part] = part < ba.ds ? ba.row[(((size_t)part * g.B + b) * 2 * e + rl) * n1 + k] : cmk(0.0, 0.0);
-#pragma unroll
-        for (int part = 0; part < BAND_MAX_DS; ++part) s = cadd(s, v[part]);
-    }
-    if (cb) {
-        const int cl = k < e ? k : k - (n1 - 2 * e);
-        double2 v[BAND_MAX_DS];
-#pragma unroll
-        for (int part = 0; part < BAND_MAX_DS; ++part)
-            v[part] = part < ba.ds ? ba.col[(((size_t)part * g.B + b) * 2 * e + cl) * n2 + j2] : cmk(0.0, 0.0);
-#pragma unroll
-        for (int part = 0; part < BAND_MAX_DS; ++part) s = cadd(s, v[part]);
-    }
-    if (rb && cb) {
-        const int corner = (j2 < e ? 0 : 1) | (k < e ? 0 : 2);
-        const int rr = j2 < e ? j2 : j2 - (n2 - e), cc = k < e ? k : k - (n1 - e);
-        s = cadd(s, ba.corner[(size_t)b * 4 * e * e + corner * e * e + rr * e + cc]);
-    }
-    return s;
-}
-
 // ---------------------------------------------------------------------------
-// CG vector kernels (fixed grid, grid-stride, per-block FP64 partials).
+// Plain vector kernels (fixed grid, grid-stride).
 // ---------------------------------------------------------------------------
-// r = b - q; partial sum |r|^2
-__global__ void k_cg_init(long n, const double2* __restrict__ b, const double2* __restrict__ q,
-                          double2* __restrict__ r, double* __restrict__ pr_part) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const double2 v = csub(b[k], q[k]);
-        r[k] = v;
-        s += cabs2(v);
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) pr_part[blockIdx.x] = s;
-}
-
-// alpha = rr / Re<p, q>; x += alpha p; r -= alpha q; partial |r|^2.
-// rr == 0 (exact solution reached) leaves x, r unchanged; a non-finite or
-// non-positive curvature sets flags[0].
-__global__ void k_cg_update(long n, double2* __restrict__ x, const double2* __restrict__ p,
-                            double2* __restrict__ r, const double2* __restrict__ q,
-                            const double* __restrict__ pr_cur, int npr, const double* __restrict__ pq_part,
-                            int npq, double* __restrict__ pr_next, int* __restrict__ flags) {
-    __shared__ double red[16];
-    const double rr = sum_partials(pr_cur, npr, red);
-    const double pq = sum_partials(pq_part, npq, red);
-    double alpha = 0.0;
-    if (rr > 0.0) {
-        alpha = rr / pq;
-        if (!(pq > 0.0) || !isfinite(alpha)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
-            alpha = 0.0;
-        }
-    }
-    double s = 0.0;
-    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        x[k] = cadd(x[k], cscale(p[k], alpha));
-        const double2 v = csub(r[k], cscale(q[k], alpha));
-        r[k] = v;
-        s += cabs2(v);
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) pr_next[blockIdx.x] = s;
-}
-
 __global__ void k_copy_c128(long n, const double2* __restrict__ a, double2* __restrict__ b) {
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) b[k] = a[k];
 }

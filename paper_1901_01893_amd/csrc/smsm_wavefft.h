@@ -74,23 +74,15 @@ struct WaveFft {
 // transposed read (row pass 3), so global accesses stay coalesced.
 // TR must be a multiple of (blockDim / 64) * (64 / LANES), and TR * N <= 8 * blockDim.
 // ---------------------------------------------------------------------------
-template <int N, int MODE>
+template <int N>
 __global__ void __launch_bounds__(256)
-k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ rvec,
-             double2* __restrict__ pvec, const double* __restrict__ pr_new, const double* __restrict__ pr_old,
-             int npart, const double2* __restrict__ tw1, int TR) {
+k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ tw1,
+             int TR) {
     using F = WaveFft<N>;
     constexpr int R = F::R, LANES = F::LANES, G = 64 / LANES, ST = N + 1;
     extern __shared__ double2 sm[];
-    double* red = (double*)(sm + TR * ST);
     const int b = blockIdx.y, j0 = blockIdx.x * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    double beta = 0.0;
-    if (MODE == ROWS_CG_UPDATE) {
-        const double rn = sum_partials(pr_new, npart, red);
-        const double ro = sum_partials(pr_old, npart, red);
-        beta = (ro > 0.0) ? rn / ro : 0.0;
-    }
     F f;
     f.setup(tw1, lane);
     const int grp = lane / LANES;
@@ -103,17 +95,7 @@ k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
 #pragma unroll
         for (int t = 0; t < R; ++t) {
             const int k = f.m + 64 * t;
-            double2 val;
-            if (MODE == ROWS_PLAIN) {
-                val = in[o + k];
-            } else if (MODE == ROWS_CG_UPDATE) {
-                val = cadd(rvec[o + k], cscale(pvec[o + k], beta));
-                pvec[o + k] = val;
-            } else {
-                val = rvec[o + k];
-                pvec[o + k] = val;
-            }
-            v[t] = cscale(val, sgn_pow(k));
+            v[t] = cscale(in[o + k], sgn_pow(k));
         }
         f.template run<true>(v);
 #pragma unroll
@@ -130,33 +112,16 @@ k_rows_inv_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
     }
 }
 
-template <int N, bool CG, bool BAND>
+template <int N>
 __global__ void __launch_bounds__(256)
-k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, BandAdd ba,
-             const double2* __restrict__ pvec, double* __restrict__ pq_part, const double2* __restrict__ tw1,
+k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ tw1,
              int TR) {
     using F = WaveFft<N>;
     constexpr int R = F::R, LANES = F::LANES, G = 64 / LANES, ST = N + 1;
     extern __shared__ double2 sm[];
-    double* red = (double*)(sm + TR * ST);
     const int b = blockIdx.y, j0 = blockIdx.x * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t ib = (size_t)b * N * g.n2;
-    // band terms of this thread's outputs, loaded first so their latency
-    // overlaps the transform (TR * N <= 8 * blockDim)
-    const size_t img = (size_t)b * g.n2 * N;
-    double2 bandv[8], pv[8];
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-        const int idx = threadIdx.x + it * blockDim.x;
-        bandv[it] = cmk(0.0, 0.0);
-        pv[it] = cmk(0.0, 0.0);
-        if (idx < TR * N) {
-            const int jr = idx / N, k = idx - jr * N;
-            if (BAND) bandv[it] = band_add(g, ba, b, j0 + jr, k);
-            if (CG) pv[it] = pvec[img + (size_t)(j0 + jr) * N + k];
-        }
-    }
     for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
         const int c = idx / TR, jr = idx - c * TR;
         sm[jr * ST + c] = in[ib + (size_t)c * g.n2 + j0 + jr];
@@ -182,21 +147,9 @@ k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, B
         }
     }
     __syncthreads();
-    double acc = 0.0;
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-        const int idx = threadIdx.x + it * blockDim.x;
-        if (idx >= TR * N) break;
+    const size_t img = (size_t)b * g.n2 * N;
+    for (int idx = threadIdx.x; idx < TR * N; idx += blockDim.x) {
         const int jr = idx / N, k = idx - jr * N;
-        const int j2 = j0 + jr;
-        double2 val = sm[jr * ST + k];
-        if (BAND) val = cadd(val, bandv[it]);
-        const size_t o = img + (size_t)j2 * N + k;
-        out[o] = val;
-        if (CG) acc += pv[it].x * val.x + pv[it].y * val.y;
-    }
-    if (CG) {
-        const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) pq_part[blockIdx.y * gridDim.x + blockIdx.x] = s;
+        out[img + (size_t)(j0 + jr) * N + k] = sm[jr * ST + k];
     }
 }
