@@ -65,6 +65,7 @@ struct smsm_plan {
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
     double *pr = nullptr, *pq = nullptr, *bpart = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr, *nsmu = nullptr;
+    double* cgs = nullptr;   // CG scalars: |r|^2 of the last three residuals [0..2], step length [3]
     int *done = nullptr, *flags = nullptr;
 
     int ns_iters = kNsDefaultIters;
@@ -184,8 +185,8 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
     }
     const long nvec = (long)g.B * g.n1 * g.n2;
     if (pc.mode != 0) {
-        hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p, pc.rr_new, pc.rr_old,
-                           pc.nrr, pc.mode == 1 ? 1 : 0);
+        hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p, pc.rr_new, pc.nrr,
+                           pc.rr_old, pc.mode == 1 ? 1 : 0);
         LAUNCH_CHECK();
         in = pc.p;
     }
@@ -264,12 +265,19 @@ const void* hyb_update_fn(int mode, int xw, bool wu, bool band) {
 smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
     a.g = P->g;
     a.bi = BandInj{P->crow, P->ccol, P->ccorner, P->finv, band_ds(P->g.Ns, P->g.nc)};
-    a.nrr = P->npr;
-    a.pq = P->pq;
-    a.npq = P->npc + (a.use_band ? band_items(P->g) * P->g.L : 0);
+    a.alpha = P->cgs + 3;
     const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
     void* args[] = {&a};
     if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(kThreads), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// alpha = |r|^2 / Re <p, N p> and |r|^2 (into *rr_out) from their partials.
+smsm_status cg_alpha(smsm_plan* P, const double* rr_part, double* rr_out, bool band, hipStream_t st) {
+    const int npq = P->npc + (band ? band_items(P->g) * P->g.L : 0);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, rr_part, P->npr, P->pq, npq, rr_out, P->cgs + 3,
+                       P->flags);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -567,6 +575,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
     const size_t oei = cv.take<double>(L), onsmu = cv.take<double>((size_t)P->ns_iters * L);
     const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
+    const size_t ocgs = cv.take<double>(8);
 
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
@@ -592,11 +601,12 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
     P->epsin = (double*)(base + oei); P->nsmu = (double*)(base + onsmu);
     P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
+    P->cgs = (double*)(base + ocgs);
     {   // every carved pointer must be set before any launch
         const void* carved[] = {P->ST, P->tw1, P->tw2, P->twM, P->theta, P->tau, P->x, P->b, P->r, P->p, P->q,
                                 P->h1, P->h2, P->ytil, P->G, P->W, P->Kc, P->Khat, P->Dside, P->Dx, P->Dhat,
                                 P->crow, P->ccol, P->ccorner, P->pcol, P->prow, P->fx, P->finv, P->pr, P->pq,
-                                P->bpart, P->part0, P->part1};
+                                P->bpart, P->part0, P->part1, P->cgs};
         for (const void* c : carved)
             if (!c) { (void)hipFree(P->arena); delete P; return SMSM_E_DEVICE; }
     }
@@ -753,8 +763,8 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
             pc.r = P->r;
             pc.p = P->p;
             pc.rr_new = RR[j % 3];
-            pc.rr_old = RR[(j + 2) % 3];
             pc.nrr = P->npr;
+            pc.rr_old = P->cgs + (j + 2) % 3;
             pc.mode = j == 0 ? 1 : 2;
             pc.pq = P->pq;
             if ((s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st))) return s;
@@ -762,6 +772,7 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
                 if ((s = band_extract(P, P->p, P->col_fast < 0, st))) return s;
                 if ((s = band_corr(P, st))) return s;
             }
+            if ((s = cg_alpha(P, RR[j % 3], P->cgs + j % 3, reg, st))) return s;
             HybArgs a{};
             a.mode = 2;
             a.use_band = reg ? 1 : 0;
@@ -769,9 +780,7 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
             a.x = P->x;
             a.p = P->p;
             a.r = P->r;
-            a.rr_cur = RR[j % 3];
             a.part = RR[(j + 1) % 3];
-            a.flags = P->flags;
             if ((s = hyb_update(P, a, st))) return s;
         }
     }
@@ -927,6 +936,10 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
             f = 8.0 * B * n1 * n2 * 4.0 * e;
             b = vec + B * 4.0 * e * n2 * 16.0;
             break;
+        case SMSM_KERNEL_CG_ALPHA:
+            f = 0.0;
+            b = 0.0;
+            break;
         default:
             break;
     }
@@ -940,13 +953,13 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
 extern "C" {
 
 smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* bytes) {
-    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
+    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_CG_ALPHA) return SMSM_E_INVALID;
     kernel_cost(P->g, id, flops, bytes);
     return SMSM_OK;
 }
 
 smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
-    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
+    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_CG_ALPHA) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     const bool reg = P->prm.lambda > 0.0 && P->have_weights;
@@ -958,8 +971,8 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
                 pc.r = P->r;
                 pc.p = P->p;
                 pc.rr_new = P->pr + P->npr;
-                pc.rr_old = P->pr;
                 pc.nrr = P->npr;
+                pc.rr_old = P->cgs;
                 pc.mode = 2;
                 pc.pq = P->pq;
                 s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st);
@@ -969,6 +982,7 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
             case SMSM_KERNEL_ROWS_FWD: s = rows_fwd(P, P->x, P->q, st); break;
             case SMSM_KERNEL_BAND_CORR: s = band_corr(P, st); break;
             case SMSM_KERNEL_BAND_EXTRACT: s = band_extract(P, P->p, P->col_fast < 0, st); break;
+            case SMSM_KERNEL_CG_ALPHA: s = cg_alpha(P, P->pr, P->cgs + 1, reg, st); break;
             case SMSM_KERNEL_CG_UPDATE: {
                 HybArgs a{};
                 a.mode = 2;
@@ -977,9 +991,7 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
                 a.x = P->x;
                 a.p = P->p;
                 a.r = P->r;
-                a.rr_cur = P->pr;
                 a.part = P->pr + 2 * P->npr;
-                a.flags = P->flags;
                 s = hyb_update(P, a, st);
                 break;
             }

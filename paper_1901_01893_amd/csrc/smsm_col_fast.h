@@ -135,16 +135,16 @@ template <int N> struct WaveFft;
 
 // Optional CG direction update fused into the column pass (hybrid layout):
 // mode 0: the input is h1; mode 1: p = r; mode 2: p = r + beta p with
-// beta = sum(rr_new[0..nrr)) / sum(rr_old[0..nrr)) (0 when the old sum is 0).
+// beta = sum(rr_new[0..nrr)) / *rr_old (0 when *rr_old is 0).
 // In modes 1 and 2 the new p is written back and the input is p; each
 // workgroup also stores Re <p, output> of its column in pq[blockIdx.x],
 // evaluated in the image domain (the ky transforms are unitary).
 struct ColCg {
     const double2* r;
     double2* p;
-    const double* rr_new;
-    const double* rr_old;
+    const double* rr_new;    // partials of the new |r|^2
     int nrr;
+    const double* rr_old;    // the previous |r|^2 (scalar)
     int mode;
     double* pq;
 };
@@ -181,8 +181,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
     double beta = 0.0;
     if (pc.mode == 2) {
-        double rn, ro;
-        sum_partials2(pc.rr_new, pc.nrr, pc.rr_old, pc.nrr, rn, ro, (double*)ACC);
+        const double rn = sum_partials(pc.rr_new, pc.nrr, (double*)ACC), ro = *pc.rr_old;
         beta = ro > 0.0 ? rn / ro : 0.0;
     }
     __syncthreads();

@@ -50,10 +50,23 @@ SMSM_DEV double block_sum(double v, double* scratch) {
 }
 
 // Sum of `n` partial values in a fixed order (each thread of the block gets
-// the same result).  Used to turn per-block partials into a scalar.
+// the same result).  Used to turn per-block partials into a scalar.  A thread
+// adds its slots threadIdx.x + k blockDim.x in increasing k, loading eight
+// slots at a time so they are in flight together.
 SMSM_DEV double sum_partials(const double* __restrict__ part, int n, double* scratch) {
+    const int nt = blockDim.x;
     double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) v += part[k];
+    for (int base = threadIdx.x; base < n; base += 8 * nt) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = base + u * nt;
+            pv[u] = part[k < n ? k : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * nt < n) v += pv[u];
+    }
     return block_sum(v, scratch);
 }
 

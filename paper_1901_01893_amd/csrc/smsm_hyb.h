@@ -81,11 +81,8 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
 // kernel when BAND): q = h2 + band correction, then
 //   mode 0: out = q
 //   mode 1: out = bvec - q (CG residual); per-block partials of |out|^2
-//   mode 2: CG step alpha = rr / pq, rr = sum rr_cur[0..nrr) (|r|^2),
-//           pq = sum pq[0..npq) (Re <p, N p>: column-pass then band
-//           partials), x += alpha p, r -= alpha q; partials of |r|^2.
-//           rr == 0 (exact solution) leaves x, r unchanged; non-positive or
-//           non-finite curvature sets flags[0].
+//   mode 2: CG step with alpha = *alpha (from k_cg_alpha): x += alpha p,
+//           r -= alpha q; partials of |r|^2.
 // Thread layout: lane = ky (LY = min(64, n2) lanes per x, 64 / LY x per
 // step), so the natural band-column corrections of a lane's ky (shares
 // summed, corner cross terms added; staged once per workgroup) stay in
@@ -103,12 +100,8 @@ struct HybArgs {
     const double2* p;
     double2* r;
     BandInj bi;
-    const double* rr_cur;
-    int nrr;
-    const double* pq;
-    int npq;
-    double* part;            // per-block partials of |r|^2 (nrr of them)
-    int* flags;
+    const double* alpha;     // scalar step length (mode 2)
+    double* part;            // per-block partials of |r|^2
 };
 
 #define HYB_MAX_E2 16
@@ -175,16 +168,7 @@ __global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
         }
         if (BAND) cr[t] = a.bi.crow[((size_t)b * e2 + rrow) * n1 + xx[t]];
     }
-    // step length (branch-free, so the loads above stay in flight)
-    double alpha = 0.0;
-    bool bad = false;
-    if (MODE == 2) {
-        double rr, pq;
-        sum_partials2(a.rr_cur, a.nrr, a.pq, a.npq, rr, pq, red);
-        const double al = rr / pq;
-        bad = rr > 0.0 && (!(pq > 0.0) || !isfinite(al));
-        alpha = (rr > 0.0 && !bad) ? al : 0.0;
-    }
+    const double alpha = MODE == 2 ? *a.alpha : 0.0;
     double2 c[HYB_MAX_E2];
     if (BAND) {
         const int ncs = e2 * LY;
@@ -236,19 +220,38 @@ __global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
         s = block_sum(s, red);
         if (threadIdx.x == 0) a.part[blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
-    if (MODE == 2 && bad && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.flags[0] = 1;
 }
 
-// p = r (first step) or p = r + beta p, beta = sum rr_new / sum rr_old
-// (nrr partials each), for column passes that do not fuse the update.
+// CG scalars of one step, once for the whole grid: rr = sum rr_part[0..nrr)
+// (|r|^2), pq = sum pq_part[0..npq) (Re <p, N p>: column-pass then band
+// partials); *rr_out = rr, *alpha = rr / pq.  rr == 0 (exact solution) gives
+// alpha = 0; non-positive or non-finite curvature gives alpha = 0 and sets
+// flags[0].  One block.
+__global__ void __launch_bounds__(1024) k_cg_alpha(const double* __restrict__ rr_part, int nrr,
+                                                   const double* __restrict__ pq_part, int npq,
+                                                   double* __restrict__ rr_out, double* __restrict__ alpha,
+                                                   int* __restrict__ flags) {
+    __shared__ double red[32];
+    double rr, pq;
+    sum_partials2(rr_part, nrr, pq_part, npq, rr, pq, red);
+    if (threadIdx.x == 0) {
+        const double al = rr / pq;
+        const bool bad = rr > 0.0 && (!(pq > 0.0) || !isfinite(al));
+        *rr_out = rr;
+        *alpha = (rr > 0.0 && !bad) ? al : 0.0;
+        if (bad) flags[0] = 1;
+    }
+}
+
+// p = r (first step) or p = r + beta p, beta = sum rr_new[0..nrr) / *rr_old,
+// for column passes that do not fuse the update.
 __global__ void k_hyb_pupdate(long n, const double2* __restrict__ r, double2* __restrict__ p,
-                              const double* __restrict__ rr_new, const double* __restrict__ rr_old, int nrr,
+                              const double* __restrict__ rr_new, int nrr, const double* __restrict__ rr_old,
                               int first) {
     __shared__ double red[8];
     double beta = 0.0;
     if (!first) {
-        double rn, ro;
-        sum_partials2(rr_new, nrr, rr_old, nrr, rn, ro, red);
+        const double rn = sum_partials(rr_new, nrr, red), ro = *rr_old;
         beta = ro > 0.0 ? rn / ro : 0.0;
     }
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)

@@ -31,7 +31,7 @@ ABI_SYMBOLS = (
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_launch_kernel", "smsm_kernel_cost",
 )
-KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
+KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5, "cg_alpha": 6}
 
 
 class Geometry(ctypes.Structure):
