@@ -304,9 +304,8 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
                        P->Kc, P->Dside, P->Dx);
     LAUNCH_CHECK();
-    const long nhat = (long)g.L * 2 * g.e * g.Ns * g.nc * g.Ns * g.n1;
-    hipLaunchKernelGGL(k_band_rowhat, dim3((int)std::min<long>(4096, (nhat + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, g, P->Dside, P->tw1, P->Dhat);
+    hipLaunchKernelGGL(k_band_rowhat, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g, P->Dside,
+                       P->tw1, P->Dhat);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * g.Ns), dim3(kThreads), 0, st, g, P->Kc, P->tw1,

@@ -111,22 +111,32 @@ __host__ __device__ inline int colfast_lds_total(const Geo& g) { return 2 * g.B 
 
 // Image-domain kernel of the circular Hankel term, one table per IRLS step:
 //   Khat[l][j][i][x][n] = sum_{d2,d1} Kc[l][j][i][d2][d1] e^{-2 pi i ((d1-e)(x-n1/2)/n1 + (d2-e)(n-n2/2)/n2)}
-// (input shot j, output shot i).  grid (n1, L Ns Ns), block 256.
-__global__ void k_hankel_image(Geo g, const double2* __restrict__ Kc, const double2* __restrict__ tw1,
-                               const double2* __restrict__ tw2, double2* __restrict__ Khat) {
+// (input shot j, output shot i).  grid (n1, L Ns Ns), block 256: the taps'
+// x transform A[d2] (products formed in parallel, summed in d1 order), then
+// one output n per thread from shared-memory twiddles.
+__global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __restrict__ Kc,
+                                                      const double2* __restrict__ tw1,
+                                                      const double2* __restrict__ tw2, double2* __restrict__ Khat) {
     __shared__ double2 A[BAND_MAX_NC];
+    __shared__ double2 PR[BAND_MAX_NC * BAND_MAX_NC];
+    __shared__ double2 T2[256];
     const int x = blockIdx.x, sji = blockIdx.y, nc = g.nc, e = g.e, n1 = g.n1, n2 = g.n2;
     const int nu1 = x - n1 / 2;
-    for (int d2 = threadIdx.x; d2 < nc; d2 += blockDim.x) {
-        const double2* kr = Kc + ((size_t)sji * nc + d2) * nc;
+    for (int n = threadIdx.x; n < n2; n += blockDim.x) T2[n] = tw2[n];
+    for (int t = threadIdx.x; t < nc * nc; t += blockDim.x) {
+        const int d1 = t % nc;
+        PR[t] = cmul(Kc[(size_t)sji * nc * nc + t], tw1[((d1 - e) * nu1) & (n1 - 1)]);
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
         double2 a = cmk(0.0, 0.0);
-        for (int d1 = 0; d1 < nc; ++d1) a = cfma(kr[d1], tw1[((d1 - e) * nu1) & (n1 - 1)], a);
-        A[d2] = a;
+        for (int d1 = 0; d1 < nc; ++d1) a = cadd(a, PR[threadIdx.x * nc + d1]);
+        A[threadIdx.x] = a;
     }
     __syncthreads();
     for (int n = threadIdx.x; n < n2; n += blockDim.x) {
         double2 k = cmk(0.0, 0.0);
-        for (int d2 = 0; d2 < nc; ++d2) k = cfma(A[d2], tw2[((d2 - e) * (n - n2 / 2)) & (n2 - 1)], k);
+        for (int d2 = 0; d2 < nc; ++d2) k = cfma(A[d2], T2[((d2 - e) * (n - n2 / 2)) & (n2 - 1)], k);
         Khat[((size_t)sji * n1 + x) * n2 + n] = k;
     }
 }

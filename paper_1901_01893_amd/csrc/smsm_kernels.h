@@ -595,25 +595,27 @@ inline BandFn band_fn(int nc, int ns) {
 
 // Row tables along x: Dhat[l][row][i][d2][i'][x] = sum_d1 Drow[l][row][i][d2][d1][i']
 // e^{-2 pi i (d1 - e)(x - n1/2)/n1}, rows 0..e-1 top and e..2e-1 bottom
-// (side tables 0 and 1).  One thread per output.
-__global__ void k_band_rowhat(Geo g, const double2* __restrict__ Dside, const double2* __restrict__ tw1,
-                              double2* __restrict__ Dhat) {
+// (side tables 0 and 1).  One workgroup per (l, row, i, d2) with its taps and
+// the kx twiddles in shared memory; thread = x, all i'.
+__global__ void __launch_bounds__(256) k_band_rowhat(Geo g, const double2* __restrict__ Dside,
+                                                     const double2* __restrict__ tw1, double2* __restrict__ Dhat) {
+    __shared__ double2 T1[256];
+    __shared__ double2 DR[BAND_MAX_NC * 8];   // [d1][i'], Ns <= 8
     const int n1 = g.n1, Ns = g.Ns, nc = g.nc, e = g.e;
-    const long total = (long)g.L * 2 * e * Ns * nc * Ns * n1;
-    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
-         idx += (long)gridDim.x * blockDim.x) {
-        long t = idx;
-        const int x = t % n1; t /= n1;
-        const int ip = t % Ns; t /= Ns;
-        const int d2 = t % nc; t /= nc;
-        const int i = t % Ns; t /= Ns;
-        const int row = t % (2 * e);
-        const int l = (int)(t / (2 * e));
-        // rows 0..2e-1 are the side tables 0 (top) and 1 (bottom), in that order
-        const double2* dr = Dside + ((((size_t)l * 4 * e + row) * Ns + i) * nc + d2) * nc * Ns + ip;
-        double2 s = cmk(0.0, 0.0);
-        for (int d1 = 0; d1 < nc; ++d1) s = cfma(dr[(size_t)d1 * Ns], tw1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
-        Dhat[idx] = s;
+    const int lrid = blockIdx.x;                            // ((l * 2e + row) * Ns + i) * nc + d2
+    // rows 0..2e-1 are the side tables 0 (top) and 1 (bottom), in that order
+    const int d2 = lrid % nc, i = (lrid / nc) % Ns, row = (lrid / (nc * Ns)) % (2 * e), l = lrid / (nc * Ns * 2 * e);
+    const double2* dr = Dside + ((((size_t)l * 4 * e + row) * Ns + i) * nc + d2) * nc * Ns;
+    for (int t = threadIdx.x; t < n1; t += blockDim.x) T1[t] = tw1[t];
+    for (int t = threadIdx.x; t < nc * Ns; t += blockDim.x) DR[t] = dr[t];
+    __syncthreads();
+    double2* out = Dhat + (size_t)lrid * Ns * n1;
+    for (int x = threadIdx.x; x < n1; x += blockDim.x) {
+        for (int ip = 0; ip < Ns; ++ip) {
+            double2 s = cmk(0.0, 0.0);
+            for (int d1 = 0; d1 < nc; ++d1) s = cfma(DR[d1 * Ns + ip], T1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
+            out[(size_t)ip * n1 + x] = s;
+        }
     }
 }
 
