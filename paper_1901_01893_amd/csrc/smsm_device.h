@@ -49,6 +49,29 @@ SMSM_DEV double block_sum(double v, double* scratch) {
     return s;
 }
 
+// N block sums with one exchange through shared memory (scratch: N *
+// blockDim.x/64 doubles).  Every thread must call it; results in all threads.
+template <int N>
+SMSM_DEV void block_sum_n(double (&v)[N], double* scratch) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    const int lane = threadIdx.x & 63, warp = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) scratch[k * nw + warp] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += scratch[k * nw + w];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
 // Sum of `n` partial values in a fixed order (each thread of the block gets
 // the same result).  Used to turn per-block partials into a scalar.  A thread
 // adds its slots threadIdx.x + k blockDim.x in increasing k, loading eight

@@ -517,16 +517,24 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
             const double2 pout = a.prow[((size_t)(l * NS + ip) * 4 * e + band_pcol(ky, n2, e)) * n1 + x];
             const double2* dh = a.Dhat + ((size_t)(l * 2 * e + line) * NS * NC * NS) * n1 + x;
             double2 s = cmk(0.0, 0.0);
-            for (int i = 0; i < NS; ++i) {
-                const double2* pri = a.prow + (size_t)(l * NS + i) * 4 * e * n1 + x;
-                double2 dv[NC], pv[NC];
+            // two input shots per round: 4 NC loads in flight
+            constexpr int IR = NS >= 2 ? 2 : 1;
+            for (int i0 = 0; i0 < NS; i0 += IR) {
+                double2 dv[IR][NC], pv[IR][NC];
 #pragma unroll
-                for (int d2 = 0; d2 < NC; ++d2) {
-                    dv[d2] = dh[(((size_t)i * NC + d2) * NS + ip) * n1];
-                    pv[d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
+                for (int u = 0; u < IR; ++u) {
+                    const int i = i0 + u;
+                    const double2* pri = a.prow + (size_t)(l * NS + i) * 4 * e * n1 + x;
+#pragma unroll
+                    for (int d2 = 0; d2 < NC; ++d2) {
+                        dv[u][d2] = dh[(((size_t)i * NC + d2) * NS + ip) * n1];
+                        pv[u][d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
+                    }
                 }
 #pragma unroll
-                for (int d2 = 0; d2 < NC; ++d2) s = cfma(dv[d2], pv[d2], s);
+                for (int u = 0; u < IR; ++u)
+#pragma unroll
+                    for (int d2 = 0; d2 < NC; ++d2) s = cfma(dv[u][d2], pv[u][d2], s);
             }
             a.crow[((size_t)(l * NS + ip) * 2 * e + line) * n1 + x] = s;
             contrib = pout.x * s.x + pout.y * s.y;
@@ -544,21 +552,37 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
         double2 acc[NS];
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
-        constexpr int nt = NS * NC * NC;
-        for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        // the taps spread over the threads, all loads of a thread issued together
+        constexpr int nt = NS * NC * NC, TPB = 64 * NS, IT = (nt + TPB - 1) / TPB;
+        double2 pv[IT], dc[IT][NS];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int t0 = threadIdx.x + it * TPB, t = t0 < nt ? t0 : nt - 1;
             const int i = t / (NC * NC), d = t - i * NC * NC, d2 = d / NC, d1 = d - d2 * NC;
             const int kx = (q1 - e + d1) & (n1 - 1), ky = (q2 - e + d2) & (n2 - 1);
-            const double2 pv = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
+            pv[it] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
 #pragma unroll
-            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(Dc[(size_t)t * NS + ip], pv, acc[ip]);
+            for (int ip = 0; ip < NS; ++ip) dc[it][ip] = Dc[(size_t)t * NS + ip];
         }
 #pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const double live = threadIdx.x + it * TPB < nt ? 1.0 : 0.0;
+#pragma unroll
+            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(dc[it][ip], cscale(pv[it], live), acc[ip]);
+        }
+        // all 2 NS sums in one exchange
+        double v[2 * NS];
+#pragma unroll
         for (int ip = 0; ip < NS; ++ip) {
-            const double sr = block_sum(acc[ip].x, red);
-            const double si = block_sum(acc[ip].y, red);
-            if (threadIdx.x == 0) {
-                a.ccorner[((size_t)l * NS + ip) * 4 * e * e + cp] = cmk(sr, si);
-                contrib += pq[ip].x * sr + pq[ip].y * si;
+            v[2 * ip] = acc[ip].x;
+            v[2 * ip + 1] = acc[ip].y;
+        }
+        block_sum_n<2 * NS>(v, (double*)sm);   // 2 NS NS doubles; the corner items use no other shared memory
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int ip = 0; ip < NS; ++ip) {
+                a.ccorner[((size_t)l * NS + ip) * 4 * e * e + cp] = cmk(v[2 * ip], v[2 * ip + 1]);
+                contrib += pq[ip].x * v[2 * ip] + pq[ip].y * v[2 * ip + 1];
             }
         }
     }
