@@ -34,7 +34,9 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
     // k steps of 4 x per wave: nks / 4 <= EXTRACT_KS (n1 <= 256); every load
     // of the wave is issued before the first product
     const int nks = n1 / 4, ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
-    hd4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    // complex product with three real products (Gauss):
+    //   t1 = (ar + ai) br, t2 = ar (bi - br), t3 = ai (br + bi); re = t1 - t3, im = t1 + t2
+    hd4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0}, t3 = {0.0, 0.0, 0.0, 0.0};
     double2 av[EXTRACT_KS], bv[EXTRACT_KS];
 #pragma unroll
     for (int u = 0; u < EXTRACT_KS; ++u) {
@@ -54,16 +56,15 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
 #pragma unroll
     for (int u = 0; u < EXTRACT_KS; ++u) {
         if (ks0 + u < ks1) {
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].x, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u].y, bv[u].y, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x, ci, 0, 0, 0);
+            t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x + av[u].y, bv[u].x, t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y - bv[u].x, t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x + bv[u].y, t3, 0, 0, 0);
         }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        acc[w][v][lane] = cr[v];
-        acc[w][4 + v][lane] = ci[v];
+        acc[w][v][lane] = t1[v] - t3[v];
+        acc[w][4 + v][lane] = t1[v] + t2[v];
     }
     __syncthreads();
     const int v = threadIdx.x >> 6, ln = threadIdx.x & 63;

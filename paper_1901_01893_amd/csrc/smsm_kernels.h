@@ -360,7 +360,7 @@ __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_
 __host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
 // shares of the tap columns (more workgroups for the same work: finer balance)
 __host__ __device__ inline int band_ds(int Ns, int nc) {
-    const int d = Ns >= 8 ? 2 : (Ns >= 4 ? 3 : BAND_MAX_DS);
+    const int d = Ns >= 8 ? 2 : BAND_MAX_DS;   // measured best at 4 shots, r = 7
     return d < nc ? d : nc;
 }
 __host__ __device__ inline int band_col_items(const Geo& g) {
