@@ -49,7 +49,7 @@ struct smsm_plan {
     int KP = 0;              // padded stride of the Newton-Schulz matrices
     int ntile = 0;           // 16x16 tiles per slice of the dense products
     int npmax = 0;           // partial sums per slice (max over producers)
-    size_t lds_rows = 0, lds_col = 0, lds_gram = 0;
+    size_t lds_rows = 0, lds_col = 0, lds_gram = 0, lds_gram_lines = 0;
     bool have_weights = false;
     void* arena = nullptr;
     size_t bytes = 0;
@@ -340,9 +340,9 @@ smsm_status chain_normal(smsm_plan* P, const double2* v, double2* out, int mode_
 // G = Gram of the natural vector v; vh is its hybrid form, or null to compute it.
 smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double2* G, hipStream_t st) {
     const Geo& g = P->g;
+    smsm_status s = SMSM_OK;
     if (!vh) {
-        smsm_status s = rows_inv(P, v, P->h1, st);
-        if (s) return s;
+        if ((s = rows_inv(P, v, P->h1, st))) return s;
         vh = P->h1;
     }
     const size_t lds = P->lds_gram;
@@ -358,16 +358,16 @@ smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double
     const int nwc = g.L * g.npairs * g.nc;
     hipLaunchKernelGGL(k_gram_c, dim3((nwc + wpb - 1) / wpb), dim3(kThreads), 0, st, g, P->gpart, P->tw1, P->gC);
     LAUNCH_CHECK();
-    const int nwl = 2 * nwc * 2 * g.e;
-    hipLaunchKernelGGL(k_gram_lines, dim3((nwl + wpb - 1) / wpb), dim3(kThreads), 0, st, g, v, P->grow, P->gcol);
+    // natural band columns of v (contiguous in ky) for the column sums
+    if ((s = band_extract(P, vh, false, st))) return s;
+    hipLaunchKernelGGL(k_gram_lines, dim3(2 * g.e * g.L * g.npairs, 2), dim3(kThreads), P->lds_gram_lines, st, g, v,
+                       P->pcol, P->grow, P->gcol);
     LAUNCH_CHECK();
     const long ncor = (long)nwc * g.nc * 4 * g.e * g.e;
     hipLaunchKernelGGL(k_gram_corners, dim3((int)std::min<long>(4096, (ncor + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, st, g, v, P->gcor);
     LAUNCH_CHECK();
-    const long tot = (long)g.L * g.K * g.K;
-    hipLaunchKernelGGL(k_gram_assemble, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
-                       g, P->gC, P->grow, P->gcol, P->gcor, G);
+    hipLaunchKernelGGL(k_gram_assemble, dim3(nwc * g.nc), dim3(64), 0, st, g, P->gC, P->grow, P->gcol, P->gcor, G);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -502,6 +502,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
+    P->lds_gram_lines = (size_t)(1 + g.nc) * std::max(n1, n2) * sizeof(double2);
     P->TRw = (n1 == 16) ? 16 : (n1 == 32 ? 8 : 4);
     P->rows_blk = std::min(256, 64 * P->TRw / std::max(1, 64 / n1));
     P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
@@ -525,7 +526,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
     if (max_lds <= 0) max_lds = 65536;
-    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_band + 16 * sizeof(double) > (size_t)max_lds) {
+    if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_gram_lines > (size_t)max_lds ||
+        P->lds_band + 16 * sizeof(double) > (size_t)max_lds) {
         delete P;
         return SMSM_E_UNSUPPORTED;
     }
@@ -679,7 +681,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                             {(const void*)&k_col<COL_ADJ>, P->lds_col}, {(const void*)&k_col<COL_REG>, P->lds_col},
                             {(const void*)&k_gram_q<16>, P->lds_gram}, {(const void*)&k_gram_q<32>, P->lds_gram},
                             {(const void*)&k_gram_q<64>, P->lds_gram}, {(const void*)&k_gram_q<128>, P->lds_gram},
-                            {(const void*)&k_gram_q<256>, P->lds_gram}, {(const void*)P->band, P->lds_band}};
+                            {(const void*)&k_gram_q<256>, P->lds_gram}, {(const void*)P->band, P->lds_band},
+                            {(const void*)&k_gram_lines, P->lds_gram_lines}};
         for (const Opt& o : opts)
             if (hipFuncSetAttribute(o.f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)o.bytes) != hipSuccess)
                 ok = false;

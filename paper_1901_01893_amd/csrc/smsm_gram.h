@@ -103,74 +103,103 @@ k_gram_q(Geo g, const double2* __restrict__ h1, const double2* __restrict__ tw2,
 }
 
 // C[l][pair][d2][d1] = sum_x Q[l][pair][x][d2] e^{-2 pi i (d1-e)(x-n1/2)/n1}.
-// One wave per (l, pair, d2); lane = d1 + GS g sums the x of group g.
+// One wave per (l, pair, d2): the wave's Q column and the kx twiddles are
+// staged in shared memory in one batch, then lane = d1 + GS g sums the x of
+// group g (fixed order) and the groups are added in order.
 __global__ void __launch_bounds__(256)
 k_gram_c(Geo g, const double2* __restrict__ Q, const double2* __restrict__ tw1, double2* __restrict__ C) {
+    __shared__ double2 qs[4][256];
+    __shared__ double2 ts[256];
     const int n1 = g.n1, nc = g.nc, e = g.e;
-    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int wl = threadIdx.x >> 6;
+    const int wv = blockIdx.x * (blockDim.x >> 6) + wl;
     const int nwv = g.L * g.npairs * nc;
-    if (wv >= nwv) return;
-    const int gs = gram_gs(nc), ng = 64 / gs;
-    const int lane = threadIdx.x & 63, d1 = lane & (gs - 1), qg = lane / gs;
+    const int lane = threadIdx.x & 63;
     const int lp = wv / nc, d2 = wv - lp * nc;      // lp = l * npairs + pair
+    const bool live_wave = wv < nwv;
+    const double2* q = Q + (size_t)(live_wave ? lp : 0) * n1 * nc + d2;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int x = lane + 64 * u;
+        if (x < n1) qs[wl][x] = q[(size_t)x * nc];
+        if (wl == 0 && x < n1) ts[x] = tw1[x];
+    }
+    __syncthreads();
+    if (!live_wave) return;
+    const int gs = gram_gs(nc), ng = 64 / gs;
+    const int d1 = lane & (gs - 1), qg = lane / gs;
     const int xq = n1 / ng, x0 = qg * xq;
-    const double2* q = Q + (size_t)lp * n1 * nc + d2;
     double2 s = cmk(0.0, 0.0);
     if (d1 < nc) {
 #pragma unroll 8
-        for (int x = x0; x < x0 + xq; ++x)
-            s = cfma(q[(size_t)x * nc], tw1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
+        for (int x = x0; x < x0 + xq; ++x) s = cfma(qs[wl][x], ts[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
     }
     s = gram_reduce_groups(s, gs);
     if (qg == 0 && d1 < nc) C[((size_t)lp * nc + d2) * nc + d1] = s;
 }
 
-// Band row and column sums of z_d.  One wave per (kind, l, pair, fixed lag,
-// band line qa); lane = (free lag) + GS g sums the positions of group g:
+// Band row and column sums of z_d.  One workgroup per (band line qa, l,
+// pair) and kind (blockIdx.y: 0 rows, 1 columns):
 //   rows[l][pair][d2][d1][qa] = sum_q1 conj(x_i[q2][q1]) x_i'[q2+d2-e][q1+d1-e],  q2 = band row qa
 //   cols[l][pair][d2][d1][qa] = sum_q2 conj(x_i[q2][q1]) x_i'[q2+d2-e][q1+d1-e],  q1 = band col qa
-// (rows: wave fixes d2, lanes d1; cols: wave fixes d1, lanes d2).
+// The line of x_i and the 2r-1 lines of x_i' it meets are staged in shared
+// memory in one batch of loads (rows from the natural x, columns from the
+// natural band columns xcol = pcol of x, contiguous in ky); each (fixed lag,
+// free lag) is then summed by one thread from shared memory, in order.
+// Dynamic shared memory: (1 + 2r-1) max(n1, n2) double2.
+#define GRAM_STAGE 16
 __global__ void __launch_bounds__(256)
-k_gram_lines(Geo g, const double2* __restrict__ x, double2* __restrict__ rows, double2* __restrict__ cols) {
+k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ xcol, double2* __restrict__ rows,
+             double2* __restrict__ cols) {
+    extern __shared__ double2 sm[];
     const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
-    const int per = g.L * g.npairs * nc * e2;
-    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (wv >= 2 * per) return;
-    const bool col = wv >= per;
-    int t = col ? wv - per : wv;
-    const int qa = t % e2;
-    t /= e2;
-    const int fixed = t % nc;
-    const int lp = t / nc, l = lp / g.npairs, pair = lp - l * g.npairs;
+    const bool col = blockIdx.y == 1;
+    const int qa = blockIdx.x % e2, lp = blockIdx.x / e2, l = lp / g.npairs, pair = lp - l * g.npairs;
     int i, ip;
     gram_pair(pair, Ns, i, ip);
-    const int gs = gram_gs(nc), ng = 64 / gs;
-    const int lane = threadIdx.x & 63, fr = lane & (gs - 1), qg = lane / gs;
-    const double2* xi = x + ((size_t)l * Ns + i) * n2 * n1;
-    const double2* xj = x + ((size_t)l * Ns + ip) * n2 * n1;
-    double2 s = cmk(0.0, 0.0);
-    if (fr < nc) {
-        if (!col) {
-            const int q2 = qa < e ? qa : n2 - e2 + qa;
-            const double2* a = xi + (size_t)q2 * n1;
-            const double2* b = xj + (size_t)((q2 + fixed - e) & (n2 - 1)) * n1;
-            const int len = n1 / ng, q0 = qg * len;
-#pragma unroll 8
-            for (int q1 = q0; q1 < q0 + len; ++q1) s = cfma(cconj(a[q1]), b[(q1 + fr - e) & (n1 - 1)], s);
-        } else {
-            const int q1 = qa < e ? qa : n1 - e2 + qa;
-            const int c1 = (q1 + fixed - e) & (n1 - 1);
-            const int len = n2 / ng, q0 = qg * len;
-#pragma unroll 8
-            for (int q2 = q0; q2 < q0 + len; ++q2)
-                s = cfma(cconj(xi[(size_t)q2 * n1 + q1]), xj[(size_t)((q2 + fr - e) & (n2 - 1)) * n1 + c1], s);
+    const int n = col ? n2 : n1;
+    double2* a = sm;           // [n]
+    double2* b = sm + n;       // [nc][n]
+    // stage: entry k < n is a[k]; entry n + f n + q is b[f][q].  Each entry is
+    // base[line * ls + q] with the line picked arithmetically, so the loads of
+    // a batch carry no branches and are all in flight together.
+    const int q2a = qa < e ? qa : n2 - e2 + qa, q1a = qa < e ? qa : n1 - e2 + qa;
+    const double2* base_i = col ? xcol + ((size_t)l * Ns + i) * 4 * e * n2 : x + ((size_t)l * Ns + i) * n2 * n1;
+    const double2* base_j = col ? xcol + ((size_t)l * Ns + ip) * 4 * e * n2 : x + ((size_t)l * Ns + ip) * n2 * n1;
+    const int ls = col ? n2 : n1;
+    const int line_a = col ? band_pcol(q1a, n1, e) : q2a;
+    const int tot = (1 + nc) * n;
+    for (int base = threadIdx.x; base < tot; base += GRAM_STAGE * blockDim.x) {
+        double2 v[GRAM_STAGE];
+#pragma unroll
+        for (int u = 0; u < GRAM_STAGE; ++u) {
+            const int k0 = base + u * blockDim.x, k = k0 < tot ? k0 : tot - 1;
+            const bool isa = k < n;
+            const int f = isa ? 0 : (k - n) / n, q = isa ? k : (k - n) - f * n;
+            const int line_b = col ? band_pcol((q1a + f - e) & (n1 - 1), n1, e) : (q2a + f - e) & (n2 - 1);
+            const double2* bp = isa ? base_i : base_j;
+            v[u] = bp[(size_t)(isa ? line_a : line_b) * ls + q];
+        }
+#pragma unroll
+        for (int u = 0; u < GRAM_STAGE; ++u) {
+            const int k0 = base + u * blockDim.x;
+            sm[k0 < tot ? k0 : tot - 1] = v[u];
         }
     }
-    s = gram_reduce_groups(s, gs);
-    if (qg == 0 && fr < nc) {
-        const int d2 = col ? fr : fixed, d1 = col ? fixed : fr;
-        const size_t o = (((size_t)lp * nc + d2) * nc + d1) * e2 + qa;
-        (col ? cols : rows)[o] = s;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc * nc; t += blockDim.x) {
+        const int fx = t / nc, fr = t - fx * nc;   // fixed lag, free lag
+        const double2* bf = b + (size_t)fx * n;
+        // four interleaved partial sums (q mod 4), added in a fixed order at the end
+        double2 s4[4] = {cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0)};
+#pragma unroll 2
+        for (int q = 0; q < n; q += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] = cfma(cconj(a[q + u]), bf[(q + u + fr - e) & (n - 1)], s4[u]);
+        }
+        const double2 s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
+        const int d2 = col ? fr : fx, d1 = col ? fx : fr;
+        (col ? cols : rows)[(((size_t)lp * nc + d2) * nc + d1) * e2 + qa] = s;
     }
 }
 
@@ -199,42 +228,49 @@ __global__ void k_gram_corners(Geo g, const double2* __restrict__ x, double2* __
 
 // G[l][row][col] for row <= col (mirrored as the conjugate).  The band lines
 // an anchor window at offset b misses are [0, b) and [e + b, 2e) in band order.
-__global__ void k_gram_assemble(Geo g, const double2* __restrict__ C, const double2* __restrict__ rows,
-                                const double2* __restrict__ cols, const double2* __restrict__ cor,
-                                double2* __restrict__ G) {
+// One 64-thread workgroup per lag group o = (l, pair, d2, d1): its band row,
+// column and corner sums are staged in shared memory once, then each thread
+// assembles the entries (b2, b1) of the group, summing in band order.
+__global__ void __launch_bounds__(64)
+k_gram_assemble(Geo g, const double2* __restrict__ C, const double2* __restrict__ rows,
+                const double2* __restrict__ cols, const double2* __restrict__ cor, double2* __restrict__ G) {
+    __shared__ double2 rs[16], cs[16], xs[256];
     const int K = g.K, r = g.r, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
-    const long total = (long)g.L * K * K;
-    const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    const int l = (int)(idx / ((long)K * K));
-    const int rc = (int)(idx - (long)l * K * K);
-    const int row = rc / K, col = rc - row * K;
-    if (row > col) return;
-    const int rr2 = r * r;
-    const int i = row / rr2, b2 = (row % rr2) / r, b1 = row % r;
-    const int ip = col / rr2, c2 = (col % rr2) / r, c1 = col % r;
-    const int pair = i * Ns - (i * (i - 1)) / 2 + (ip - i);
-    const int d2 = c2 - b2 + e, d1 = c1 - b1 + e;
-    const size_t o = (((size_t)l * g.npairs + pair) * nc + d2) * nc + d1;
-    const double2* ro = rows + o * e2;
-    const double2* co = cols + o * e2;
-    const double2* cr = cor + o * e2 * e2;
-    double2 sr = cmk(0.0, 0.0), sc = cmk(0.0, 0.0), sx = cmk(0.0, 0.0);
-    for (int q = 0; q < b2; ++q) sr = cadd(sr, ro[q]);
-    for (int q = e + b2; q < e2; ++q) sr = cadd(sr, ro[q]);
-    for (int q = 0; q < b1; ++q) sc = cadd(sc, co[q]);
-    for (int q = e + b1; q < e2; ++q) sc = cadd(sc, co[q]);
-    for (int seg = 0; seg < 2; ++seg) {
-        const int qa0 = seg ? e + b2 : 0, qa1 = seg ? e2 : b2;
-        for (int qa = qa0; qa < qa1; ++qa) {
-            const double2* crow = cr + qa * e2;
-            for (int qb = 0; qb < b1; ++qb) sx = cadd(sx, crow[qb]);
-            for (int qb = e + b1; qb < e2; ++qb) sx = cadd(sx, crow[qb]);
-        }
+    const int o = blockIdx.x;                         // ((l npairs + pair) nc + d2) nc + d1
+    const int d1 = o % nc, d2 = (o / nc) % nc, lp = o / (nc * nc);
+    const int l = lp / g.npairs, pair = lp - l * g.npairs;
+    int i, ip;
+    gram_pair(pair, Ns, i, ip);
+    if (threadIdx.x < e2) {
+        rs[threadIdx.x] = rows[(size_t)o * e2 + threadIdx.x];
+        cs[threadIdx.x] = cols[(size_t)o * e2 + threadIdx.x];
     }
-    double2 v = cadd(csub(csub(C[o], sr), sc), sx);
+    for (int k = threadIdx.x; k < e2 * e2; k += blockDim.x) xs[k] = cor[(size_t)o * e2 * e2 + k];
+    const double2 c0 = C[o];
+    __syncthreads();
     double2* Gl = G + (size_t)l * K * K;
-    if (row == col) v.y = 0.0;
-    Gl[(size_t)row * K + col] = v;
-    if (row != col) Gl[(size_t)col * K + row] = cconj(v);
+    for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+        const int b2 = t / r, b1 = t - b2 * r;
+        const int c2 = b2 + d2 - e, c1 = b1 + d1 - e;
+        if (c2 < 0 || c2 >= r || c1 < 0 || c1 >= r) continue;
+        const int row = (i * r + b2) * r + b1, col = (ip * r + c2) * r + c1;
+        if (row > col) continue;
+        double2 sr = cmk(0.0, 0.0), sc = cmk(0.0, 0.0), sx = cmk(0.0, 0.0);
+        for (int q = 0; q < b2; ++q) sr = cadd(sr, rs[q]);
+        for (int q = e + b2; q < e2; ++q) sr = cadd(sr, rs[q]);
+        for (int q = 0; q < b1; ++q) sc = cadd(sc, cs[q]);
+        for (int q = e + b1; q < e2; ++q) sc = cadd(sc, cs[q]);
+        for (int seg = 0; seg < 2; ++seg) {
+            const int qa0 = seg ? e + b2 : 0, qa1 = seg ? e2 : b2;
+            for (int qa = qa0; qa < qa1; ++qa) {
+                const double2* crow = xs + qa * e2;
+                for (int qb = 0; qb < b1; ++qb) sx = cadd(sx, crow[qb]);
+                for (int qb = e + b1; qb < e2; ++qb) sx = cadd(sx, crow[qb]);
+            }
+        }
+        double2 v = cadd(csub(csub(c0, sr), sc), sx);
+        if (row == col) v.y = 0.0;
+        Gl[(size_t)row * K + col] = v;
+        if (row != col) Gl[(size_t)col * K + row] = cconj(v);
+    }
 }
