@@ -210,7 +210,8 @@ ColCg no_cg() {
 // band rows (prow) unless the fast column pass already wrote them.
 smsm_status band_extract(smsm_plan* P, const double2* in, bool write_prow, hipStream_t st) {
     const Geo& g = P->g;
-    hipLaunchKernelGGL(k_band_extract, dim3((g.n2 / 16) * (P->np_band / 16), g.B), dim3(kThreads), 0, st, g.n1,
+    hipLaunchKernelGGL(k_band_extract, dim3((g.n2 / 16) * (P->np_band / 16), g.B), dim3(64 * EXTRACT_WAVES), 0, st,
+                       g.n1,
                        g.n2, g.e, P->np_band, in, P->fx, P->pcol, P->prow, write_prow ? 1 : 0);
     LAUNCH_CHECK();
     return SMSM_OK;
@@ -268,7 +269,7 @@ smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
     a.alpha = P->cgs + 3;
     const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
     void* args[] = {&a};
-    if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(kThreads), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
+    if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(64 * HYB_WAVES), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -508,8 +509,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     {
         const int LY = std::min(64, n2), XPS = 64 / LY;
-        P->hyb_xw = std::min(4, n1 / (4 * XPS));
-        P->hyb_grid = dim3((n2 / LY) * (n1 / (4 * P->hyb_xw * XPS)), g.B);
+        P->hyb_xw = std::min(4, n1 / (HYB_WAVES * XPS));
+        if (P->hyb_xw < 1) { delete P; return SMSM_E_UNSUPPORTED; }   // n1 < HYB_WAVES (64 / min(n2, 64))
+        P->hyb_grid = dim3((n2 / LY) * (n1 / (HYB_WAVES * P->hyb_xw * XPS)), g.B);
         P->npr = (int)(P->hyb_grid.x * P->hyb_grid.y);
     }
     P->np_band = 16 * ((4 * g.e + 15) / 16);

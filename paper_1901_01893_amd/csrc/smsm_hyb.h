@@ -7,7 +7,8 @@
 #pragma once
 #include "smsm_dense.h"
 
-#define EXTRACT_KS 16   // k steps (4 x each) per wave of k_band_extract: n1 / 16
+#define EXTRACT_WAVES 8                      // waves per workgroup of k_band_extract (split x)
+#define EXTRACT_KS (64 / EXTRACT_WAVES)      // k steps (4 x each) per wave at most (n1 <= 256)
 
 // Natural columns of p within 2e of the kx edges:
 //   pcol[b][c][ky] = sum_x fx[x][c] pt[b][x][ky],
@@ -20,11 +21,11 @@
 // rows within 2e of the ky edges, transposed: prow[b][j][x], j = ky for
 // ky < 2e, else ky - (n2 - 4e) (the band rows' kx taps then read contiguous
 // x); the fast column pass writes that copy itself.
-// grid (n2/16 * np/16, B), block 256; np = padded width of fx.
-__global__ void __launch_bounds__(256)
+// grid (n2/16 * np/16, B), block 64 EXTRACT_WAVES; np = padded width of fx.
+__global__ void __launch_bounds__(64 * EXTRACT_WAVES)
 k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, const double2* __restrict__ fx,
                double2* __restrict__ pcol, double2* __restrict__ prow, int write_prow) {
-    __shared__ double acc[4][8][64];
+    __shared__ double acc[EXTRACT_WAVES][8][64];
     const int b = blockIdx.y;
     const int nct = np / 16, t = blockIdx.x, mt = t / nct, ct = t - mt * nct;
     const int ky0 = mt * 16, c0 = ct * 16;
@@ -33,14 +34,14 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
     const double2* Bp = fx + (size_t)kq * np + c0 + (lane & 15);               // fx[x][c]
     // k steps of 4 x per wave: nks / 4 <= EXTRACT_KS (n1 <= 256); every load
     // of the wave is issued before the first product
-    const int nks = n1 / 4, ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
+    const int nks = n1 / 4, ks0 = (w * nks) / EXTRACT_WAVES, ks1 = ((w + 1) * nks) / EXTRACT_WAVES;
     // complex product with three real products (Gauss):
     //   t1 = (ar + ai) br, t2 = ar (bi - br), t3 = ai (br + bi); re = t1 - t3, im = t1 + t2
     hd4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0}, t3 = {0.0, 0.0, 0.0, 0.0};
     double2 av[EXTRACT_KS], bv[EXTRACT_KS];
 #pragma unroll
     for (int u = 0; u < EXTRACT_KS; ++u) {
-        const int k = 4 * min(ks0 + u, ks1 - 1);
+        const int k = 4 * max(min(ks0 + u, ks1 - 1), 0);   // a wave with no k step reads row 0
         av[u] = Ap[(size_t)k * n2];
         bv[u] = Bp[(size_t)k * np];
     }
@@ -67,15 +68,17 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
         acc[w][4 + v][lane] = t1[v] + t2[v];
     }
     __syncthreads();
-    const int v = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    double2 c = cmk(0.0, 0.0);
+    if (threadIdx.x < 256) {   // one thread per tile element: register v of lane ln
+        const int v = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        double2 c = cmk(0.0, 0.0);
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
-        c.x += acc[ww][v][ln];
-        c.y += acc[ww][4 + v][ln];
+        for (int ww = 0; ww < EXTRACT_WAVES; ++ww) {
+            c.x += acc[ww][v][ln];
+            c.y += acc[ww][4 + v][ln];
+        }
+        const int ky = ky0 + 4 * v + (ln >> 4), col = c0 + (ln & 15);
+        if (col < 4 * e) pcol[((size_t)b * 4 * e + col) * n2 + ky] = c;
     }
-    const int ky = ky0 + 4 * v + (ln >> 4), col = c0 + (ln & 15);
-    if (col < 4 * e) pcol[((size_t)b * 4 * e + col) * n2 + ky] = c;
 }
 
 // Vector pass on the hybrid layout after the column pass (and the band
@@ -107,9 +110,10 @@ struct HybArgs {
 
 #define HYB_MAX_E2 16
 #define HYB_CONST __attribute__((address_space(4)))
-#define HYB_CS_PER_THREAD 4   // HYB_MAX_E2 * 64 / 256 staged values per thread (corrections, finv rows)
+#define HYB_WAVES 4   // waves per workgroup of the vector pass
+#define HYB_CS_PER_THREAD (HYB_MAX_E2 / HYB_WAVES)   // staged corrections per thread (HYB_MAX_E2 x 64 entries)
 template <int MODE, int XW, bool WU, bool BAND>
-__global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
+__global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     __shared__ double red[8];
     __shared__ double2 cs[BAND ? HYB_MAX_E2 * 64 : 1];    // corrections [cl][ky in chunk]
     const Geo& g = a.g;
@@ -119,7 +123,7 @@ __global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int kc = blockIdx.x % nkc, xb = blockIdx.x / nkc, b = blockIdx.y;
     const int ky = kc * LY + lane % LY, xs = lane / LY;
-    const int x0 = (xb * 4 + wave) * XW * XPS;
+    const int x0 = (xb * HYB_WAVES + wave) * XW * XPS;
     const double2* __restrict__ h2 = a.h2;
     const double2* __restrict__ pv = a.p;
     double2* __restrict__ xv = a.x;
@@ -134,7 +138,7 @@ __global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
         const int ncs = e2 * LY, ds = a.bi.ds;
 #pragma unroll
         for (int u = 0; u < HYB_CS_PER_THREAD; ++u) {
-            const int idx0 = threadIdx.x + u * 256;
+            const int idx0 = threadIdx.x + u * 64 * HYB_WAVES;
             const int idx = idx0 < ncs ? idx0 : ncs - 1;
             const int cl = idx / LY, kyl = idx - cl * LY, kyc = kc * LY + kyl;
             double2 v[BAND_MAX_DS];
@@ -176,7 +180,7 @@ __global__ void __launch_bounds__(256) k_hyb_update(HybArgs a) {
         // (threads past the end rewrite the last entry with its own value)
 #pragma unroll
         for (int u = 0; u < HYB_CS_PER_THREAD; ++u) {
-            const int i0 = threadIdx.x + u * 256;
+            const int i0 = threadIdx.x + u * 64 * HYB_WAVES;
             const int ic = i0 < ncs ? i0 : ncs - 1, cl = ic / LY, kyl = ic - cl * LY;
             cs[cl * 64 + kyl] = cv[u];
         }
