@@ -12,9 +12,9 @@
 //   inverse  M-point inverse DFT (decimation in time: bit-reversed in,
 //            natural order out)
 //   unfold   acc_s[t] += conj(S_{s,c}[m + M t]) g_s[m]
-// Lane exchanges use DPP for xor distances 1..8 and the LDS crossbar
-// (ds_swizzle / ds_bpermute) for 16 and 32; all 64 lanes stay active through
-// every exchange.
+// Lane exchanges use DPP for xor distances 1, 2 and 8 and the LDS crossbar
+// (ds_swizzle / ds_bpermute) for 4, 16 and 32; all 64 lanes stay active
+// through every exchange.
 #pragma once
 #include "smsm_kernels.h"
 
@@ -26,14 +26,17 @@ SMSM_DEV double dpp_d(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// xor 16 and xor 32 go through the LDS crossbar (ds_swizzle in xor mode
-// within 32-lane halves, ds_bpermute across halves): they issue on the LDS
-// pipe and leave the vector ALU to the butterflies.  (A DPP pair or a
-// permlane swap plus select costs two VALU issues per dword.)
-SMSM_DEV double swz_xor16_d(double v) {
+// xor 4, xor 16 and xor 32 go through the LDS crossbar (ds_swizzle in xor
+// mode within 32-lane halves, ds_bpermute across halves): they issue on the
+// LDS pipe and leave the vector ALU to the butterflies.  (A DPP pair or a
+// permlane swap plus select costs two VALU issues per dword; xor 1, 2 and 8
+// are single DPP moves and stay on the vector ALU, which measured faster than
+// moving them to the LDS pipe as well.)
+template <int H>
+SMSM_DEV double swz_xor_d(double v) {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x1F | (16 << 10));
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x1F | (16 << 10));
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x1F | (H << 10));
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x1F | (H << 10));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 SMSM_DEV double perm_xor32_d(double v) {
@@ -49,9 +52,9 @@ template <int MASK>
 SMSM_DEV double lane_xor(double v) {
     if constexpr (MASK == 1) return dpp_d<0xB1>(v);                 // quad_perm [1,0,3,2]
     else if constexpr (MASK == 2) return dpp_d<0x4E>(v);            // quad_perm [2,3,0,1]
-    else if constexpr (MASK == 4) return dpp_d<0x1B>(dpp_d<0x141>(v));  // half-mirror (^7), then ^3
+    else if constexpr (MASK == 4) return swz_xor_d<4>(v);
     else if constexpr (MASK == 8) return dpp_d<0x128>(v);           // row_ror:8 (within 16 lanes: ^8)
-    else if constexpr (MASK == 16) return swz_xor16_d(v);
+    else if constexpr (MASK == 16) return swz_xor_d<16>(v);
     else return perm_xor32_d(v);
 }
 

@@ -2,7 +2,8 @@
 generic column pass (shot counts without a register-resident instance), the
 band kernel for 1, 2 and 8 shots, the vector pass with fewer than 64 ky per
 row, a coil count that leaves a partial coil group, and the fast column pass
-at a folded length of 32.  Each case checks the normal operator with the
+at folded lengths 32 and 64 (the latter with two slices and an odd coil
+count).  Each case checks the normal operator with the
 oracle's weights and a short IRLS solve against the oracle's."""
 import numpy as np
 import pytest
@@ -29,6 +30,10 @@ GEOMS = {
     # fast column pass <32, 2>, 6 coils (a partial coil group), band kernel <7, 4>
     "n128_L2_Ns4_r4": (si.Geometry(n=128, n_slices=2, n_shots=4, n_coils=6, filt=4, lam=1e-3, n_irls=3, n_cg=4,
                                    phase_order=2, snr=30.0), 104),
+    # fast column pass <64, 2> (two slices at folded length 64), 5 coils (the last
+    # coil group has a clamped, zero-weighted member), band kernel <5, 4>
+    "n256_L2_Ns4_r3": (si.Geometry(n=256, n_slices=2, n_shots=4, n_coils=5, filt=3, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=2, snr=30.0), 105),
 }
 
 
