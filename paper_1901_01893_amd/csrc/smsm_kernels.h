@@ -370,17 +370,15 @@ __host__ __device__ inline int band_row_items(const Geo& g) { return 2 * g.e * (
 __host__ __device__ inline int band_items(const Geo& g) {
     return band_col_items(g) + band_row_items(g) + 4 * g.e * g.e;
 }
-// shared memory of a column item: the p patch, then the share's side-table
-// slice (reused for the cross-shot reduction afterwards)
+// shared memory of a column item: the p patch (reused for the cross-shot
+// reduction afterwards)
 __host__ __device__ inline size_t band_patch_len(const Geo& g) {
     const int ds = band_ds(g.Ns, g.nc);
     return (size_t)g.Ns * ((g.nc + ds - 1) / ds) * (BAND_SEG + 2 * g.e);
 }
 __host__ __device__ inline size_t band_lds_bytes(const Geo& g) {
-    const int ds = band_ds(g.Ns, g.nc);
-    const size_t tab = (size_t)g.Ns * g.nc * ((g.nc + ds - 1) / ds) * g.Ns;
     const size_t red = (size_t)g.Ns * g.Ns * BAND_SEG;
-    const size_t m = band_patch_len(g) + tab > red ? band_patch_len(g) + tab : red;
+    const size_t m = band_patch_len(g) > red ? band_patch_len(g) : red;
     return (m > 8 ? m : 8) * sizeof(double2);
 }
 // slot of line k (within 2e of an edge of a length-n axis) in the band copies
@@ -401,11 +399,14 @@ struct BandArgs {
 };
 
 template <int NC, int NS>
-SMSM_DEV void band_col_sum(const double2* __restrict__ Pw, int PP, const double2* __restrict__ Dl, int nr,
+SMSM_DEV void band_col_sum(const double2* __restrict__ Pw, int PP, const double2* Dg, int nr,
                            double2 (&acc)[NS]) {
     // Pw: patch of this wave's shot at (first tap column of the share, this
-    // lane's pixel); Dl: the share's side-table slice of this wave's shot in
-    // shared memory, [d2][d1 - dl0][i'] (wave-uniform reads)
+    // lane's pixel); Dg: the side table of this wave's shot at the share's
+    // first tap column, [d2][d1][i'] in global memory, read through the
+    // constant address space (wave-uniform scalar loads)
+    const __attribute__((address_space(4))) double* D4 =
+        (const __attribute__((address_space(4))) double*)(uintptr_t)Dg;
     for (int rr = 0; rr < nr; ++rr) {
         const double2* Pr = Pw + rr * PP;
         double2 pv[NC];
@@ -413,9 +414,9 @@ SMSM_DEV void band_col_sum(const double2* __restrict__ Pw, int PP, const double2
         for (int dp = 0; dp < NC; ++dp) pv[dp] = Pr[dp];
 #pragma unroll
         for (int dp = 0; dp < NC; ++dp) {
-            const double2* dd = Dl + (dp * nr + rr) * NS;
+            const int o = 2 * ((dp * NC + rr) * NS);
 #pragma unroll
-            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(dd[ip], pv[dp], acc[ip]);
+            for (int ip = 0; ip < NS; ++ip) acc[ip] = cfma(cmk(D4[o + 2 * ip], D4[o + 2 * ip + 1]), pv[dp], acc[ip]);
         }
     }
 }
@@ -468,31 +469,13 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
                 sm[i0 < tot ? i0 : tot - 1] = v[u];
             }
         }
-        // the share's side-table slice: Ds[i][d2][d1 - dl0][i'] (contiguous in
-        // d1, i' for each i, d2)
-        double2* Ds = sm + band_patch_len(g);
         const double2* Dsrc = a.Dside + ((size_t)l * 4 * e + side * e + delta) * NS * NC * NC * NS;
-        const int ndt = NS * NC * nr * NS, run = nr * NS;
-        for (int base = threadIdx.x; base < ndt; base += BAND_STAGE * blockDim.x) {
-            double2 v[BAND_STAGE];
-#pragma unroll
-            for (int u = 0; u < BAND_STAGE; ++u) {
-                const int i0 = base + u * blockDim.x, idx = i0 < ndt ? i0 : ndt - 1;
-                const int idp = idx / run, k = idx - idp * run;   // idp = i * NC + d2
-                v[u] = Dsrc[((size_t)idp * NC + dl0) * NS + k];
-            }
-#pragma unroll
-            for (int u = 0; u < BAND_STAGE; ++u) {
-                const int i0 = base + u * blockDim.x;
-                Ds[i0 < ndt ? i0 : ndt - 1] = v[u];
-            }
-        }
         __syncthreads();
         const double2* Pw = sm + (size_t)w * nr * PP + min(lane, npos - 1);
         double2 acc[NS];
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) acc[ip] = cmk(0.0, 0.0);
-        band_col_sum<NC, NS>(Pw, PP, Ds + (size_t)w * NC * run, nr, acc);
+        band_col_sum<NC, NS>(Pw, PP, Dsrc + ((size_t)w * NC * NC + dl0) * NS, nr, acc);
         __syncthreads();
 #pragma unroll
         for (int ip = 0; ip < NS; ++ip) sm[((size_t)w * NS + ip) * BAND_SEG + lane] = acc[ip];
@@ -517,8 +500,10 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
             const double2 pout = a.prow[((size_t)(l * NS + ip) * 4 * e + band_pcol(ky, n2, e)) * n1 + x];
             const double2* dh = a.Dhat + ((size_t)(l * 2 * e + line) * NS * NC * NS) * n1 + x;
             double2 s = cmk(0.0, 0.0);
-            // two input shots per round: 4 NC loads in flight
-            constexpr int IR = NS >= 2 ? 2 : 1;
+            // one input shot per round, its 2 NC loads issued as one batch
+            // (two shots per round need more registers than the column items
+            // sharing this kernel can spare)
+            constexpr int IR = 1;
             for (int i0 = 0; i0 < NS; i0 += IR) {
                 double2 dv[IR][NC], pv[IR][NC];
 #pragma unroll
@@ -531,6 +516,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
                         pv[u][d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int u = 0; u < IR; ++u)
 #pragma unroll
@@ -564,6 +550,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
 #pragma unroll
             for (int ip = 0; ip < NS; ++ip) dc[it][ip] = Dc[(size_t)t * NS + ip];
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const double live = threadIdx.x + it * TPB < nt ? 1.0 : 0.0;
