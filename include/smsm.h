@@ -160,6 +160,18 @@ smsm_status smsm_apply_reg(smsm_plan* plan, const void* x_dev, void* out_dev, vo
 /* out = N(x) = A^H A x + (lambda/2) sum_l H_l^H(H_l(x_l) W_l), c128 -> c128. */
 smsm_status smsm_apply_normal(smsm_plan* plan, const void* x_dev, void* out_dev, void* stream);
 
+/* Root-sum-of-squares image of each slice,
+ *     img[l][y][x] = sqrt(sum_i |F^-1(x_{l,i})[y][x]|^2),
+ * with F^-1 the centred unitary inverse 2-D DFT of the forward model (Fig. 1):
+ * the per-shot images of the reconstructed k-space combined over shots (the
+ * paper compares against single-band images without saying how shots are
+ * combined; root-sum-of-squares is the reading used).  x_dev c128
+ * [L][Ns][n2][n1] (k-space, as smsm_solve writes it with SMSM_FLAG_X_C128) ->
+ * img_dev double [L][n2][n1] (image, y-major, x contiguous), caller-owned
+ * device memory.  Uses the plan's scratch vectors; asynchronous on `stream`.
+ * Errors: SMSM_E_INVALID for null arguments, SMSM_E_DEVICE if a launch fails. */
+smsm_status smsm_images_sos(smsm_plan* plan, const void* x_dev, void* img_dev, void* stream);
+
 /* ---- diagnostics ------------------------------------------------------- */
 
 /* Kernels that smsm_launch_kernel can re-run.  CG runs on the hybrid layout

@@ -892,6 +892,26 @@ smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, vo
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, true, S(stream));
 }
 
+smsm_status smsm_images_sos(smsm_plan* P, const void* x_dev, void* img_dev, void* stream) {
+    if (!P || !x_dev || !img_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const Geo& g = P->g;
+    hipStream_t st = S(stream);
+    smsm_status s = rows_inv(P, (const double2*)x_dev, P->h1, st);
+    if (s) return s;
+    const dim3 grid(g.n1, g.L);
+    double* img = (double*)img_dev;
+    switch (g.n2) {
+        case 16: hipLaunchKernelGGL(k_sos_cols<16>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
+        case 32: hipLaunchKernelGGL(k_sos_cols<32>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
+        case 64: hipLaunchKernelGGL(k_sos_cols<64>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
+        case 128: hipLaunchKernelGGL(k_sos_cols<128>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
+        default: hipLaunchKernelGGL(k_sos_cols<256>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
+    }
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
 }  // extern "C"
 
 namespace {

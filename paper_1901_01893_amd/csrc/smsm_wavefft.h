@@ -153,3 +153,54 @@ k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
         out[img + (size_t)(j0 + jr) * N + k] = sm[jr * ST + k];
     }
 }
+
+// ---------------------------------------------------------------------------
+// Root-sum-of-squares image of each slice (the per-shot images of the forward
+// model combined over shots):
+//   out[l][y][x] = sqrt(sum_i |u_{l,i}[y][x]|^2),
+// u the centred unitary inverse DFT along ky of the hybrid rows
+// h[l Ns + i][x][.] (the kx transform is already done).  grid (n1, L),
+// block 64: lanes in groups of LANES = min(N, 64) points, one shot per group
+// at a time; the groups' partial sums are added in group order.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64) k_sos_cols(Geo g, const double2* __restrict__ h,
+                                                 const double2* __restrict__ tw2, double* __restrict__ out) {
+    using F = WaveFft<N>;
+    constexpr int R = F::R, LANES = F::LANES, G = 64 / LANES;
+    __shared__ double part[G][N];
+    const int x = blockIdx.x, l = blockIdx.y, lane = threadIdx.x;
+    F f;
+    f.setup(tw2, lane);
+    const int grp = lane / LANES;
+    const double sc = 1.0 / sqrt((double)N);
+    double acc[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) acc[t] = 0.0;
+    for (int i0 = 0; i0 < g.Ns; i0 += G) {
+        const int i = i0 + grp;
+        const double live = i < g.Ns ? 1.0 : 0.0;
+        const size_t o = ((size_t)(l * g.Ns + min(i, g.Ns - 1)) * g.n1 + x) * N;
+        double2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int k = f.m + 64 * t;
+            v[t] = cscale(h[o + k], sgn_pow(k));
+        }
+        f.template run<true>(v);
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int n = f.out_index(t);
+            acc[t] += live * cabs2(cscale(v[t], sc * sgn_pow(n)));
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) part[grp][f.out_index(t)] = acc[t];
+    __syncthreads();
+    for (int y = lane; y < N; y += 64) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) s += part[q][y];
+        out[((size_t)l * g.n2 + y) * g.n1 + x] = sqrt(s);
+    }
+}

@@ -29,7 +29,7 @@ ABI_SYMBOLS = (
     "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_plan_set_params",
     "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
-    "smsm_apply_reg", "smsm_apply_normal", "smsm_launch_kernel", "smsm_kernel_cost",
+    "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5, "cg_alpha": 6}
 
@@ -80,7 +80,7 @@ def lib() -> ctypes.CDLL:
         L.smsm_status_string.argtypes = [st]
         L.smsm_status_string.restype = ctypes.c_char_p
         for name in ("smsm_apply_A", "smsm_apply_AH", "smsm_apply_AHA", "smsm_gram", "smsm_lambda_max",
-                     "smsm_apply_reg", "smsm_apply_normal"):
+                     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos"):
             f = getattr(L, name)
             f.argtypes = [vp, vp, vp, vp]
             f.restype = st
@@ -233,6 +233,17 @@ class Plan:
     def apply_normal(self, x, out=None, stream=None):
         import torch
         return self._unary("smsm_apply_normal", x, torch.complex128, self.shape_x, self.shape_x, out, stream)
+
+    def images_sos(self, x, out=None, stream=None):
+        """Root-sum-of-squares image per slice of k-space x (c128 [L][Ns][n2][n1]) -> float64 [L][n2][n1]."""
+        import torch
+        shape = (self.geom.n_slices, self.geom.n2, self.geom.n1)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=x.device)
+        xp = _dev_ptr(x, torch.complex128, self.shape_x, "x")
+        op = _dev_ptr(out, torch.float64, shape, "img")
+        _check(lib().smsm_images_sos(self._h, xp, op, _stream_ptr(stream)), "smsm_images_sos")
+        return out
 
     def lambda_max(self, G, stream=None):
         import torch

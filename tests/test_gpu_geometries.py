@@ -96,3 +96,14 @@ def test_solve_matches_oracle(geo):
     err = o.nrmse(x, ref)
     print(f"[solve {geo['name']}] NRMSE vs oracle = {err:.3e}", flush=True)
     assert err < SOLVE_TOL
+
+
+def test_images_sos_matches_oracle(geo):
+    # root-sum-of-squares images of random k-space (every n2 and shot count of the geometries)
+    torch, dev, g = geo["torch"], geo["dev"], geo["g"]
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((g.n_slices, g.n_shots, g.n, g.n)) + 1j * rng.standard_normal(
+        (g.n_slices, g.n_shots, g.n, g.n))
+    got = geo["plan"].images_sos(to_dev(torch, dev, x)).cpu().numpy()
+    assert got.shape == (g.n_slices, g.n, g.n)
+    assert rel(got, o.sos_images(x)) < 1e-12

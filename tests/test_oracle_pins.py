@@ -410,3 +410,35 @@ def test_objective_is_smoothed_objective_at_zero_eps():
     a = o.objective(x, y, coils, masks, theta, 0.3, 3)
     b = o.smoothed_objective(x, y, coils, masks, theta, 0.3, 3, [0.0, 0.0])
     assert abs(a - b) < 1e-10 * abs(a)
+
+
+# ----------------------------------------------------------------------------
+# Root-sum-of-squares shot combination (the optional image output)
+# ----------------------------------------------------------------------------
+def test_sos_images_parseval_per_slice():
+    # the image transform is unitary: sum over pixels of sos^2 is the k-space energy of the slice's shots
+    rng = np.random.default_rng(31)
+    x = crand(rng, 2, 3, 16, 8)
+    img = o.sos_images(x)
+    assert img.shape == (2, 16, 8) and np.all(img >= 0)
+    for l in range(2):
+        assert abs(np.sum(img[l] ** 2) - np.sum(np.abs(x[l]) ** 2)) <= RTOL * np.sum(np.abs(x[l]) ** 2)
+
+
+def test_sos_images_unit_modulus_phases_closed_form():
+    # shots rho * phi_i with |phi_i| = 1 combine to sqrt(Ns) |rho|, whatever the phases
+    rng = np.random.default_rng(32)
+    n, Ns = 16, 4
+    rho = crand(rng, 2, n, n)
+    phi = np.exp(1j * rng.uniform(0, 2 * np.pi, (2, Ns, n, n)))
+    img = o.sos_images(np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(rho[:, None] * phi, axes=(-2, -1)),
+                                                   norm="ortho"), axes=(-2, -1)))
+    assert rel(img, np.sqrt(Ns) * np.abs(rho)) < RTOL
+
+
+def test_sos_images_single_shot_delta():
+    # one shot, a k-space delta at the centre: a flat image of height 1/N
+    n = 8
+    x = np.zeros((1, 1, n, n), complex)
+    x[0, 0, n // 2, n // 2] = 1.0
+    assert np.allclose(o.sos_images(x), 1.0 / n, rtol=0, atol=1e-15)
