@@ -201,6 +201,26 @@ smsm_status smsm_launch_kernel(smsm_plan* plan, int kernel_id, int reps, void* s
  * plan's geometry: FP64 flops and compulsory HBM bytes (reads + writes). */
 smsm_status smsm_kernel_cost(const smsm_plan* plan, int kernel_id, double* flops, double* bytes);
 
+/* Per-launch timing of one kernel inside whatever the plan runs next (a
+ * solve, operator chains, smsm_launch_kernel): one launch in every `stride`
+ * of `kernel_id` (the first, then every stride-th), up to `capacity` of them,
+ * is dispatched with a start/stop event pair (the timestamps of the dispatch
+ * itself; nothing is added to the stream, but a timed dispatch starts a few
+ * microseconds later, so a stride well above 1 keeps the timed work close to
+ * the untimed one).  capacity 0 turns timing off and releases the events.
+ * Only SMSM_KERNEL_COL_NORMAL on the fast column pass is supported
+ * (otherwise SMSM_E_UNSUPPORTED); the events are created here, never on a
+ * solve path.  Errors: SMSM_E_INVALID for a null plan, capacity outside
+ * [0, 2^20] or stride < 1, SMSM_E_DEVICE if an event cannot be created. */
+smsm_status smsm_kernel_timer_start(smsm_plan* plan, int kernel_id, int capacity, int stride);
+
+/* Waits for the last timed launch, then returns the summed durations (ms) of
+ * the launches timed since smsm_kernel_timer_start or the previous read and
+ * their count, and starts a new count (the capacity is not renewed: launches
+ * past it are not timed).  Errors: SMSM_E_INVALID for null arguments,
+ * SMSM_E_DEVICE if an event query fails. */
+smsm_status smsm_kernel_timer_read(smsm_plan* plan, double* total_ms, int* launches);
+
 #ifdef __cplusplus
 }
 #endif

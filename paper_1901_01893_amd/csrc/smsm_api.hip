@@ -8,6 +8,8 @@
 #include "smsm_hyb.h"
 #include "smsm.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -70,6 +72,10 @@ struct smsm_plan {
 
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
+    // per-launch timing of the fast column pass (diagnostic, off by default):
+    // start/stop event pairs recorded with the dispatches
+    std::vector<hipEvent_t> kt_ev;
+    int kt_cap = 0, kt_n = 0, kt_stride = 1, kt_seen = 0;
     size_t lds_colfast = 0;
     size_t lds_band = 0;
     BandFn band = nullptr;   // band-correction kernel for (2r-1, Ns)
@@ -161,8 +167,15 @@ const ColFastInst kColFast[] = {COLFAST(16, 2), COLFAST(16, 3), COLFAST(32, 2),
 template <int M_, int L_>
 void launch_colfast(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
-    hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in, out,
-                       P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
+    if (P->kt_n < P->kt_cap && P->kt_seen++ % P->kt_stride == 0) {
+        const int n = P->kt_n++;
+        hipExtLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st,
+                              P->kt_ev[2 * n], P->kt_ev[2 * n + 1], 0, g, in, out, P->ST, P->theta, P->tw2,
+                              P->twM, P->Khat, use_reg, pc, P->prow);
+    } else {
+        hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in,
+                           out, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
+    }
 }
 
 // Column pass (hybrid in -> hybrid out).  For MODE == COL_NORMAL, `pc` may
@@ -706,6 +719,7 @@ smsm_status smsm_plan_destroy(smsm_plan* plan) {
     if (!plan) return SMSM_OK;
     (void)hipSetDevice(plan->dev);
     (void)hipDeviceSynchronize();
+    for (hipEvent_t ev : plan->kt_ev) (void)hipEventDestroy(ev);
     (void)hipFree(plan->arena);
     delete plan;
     return SMSM_OK;
@@ -890,6 +904,44 @@ smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, vo
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, true, S(stream));
+}
+
+smsm_status smsm_kernel_timer_start(smsm_plan* P, int kernel_id, int capacity, int stride) {
+    if (!P || capacity < 0 || capacity > (1 << 20) || stride < 1) return SMSM_E_INVALID;
+    if (kernel_id != SMSM_KERNEL_COL_NORMAL) return SMSM_E_UNSUPPORTED;
+    if (capacity > 0 && P->col_fast < 0) return SMSM_E_UNSUPPORTED;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    P->kt_cap = P->kt_n = P->kt_seen = 0;
+    P->kt_stride = stride;
+    const size_t need = 2 * (size_t)capacity;
+    while (P->kt_ev.size() > need) {
+        (void)hipEventDestroy(P->kt_ev.back());
+        P->kt_ev.pop_back();
+    }
+    while (P->kt_ev.size() < need) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return SMSM_E_DEVICE;
+        P->kt_ev.push_back(ev);
+    }
+    P->kt_cap = capacity;
+    return SMSM_OK;
+}
+
+smsm_status smsm_kernel_timer_read(smsm_plan* P, double* total_ms, int* launches) {
+    if (!P || !total_ms || !launches) return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    double tot = 0.0;
+    const int n = P->kt_n;
+    if (n > 0 && hipEventSynchronize(P->kt_ev[2 * (n - 1) + 1]) != hipSuccess) return SMSM_E_DEVICE;
+    for (int k = 0; k < n; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, P->kt_ev[2 * k], P->kt_ev[2 * k + 1]) != hipSuccess) return SMSM_E_DEVICE;
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = n;
+    P->kt_n = 0;
+    return SMSM_OK;
 }
 
 smsm_status smsm_images_sos(smsm_plan* P, const void* x_dev, void* img_dev, void* stream) {

@@ -30,6 +30,7 @@ ABI_SYMBOLS = (
     "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
+    "smsm_kernel_timer_start", "smsm_kernel_timer_read",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5, "cg_alpha": 6}
 
@@ -92,6 +93,10 @@ def lib() -> ctypes.CDLL:
         L.smsm_launch_kernel.restype = st
         L.smsm_kernel_cost.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.smsm_kernel_cost.restype = st
+        L.smsm_kernel_timer_start.argtypes = [vp, st, st, st]
+        L.smsm_kernel_timer_start.restype = st
+        L.smsm_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+        L.smsm_kernel_timer_read.restype = st
         _lib = L
     return _lib
 
@@ -278,6 +283,18 @@ class Plan:
         _check(lib().smsm_launch_kernel(self._h, KERNEL_IDS[name], int(reps), _stream_ptr(stream)),
                "smsm_launch_kernel")
 
+    def kernel_timer_start(self, name: str, capacity: int, stride: int = 1):
+        """Time (start/stop events per dispatch) one launch of a kernel in every `stride`, up to
+        `capacity` of them; capacity 0 turns it off."""
+        _check(lib().smsm_kernel_timer_start(self._h, KERNEL_IDS[name], int(capacity), int(stride)),
+               "smsm_kernel_timer_start")
+
+    def kernel_timer_read(self):
+        """(summed milliseconds, launches) of the timed launches since the start or the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _check(lib().smsm_kernel_timer_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "smsm_kernel_timer_read")
+        return ms.value, n.value
+
     def kernel_cost(self, name: str):
         """(FP64 flops, compulsory HBM bytes) of one launch of a CG-iteration kernel."""
         f, b = ctypes.c_double(), ctypes.c_double()
@@ -346,3 +363,27 @@ def smsm_launch_kernel(plan: Plan, name: str, reps: int = 1, stream=None):
 
 def smsm_kernel_cost(plan: Plan, name: str):
     return plan.kernel_cost(name)
+
+
+def smsm_images_sos(plan: Plan, x, out=None, stream=None):
+    return plan.images_sos(x, out, stream)
+
+
+def smsm_kernel_timer_start(plan: Plan, name: str, capacity: int, stride: int = 1):
+    plan.kernel_timer_start(name, capacity, stride)
+
+
+def smsm_kernel_timer_read(plan: Plan):
+    return plan.kernel_timer_read()
+
+
+def smsm_plan_device_bytes(plan: Plan) -> int:
+    return plan.device_bytes()
+
+
+def smsm_plan_set_params(plan: Plan, params: Params):
+    plan.set_params(params)
+
+
+def smsm_status_string(status: int) -> str:
+    return status_string(status)

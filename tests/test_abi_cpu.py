@@ -28,6 +28,12 @@ def test_binding_lists_every_declared_symbol():
     assert sorted(smsm.ABI_SYMBOLS) == declared_symbols()
 
 
+def test_binding_has_a_function_per_declared_symbol():
+    # the thin binding mirrors every C entry point under the same name
+    for name in declared_symbols():
+        assert callable(getattr(smsm, name, None)), name
+
+
 @needs_lib
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(smsm.LIB_PATH)
