@@ -53,6 +53,59 @@ def synth_inputs(torch, dev, plan, g, case, n_draws=1):
     return ys
 
 
+# Batched form: uneven slice groups (32 coils, 15 x 15 iterations), power-of-two
+# matrix sizes; (n, MB, shots, filter).  8 shots need a filter of at most 5 x 5.
+BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (128, 3, 4, 7), (128, 2, 2, 7), (128, 2, 8, 5))
+
+
+def batched_measurement(torch, dev, n_streams, reps):
+    """Slice-groups/s of the batch as plain sequential solves and as one graph
+    on n_streams streams (0: chosen by the library's autotuner); the graph's
+    outputs must equal the plain ones bit for bit."""
+    autotuned = n_streams == 0
+    import smsm_inputs as si
+    from paper_1901_01893_amd import smsm
+    plans, ys, xs_plain, xs_graph = [], [], [], []
+    for k, (n, L, Ns, r) in enumerate(BATCH_GEOMS):
+        g = si.Geometry(n=n, n_slices=L, n_shots=Ns, n_coils=32, filt=r, lam=1e-3, n_irls=15, n_cg=15,
+                        phase_order=3, snr=20.0)
+        case = si.make_case(g, k, 30)
+        coils = torch.from_numpy(case["coils"]).to(dev)
+        plan = smsm.Plan(n, n, L, Ns, 32, r, coils, case["masks"], case["shifts"],
+                         smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
+        plans.append(plan)
+        ys.append(synth_inputs(torch, dev, plan, g, case)[0])
+        xs_plain.append(torch.empty(plan.shape_x, dtype=torch.complex64, device=dev))
+        xs_graph.append(torch.empty(plan.shape_x, dtype=torch.complex64, device=dev))
+    batch = smsm.Batch(plans, ys, xs_graph, n_streams=n_streams)
+    n_streams = batch.n_streams
+    try:
+        def plain():
+            for plan, y, x in zip(plans, ys, xs_plain):
+                plan.solve(y, x)
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+        t_plain = timed(plain)
+        t_graph = timed(batch.launch)
+        equal = all(torch.equal(a, b) for a, b in zip(xs_plain, xs_graph))
+    finally:
+        batch.close()
+        for plan in plans:
+            plan.close()
+    n = len(BATCH_GEOMS)
+    return {"groups": [f"{a}x{a} MB{b} Ns{c} r{d}" for a, b, c, d in BATCH_GEOMS], "coils": 32,
+            "iterations": "15 IRLS x 15 CG", "streams": n_streams, "streams_chosen_by": "autotuner" if autotuned else "caller",
+            "reps": reps,
+            "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
+            "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
+
+
 def time_kernel(torch, plan, name, reps):
     stream = torch.cuda.current_stream()
     plan.launch_kernel(name, 2)
@@ -135,6 +188,8 @@ def main():
     ap.add_argument("--profile-kernel", default=None,
                     help="profiling mode: one solve, a calibration copy, then REPS launches of this kernel")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -227,6 +282,8 @@ def main():
            "roofline": roofline,
            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
            "solve_status": smsm.status_string(status)}
+    if not args.no_batched:
+        out["batched"] = batched_measurement(torch, dev, args.batch_streams, 5)
 
     if not args.no_cpu_baseline and args.gpus == 1:
         from oracle import smsm_oracle as o

@@ -10,6 +10,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -904,6 +905,153 @@ smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, vo
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, true, S(stream));
+}
+
+// ---- batches of solves under one graph -----------------------------------
+struct smsm_batch {
+    int dev = 0;
+    int n_streams = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+};
+
+static void batch_release(smsm_batch* B) {
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (hipEvent_t ev : B->events) (void)hipEventDestroy(ev);
+    for (hipStream_t st : B->streams) (void)hipStreamDestroy(st);
+    delete B;
+}
+
+static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* const* y_devs, void* const* x_devs,
+                                 int n_streams, smsm_batch** out);
+
+// Times one launch of a captured batch (after one untimed launch), in ms.
+static smsm_status batch_time(smsm_batch* B, hipStream_t st, float* ms) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SMSM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SMSM_E_DEVICE; }
+    bool ok = hipGraphLaunch(B->exec, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k) ok = hipGraphLaunch(B->exec, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ok ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_batch_create(smsm_plan* const* plans, int n, const void* const* y_devs, void* const* x_devs,
+                              int n_streams, smsm_batch** out) {
+    if (!out || n_streams < 0 || n_streams > 64) return SMSM_E_INVALID;
+    if (n_streams > 0) return batch_capture(plans, n, y_devs, x_devs, n_streams, out);
+    // autotune the stream count: capture each candidate, time it, keep the fastest
+    *out = nullptr;
+    static const int kCand[] = {1, 2, 3, 4, 6, 8};
+    smsm_batch* best = nullptr;
+    float best_ms = 0.0f;
+    hipStream_t st = nullptr;
+    for (int c : kCand) {
+        if (c > n && c != 1) break;
+        smsm_batch* B = nullptr;
+        smsm_status s = batch_capture(plans, n, y_devs, x_devs, c, &B);
+        if (s == SMSM_OK && !st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            st = nullptr;
+            s = SMSM_E_DEVICE;
+        }
+        float ms = 0.0f;
+        if (s == SMSM_OK) s = batch_time(B, st, &ms);
+        if (s != SMSM_OK) {
+            if (B) batch_release(B);
+            if (best) batch_release(best);
+            if (st) (void)hipStreamDestroy(st);
+            return s;
+        }
+        if (!best || ms < best_ms) {
+            if (best) batch_release(best);
+            best = B;
+            best_ms = ms;
+        } else {
+            batch_release(B);
+        }
+    }
+    if (st) (void)hipStreamDestroy(st);
+    *out = best;
+    return SMSM_OK;
+}
+
+int smsm_batch_streams(const smsm_batch* batch) { return batch ? batch->n_streams : 0; }
+
+static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* const* y_devs, void* const* x_devs,
+                                 int n_streams, smsm_batch** out) {
+    if (!plans || !y_devs || !x_devs || !out || n < 1 || n_streams < 1 || n_streams > 64) return SMSM_E_INVALID;
+    *out = nullptr;
+    for (int k = 0; k < n; ++k) {
+        if (!plans[k] || !y_devs[k] || !x_devs[k]) return SMSM_E_INVALID;
+        if (plans[k]->dev != plans[0]->dev) return SMSM_E_INVALID;
+        if (plans[k]->kt_cap > 0) return SMSM_E_INVALID;      // no per-launch timing inside a graph
+        for (int j = 0; j < k; ++j)
+            if (plans[j] == plans[k]) return SMSM_E_INVALID;   // one branch per plan: its scratch is private
+    }
+    if (hipSetDevice(plans[0]->dev) != hipSuccess) return SMSM_E_DEVICE;
+    smsm_batch* B = new (std::nothrow) smsm_batch;
+    if (!B) return SMSM_E_NOMEM;
+    B->dev = plans[0]->dev;
+    const int ns = std::min(n_streams, n);
+    B->n_streams = ns;
+    for (int k = 0; k < ns; ++k) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) { batch_release(B); return SMSM_E_DEVICE; }
+        B->streams.push_back(st);
+    }
+    for (int k = 0; k < ns; ++k) {   // event 0 forks, events 1.. join
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { batch_release(B); return SMSM_E_DEVICE; }
+        B->events.push_back(ev);
+    }
+    hipStream_t origin = B->streams[0];
+    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        batch_release(B);
+        return SMSM_E_DEVICE;
+    }
+    bool ok = hipEventRecord(B->events[0], origin) == hipSuccess;
+    for (int k = 1; k < ns && ok; ++k) ok = hipStreamWaitEvent(B->streams[k], B->events[0], 0) == hipSuccess;
+    smsm_status s = ok ? SMSM_OK : SMSM_E_DEVICE;
+    for (int k = 0; k < n && s == SMSM_OK; ++k) s = smsm_solve(plans[k], y_devs[k], x_devs[k], B->streams[k % ns]);
+    for (int k = 1; k < ns && s == SMSM_OK; ++k) {
+        if (hipEventRecord(B->events[k], B->streams[k]) != hipSuccess ||
+            hipStreamWaitEvent(origin, B->events[k], 0) != hipSuccess)
+            s = SMSM_E_DEVICE;
+    }
+    hipGraph_t graph = nullptr;
+    const bool ended = hipStreamEndCapture(origin, &graph) == hipSuccess;
+    B->graph = graph;
+    if (s != SMSM_OK || !ended || !graph) {
+        batch_release(B);
+        return s != SMSM_OK ? s : SMSM_E_DEVICE;
+    }
+    if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess) {
+        B->exec = nullptr;
+        batch_release(B);
+        return SMSM_E_DEVICE;
+    }
+    *out = B;
+    return SMSM_OK;
+}
+
+smsm_status smsm_batch_launch(smsm_batch* B, void* stream) {
+    if (!B) return SMSM_E_INVALID;
+    if (hipSetDevice(B->dev) != hipSuccess) return SMSM_E_DEVICE;
+    return hipGraphLaunch(B->exec, S(stream)) == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_batch_destroy(smsm_batch* B) {
+    if (!B) return SMSM_OK;
+    (void)hipSetDevice(B->dev);
+    (void)hipDeviceSynchronize();
+    batch_release(B);
+    return SMSM_OK;
 }
 
 smsm_status smsm_kernel_timer_start(smsm_plan* P, int kernel_id, int capacity, int stride) {

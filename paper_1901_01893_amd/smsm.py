@@ -30,7 +30,8 @@ ABI_SYMBOLS = (
     "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
-    "smsm_kernel_timer_start", "smsm_kernel_timer_read",
+    "smsm_kernel_timer_start", "smsm_kernel_timer_read", "smsm_batch_create", "smsm_batch_launch",
+    "smsm_batch_destroy", "smsm_batch_streams",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5, "cg_alpha": 6}
 
@@ -97,6 +98,15 @@ def lib() -> ctypes.CDLL:
         L.smsm_kernel_timer_start.restype = st
         L.smsm_kernel_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         L.smsm_kernel_timer_read.restype = st
+        pvp = ctypes.POINTER(vp)
+        L.smsm_batch_create.argtypes = [pvp, st, pvp, pvp, st, pvp]
+        L.smsm_batch_create.restype = st
+        L.smsm_batch_launch.argtypes = [vp, vp]
+        L.smsm_batch_launch.restype = st
+        L.smsm_batch_destroy.argtypes = [vp]
+        L.smsm_batch_destroy.restype = st
+        L.smsm_batch_streams.argtypes = [vp]
+        L.smsm_batch_streams.restype = st
         _lib = L
     return _lib
 
@@ -387,3 +397,61 @@ def smsm_plan_set_params(plan: Plan, params: Params):
 
 def smsm_status_string(status: int) -> str:
     return status_string(status)
+
+
+class Batch:
+    """Solves of several plans captured as one graph on concurrent streams
+    (smsm_batch_*): launch() runs x_k = solve(plan_k, y_k) for every k.  The
+    tensors are baked in: refill ys in place before a launch."""
+
+    def __init__(self, plans, ys, xs, n_streams: int = 2):
+        """n_streams = 0 lets the library pick the stream count by timing the candidates."""
+        import torch
+        n = len(plans)
+        if not (len(ys) == len(xs) == n):
+            raise ValueError("one y and one x per plan")
+        yp, xp = [], []
+        for pl, y, x in zip(plans, ys, xs):
+            c128 = bool(pl.params.flags & SMSM_FLAG_X_C128)
+            yp.append(_dev_ptr(y, torch.complex64, pl.shape_y, "y").value)
+            xp.append(_dev_ptr(x, torch.complex128 if c128 else torch.complex64, pl.shape_x, "x").value)
+        arr = ctypes.c_void_p * n
+        h = ctypes.c_void_p()
+        _check(lib().smsm_batch_create(arr(*[pl._h for pl in plans]), n, arr(*yp), arr(*xp), int(n_streams),
+                                       ctypes.byref(h)), "smsm_batch_create")
+        self._h = h
+        self._keep = (list(plans), list(ys), list(xs))
+
+    def launch(self, stream=None):
+        _check(lib().smsm_batch_launch(self._h, _stream_ptr(stream)), "smsm_batch_launch")
+
+    @property
+    def n_streams(self) -> int:
+        return int(lib().smsm_batch_streams(self._h))
+
+    def close(self):
+        if self._h is not None:
+            lib().smsm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def smsm_batch_create(plans, ys, xs, n_streams: int = 2) -> Batch:
+    return Batch(plans, ys, xs, n_streams)
+
+
+def smsm_batch_launch(batch: Batch, stream=None):
+    batch.launch(stream)
+
+
+def smsm_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def smsm_batch_streams(batch: Batch) -> int:
+    return batch.n_streams

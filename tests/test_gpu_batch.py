@@ -1,0 +1,111 @@
+"""Batches of slice groups under one graph (smsm_batch_*): every solve of a
+batch equals the plain solve of its plan bit for bit, on every replay, with
+eager work between the replays; a plan cannot appear twice in a batch."""
+import numpy as np
+import pytest
+
+import smsm_inputs as si
+from oracle import smsm_oracle as o
+
+pytestmark = pytest.mark.gpu
+
+# uneven geometries: fast column pass <16, 2>, generic column pass at 2 shots, one slice at 8 shots
+GEOMS = [
+    si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=8, filt=5, lam=1e-3, n_irls=3, n_cg=4, phase_order=2, snr=30.0),
+    si.Geometry(n=32, n_slices=2, n_shots=2, n_coils=4, filt=3, lam=1e-3, n_irls=3, n_cg=4, phase_order=2, snr=30.0),
+    si.Geometry(n=64, n_slices=1, n_shots=8, n_coils=4, filt=2, lam=1e-3, n_irls=2, n_cg=3, phase_order=2, snr=30.0),
+]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_01893_amd  # noqa: F401  (fails loudly if the library is missing)
+    return torch, torch.device("cuda:0")
+
+
+def make_plan(torch, dev, g, seed):
+    from paper_1901_01893_amd import smsm
+    case = si.make_case(g, seed, 200 + seed)
+    _, y = o.simulate(case, g.n_slices, g.snr)
+    coils = torch.from_numpy(case["coils"]).to(dev)
+    plan = smsm.Plan(g.n, g.n, g.n_slices, g.n_shots, g.n_coils, g.filt, coils, case["masks"], case["shifts"],
+                     smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg, flags=smsm.SMSM_FLAG_X_C128))
+    return plan, torch.from_numpy(y.astype(np.complex64)).to(dev)
+
+
+def test_batch_matches_plain_solves_bitwise(torch_dev):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    plans, ys, refs = [], [], []
+    try:
+        for k, g in enumerate(GEOMS):
+            plan, y = make_plan(torch, dev, g, k)
+            plans.append(plan)
+            ys.append(y)
+            refs.append(plan.solve(y).clone())
+        torch.cuda.synchronize()
+        xs = [torch.zeros_like(r) for r in refs]
+        batch = smsm.Batch(plans, ys, xs, n_streams=2)
+        try:
+            for rep in range(3):
+                print(f"[batch] replay {rep}", flush=True)
+                for x in xs:
+                    x.zero_()
+                batch.launch()
+                torch.cuda.synchronize()
+                for k in range(len(plans)):
+                    assert torch.equal(xs[k], refs[k]), (rep, k)
+                # eager work between the replays: a plain solve on one of the plans
+                j = rep % len(plans)
+                assert torch.equal(plans[j].solve(ys[j]), refs[j])
+                torch.cuda.synchronize()
+        finally:
+            batch.close()
+    finally:
+        for plan in plans:
+            plan.close()
+
+
+def test_batch_rejects_a_repeated_plan(torch_dev):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    plan, y = make_plan(torch, dev, GEOMS[1], 5)
+    try:
+        x = torch.empty(plan.shape_x, dtype=torch.complex128, device=dev)
+        with pytest.raises(smsm.SmsmError) as err:
+            smsm.Batch([plan, plan], [y, y], [x, x])
+        assert err.value.status == smsm.SMSM_E_INVALID
+    finally:
+        plan.close()
+
+
+def test_autotuned_batch_matches_plain_solves(torch_dev):
+    # n_streams = 0: the library times the candidate stream counts and keeps the fastest
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    plans, ys, refs = [], [], []
+    try:
+        for k, g in enumerate(GEOMS[:2]):
+            plan, y = make_plan(torch, dev, g, 10 + k)
+            plans.append(plan)
+            ys.append(y)
+            refs.append(plan.solve(y).clone())
+        torch.cuda.synchronize()
+        xs = [torch.zeros_like(r) for r in refs]
+        batch = smsm.Batch(plans, ys, xs, n_streams=0)
+        try:
+            assert batch.n_streams in (1, 2)
+            for x in xs:
+                x.zero_()
+            batch.launch()
+            torch.cuda.synchronize()
+            for k in range(len(plans)):
+                assert torch.equal(xs[k], refs[k]), k
+        finally:
+            batch.close()
+    finally:
+        for plan in plans:
+            plan.close()
