@@ -12,9 +12,12 @@
 // A 16 x 16 tile C[i0:i0+16, j0:j0+16] = sum_k A[i][k] B[k][j] is built from
 // v_mfma_f64_16x16x4f64: lane l supplies A[i0 + l%16][k0 + l/16] and
 // B[k0 + l/16][j0 + l%16]; register v of lane l returns C[4 v + l/16][l%16].
-// A complex product takes four real products per step of 4
-// (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br).  The 4 waves of a workgroup
-// split the inner dimension; their partial tiles are summed in a fixed order.
+// A complex product takes three real products per step of 4 (Gauss):
+// T1 += (Ar + Ai) Br, T2 += Ar (Bi - Br), T3 += Ai (Br + Bi), then
+// Cr = T1 - T3 and Ci = T1 + T2 (a quarter fewer MFMAs than the four-product
+// form; the iterates are O(1), so the cancellation in Cr costs nothing at
+// the 1e-10 convergence threshold).  The 4 waves of a workgroup split the
+// inner dimension; their partial tiles are summed in a fixed order.
 #pragma once
 #include "smsm_device.h"
 
@@ -131,7 +134,7 @@ __global__ void __launch_bounds__(64 * HW) k_zgemm(int K, int KP, HgArgs a) {
     const double2* Bp = B + off + (size_t)kq * KP + j0 + (lane & 15);     // B[kq + 4 s][j]
     const int nks = KP / 4;
     const int ks0 = (w * nks) / HW, ks1 = ((w + 1) * nks) / HW;
-    hd4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    hd4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0}, t3 = {0.0, 0.0, 0.0, 0.0};
     int ks = ks0;
     // batches of 4 steps: all 8 loads issued before the 16 products
     for (; ks + 4 <= ks1; ks += 4) {
@@ -143,19 +146,18 @@ __global__ void __launch_bounds__(64 * HW) k_zgemm(int K, int KP, HgArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].x, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u].y, bv[u].y, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x, ci, 0, 0, 0);
+            t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x + av[u].y, bv[u].x, t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y - bv[u].x, t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x + bv[u].y, t3, 0, 0, 0);
         }
     }
     for (; ks < ks1; ++ks) {
         const double2 av = Ap[4 * ks], bv = Bp[(size_t)4 * ks * KP];
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, cr, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, ci, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, ci, 0, 0, 0);
+        t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x + av.y, bv.x, t1, 0, 0, 0);
+        t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y - bv.x, t2, 0, 0, 0);
+        t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x + bv.y, t3, 0, 0, 0);
     }
+    const hd4 cr = t1 - t3, ci = t1 + t2;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         acc[w][v][lane] = cr[v];
