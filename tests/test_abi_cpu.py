@@ -91,3 +91,26 @@ def test_entry_points_reject_null_plan():
     assert lib.smsm_set_weights(None, None, None) == pkg.SMSM_E_INVALID
     assert lib.smsm_plan_destroy(None) == pkg.SMSM_OK
     assert lib.smsm_plan_device_bytes(None) == 0
+
+
+@needs_lib
+def test_batch_timer_and_image_entry_points_reject_bad_arguments():
+    lib = smsm.lib()
+    vp = ctypes.c_void_p
+    assert lib.smsm_images_sos(None, None, None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_kernel_timer_start(None, 0, 1, 1) == pkg.SMSM_E_INVALID
+    ms, n = ctypes.c_double(), ctypes.c_int()
+    assert lib.smsm_kernel_timer_read(None, ctypes.byref(ms), ctypes.byref(n)) == pkg.SMSM_E_INVALID
+    out = vp()
+    arr = (vp * 1)(vp(0x1000))              # never dereferenced: validation fails first
+    null = (vp * 1)(None)
+    assert lib.smsm_batch_create(None, 1, arr, arr, 1, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_create(null, 1, arr, arr, 1, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_create(arr, 0, arr, arr, 1, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_create(arr, 1, arr, arr, -1, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_create(arr, 1, arr, arr, 65, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_create(arr, 1, arr, arr, 1, None) == pkg.SMSM_E_INVALID
+    assert out.value is None
+    assert lib.smsm_batch_launch(None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_batch_destroy(None) == pkg.SMSM_OK
+    assert lib.smsm_batch_streams(None) == 0
