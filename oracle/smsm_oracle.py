@@ -22,6 +22,17 @@ What it computes (Mani et al., "SMS MUSSELS", arXiv 1901.01893):
     objective, and the factor lam/2 follows from majorising the concave
     t -> sqrt(t) at the current Gram eigenvalues.
 
+  * the root-sum-of-squares image of each slice over its shots' images (the
+    paper compares against single-band images without saying how shots are
+    combined; pinned by Parseval, a unit-modulus-phase closed form and a
+    k-space delta).
+
+Pins: every operator above, the weights, one CG step, the lam = 0 solve and
+the monotone decrease of the smoothed objective are checked against
+definitions, closed forms and brute force in tests/test_oracle_pins.py.  The
+whole fixed-iteration solve at the workload sizes is parity unpinned beyond
+those parts: its own iteration is the reference.
+
 Readings taken where the paper is silent (every one listed in the design
 notes): centred unitary DFT; CAIPI phase exp(-2 pi i s_l (j2 - N2/2)) on the
 global ky index with s_l = l/L; per-slice coil maps; Hankel rows p2-major and
