@@ -58,14 +58,15 @@ def synth_inputs(torch, dev, plan, g, case, n_draws=1):
 BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (128, 3, 4, 7), (128, 2, 2, 7), (128, 2, 8, 5))
 
 
-def batched_measurement(torch, dev, n_streams, reps):
-    """Slice-groups/s of the batch as plain sequential solves and as one graph
-    on n_streams streams (0: chosen by the library's autotuner); the graph's
-    outputs must equal the plain ones bit for bit."""
-    autotuned = n_streams == 0
+def batched_measurement(torch, dev, n_streams, reps, directions=5):
+    """Slice-groups/s of a batch (every group of BATCH_GEOMS with `directions`
+    inputs each, seeded noise draws, one plan per group) as plain sequential
+    solves and as one graph on n_streams streams (0: chosen by the library's
+    autotuner); the graph's outputs must equal the plain ones bit for bit."""
     import smsm_inputs as si
     from paper_1901_01893_amd import smsm
-    plans, ys, xs_plain, xs_graph = [], [], [], []
+    autotuned = n_streams == 0
+    plans, entries = [], []
     for k, (n, L, Ns, r) in enumerate(BATCH_GEOMS):
         g = si.Geometry(n=n, n_slices=L, n_shots=Ns, n_coils=32, filt=r, lam=1e-3, n_irls=15, n_cg=15,
                         phase_order=3, snr=20.0)
@@ -74,14 +75,18 @@ def batched_measurement(torch, dev, n_streams, reps):
         plan = smsm.Plan(n, n, L, Ns, 32, r, coils, case["masks"], case["shifts"],
                          smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
         plans.append(plan)
-        ys.append(synth_inputs(torch, dev, plan, g, case)[0])
-        xs_plain.append(torch.empty(plan.shape_x, dtype=torch.complex64, device=dev))
-        xs_graph.append(torch.empty(plan.shape_x, dtype=torch.complex64, device=dev))
-    batch = smsm.Batch(plans, ys, xs_graph, n_streams=n_streams)
+        for y in synth_inputs(torch, dev, plan, g, case, directions):
+            entries.append((plan, y))
+    # directions interleaved across groups: (g0 d0, g1 d0, ..., g0 d1, ...)
+    order = [entries[k * directions + d] for d in range(directions) for k in range(len(plans))]
+    ys = [y for _, y in order]
+    xs_plain = [torch.empty(pl.shape_x, dtype=torch.complex64, device=dev) for pl, _ in order]
+    xs_graph = [torch.empty_like(x) for x in xs_plain]
+    batch = smsm.Batch([pl for pl, _ in order], ys, xs_graph, n_streams=n_streams)
     n_streams = batch.n_streams
     try:
         def plain():
-            for plan, y, x in zip(plans, ys, xs_plain):
+            for (plan, y), x in zip(order, xs_plain):
                 plan.solve(y, x)
         def timed(fn):
             fn()
@@ -98,10 +103,10 @@ def batched_measurement(torch, dev, n_streams, reps):
         batch.close()
         for plan in plans:
             plan.close()
-    n = len(BATCH_GEOMS)
+    n = len(order)
     return {"groups": [f"{a}x{a} MB{b} Ns{c} r{d}" for a, b, c, d in BATCH_GEOMS], "coils": 32,
-            "iterations": "15 IRLS x 15 CG", "streams": n_streams, "streams_chosen_by": "autotuner" if autotuned else "caller",
-            "reps": reps,
+            "directions_per_group": directions, "solves": n, "iterations": "15 IRLS x 15 CG",
+            "streams": n_streams, "streams_chosen_by": "autotuner" if autotuned else "caller", "reps": reps,
             "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 
@@ -283,7 +288,7 @@ def main():
            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
            "solve_status": smsm.status_string(status)}
     if not args.no_batched:
-        out["batched"] = batched_measurement(torch, dev, args.batch_streams, 5)
+        out["batched"] = batched_measurement(torch, dev, args.batch_streams, 3)
 
     if not args.no_cpu_baseline and args.gpus == 1:
         from oracle import smsm_oracle as o

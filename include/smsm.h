@@ -128,24 +128,29 @@ const char* smsm_status_string(smsm_status s);
 /* ---- batches: many slice groups as one submission ---------------------- */
 
 /* Captures the solves x_devs[k] = solve(plans[k], y_devs[k]), k < n, into one
- * hipGraph: the plans are dealt round-robin to min(n_streams, n) concurrent
- * streams (default priority) joined at the end, so independent slice groups
- * (any mix of the geometries the plans were created for) overlap on the GPU.
+ * hipGraph: the plans are dealt round-robin to min(n_streams, distinct plans)
+ * concurrent streams (default priority) joined at the end, so independent
+ * slice groups (any mix of the geometries the plans were created for) overlap
+ * on the GPU.
  * Each solve computes exactly what smsm_solve computes (same kernels, same
- * order within its plan: results are bitwise equal).  Ownership: the plans
- * must be distinct (a plan's scratch memory belongs to its branch), stay alive
- * and unused by other calls while the batch exists; y_devs/x_devs (layouts as
- * for smsm_solve) are baked into the graph, so the caller keeps them allocated
- * and refills y_devs before each launch.  Per-launch kernel timing must be off
- * on every plan.  Errors: SMSM_E_INVALID (null or repeated plan, n < 1,
+ * order within its plan: results are bitwise equal).  A plan may appear
+ * several times (e.g. the diffusion directions of one slice group): its solves
+ * share its scratch memory, so they all run in entry order on the stream of
+ * its first entry, while distinct plans are dealt round-robin to the streams.
+ * Ownership: the plans stay alive and unused by other calls while the batch
+ * exists; y_devs/x_devs (layouts as for smsm_solve; every x distinct) are
+ * baked into the graph, so the caller keeps them allocated and refills y_devs
+ * before each launch.  Per-launch kernel timing must be off on every plan.
+ * Errors: SMSM_E_INVALID (null plan or buffer, n < 1,
  * n_streams outside [1, 64], plans on different devices, timing on),
  * SMSM_E_NOMEM, SMSM_E_DEVICE (stream, capture or instantiation failure), or
  * the first error a captured solve returned.
  * n_streams = 0 autotunes the launch shape: a graph is captured for each
- * stream count in {1, 2, 3, 4, 6, 8} up to n, each is launched once untimed and
- * twice timed (hipEvents on an internal stream), and the fastest is kept
- * (smsm_batch_streams tells which).  Autotuning runs the batch 3 times per
- * candidate, writing x_devs, and synchronises with those launches. */
+ * stream count in {1, 2, 3, 4, 6, 8} up to the number of distinct plans, each
+ * is launched once untimed and twice timed (hipEvents on an internal stream),
+ * and the fastest is kept (smsm_batch_streams tells which).  Autotuning runs
+ * the batch 3 times per candidate, writing x_devs, and synchronises with
+ * those launches. */
 smsm_status smsm_batch_create(smsm_plan* const* plans, int n, const void* const* y_devs,
                               void* const* x_devs, int n_streams, smsm_batch** out);
 

@@ -952,8 +952,14 @@ smsm_status smsm_batch_create(smsm_plan* const* plans, int n, const void* const*
     smsm_batch* best = nullptr;
     float best_ms = 0.0f;
     hipStream_t st = nullptr;
+    int distinct = 0;
+    for (int k = 0; k < n; ++k) {
+        bool seen = false;
+        for (int j = 0; j < k && !seen; ++j) seen = plans && plans[j] == plans[k];
+        distinct += seen ? 0 : 1;
+    }
     for (int c : kCand) {
-        if (c > n && c != 1) break;
+        if (c > distinct && c != 1) break;
         smsm_batch* B = nullptr;
         smsm_status s = batch_capture(plans, n, y_devs, x_devs, c, &B);
         if (s == SMSM_OK && !st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -987,18 +993,24 @@ static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* con
                                  int n_streams, smsm_batch** out) {
     if (!plans || !y_devs || !x_devs || !out || n < 1 || n_streams < 1 || n_streams > 64) return SMSM_E_INVALID;
     *out = nullptr;
+    // a plan's solves share its scratch memory: they all go, in order, to the
+    // stream of its first entry; distinct plans are dealt round-robin
+    std::vector<int> owner(n);
+    int distinct = 0;
     for (int k = 0; k < n; ++k) {
         if (!plans[k] || !y_devs[k] || !x_devs[k]) return SMSM_E_INVALID;
         if (plans[k]->dev != plans[0]->dev) return SMSM_E_INVALID;
         if (plans[k]->kt_cap > 0) return SMSM_E_INVALID;      // no per-launch timing inside a graph
-        for (int j = 0; j < k; ++j)
-            if (plans[j] == plans[k]) return SMSM_E_INVALID;   // one branch per plan: its scratch is private
+        owner[k] = -1;
+        for (int j = 0; j < k && owner[k] < 0; ++j)
+            if (plans[j] == plans[k]) owner[k] = owner[j];
+        if (owner[k] < 0) owner[k] = distinct++;
     }
     if (hipSetDevice(plans[0]->dev) != hipSuccess) return SMSM_E_DEVICE;
     smsm_batch* B = new (std::nothrow) smsm_batch;
     if (!B) return SMSM_E_NOMEM;
     B->dev = plans[0]->dev;
-    const int ns = std::min(n_streams, n);
+    const int ns = std::min(n_streams, distinct);
     B->n_streams = ns;
     for (int k = 0; k < ns; ++k) {
         hipStream_t st;
@@ -1018,7 +1030,8 @@ static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* con
     bool ok = hipEventRecord(B->events[0], origin) == hipSuccess;
     for (int k = 1; k < ns && ok; ++k) ok = hipStreamWaitEvent(B->streams[k], B->events[0], 0) == hipSuccess;
     smsm_status s = ok ? SMSM_OK : SMSM_E_DEVICE;
-    for (int k = 0; k < n && s == SMSM_OK; ++k) s = smsm_solve(plans[k], y_devs[k], x_devs[k], B->streams[k % ns]);
+    for (int k = 0; k < n && s == SMSM_OK; ++k)
+        s = smsm_solve(plans[k], y_devs[k], x_devs[k], B->streams[owner[k] % ns]);
     for (int k = 1; k < ns && s == SMSM_OK; ++k) {
         if (hipEventRecord(B->events[k], B->streams[k]) != hipSuccess ||
             hipStreamWaitEvent(origin, B->events[k], 0) != hipSuccess)

@@ -1,6 +1,7 @@
 """Batches of slice groups under one graph (smsm_batch_*): every solve of a
 batch equals the plain solve of its plan bit for bit, on every replay, with
-eager work between the replays; a plan cannot appear twice in a batch."""
+eager work between the replays; a plan that appears several times (several
+inputs of one slice group) runs its solves in order."""
 import numpy as np
 import pytest
 
@@ -69,17 +70,33 @@ def test_batch_matches_plain_solves_bitwise(torch_dev):
             plan.close()
 
 
-def test_batch_rejects_a_repeated_plan(torch_dev):
+def test_batch_runs_a_repeated_plan_in_order(torch_dev):
+    # two inputs of one slice group (one plan) and a second group: the repeated
+    # plan's solves share its scratch, so they run in order on one stream
     torch, dev = torch_dev
     from paper_1901_01893_amd import smsm
-    plan, y = make_plan(torch, dev, GEOMS[1], 5)
+    plan_a, y_a = make_plan(torch, dev, GEOMS[1], 5)
+    plan_b, y_b = make_plan(torch, dev, GEOMS[0], 6)
     try:
-        x = torch.empty(plan.shape_x, dtype=torch.complex128, device=dev)
-        with pytest.raises(smsm.SmsmError) as err:
-            smsm.Batch([plan, plan], [y, y], [x, x])
-        assert err.value.status == smsm.SMSM_E_INVALID
+        y_a2 = (0.5 * y_a).contiguous()
+        refs = [plan_a.solve(y_a).clone(), plan_b.solve(y_b).clone(), plan_a.solve(y_a2).clone()]
+        torch.cuda.synchronize()
+        xs = [torch.zeros_like(r) for r in refs]
+        batch = smsm.Batch([plan_a, plan_b, plan_a], [y_a, y_b, y_a2], xs, n_streams=2)
+        try:
+            assert batch.n_streams == 2
+            for rep in range(2):
+                for x in xs:
+                    x.zero_()
+                batch.launch()
+                torch.cuda.synchronize()
+                for k in range(3):
+                    assert torch.equal(xs[k], refs[k]), (rep, k)
+        finally:
+            batch.close()
     finally:
-        plan.close()
+        plan_a.close()
+        plan_b.close()
 
 
 def test_autotuned_batch_matches_plain_solves(torch_dev):
