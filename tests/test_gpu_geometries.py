@@ -34,6 +34,10 @@ GEOMS = {
     # coil group has a clamped, zero-weighted member), band kernel <5, 4>
     "n256_L2_Ns4_r3": (si.Geometry(n=256, n_slices=2, n_shots=4, n_coils=5, filt=3, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=2, snr=30.0), 105),
+    # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
+    # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
+    "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
+                                     phase_order=2, snr=30.0), 106),
 }
 
 
