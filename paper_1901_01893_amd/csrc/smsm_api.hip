@@ -323,7 +323,7 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
                        P->tw1, P->Dhat);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
-        hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * g.Ns), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
+        hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * (g.Ns + 1) / 2), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
                            P->tw2, P->Khat);
         LAUNCH_CHECK();
     }
@@ -571,7 +571,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oY0 = cv.take<double2>(KKP), oY1 = cv.take<double2>(KKP);
     const size_t oZ0 = cv.take<double2>(KKP), oZ1 = cv.take<double2>(KKP), oT = cv.take<double2>(KKP);
     const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
-    const size_t oKh = cv.take<double2>((size_t)L * Ns * Ns * n1 * n2);
+    const size_t oKh = cv.take<double2>((size_t)L * Ns * (Ns + 1) / 2 * n1 * n2);   // Hermitian pairs j <= i
     const size_t oD = cv.take<double2>(ntab);
     const size_t oDx = cv.take<double2>(ntab * g.e);
     const size_t ocrow = cv.take<double2>((size_t)g.B * 2 * g.e * n1);
@@ -1149,7 +1149,7 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                 + B * n2 * 8.0;                                   // p = r + beta p and Re <p, q>
             f = n1 * per_col;
             b = 4.0 * vec + L * Nc * n1 * n2 * 16.0                // r, p in; p, q out; coil maps (c128)
-                + L * Ns * Ns * n1 * n2 * 16.0;                    // image-domain Hankel kernel
+                + L * Ns * (Ns + 1) / 2.0 * n1 * n2 * 16.0;        // image-domain Hankel kernel (pairs j <= i)
             break;
         }
         case SMSM_KERNEL_ROWS_INV:

@@ -114,16 +114,24 @@ __host__ __device__ inline int colfast_lds_total(const Geo& g) { return 2 * g.B 
 
 // Image-domain kernel of the circular Hankel term, one table per IRLS step:
 //   Khat[l][j][i][x][n] = sum_{d2,d1} Kc[l][j][i][d2][d1] e^{-2 pi i ((d1-e)(x-n1/2)/n1 + (d2-e)(n-n2/2)/n2)}
-// (input shot j, output shot i).  grid (n1, L Ns Ns), block 256: the taps'
-// x transform A[d2] (products formed in parallel, summed in d1 order), then
-// one output n per thread from shared-memory twiddles.
+// (input shot j, output shot i).  W is Hermitian, so Kc[l][i][j][d] =
+// conj(Kc[l][j][i][2e - d]) and Khat[l][i][j] = conj(Khat[l][j][i]): only the
+// pairs j <= i are stored, pair p = i (i + 1) / 2 + j (khat_pair), as
+// Khat[l][p][x][n].  grid (n1, L Ns (Ns + 1) / 2), block 256: the taps' x
+// transform A[d2] (products formed in parallel, summed in d1 order), then one
+// output n per thread from shared-memory twiddles.
+SMSM_HD inline int khat_pair(int j, int i) { return i * (i + 1) / 2 + j; }   // j <= i
 __global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __restrict__ Kc,
                                                       const double2* __restrict__ tw1,
                                                       const double2* __restrict__ tw2, double2* __restrict__ Khat) {
     __shared__ double2 A[BAND_MAX_NC];
     __shared__ double2 PR[BAND_MAX_NC * BAND_MAX_NC];
     __shared__ double2 T2[256];
-    const int x = blockIdx.x, sji = blockIdx.y, nc = g.nc, e = g.e, n1 = g.n1, n2 = g.n2;
+    const int np = g.Ns * (g.Ns + 1) / 2, s = blockIdx.y / np, p = blockIdx.y - s * np;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    const int j = p - i * (i + 1) / 2;
+    const int x = blockIdx.x, sji = (s * g.Ns + j) * g.Ns + i, nc = g.nc, e = g.e, n1 = g.n1, n2 = g.n2;
     const int nu1 = x - n1 / 2;
     for (int n = threadIdx.x; n < n2; n += blockDim.x) T2[n] = tw2[n];
     for (int t = threadIdx.x; t < nc * nc; t += blockDim.x) {
@@ -140,7 +148,7 @@ __global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __re
     for (int n = threadIdx.x; n < n2; n += blockDim.x) {
         double2 k = cmk(0.0, 0.0);
         for (int d2 = 0; d2 < nc; ++d2) k = cfma(A[d2], T2[((d2 - e) * (n - n2 / 2)) & (n2 - 1)], k);
-        Khat[((size_t)sji * n1 + x) * n2 + n] = k;
+        Khat[((size_t)blockIdx.y * n1 + x) * n2 + n] = k;
     }
 }
 
@@ -299,7 +307,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         }
     // ---- normal-operator scaling conj(tau_i[n]) / n2, then the circular Hankel
     // term for the positions t = cg (mod CG) of this wave (output shot i):
-    //   sum_j Khat[s][j][i][x][n] u_{s,j}[n]
+    //   sum_j Khat[s][j][i][x][n] u_{s,j}[n]   (stored pairs j <= i; conjugate for j > i)
     const bool writer = (grp == 0);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -313,7 +321,9 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
                 double2 rg = cmk(0.0, 0.0);
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
-                    const double2 kv = Khat[((size_t)((s * NS + j) * NS + i) * n1 + x1) * N2 + n];
+                    const int pr = j <= i ? khat_pair(j, i) : khat_pair(i, j);
+                    double2 kv = Khat[((size_t)(s * (NS * (NS + 1) / 2) + pr) * n1 + x1) * N2 + n];
+                    kv.y = j <= i ? kv.y : -kv.y;
                     const double2 taj = cscale(TW2[(j * n) & (N2 - 1)], sgn_pow(n));
                     rg = cfma(kv, cmulc(U[(s * NS + j) * N2 + n], taj), rg);
                 }
