@@ -192,10 +192,15 @@ k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ x
         const double2* bf = b + (size_t)fx * n;
         // four interleaved partial sums (q mod 4), added in a fixed order at the end
         double2 s4[4] = {cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0)};
+        // a is the same for every thread: read it from global memory through the
+        // constant address space (scalar loads) instead of shared memory
+        const __attribute__((address_space(4))) double* a4 =
+            (const __attribute__((address_space(4))) double*)(uintptr_t)(base_i + (size_t)line_a * ls);
 #pragma unroll 2
         for (int q = 0; q < n; q += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s4[u] = cfma(cconj(a[q + u]), bf[(q + u + fr - e) & (n - 1)], s4[u]);
+            for (int u = 0; u < 4; ++u)
+                s4[u] = cfma(cmk(a4[2 * (q + u)], -a4[2 * (q + u) + 1]), bf[(q + u + fr - e) & (n - 1)], s4[u]);
         }
         const double2 s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
         const int d2 = col ? fr : fx, d1 = col ? fx : fr;
