@@ -1,9 +1,9 @@
 """GPU parity on geometries that exercise the other kernel instances: the
 generic column pass (shot counts without a register-resident instance), the
 band kernel for 1, 2 and 8 shots, the vector pass with fewer than 64 ky per
-row, a coil count that leaves a partial coil group, and the fast column pass
-at folded lengths 32 and 64 (the latter with two slices and an odd coil
-count).  Each case checks the normal operator with the
+row, a coil count that leaves a partial coil group, every instance of the fast
+column pass (folded lengths 16, 32 and 64, two and three slices, odd coil
+counts), and one coil with a 1 x 1 schedule.  Each case checks the normal operator with the
 oracle's weights and a short IRLS solve against the oracle's."""
 import numpy as np
 import pytest
@@ -34,6 +34,11 @@ GEOMS = {
     # coil group has a clamped, zero-weighted member), band kernel <5, 4>
     "n256_L2_Ns4_r3": (si.Geometry(n=256, n_slices=2, n_shots=4, n_coils=5, filt=3, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=2, snr=30.0), 105),
+    # fast column pass <32, 3> and <16, 3> (three slices at folded lengths 32 and 16), odd coil counts
+    "n128_L3_Ns4_r5": (si.Geometry(n=128, n_slices=3, n_shots=4, n_coils=7, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=2, snr=30.0), 107),
+    "n64_L3_Ns4_r3": (si.Geometry(n=64, n_slices=3, n_shots=4, n_coils=3, filt=3, lam=1e-3, n_irls=2, n_cg=3,
+                                  phase_order=2, snr=30.0), 108),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
