@@ -260,7 +260,7 @@ def main():
 
     # dominant kernel: per-column SENSE + Hankel pass of every CG matvec
     kern = {}
-    for name in ("col_normal", "band_extract", "band_corr", "cg_alpha", "cg_update", "rows_inv", "rows_fwd"):
+    for name in ("col_normal", "band_extract", "band_corr", "cg_update", "rows_inv", "rows_fwd"):
         t = time_kernel(torch, plan, name, args.kernel_reps)
         f, b = plan.kernel_cost(name)
         kern[name] = {"us": t * 1e6, "gflop": f / 1e9, "mb": b / 1e6,

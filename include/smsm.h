@@ -218,17 +218,17 @@ smsm_status smsm_images_sos(smsm_plan* plan, const void* x_dev, void* img_dev, v
 
 /* Kernels that smsm_launch_kernel can re-run.  CG runs on the hybrid layout
  * (image x, k-space ky; the kx transform is unitary): one CG iteration is
- * COL_NORMAL, BAND_EXTRACT, BAND_CORR, CG_ALPHA and CG_UPDATE (BAND_EXTRACT
- * and BAND_CORR only when lambda > 0 adds the band). */
+ * COL_NORMAL, BAND_EXTRACT, BAND_CORR and CG_UPDATE (BAND_EXTRACT and
+ * BAND_CORR only when lambda > 0 adds the band). */
 typedef enum {
     SMSM_KERNEL_COL_NORMAL = 0,  /* p = r + beta p, then per column: SENSE coil loop, image-domain
                                     Hankel term, Re <p, q> partials */
     SMSM_KERNEL_ROWS_INV = 1,    /* kx inverse DFT, natural -> hybrid (Gram and operator entry points) */
     SMSM_KERNEL_ROWS_FWD = 2,    /* kx forward DFT, hybrid -> natural (Gram and the solve's output) */
     SMSM_KERNEL_BAND_CORR = 3,   /* Hankel band correction (rows hybrid, columns and corners natural) */
-    SMSM_KERNEL_CG_UPDATE = 4,   /* band injection, x and r update, |r|^2 partials */
-    SMSM_KERNEL_BAND_EXTRACT = 5, /* natural kx columns of p within 2(r-1) of the kx edges */
-    SMSM_KERNEL_CG_ALPHA = 6      /* one-block reduction of the CG partial sums to the step length */
+    SMSM_KERNEL_CG_UPDATE = 4,   /* step length from the Re <p, q> partials, band injection,
+                                    x and r update, |r|^2 partials */
+    SMSM_KERNEL_BAND_EXTRACT = 5 /* natural kx columns of p within 2(r-1) of the kx edges */
 } smsm_kernel_id;
 
 /*

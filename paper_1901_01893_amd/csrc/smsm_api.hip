@@ -200,7 +200,7 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
     const long nvec = (long)g.B * g.n1 * g.n2;
     if (pc.mode != 0) {
         hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p, pc.rr_new, pc.nrr,
-                           pc.rr_old, pc.mode == 1 ? 1 : 0);
+                           pc.rr_old, pc.rr_out, pc.mode == 1 ? 1 : 0);
         LAUNCH_CHECK();
         in = pc.p;
     }
@@ -280,19 +280,13 @@ const void* hyb_update_fn(int mode, int xw, bool wu, bool band) {
 smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
     a.g = P->g;
     a.bi = BandInj{P->crow, P->ccol, P->ccorner, P->finv, band_ds(P->g.Ns, P->g.nc)};
-    a.alpha = P->cgs + 3;
+    a.pq = P->pq;
+    a.npq = P->npc + (a.use_band ? band_items(P->g) * P->g.L : 0);
+    a.alpha_out = P->cgs + 3;
+    a.flags = P->flags;
     const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
     void* args[] = {&a};
     if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(64 * HYB_WAVES), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
-    LAUNCH_CHECK();
-    return SMSM_OK;
-}
-
-// alpha = |r|^2 / Re <p, N p> and |r|^2 (into *rr_out) from their partials.
-smsm_status cg_alpha(smsm_plan* P, const double* rr_part, double* rr_out, bool band, hipStream_t st) {
-    const int npq = P->npc + (band ? band_items(P->g) * P->g.L : 0);
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(1024), 0, st, rr_part, P->npr, P->pq, npq, rr_out, P->cgs + 3,
-                       P->flags);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -784,6 +778,7 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
             pc.rr_new = RR[j % 3];
             pc.nrr = P->npr;
             pc.rr_old = P->cgs + (j + 2) % 3;
+            pc.rr_out = P->cgs + j % 3;
             pc.mode = j == 0 ? 1 : 2;
             pc.pq = P->pq;
             if ((s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st))) return s;
@@ -791,9 +786,9 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
                 if ((s = band_extract(P, P->p, P->col_fast < 0, st))) return s;
                 if ((s = band_corr(P, st))) return s;
             }
-            if ((s = cg_alpha(P, RR[j % 3], P->cgs + j % 3, reg, st))) return s;
             HybArgs a{};
             a.mode = 2;
+            a.rr = P->cgs + j % 3;
             a.use_band = reg ? 1 : 0;
             a.h2 = P->h2;
             a.x = P->x;
@@ -1173,10 +1168,6 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
             f = 8.0 * B * n1 * n2 * 4.0 * e;
             b = vec + B * 4.0 * e * n2 * 16.0;
             break;
-        case SMSM_KERNEL_CG_ALPHA:
-            f = 0.0;
-            b = 0.0;
-            break;
         default:
             break;
     }
@@ -1190,13 +1181,13 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
 extern "C" {
 
 smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* bytes) {
-    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_CG_ALPHA) return SMSM_E_INVALID;
+    if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
     kernel_cost(P->g, id, flops, bytes);
     return SMSM_OK;
 }
 
 smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
-    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_CG_ALPHA) return SMSM_E_INVALID;
+    if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     const bool reg = P->prm.lambda > 0.0 && P->have_weights;
@@ -1210,6 +1201,7 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
                 pc.rr_new = P->pr + P->npr;
                 pc.nrr = P->npr;
                 pc.rr_old = P->cgs;
+                pc.rr_out = P->cgs + 1;
                 pc.mode = 2;
                 pc.pq = P->pq;
                 s = col<COL_NORMAL>(P, nullptr, P->h2, reg ? 1 : 0, pc, st);
@@ -1219,10 +1211,10 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
             case SMSM_KERNEL_ROWS_FWD: s = rows_fwd(P, P->x, P->q, st); break;
             case SMSM_KERNEL_BAND_CORR: s = band_corr(P, st); break;
             case SMSM_KERNEL_BAND_EXTRACT: s = band_extract(P, P->p, P->col_fast < 0, st); break;
-            case SMSM_KERNEL_CG_ALPHA: s = cg_alpha(P, P->pr, P->cgs + 1, reg, st); break;
             case SMSM_KERNEL_CG_UPDATE: {
                 HybArgs a{};
                 a.mode = 2;
+                a.rr = P->cgs + 1;
                 a.use_band = reg ? 1 : 0;
                 a.h2 = P->h2;
                 a.x = P->x;

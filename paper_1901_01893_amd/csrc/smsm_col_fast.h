@@ -159,7 +159,9 @@ template <int N> struct WaveFft;
 // beta = sum(rr_new[0..nrr)) / *rr_old (0 when *rr_old is 0).
 // In modes 1 and 2 the new p is written back and the input is p; each
 // workgroup also stores Re <p, output> of its column in pq[blockIdx.x],
-// evaluated in the image domain (the ky transforms are unitary).
+// evaluated in the image domain (the ky transforms are unitary), and the
+// first workgroup stores sum(rr_new[0..nrr)) (the new |r|^2) in *rr_out for
+// the step length of the vector update.
 struct ColCg {
     const double2* r;
     double2* p;
@@ -168,6 +170,7 @@ struct ColCg {
     const double* rr_old;    // the previous |r|^2 (scalar)
     int mode;
     double* pq;
+    double* rr_out;          // receives the new |r|^2 (scalar)
 };
 
 // Normal operator column pass; same input/output contract as k_col<COL_NORMAL>.
@@ -201,9 +204,13 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
 
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
     double beta = 0.0;
-    if (pc.mode == 2) {
-        const double rn = sum_partials(pc.rr_new, pc.nrr, (double*)ACC), ro = *pc.rr_old;
-        beta = ro > 0.0 ? rn / ro : 0.0;
+    if (pc.mode != 0) {
+        const double rn = sum_partials(pc.rr_new, pc.nrr, (double*)ACC);
+        if (pc.mode == 2) {
+            const double ro = *pc.rr_old;
+            beta = ro > 0.0 ? rn / ro : 0.0;
+        }
+        if (x1 == 0 && tid == 0) *pc.rr_out = rn;
     }
     __syncthreads();
 

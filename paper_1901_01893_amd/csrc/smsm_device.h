@@ -93,6 +93,28 @@ SMSM_DEV double sum_partials(const double* __restrict__ part, int n, double* scr
     return block_sum(v, scratch);
 }
 
+// Sum of `n` partial values by one wave, in a fixed order (every lane, and
+// every wave that calls it on the same data, gets the same result): lane
+// adds slots lane + 64 k in increasing k, eight loads in flight, then a
+// butterfly across the lanes (IEEE addition is commutative, so the partners
+// of each step form identical sums).
+SMSM_DEV double wave_sum_partials(const double* __restrict__ part, int n, int lane) {
+    double v = 0.0;
+    for (int base = lane; base < n; base += 8 * 64) {
+        double pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = base + u * 64;
+            pv[u] = part[k < n ? k : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * 64 < n) v += pv[u];
+    }
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // Sums of two ranges of per-block partials, a[0..na) and b[0..nb), each in
 // a fixed order (deterministic), with every load of a thread issued before the
 // first add (8 slots per range per pass).  Every thread must call it; the

@@ -85,8 +85,13 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
 // kernel when BAND): q = h2 + band correction, then
 //   mode 0: out = q
 //   mode 1: out = bvec - q (CG residual); per-block partials of |out|^2
-//   mode 2: CG step with alpha = *alpha (from k_cg_alpha): x += alpha p,
-//           r -= alpha q; partials of |r|^2.
+//   mode 2: CG step x += alpha p, r -= alpha q; partials of |r|^2.  Wave 0
+//           of every workgroup forms alpha = *rr / sum(pq[0..npq)) before
+//           its own vector loads and shares it through shared memory (the
+//           same fixed-order sum everywhere, so all workgroups agree);
+//           rr == 0 (exact solution) gives alpha = 0, non-positive or
+//           non-finite curvature gives alpha = 0 and sets flags[0]; the
+//           first workgroup stores alpha in *alpha_out.
 // Thread layout: lane = ky (LY = min(64, n2) lanes per x, 64 / LY x per
 // step), so the natural band-column corrections of a lane's ky (shares
 // summed, corner cross terms added; staged once per workgroup) stay in
@@ -104,7 +109,11 @@ struct HybArgs {
     const double2* p;
     double2* r;
     BandInj bi;
-    const double* alpha;     // scalar step length (mode 2)
+    const double* rr;        // |r|^2 of the current residual (mode 2, scalar)
+    const double* pq;        // partials of Re <p, N p> (mode 2): column pass, then band
+    int npq;
+    double* alpha_out;       // the step length (mode 2, written by the first workgroup)
+    int* flags;
     double* part;            // per-block partials of |r|^2
 };
 
@@ -115,6 +124,7 @@ struct HybArgs {
 template <int MODE, int XW, bool WU, bool BAND>
 __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     __shared__ double red[8];
+    __shared__ double alpha_sh;
     __shared__ double2 cs[BAND ? HYB_MAX_E2 * 64 : 1];    // corrections [cl][ky in chunk]
     const Geo& g = a.g;
     const int n1 = g.n1, n2 = g.n2, e = g.e, e2 = 2 * g.e;
@@ -131,6 +141,21 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     double2* __restrict__ out = a.out;
     const bool rb = ky < e || ky >= n2 - e;            // this lane's ky is a band row
     const int rrow = rb ? (ky < e ? ky : ky - (n2 - e2)) : 0;
+
+    // ---- step length (wave 0, before its vector loads)
+    if (MODE == 2 && wave == 0) {
+        const double pq = wave_sum_partials(a.pq, a.npq, lane), rr = *a.rr;
+        const double al = rr / pq;
+        const bool bad = rr > 0.0 && (!(pq > 0.0) || !isfinite(al));
+        const double alpha0 = (rr > 0.0 && !bad) ? al : 0.0;
+        if (lane == 0) {
+            alpha_sh = alpha0;
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+                *a.alpha_out = alpha0;
+                if (bad) a.flags[0] = 1;
+            }
+        }
+    }
 
     // ---- band-column corrections of this workgroup's ky: shares and corner terms
     double2 cv[HYB_CS_PER_THREAD];
@@ -173,7 +198,7 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
         }
         if (BAND) cr[t] = a.bi.crow[((size_t)b * e2 + rrow) * n1 + xx[t]];
     }
-    const double alpha = MODE == 2 ? *a.alpha : 0.0;
+    if (MODE == 2 && !BAND) __syncthreads();          // alpha_sh (BAND: the staging barrier below)
     double2 c[HYB_MAX_E2];
     if (BAND) {
         const int ncs = e2 * LY;
@@ -188,6 +213,7 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
 #pragma unroll
         for (int cl = 0; cl < HYB_MAX_E2; ++cl) c[cl] = cl < e2 ? cs[cl * 64 + lane % LY] : cmk(0.0, 0.0);
     }
+    const double alpha = MODE == 2 ? alpha_sh : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int t = 0; t < XW; ++t) {
@@ -227,38 +253,20 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     }
 }
 
-// CG scalars of one step, once for the whole grid: rr = sum rr_part[0..nrr)
-// (|r|^2), pq = sum pq_part[0..npq) (Re <p, N p>: column-pass then band
-// partials); *rr_out = rr, *alpha = rr / pq.  rr == 0 (exact solution) gives
-// alpha = 0; non-positive or non-finite curvature gives alpha = 0 and sets
-// flags[0].  One block.
-__global__ void __launch_bounds__(1024) k_cg_alpha(const double* __restrict__ rr_part, int nrr,
-                                                   const double* __restrict__ pq_part, int npq,
-                                                   double* __restrict__ rr_out, double* __restrict__ alpha,
-                                                   int* __restrict__ flags) {
-    __shared__ double red[32];
-    double rr, pq;
-    sum_partials2(rr_part, nrr, pq_part, npq, rr, pq, red);
-    if (threadIdx.x == 0) {
-        const double al = rr / pq;
-        const bool bad = rr > 0.0 && (!(pq > 0.0) || !isfinite(al));
-        *rr_out = rr;
-        *alpha = (rr > 0.0 && !bad) ? al : 0.0;
-        if (bad) flags[0] = 1;
-    }
-}
-
 // p = r (first step) or p = r + beta p, beta = sum rr_new[0..nrr) / *rr_old,
-// for column passes that do not fuse the update.
+// for column passes that do not fuse the update; the first block stores
+// sum rr_new[0..nrr) (the new |r|^2) in *rr_out.
 __global__ void k_hyb_pupdate(long n, const double2* __restrict__ r, double2* __restrict__ p,
                               const double* __restrict__ rr_new, int nrr, const double* __restrict__ rr_old,
-                              int first) {
+                              double* __restrict__ rr_out, int first) {
     __shared__ double red[8];
     double beta = 0.0;
+    const double rn = sum_partials(rr_new, nrr, red);
     if (!first) {
-        const double rn = sum_partials(rr_new, nrr, red), ro = *rr_old;
+        const double ro = *rr_old;
         beta = ro > 0.0 ? rn / ro : 0.0;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *rr_out = rn;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
         p[k] = first ? r[k] : cadd(r[k], cscale(p[k], beta));
 }

@@ -33,7 +33,7 @@ ABI_SYMBOLS = (
     "smsm_kernel_timer_start", "smsm_kernel_timer_read", "smsm_batch_create", "smsm_batch_launch",
     "smsm_batch_destroy", "smsm_batch_streams",
 )
-KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5, "cg_alpha": 6}
+KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
 
 
 class Geometry(ctypes.Structure):
