@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(64 * HW) k_zgemm(int K, int KP, HgArgs a) {
     const int kq = lane >> 4;
     const double2* Ap = A + off + (size_t)(i0 + (lane & 15)) * KP + kq;   // A[i][kq + 4 s]
     const double2* Bp = B + off + (size_t)kq * KP + j0 + (lane & 15);     // B[kq + 4 s][j]
-    const int nks = KP / 4;
+    const int nks = (K + 3) / 4;   // columns of A and rows of B past K are zero: skipped
     const int ks0 = (w * nks) / HW, ks1 = ((w + 1) * nks) / HW;
     hd4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = {0.0, 0.0, 0.0, 0.0}, t3 = {0.0, 0.0, 0.0, 0.0};
     int ks = ks0;

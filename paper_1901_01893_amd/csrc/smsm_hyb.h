@@ -22,12 +22,15 @@
 // ky < 2e, else ky - (n2 - 4e) (the band rows' kx taps then read contiguous
 // x); the fast column pass writes that copy itself.
 // grid (n2/16 * np/16, B), block 64 EXTRACT_WAVES; np = padded width of fx.
+// The c tile varies slowest within a row of the grid, so the workgroups that
+// read the same 16 ky of p are n2/16 ids apart (a multiple of 8 for n2 >= 128:
+// the same XCD, whose L2 then serves the second read).
 __global__ void __launch_bounds__(64 * EXTRACT_WAVES)
 k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, const double2* __restrict__ fx,
                double2* __restrict__ pcol, double2* __restrict__ prow, int write_prow) {
     __shared__ double acc[EXTRACT_WAVES][8][64];
     const int b = blockIdx.y;
-    const int nct = np / 16, t = blockIdx.x, mt = t / nct, ct = t - mt * nct;
+    const int nmt = n2 / 16, t = blockIdx.x, ct = t / nmt, mt = t - ct * nmt;
     const int ky0 = mt * 16, c0 = ct * 16;
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), kq = lane >> 4;
     const double2* Ap = pt + ((size_t)b * n1 + kq) * n2 + ky0 + (lane & 15);   // pt[b][x][ky]
