@@ -211,6 +211,21 @@ def test_solve_with_unregularised_zero_slice(torch_dev):
     plan.close()
 
 
+def test_solve_zero_data_is_exactly_zero(torch_dev):
+    """y = 0: x = 0 minimises the objective exactly.  Every residual is zero,
+    so each CG step length must come out 0 without the numeric flag (the
+    |r|^2 = 0 branch of the step-length rule), and x stays exactly zero."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, x_true, y = case_for("small", 5)
+    p = smsm.make_params(lam=g.lam, n_irls=2, n_cg=3, flags=smsm.SMSM_FLAG_X_C128)
+    plan = make_plan(torch, dev, g, case, p)
+    x = plan.solve(to_dev(torch, dev, np.zeros_like(y))).cpu().numpy()
+    assert plan.status() == smsm.SMSM_OK
+    assert np.all(x == 0)
+    plan.close()
+
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
