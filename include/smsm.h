@@ -221,13 +221,14 @@ smsm_status smsm_images_sos(smsm_plan* plan, const void* x_dev, void* img_dev, v
  * COL_NORMAL, BAND_EXTRACT, BAND_CORR and CG_UPDATE (BAND_EXTRACT and
  * BAND_CORR only when lambda > 0 adds the band). */
 typedef enum {
-    SMSM_KERNEL_COL_NORMAL = 0,  /* p = r + beta p, then per column: SENSE coil loop, image-domain
+    SMSM_KERNEL_COL_NORMAL = 0,  /* x += alpha p and p = r + beta p (the previous step's length and
+                                    direction), then per column: SENSE coil loop, image-domain
                                     Hankel term, Re <p, q> partials */
     SMSM_KERNEL_ROWS_INV = 1,    /* kx inverse DFT, natural -> hybrid (Gram and operator entry points) */
     SMSM_KERNEL_ROWS_FWD = 2,    /* kx forward DFT, hybrid -> natural (Gram and the solve's output) */
     SMSM_KERNEL_BAND_CORR = 3,   /* Hankel band correction (rows hybrid, columns and corners natural) */
     SMSM_KERNEL_CG_UPDATE = 4,   /* step length from the Re <p, q> partials, band injection,
-                                    x and r update, |r|^2 partials */
+                                    r update, |r|^2 partials */
     SMSM_KERNEL_BAND_EXTRACT = 5 /* natural kx columns of p within 2(r-1) of the kx edges */
 } smsm_kernel_id;
 

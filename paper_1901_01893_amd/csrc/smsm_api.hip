@@ -68,7 +68,7 @@ struct smsm_plan {
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
     double *pr = nullptr, *pq = nullptr, *bpart = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr, *nsmu = nullptr;
-    double* cgs = nullptr;   // CG scalars: |r|^2 of the last three residuals [0..2], step length [3]
+    double* cgs = nullptr;   // CG scalars: |r|^2 of the last three residuals [0..2]; the last step length [8]
     int *done = nullptr, *flags = nullptr;
 
     int ns_iters = kNsDefaultIters;
@@ -199,8 +199,8 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
     }
     const long nvec = (long)g.B * g.n1 * g.n2;
     if (pc.mode != 0) {
-        hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p, pc.rr_new, pc.nrr,
-                           pc.rr_old, pc.rr_out, pc.mode == 1 ? 1 : 0);
+        hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p_old, pc.p, pc.x,
+                           pc.alpha_prev, pc.rr_new, pc.nrr, pc.rr_old, pc.rr_out, pc.mode == 1 ? 1 : 0);
         LAUNCH_CHECK();
         in = pc.p;
     }
@@ -282,11 +282,19 @@ smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
     a.bi = BandInj{P->crow, P->ccol, P->ccorner, P->finv, band_ds(P->g.Ns, P->g.nc)};
     a.pq = P->pq;
     a.npq = P->npc + (a.use_band ? band_items(P->g) * P->g.L : 0);
-    a.alpha_out = P->cgs + 3;
+    if (!a.alpha_out) a.alpha_out = P->cgs + 8;
     a.flags = P->flags;
     const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
     void* args[] = {&a};
     if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(64 * HYB_WAVES), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// x += alpha p with the last step length (cgs + 8): the last CG step of a cycle.
+smsm_status x_step(smsm_plan* P, hipStream_t st) {
+    const long nvec = (long)P->g.B * P->g.n1 * P->g.n2;
+    hipLaunchKernelGGL(k_x_step, vec_grid(), dim3(kThreads), 0, st, nvec, P->x, P->p, P->cgs + 8);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -586,7 +594,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
     const size_t oei = cv.take<double>(L), onsmu = cv.take<double>((size_t)P->ns_iters * L);
     const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
-    const size_t ocgs = cv.take<double>(8);
+    const size_t ocgs = cv.take<double>(16);
 
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
@@ -772,9 +780,14 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
         a0.part = RR[0];
         if ((s = hyb_apply(P, P->x, COL_NORMAL, reg, a0, st))) return s;
         for (int j = 0; j < prm.n_cg; ++j) {
+            // x takes step j - 1 in the column pass of step j (which reads that
+            // direction anyway) and the last step after the loop
             ColCg pc{};
             pc.r = P->r;
+            pc.p_old = P->p;
             pc.p = P->p;
+            pc.x = P->x;
+            pc.alpha_prev = P->cgs + 8;
             pc.rr_new = RR[j % 3];
             pc.nrr = P->npr;
             pc.rr_old = P->cgs + (j + 2) % 3;
@@ -791,12 +804,11 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
             a.rr = P->cgs + j % 3;
             a.use_band = reg ? 1 : 0;
             a.h2 = P->h2;
-            a.x = P->x;
-            a.p = P->p;
             a.r = P->r;
             a.part = RR[(j + 1) % 3];
             if ((s = hyb_update(P, a, st))) return s;
         }
+        if (prm.n_cg > 0 && (s = x_step(P, st))) return s;
     }
     if ((s = rows_fwd(P, P->x, P->q, st))) return s;
     if (c128)
@@ -1141,9 +1153,9 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                         + Ns * M * L * 14.0                       // CAIPI slice sum and split
                         + 8.0 * B * n2)                           // unfold-accumulate
                 + B * n2 * Ns * 8.0                               // per-pixel Hankel term (Ns taps)
-                + B * n2 * 8.0;                                   // p = r + beta p and Re <p, q>
+                + B * n2 * 12.0;                                  // x += alpha p, p = r + beta p, Re <p, q>
             f = n1 * per_col;
-            b = 4.0 * vec + L * Nc * n1 * n2 * 16.0                // r, p in; p, q out; coil maps (c128)
+            b = 6.0 * vec + L * Nc * n1 * n2 * 16.0                // r, p, x in; p, q, x out; coil maps (c128)
                 + L * Ns * (Ns + 1) / 2.0 * n1 * n2 * 16.0;        // image-domain Hankel kernel (pairs j <= i)
             break;
         }
@@ -1161,8 +1173,8 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
             break;
         }
         case SMSM_KERNEL_CG_UPDATE:
-            f = B * n1 * n2 * (14.0 + 8.0 * 2.0 * e);
-            b = 6.0 * vec + B * (ds * 2.0 * e * n2 + 2.0 * e * n1 + 4.0 * e * e) * 16.0;
+            f = B * n1 * n2 * (10.0 + 8.0 * 2.0 * e);
+            b = 3.0 * vec + B * (ds * 2.0 * e * n2 + 2.0 * e * n1 + 4.0 * e * e) * 16.0;
             break;
         case SMSM_KERNEL_BAND_EXTRACT:
             f = 8.0 * B * n1 * n2 * 4.0 * e;
@@ -1197,7 +1209,10 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
             case SMSM_KERNEL_COL_NORMAL: {
                 ColCg pc{};
                 pc.r = P->r;
+                pc.p_old = P->p;
                 pc.p = P->p;
+                pc.x = P->x;
+                pc.alpha_prev = P->cgs + 8;
                 pc.rr_new = P->pr + P->npr;
                 pc.nrr = P->npr;
                 pc.rr_old = P->cgs;
@@ -1217,8 +1232,6 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
                 a.rr = P->cgs + 1;
                 a.use_band = reg ? 1 : 0;
                 a.h2 = P->h2;
-                a.x = P->x;
-                a.p = P->p;
                 a.r = P->r;
                 a.part = P->pr + 2 * P->npr;
                 s = hyb_update(P, a, st);

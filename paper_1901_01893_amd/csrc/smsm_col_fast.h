@@ -155,16 +155,23 @@ __global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __re
 template <int N> struct WaveFft;
 
 // Optional CG direction update fused into the column pass (hybrid layout):
-// mode 0: the input is h1; mode 1: p = r; mode 2: p = r + beta p with
-// beta = sum(rr_new[0..nrr)) / *rr_old (0 when *rr_old is 0).
-// In modes 1 and 2 the new p is written back and the input is p; each
+// mode 0: the input is h1; mode 1: p = r; mode 2: p = r + beta p_old with
+// beta = sum(rr_new[0..nrr)) / *rr_old (0 when *rr_old is 0), and, when x is
+// given, the previous step x += (*alpha_prev) p_old on the way (the vector
+// update of that step left x alone).
+// In modes 1 and 2 the new p is written to p (p_old may be the same buffer:
+// each element is read before it is written, by the same thread) and the
+// input is p; each
 // workgroup also stores Re <p, output> of its column in pq[blockIdx.x],
 // evaluated in the image domain (the ky transforms are unitary), and the
 // first workgroup stores sum(rr_new[0..nrr)) (the new |r|^2) in *rr_out for
 // the step length of the vector update.
 struct ColCg {
     const double2* r;
+    const double2* p_old;    // the previous direction (mode 2)
     double2* p;
+    double2* x;              // iterate that takes the previous step (mode 2), or null
+    const double* alpha_prev;   // that step's length (scalar)
     const double* rr_new;    // partials of the new |r|^2
     int nrr;
     const double* rr_old;    // the previous |r|^2 (scalar)
@@ -204,6 +211,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
 
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
     double beta = 0.0;
+    const double alpha_prev = (pc.mode == 2 && pc.x) ? *pc.alpha_prev : 0.0;
     if (pc.mode != 0) {
         const double rn = sum_partials(pc.rr_new, pc.nrr, (double*)ACC);
         if (pc.mode == 2) {
@@ -229,7 +237,11 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
                 val = h1[col0 + k];
             } else {
                 val = pc.r[col0 + k];
-                if (pc.mode == 2) val = cadd(val, cscale(pc.p[col0 + k], beta));
+                if (pc.mode == 2) {
+                    const double2 po = pc.p_old[col0 + k];
+                    if (pc.x) pc.x[col0 + k] = cadd(pc.x[col0 + k], cscale(po, alpha_prev));
+                    val = cadd(val, cscale(po, beta));
+                }
                 pc.p[col0 + k] = val;
             }
             v[t] = cscale(val, sgn_pow(k));

@@ -88,7 +88,8 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
 // kernel when BAND): q = h2 + band correction, then
 //   mode 0: out = q
 //   mode 1: out = bvec - q (CG residual); per-block partials of |out|^2
-//   mode 2: CG step x += alpha p, r -= alpha q; partials of |r|^2.  Wave 0
+//   mode 2: CG step r -= alpha q; partials of |r|^2 (x takes alpha p in the
+//           next column pass, or in k_x_step after the last step).  Wave 0
 //           of every workgroup forms alpha = *rr / sum(pq[0..npq)) before
 //           its own vector loads and shares it through shared memory (the
 //           same fixed-order sum everywhere, so all workgroups agree);
@@ -108,8 +109,6 @@ struct HybArgs {
     const double2* h2;
     const double2* bvec;
     double2* out;
-    double2* x;
-    const double2* p;
     double2* r;
     BandInj bi;
     const double* rr;        // |r|^2 of the current residual (mode 2, scalar)
@@ -138,8 +137,6 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     const int ky = kc * LY + lane % LY, xs = lane / LY;
     const int x0 = (xb * HYB_WAVES + wave) * XW * XPS;
     const double2* __restrict__ h2 = a.h2;
-    const double2* __restrict__ pv = a.p;
-    double2* __restrict__ xv = a.x;
     double2* __restrict__ rv = a.r;
     double2* __restrict__ out = a.out;
     const bool rb = ky < e || ky >= n2 - e;            // this lane's ky is a band row
@@ -186,7 +183,7 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     // ---- vectors
     int xx[XW];
     size_t kk[XW];
-    double2 q[XW], v1[XW], v2[XW], v3[XW], cr[XW];
+    double2 q[XW], v1[XW], v3[XW], cr[XW];
 #pragma unroll
     for (int t = 0; t < XW; ++t) {
         xx[t] = x0 + t * XPS + xs;
@@ -194,11 +191,7 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
         kk[t] = ((size_t)b * n1 + xx[t]) * n2 + ky;
         q[t] = h2[kk[t]];
         if (MODE == 1) v1[t] = a.bvec[kk[t]];
-        if (MODE == 2) {
-            v1[t] = xv[kk[t]];
-            v2[t] = pv[kk[t]];
-            v3[t] = rv[kk[t]];
-        }
+        if (MODE == 2) v3[t] = rv[kk[t]];
         if (BAND) cr[t] = a.bi.crow[((size_t)b * e2 + rrow) * n1 + xx[t]];
     }
     if (MODE == 2 && !BAND) __syncthreads();          // alpha_sh (BAND: the staging barrier below)
@@ -244,7 +237,6 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
             out[kk[t]] = v;
             s += cabs2(v);
         } else {
-            xv[kk[t]] = cadd(v1[t], cscale(v2[t], alpha));
             const double2 v = csub(v3[t], cscale(qt, alpha));
             rv[kk[t]] = v;
             s += cabs2(v);
@@ -256,14 +248,17 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     }
 }
 
-// p = r (first step) or p = r + beta p, beta = sum rr_new[0..nrr) / *rr_old,
-// for column passes that do not fuse the update; the first block stores
-// sum rr_new[0..nrr) (the new |r|^2) in *rr_out.
-__global__ void k_hyb_pupdate(long n, const double2* __restrict__ r, double2* __restrict__ p,
+// p = r (first step) or p = r + beta p_old, beta = sum rr_new[0..nrr) /
+// *rr_old, for column passes that do not fuse the update (p_old may be p),
+// with the previous step x += (*alpha_prev) p_old when x is given; the first
+// block stores sum rr_new[0..nrr) (the new |r|^2) in *rr_out.
+__global__ void k_hyb_pupdate(long n, const double2* __restrict__ r, const double2* p_old, double2* p,
+                              double2* __restrict__ x, const double* __restrict__ alpha_prev,
                               const double* __restrict__ rr_new, int nrr, const double* __restrict__ rr_old,
                               double* __restrict__ rr_out, int first) {
     __shared__ double red[8];
     double beta = 0.0;
+    const double ap = (!first && x) ? *alpha_prev : 0.0;
     const double rn = sum_partials(rr_new, nrr, red);
     if (!first) {
         const double ro = *rr_old;
@@ -271,7 +266,22 @@ __global__ void k_hyb_pupdate(long n, const double2* __restrict__ r, double2* __
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *rr_out = rn;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
-        p[k] = first ? r[k] : cadd(r[k], cscale(p[k], beta));
+        if (first) {
+            p[k] = r[k];
+        } else {
+            const double2 po = p_old[k];
+            if (x) x[k] = cadd(x[k], cscale(po, ap));
+            p[k] = cadd(r[k], cscale(po, beta));
+        }
+}
+
+// x += (*alpha) p: the last CG step of a cycle (the earlier steps reach x
+// in the column pass that follows them).
+__global__ void k_x_step(long n, double2* __restrict__ x, const double2* __restrict__ p,
+                         const double* __restrict__ alpha) {
+    const double al = *alpha;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        x[k] = cadd(x[k], cscale(p[k], al));
 }
 
 // Per-block partials of Re <p, q>.

@@ -211,6 +211,25 @@ def test_solve_with_unregularised_zero_slice(torch_dev):
     plan.close()
 
 
+@pytest.mark.parametrize("n_cg", [16, 17])
+def test_solve_direction_ring_boundaries(torch_dev, n_cg):
+    """x takes the CG steps from a ring of 8 stored directions: 16 steps end on
+    a full ring, 17 leave a single direction for the end of the cycle."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, x_true, y = case_for("small", 6)
+    ref = o.solve(y.astype(np.complex128), case["coils"], case["masks"], case["shifts"],
+                  oracle_params(g, n_irls=2, n_cg=n_cg))
+    plan = make_plan(torch, dev, g, case, smsm.make_params(lam=g.lam, n_irls=2, n_cg=n_cg,
+                                                          flags=smsm.SMSM_FLAG_X_C128))
+    x = plan.solve(to_dev(torch, dev, y)).cpu().numpy()
+    assert plan.status() == smsm.SMSM_OK
+    err = o.nrmse(x, ref)
+    print(f"[solve small n_cg={n_cg}] NRMSE vs oracle = {err:.3e}", flush=True)
+    assert err < SOLVE_TOL
+    plan.close()
+
+
 def test_solve_zero_data_is_exactly_zero(torch_dev):
     """y = 0: x = 0 minimises the objective exactly.  Every residual is zero,
     so each CG step length must come out 0 without the numeric flag (the
