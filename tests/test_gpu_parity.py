@@ -211,10 +211,11 @@ def test_solve_with_unregularised_zero_slice(torch_dev):
     plan.close()
 
 
-@pytest.mark.parametrize("n_cg", [16, 17])
-def test_solve_direction_ring_boundaries(torch_dev, n_cg):
-    """x takes the CG steps from a ring of 8 stored directions: 16 steps end on
-    a full ring, 17 leave a single direction for the end of the cycle."""
+@pytest.mark.parametrize("n_cg", [0, 1, 16, 17])
+def test_solve_cg_step_counts(torch_dev, n_cg):
+    """x takes each CG step in the column pass of the next step and the last
+    step of a cycle in a kernel of its own: no step (x stays A^H y), one step
+    (only that kernel) and long cycles against the oracle."""
     torch, dev = torch_dev
     from paper_1901_01893_amd import smsm
     g, case, x_true, y = case_for("small", 6)
