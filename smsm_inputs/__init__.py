@@ -166,3 +166,20 @@ def random_complex(seed: int, shape, scale: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([99, int(seed)])))
     a = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     return (scale * a / np.sqrt(2.0)).astype(np.complex64)
+
+
+def cnn_init(seed: int, c_io: int, width: int = 64, depth: int = 5, out_scale: float = 0.1) -> list:
+    """Initial weights of the learned prior's network: `depth` 3 x 3 layers
+    c_io -> width -> ... -> width -> c_io, weights N(0, 2 / (9 c_in)) (He),
+    the last layer's scaled by out_scale, biases zero.  Float32 values, as
+    the GPU network stores them.  Returns [(w [co][ci][3][3], b [co]), ...]."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
+    chans = [c_io] + [width] * (depth - 1) + [c_io]
+    params = []
+    for k in range(depth):
+        ci, co = chans[k], chans[k + 1]
+        w = rng.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (9.0 * ci))
+        if k == depth - 1:
+            w *= out_scale
+        params.append((w.astype(np.float32), np.zeros(co, dtype=np.float32)))
+    return params
