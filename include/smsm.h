@@ -264,6 +264,64 @@ smsm_status smsm_kernel_timer_start(smsm_plan* plan, int kernel_id, int capacity
  * SMSM_E_DEVICE if an event query fails. */
 smsm_status smsm_kernel_timer_read(smsm_plan* plan, double* total_ms, int* launches);
 
+/* ---- learned unrolled solver ------------------------------------------
+ *
+ * An extension beyond the paper: a learned prior stands in for the Hankel
+ * IRLS step.  From x_0 = A^H y, each of n_unroll iterations applies
+ *     z = x + s C(x / s),   x <- (A^H A + mu I)^-1 (A^H y + mu z)
+ * with C a real CNN over the 2 Ns channels (real and imaginary part of each
+ * shot's k-space) of every slice: five 3x3 layers 2Ns -> width -> width ->
+ * width -> width -> 2Ns, zero padding, ReLU after the first four, weights
+ * shared across iterations; s = sqrt(mean |A^H y|^2).  The network runs in
+ * FP32; each data-consistency solve is n_cg CG steps in FP64 warm-started at
+ * z.  Training minimises ||x_K - x*||^2 / ||x*||^2 against a reference x*
+ * (the plain solver's output) with Adam; its backward pass takes each
+ * data-consistency solve as the exact inverse (n_cg CG steps from zero).
+ *
+ * Parameters (host layout, float32): per layer, weights [co][ci][3][3] then
+ * bias [co], layers in order.  The object holds the parameters, gradients,
+ * Adam moments and a workspace for the plan's geometry, and uses the plan's
+ * buffers: calls on one plan (solver or learned) must not overlap.
+ * Requires 2 Ns to be a multiple of 4 (SMSM_E_UNSUPPORTED otherwise).
+ * Vectors: y_dev c64 [Ns][Nc][n2][n1]; x_dev, xt_dev c128 [L][Ns][n2][n1]. */
+typedef struct smsm_learned smsm_learned;
+
+/* width: hidden channels (multiple of 8, 8..256); n_unroll, n_cg >= 1;
+ * mu > 0; params_host: smsm_learned_param_count() floats of initial
+ * parameters.  Synchronous. */
+smsm_status smsm_learned_create(smsm_plan* plan, int width, int n_unroll, int n_cg, double mu,
+                                const float* params_host, smsm_learned** out);
+/* Frees the object (not the plan).  Null is a no-op. */
+smsm_status smsm_learned_destroy(smsm_learned* net);
+/* Number of float parameters; 0 for null. */
+long smsm_learned_param_count(const smsm_learned* net);
+/* Copies the parameters to / from host memory (synchronous; setting them
+ * also resets the Adam state). */
+smsm_status smsm_learned_get_params(smsm_learned* net, float* params_host);
+smsm_status smsm_learned_set_params(smsm_learned* net, const float* params_host);
+
+/* The network alone: out = C(in), in_dev and out_dev float [L][2Ns][n2][n1]. */
+smsm_status smsm_learned_cnn_forward(smsm_learned* net, const void* in_dev, void* out_dev, void* stream);
+/* Gradients of sum(gout * C(in)): gin_dev (same layout) and all parameter
+ * gradients into grads_host (param_count floats).  Synchronous. */
+smsm_status smsm_learned_cnn_backward(smsm_learned* net, const void* in_dev, const void* gout_dev, void* gin_dev,
+                                      float* grads_host, void* stream);
+
+/* x = the unrolled solver's output for measurement y.  Asynchronous. */
+smsm_status smsm_learned_solve(smsm_learned* net, const void* y_dev, void* x_dev, void* stream);
+/* Loss against xt and the gradients of every parameter (into grads_host
+ * when it is not null); the parameters do not change.  Synchronous. */
+smsm_status smsm_learned_gradients(smsm_learned* net, const void* y_dev, const void* xt_dev, double* loss,
+                                   float* grads_host, void* stream);
+/* One Adam step (b1 0.9, b2 0.999, eps 1e-8) on the gradients of y, xt with
+ * learning rate lr > 0; *loss is the loss before the step.  Synchronous. */
+smsm_status smsm_learned_train_step(smsm_learned* net, const void* y_dev, const void* xt_dev, double lr,
+                                    double* loss, void* stream);
+/* *res = ||A x - y|| (the data-consistency residual by which a caller falls
+ * back to the plain solver).  Synchronous. */
+smsm_status smsm_learned_residual(smsm_learned* net, const void* x_dev, const void* y_dev, double* res,
+                                  void* stream);
+
 #ifdef __cplusplus
 }
 #endif

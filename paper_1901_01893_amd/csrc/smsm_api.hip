@@ -6,6 +6,7 @@
 #include "smsm_dense.h"
 #include "smsm_gram.h"
 #include "smsm_hyb.h"
+#include "smsm_cnn.h"
 #include "smsm.h"
 
 #include <hip/hip_ext.h>
@@ -1240,6 +1241,405 @@ smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
         }
         if (s) return s;
     }
+    return SMSM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned unrolled solver (network and workspace for one plan's geometry).
+// ---------------------------------------------------------------------------
+
+struct smsm_learned {
+    smsm_plan* P = nullptr;
+    int dev = 0;
+    int width = 0, nc = 0, L = 0, H = 0, W = 0;   // nc = 2 Ns channels in and out
+    int n_unroll = 0, n_cg = 0;
+    double mu = 0.0;
+    static constexpr int kDepth = 5;
+    int cin[kDepth] = {}, cout[kDepth] = {};
+    size_t woff[kDepth] = {}, boff[kDepth] = {};
+    size_t nparam = 0;
+    long adam_t = 0;
+    void* arena = nullptr;
+    float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
+    float* act[kDepth + 1] = {};          // act[0] network input, act[k] output of layer k-1, act[5] output
+    float *ga = nullptr, *gbuf = nullptr, *gio = nullptr;   // hidden-gradient ping-pong, nc-channel gradient
+    double2 *b = nullptr, *x = nullptr, *z = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr;
+    double2 *g = nullptr, *wv = nullptr, *ax = nullptr, *xs = nullptr;
+    double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] rr, [2] alpha, [3] beta, [8] loss num, [9] den
+};
+
+namespace {
+
+long lvec(const smsm_learned* Lr) { return (long)Lr->L * (Lr->nc / 2) * Lr->H * Lr->W; }
+
+smsm_status lconv(smsm_learned* Lr, int ci, int co, const float* in, const float* w, const float* bias, float* out,
+                  int relu, bool bwd, hipStream_t st) {
+    const int npx = Lr->H * Lr->W;
+    const dim3 grid((npx + CNN_THREADS - 1) / CNN_THREADS, co % 8 == 0 ? co / 8 : co / 4, Lr->L);
+    if (co % 8 == 0) {
+        if (bwd) hipLaunchKernelGGL((k_conv3x3<8, 1>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+        else hipLaunchKernelGGL((k_conv3x3<8, 0>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+    } else {
+        if (bwd) hipLaunchKernelGGL((k_conv3x3<4, 1>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+        else hipLaunchKernelGGL((k_conv3x3<4, 0>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+    }
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// act[0] -> act[1..5] (ReLU after layers 0..3).
+smsm_status lcnn_forward(smsm_learned* Lr, hipStream_t st) {
+    for (int k = 0; k < smsm_learned::kDepth; ++k) {
+        smsm_status s = lconv(Lr, Lr->cin[k], Lr->cout[k], Lr->act[k], Lr->params + Lr->woff[k],
+                              Lr->params + Lr->boff[k], Lr->act[k + 1], k < smsm_learned::kDepth - 1, false, st);
+        if (s) return s;
+    }
+    return SMSM_OK;
+}
+
+// Given the activations of a forward pass and the gradient gout of the
+// output (nc channels), the weight gradients (accumulated when asked) and
+// the gradient of the input in gin (nc channels).
+smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int accumulate, hipStream_t st) {
+    const int D = smsm_learned::kDepth;
+    const long nh = (long)Lr->L * Lr->width * Lr->H * Lr->W;
+    const float* g = gout;
+    float* bufs[2] = {Lr->ga, Lr->gbuf};
+    for (int k = D - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(Lr->cin[k] * Lr->cout[k]), dim3(CNN_THREADS), 0, st, Lr->L,
+                           Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g, Lr->grads + Lr->woff[k],
+                           Lr->grads + Lr->boff[k], accumulate);
+        LAUNCH_CHECK();
+        float* dst = k > 0 ? bufs[k & 1] : gin;
+        smsm_status s = lconv(Lr, Lr->cout[k], Lr->cin[k], g, Lr->params + Lr->woff[k], nullptr, dst, 0, true, st);
+        if (s) return s;
+        if (k > 0) {
+            hipLaunchKernelGGL(k_relu_bwd, vec_grid(), dim3(kThreads), 0, st, nh, dst, Lr->act[k]);
+            LAUNCH_CHECK();
+        }
+        g = dst;
+    }
+    return SMSM_OK;
+}
+
+smsm_status ldot(smsm_learned* Lr, const double2* a, const double2* b, hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_dot, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), a, b, Lr->part);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+smsm_status lscalar(smsm_learned* Lr, int mode, double* rr, double count, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(kThreads), 0, st, mode, Lr->part, kVecBlocks, rr, count, out);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+smsm_status laxpy(smsm_learned* Lr, const double2* a, const double2* b, const double* fp, double fm, double2* out,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_axpy, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), a, b, fp, fm, out);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// out = (A^H A + mu I) v
+smsm_status lnormal(smsm_learned* Lr, const double2* v, double2* out, hipStream_t st) {
+    smsm_status s = chain_normal(Lr->P, v, out, COL_NORMAL, false, st);
+    if (s) return s;
+    return laxpy(Lr, out, v, nullptr, Lr->mu, out, st);
+}
+
+// n_cg CG steps on (A^H A + mu I) x = rhs from the x given; step lengths
+// and |r|^2 stay on the device.  rr == 0 gives zero steps.
+smsm_status ldc_cg(smsm_learned* Lr, const double2* rhs, double2* x, hipStream_t st) {
+    double* sc = Lr->scal;
+    smsm_status s;
+    if ((s = lnormal(Lr, x, Lr->q, st))) return s;
+    if ((s = laxpy(Lr, rhs, Lr->q, nullptr, -1.0, Lr->r, st))) return s;          // r = rhs - M x
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), Lr->r, Lr->p);
+    LAUNCH_CHECK();
+    if ((s = ldot(Lr, Lr->r, Lr->r, st)) || (s = lscalar(Lr, 0, nullptr, 0.0, sc + 1, st))) return s;
+    for (int j = 0; j < Lr->n_cg; ++j) {
+        if ((s = lnormal(Lr, Lr->p, Lr->q, st))) return s;
+        if ((s = ldot(Lr, Lr->p, Lr->q, st)) || (s = lscalar(Lr, 1, sc + 1, 0.0, sc + 2, st))) return s;
+        if ((s = laxpy(Lr, x, Lr->p, sc + 2, 1.0, x, st))) return s;              // x += alpha p
+        if ((s = laxpy(Lr, Lr->r, Lr->q, sc + 2, -1.0, Lr->r, st))) return s;     // r -= alpha q
+        if ((s = ldot(Lr, Lr->r, Lr->r, st)) || (s = lscalar(Lr, 2, sc + 1, 0.0, sc + 3, st))) return s;
+        if ((s = laxpy(Lr, Lr->r, Lr->p, sc + 3, 1.0, Lr->p, st))) return s;      // p = r + beta p
+    }
+    return SMSM_OK;
+}
+
+// b = A^H y, s = sqrt(mean |b|^2).
+smsm_status lsetup(smsm_learned* Lr, const void* y_dev, hipStream_t st) {
+    smsm_plan* P = Lr->P;
+    smsm_status s = chain_AH_hyb(P, (const float2*)y_dev, P->h2, st);
+    if (s) return s;
+    if ((s = rows_fwd(P, P->h2, Lr->b, st))) return s;
+    if ((s = ldot(Lr, Lr->b, Lr->b, st))) return s;
+    return lscalar(Lr, 3, nullptr, (double)lvec(Lr), Lr->scal, st);
+}
+
+// The unrolled forward pass from b into x (keeping x_k in xs when keep).
+smsm_status lforward(smsm_learned* Lr, bool keep, hipStream_t st) {
+    const long n = lvec(Lr);
+    const int ns = Lr->nc / 2, npx = Lr->H * Lr->W;
+    smsm_status s;
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, n, Lr->b, Lr->x);
+    LAUNCH_CHECK();
+    for (int k = 0; k < Lr->n_unroll; ++k) {
+        if (keep) {
+            hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, n, Lr->x, Lr->xs + (size_t)k * n);
+            LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_cnn_pack, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L, ns, npx, Lr->x, Lr->scal, 1,
+                           Lr->act[0]);
+        LAUNCH_CHECK();
+        if ((s = lcnn_forward(Lr, st))) return s;
+        hipLaunchKernelGGL(k_cnn_unpack_add, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L, ns, npx,
+                           Lr->act[smsm_learned::kDepth], Lr->x, Lr->scal, 0, Lr->z);
+        LAUNCH_CHECK();
+        if ((s = laxpy(Lr, Lr->b, Lr->z, nullptr, Lr->mu, Lr->rhs, st))) return s;    // b + mu z
+        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, n, Lr->z, Lr->x);   // warm start at z
+        LAUNCH_CHECK();
+        if ((s = ldc_cg(Lr, Lr->rhs, Lr->x, st))) return s;
+    }
+    return SMSM_OK;
+}
+
+// Loss ||x - xt||^2 / ||xt||^2 (numerator and denominator in scal[8], scal[9])
+// and the gradients of every parameter into grads.
+smsm_status lbackward(smsm_learned* Lr, const double2* xt, hipStream_t st) {
+    const long n = lvec(Lr);
+    const int ns = Lr->nc / 2, npx = Lr->H * Lr->W;
+    double* sc = Lr->scal;
+    smsm_status s;
+    if ((s = laxpy(Lr, Lr->x, xt, nullptr, -1.0, Lr->g, st))) return s;              // x - xt
+    if ((s = ldot(Lr, Lr->g, Lr->g, st)) || (s = lscalar(Lr, 0, nullptr, 0.0, sc + 8, st))) return s;
+    if ((s = ldot(Lr, xt, xt, st)) || (s = lscalar(Lr, 0, nullptr, 0.0, sc + 9, st))) return s;
+    hipLaunchKernelGGL(k_dc_grad0, vec_grid(), dim3(kThreads), 0, st, n, Lr->g, sc + 9);   // g = 2 (x - xt) / den
+    LAUNCH_CHECK();
+    for (int k = Lr->n_unroll - 1; k >= 0; --k) {
+        hipLaunchKernelGGL(k_zero_c128, vec_grid(), dim3(kThreads), 0, st, n, Lr->wv);
+        LAUNCH_CHECK();
+        if ((s = ldc_cg(Lr, Lr->g, Lr->wv, st))) return s;                          // w = M^-1 g
+        if ((s = laxpy(Lr, nullptr, Lr->wv, nullptr, Lr->mu, Lr->z, st))) return s;   // gz = mu w (in z)
+        hipLaunchKernelGGL(k_cnn_pack, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L, ns, npx, Lr->xs + (size_t)k * n,
+                           Lr->scal, 1, Lr->act[0]);
+        LAUNCH_CHECK();
+        if ((s = lcnn_forward(Lr, st))) return s;                                    // activations of step k
+        hipLaunchKernelGGL(k_cnn_pack, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L, ns, npx, Lr->z, Lr->scal, 0,
+                           Lr->gio);                                                 // s (Re gz, Im gz)
+        LAUNCH_CHECK();
+        if ((s = lcnn_backward(Lr, Lr->gio, Lr->gio, k < Lr->n_unroll - 1 ? 1 : 0, st))) return s;
+        hipLaunchKernelGGL(k_cnn_unpack_add, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L, ns, npx, Lr->gio, Lr->z,
+                           Lr->scal, 1, Lr->g);                                      // g = gz + gin / s
+        LAUNCH_CHECK();
+    }
+    return SMSM_OK;
+}
+
+void learned_release(smsm_learned* Lr) {
+    if (!Lr) return;
+    if (Lr->arena && hipSetDevice(Lr->dev) == hipSuccess) (void)hipFree(Lr->arena);
+    delete Lr;
+}
+
+}  // namespace
+
+extern "C" {
+
+smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg, double mu, const float* params_host,
+                                smsm_learned** out) {
+    if (!P || !out || !params_host || n_unroll < 1 || n_cg < 1 || !(mu > 0.0) || width < 8 || width % 8 != 0 ||
+        width > 256)
+        return SMSM_E_INVALID;
+    *out = nullptr;
+    const Geo& g = P->g;
+    if ((2 * g.Ns) % 4 != 0) return SMSM_E_UNSUPPORTED;    // 2 Ns channels must be a multiple of 4
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    smsm_learned* Lr = new (std::nothrow) smsm_learned;
+    if (!Lr) return SMSM_E_NOMEM;
+    Lr->P = P;
+    Lr->dev = P->dev;
+    Lr->width = width;
+    Lr->nc = 2 * g.Ns;
+    Lr->L = g.L;
+    Lr->H = g.n2;
+    Lr->W = g.n1;
+    Lr->n_unroll = n_unroll;
+    Lr->n_cg = n_cg;
+    Lr->mu = mu;
+    size_t off = 0;
+    for (int k = 0; k < smsm_learned::kDepth; ++k) {
+        Lr->cin[k] = k == 0 ? Lr->nc : width;
+        Lr->cout[k] = k == smsm_learned::kDepth - 1 ? Lr->nc : width;
+        Lr->woff[k] = off;
+        off += (size_t)Lr->cout[k] * Lr->cin[k] * 9;
+        Lr->boff[k] = off;
+        off += Lr->cout[k];
+    }
+    Lr->nparam = off;
+    const size_t npx = (size_t)Lr->H * Lr->W, n = (size_t)lvec(Lr);
+    const size_t ny = (size_t)g.Ns * g.Nc * npx;
+    Carver cv;
+    const size_t oprm = cv.take<float>(off), ogr = cv.take<float>(off), oam = cv.take<float>(off),
+                 oav = cv.take<float>(off);
+    size_t oact[smsm_learned::kDepth + 1];
+    for (int k = 0; k <= smsm_learned::kDepth; ++k)
+        oact[k] = cv.take<float>((size_t)Lr->L * (k == 0 || k == smsm_learned::kDepth ? Lr->nc : width) * npx);
+    const size_t oga = cv.take<float>((size_t)Lr->L * width * npx), ogb = cv.take<float>((size_t)Lr->L * width * npx);
+    const size_t ogio = cv.take<float>((size_t)Lr->L * Lr->nc * npx);
+    size_t ov[9];
+    for (int k = 0; k < 9; ++k) ov[k] = cv.take<double2>(n);
+    const size_t oax = cv.take<double2>(ny), oxs = cv.take<double2>(n * n_unroll);
+    const size_t opart = cv.take<double>(kVecBlocks), oscal = cv.take<double>(16);
+    if (hipMalloc(&Lr->arena, cv.off) != hipSuccess) {
+        delete Lr;
+        return SMSM_E_NOMEM;
+    }
+    char* base = static_cast<char*>(Lr->arena);
+    Lr->params = (float*)(base + oprm);
+    Lr->grads = (float*)(base + ogr);
+    Lr->am = (float*)(base + oam);
+    Lr->av = (float*)(base + oav);
+    for (int k = 0; k <= smsm_learned::kDepth; ++k) Lr->act[k] = (float*)(base + oact[k]);
+    Lr->ga = (float*)(base + oga);
+    Lr->gbuf = (float*)(base + ogb);
+    Lr->gio = (float*)(base + ogio);
+    double2** vecs[9] = {&Lr->b, &Lr->x, &Lr->z, &Lr->r, &Lr->p, &Lr->q, &Lr->rhs, &Lr->g, &Lr->wv};
+    for (int k = 0; k < 9; ++k) *vecs[k] = (double2*)(base + ov[k]);
+    Lr->ax = (double2*)(base + oax);
+    Lr->xs = (double2*)(base + oxs);
+    Lr->part = (double*)(base + opart);
+    Lr->scal = (double*)(base + oscal);
+    bool ok = hipMemcpy(Lr->params, params_host, off * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemset(Lr->am, 0, off * sizeof(float)) == hipSuccess;
+    ok = ok && hipMemset(Lr->av, 0, off * sizeof(float)) == hipSuccess;
+    ok = ok && hipMemset(Lr->grads, 0, off * sizeof(float)) == hipSuccess;
+    ok = ok && hipMemset(Lr->scal, 0, 16 * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        learned_release(Lr);
+        return SMSM_E_DEVICE;
+    }
+    *out = Lr;
+    return SMSM_OK;
+}
+
+smsm_status smsm_learned_destroy(smsm_learned* Lr) {
+    learned_release(Lr);
+    return SMSM_OK;
+}
+
+long smsm_learned_param_count(const smsm_learned* Lr) { return Lr ? (long)Lr->nparam : 0; }
+
+smsm_status smsm_learned_get_params(smsm_learned* Lr, float* host) {
+    if (!Lr || !host) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
+    return hipMemcpy(host, Lr->params, Lr->nparam * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess
+               ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_learned_set_params(smsm_learned* Lr, const float* host) {
+    if (!Lr || !host) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
+    if (hipMemcpy(Lr->params, host, Lr->nparam * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return SMSM_E_DEVICE;
+    Lr->adam_t = 0;
+    const bool ok = hipMemset(Lr->am, 0, Lr->nparam * sizeof(float)) == hipSuccess &&
+                    hipMemset(Lr->av, 0, Lr->nparam * sizeof(float)) == hipSuccess;
+    return ok ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_learned_cnn_forward(smsm_learned* Lr, const void* in_dev, void* out_dev, void* stream) {
+    if (!Lr || !in_dev || !out_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    const size_t bytes = (size_t)Lr->L * Lr->nc * Lr->H * Lr->W * sizeof(float);
+    if (hipMemcpyAsync(Lr->act[0], in_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return SMSM_E_DEVICE;
+    smsm_status s = lcnn_forward(Lr, st);
+    if (s) return s;
+    return hipMemcpyAsync(out_dev, Lr->act[smsm_learned::kDepth], bytes, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_learned_cnn_backward(smsm_learned* Lr, const void* in_dev, const void* gout_dev, void* gin_dev,
+                                      float* grads_host, void* stream) {
+    if (!Lr || !in_dev || !gout_dev || !gin_dev || !grads_host) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    const size_t bytes = (size_t)Lr->L * Lr->nc * Lr->H * Lr->W * sizeof(float);
+    if (hipMemcpyAsync(Lr->act[0], in_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return SMSM_E_DEVICE;
+    smsm_status s = lcnn_forward(Lr, st);
+    if (s) return s;
+    if (hipMemcpyAsync(Lr->gio, gout_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return SMSM_E_DEVICE;
+    if ((s = lcnn_backward(Lr, Lr->gio, Lr->gio, 0, st))) return s;
+    if (hipMemcpyAsync(gin_dev, Lr->gio, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return SMSM_E_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return SMSM_E_DEVICE;
+    return hipMemcpy(grads_host, Lr->grads, Lr->nparam * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess
+               ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_learned_solve(smsm_learned* Lr, const void* y_dev, void* x_dev, void* stream) {
+    if (!Lr || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    smsm_status s = lsetup(Lr, y_dev, st);
+    if (s) return s;
+    if ((s = lforward(Lr, false, st))) return s;
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), Lr->x, (double2*)x_dev);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status smsm_learned_gradients(smsm_learned* Lr, const void* y_dev, const void* xt_dev, double* loss,
+                                   float* grads_host, void* stream) {
+    if (!Lr || !y_dev || !xt_dev || !loss) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    smsm_status s = lsetup(Lr, y_dev, st);
+    if (s) return s;
+    if ((s = lforward(Lr, true, st))) return s;
+    if ((s = lbackward(Lr, (const double2*)xt_dev, st))) return s;
+    double nd[2];
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(nd, Lr->scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMSM_E_DEVICE;
+    *loss = nd[1] > 0.0 ? nd[0] / nd[1] : 0.0;
+    if (grads_host &&
+        hipMemcpy(grads_host, Lr->grads, Lr->nparam * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMSM_E_DEVICE;
+    return SMSM_OK;
+}
+
+smsm_status smsm_learned_train_step(smsm_learned* Lr, const void* y_dev, const void* xt_dev, double lr,
+                                    double* loss, void* stream) {
+    if (!Lr || !(lr > 0.0)) return SMSM_E_INVALID;
+    smsm_status s = smsm_learned_gradients(Lr, y_dev, xt_dev, loss, nullptr, stream);
+    if (s) return s;
+    ++Lr->adam_t;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - (float)std::pow(0.9, (double)Lr->adam_t), c2 = 1.0f - (float)std::pow(0.999, (double)Lr->adam_t);
+    hipLaunchKernelGGL(k_adam, vec_grid(), dim3(kThreads), 0, S(stream), (long)Lr->nparam, Lr->params, Lr->grads,
+                       Lr->am, Lr->av, (float)lr, b1, b2, 1e-8f, c1, c2);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status smsm_learned_residual(smsm_learned* Lr, const void* x_dev, const void* y_dev, double* res, void* stream) {
+    if (!Lr || !x_dev || !y_dev || !res) return SMSM_E_INVALID;
+    hipStream_t st = S(stream);
+    smsm_status s = smsm_apply_A(Lr->P, x_dev, Lr->ax, stream);
+    if (s) return s;
+    const Geo& g = Lr->P->g;
+    const long ny = (long)g.Ns * g.Nc * g.n2 * g.n1;
+    hipLaunchKernelGGL(k_dc_resid, vec_grid(), dim3(kThreads), 0, st, ny, Lr->ax, (const float2*)y_dev, Lr->part);
+    LAUNCH_CHECK();
+    if ((s = lscalar(Lr, 0, nullptr, 0.0, Lr->scal + 10, st))) return s;
+    double v = 0.0;
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(&v, Lr->scal + 10, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMSM_E_DEVICE;
+    *res = std::sqrt(v);
     return SMSM_OK;
 }
 

@@ -1,0 +1,237 @@
+// Learned unrolled solver (an extension beyond the paper: a learned prior in
+// place of the Hankel IRLS step).  Each unrolled iteration is
+//   z = x + s C(x / s),   x <- (A^H A + mu I)^-1 (A^H y + mu z),
+// C a real CNN over the 2 Ns channels (real and imaginary part of each shot's
+// k-space) of every slice: five 3 x 3 layers with ReLU after the first four;
+// s = sqrt(mean |A^H y|^2).  The network runs in FP32 (FP32 weights and
+// accumulation, fixed summation order); the data-consistency solves run in
+// FP64 on the solver's normal operator.
+//
+// Layouts: activations [N][C][H][W] float (N = slices), weights
+// [Co][Ci][3][3] then bias [Co] per layer, layers back to back.
+#pragma once
+#include "smsm_device.h"
+
+#define CNN_THREADS 256
+#define CNN_CONST __attribute__((address_space(4)))
+
+// 3 x 3 convolution, zero padding, cross-correlation.  Forward (BWD = 0):
+//   out[n][o][i][j] = bias[o] + sum_c sum_{a,d} w[o][c][a][d] in[n][c][i+a-1][j+d-1]
+// (ReLU applied when relu != 0).  Backward data (BWD = 1), the transpose:
+//   out[n][c][i][j] = sum_o sum_{a,d} w[o][c][2-a][2-d] in[n][o][i+a-1][j+d-1]
+// with `in` the gradient of the layer output, ci = the layer's Co and co = its
+// Ci here.  One thread per pixel and COB consecutive output channels; the
+// weights of a (channel block, input channel) are wave-uniform and read
+// through the scalar cache.  Sums run over input channels, then taps (row
+// major), in order.  grid (ceil(H W / 256), co / COB, N), block 256.
+template <int COB, int BWD>
+__global__ void __launch_bounds__(CNN_THREADS)
+k_conv3x3(int ci, int co, int H, int W, const float* __restrict__ in, const float* __restrict__ w,
+          const float* __restrict__ bias, float* __restrict__ out, int relu) {
+    const int npx = H * W;
+    const int p = blockIdx.x * CNN_THREADS + threadIdx.x;
+    const int o0 = blockIdx.y * COB, n = blockIdx.z;
+    const bool live = p < npx;
+    const int pp = live ? p : 0;
+    const int i = pp / W, j = pp - i * W;
+    float acc[COB];
+#pragma unroll
+    for (int u = 0; u < COB; ++u) acc[u] = (BWD || bias == nullptr) ? 0.0f : bias[o0 + u];
+    const float* src = in + (size_t)n * ci * npx;
+    for (int c = 0; c < ci; ++c) {
+        float v[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int ii = i + a - 1, jj = j + d - 1;
+                const bool in_b = ii >= 0 && ii < H && jj >= 0 && jj < W;
+                v[3 * a + d] = in_b ? src[(size_t)c * npx + ii * W + jj] : 0.0f;
+            }
+#pragma unroll
+        for (int u = 0; u < COB; ++u) {
+            // forward: w[o0+u][c][t]; backward: w[c][o0+u][8-t]
+            const CNN_CONST float* wp = (const CNN_CONST float*)(uintptr_t)(
+                BWD ? w + ((size_t)c * co + o0 + u) * 9 : w + ((size_t)(o0 + u) * ci + c) * 9);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[u] = fmaf(wp[BWD ? 8 - t : t], v[t], acc[u]);
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int u = 0; u < COB; ++u) {
+            const float r = (relu && acc[u] < 0.0f) ? 0.0f : acc[u];
+            out[((size_t)n * co + o0 + u) * npx + p] = r;
+        }
+    }
+}
+
+// Weight and bias gradients of one layer: for the block's (o, c)
+//   gw[o][c][a][d] (+)= sum_{n,i,j} gout[n][o][i][j] in[n][c][i+a-1][j+d-1],
+//   gb[o] (+)= sum_{n,i,j} gout[n][o][i][j]   (blocks with c = 0).
+// Thread t takes pixels t, t + 256, ... of each image in order; the block
+// sums the thread partials in a fixed order (deterministic).  accumulate
+// adds to the existing gradient (weights shared across iterations).
+// grid (Ci * Co), block 256; block b -> o = b / Ci, c = b % Ci.
+__global__ void __launch_bounds__(CNN_THREADS)
+k_conv3x3_wgrad(int N, int ci, int co, int H, int W, const float* __restrict__ in, const float* __restrict__ gout,
+                float* __restrict__ gw, float* __restrict__ gb, int accumulate) {
+    __shared__ float red[10][CNN_THREADS / 64];
+    const int o = blockIdx.x / ci, c = blockIdx.x - o * ci;
+    const int npx = H * W;
+    float acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
+    for (int n = 0; n < N; ++n) {
+        const float* g = gout + ((size_t)n * co + o) * npx;
+        const float* x = in + ((size_t)n * ci + c) * npx;
+        for (int p = threadIdx.x; p < npx; p += CNN_THREADS) {
+            const int i = p / W, j = p - i * W;
+            const float gv = g[p];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int ii = i + a - 1, jj = j + d - 1;
+                    const bool in_b = ii >= 0 && ii < H && jj >= 0 && jj < W;
+                    acc[3 * a + d] = fmaf(gv, in_b ? x[ii * W + jj] : 0.0f, acc[3 * a + d]);
+                }
+            acc[9] += gv;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+        float v = acc[t];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[t][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int t = threadIdx.x;
+        float s = 0.0f;
+        for (int k = 0; k < CNN_THREADS / 64; ++k) s += red[t][k];
+        if (t < 9) {
+            float* dst = gw + ((size_t)o * ci + c) * 9 + t;
+            *dst = accumulate ? *dst + s : s;
+        } else if (c == 0) {
+            gb[o] = accumulate ? gb[o] + s : s;
+        }
+    }
+}
+
+// g[k] = 0 where the layer's ReLU output act[k] is 0 (gradient of the ReLU).
+__global__ void k_relu_bwd(long n, float* __restrict__ g, const float* __restrict__ act) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        if (!(act[k] > 0.0f)) g[k] = 0.0f;
+}
+
+// Complex k-space [L][Ns][npx] (FP64) -> channels [L][2 Ns][npx] (FP32):
+// channel 2i = f Re x_i, 2i + 1 = f Im x_i with f = 1 / *s (inv) or *s.
+__global__ void k_cnn_pack(long L, int ns, int npx, const double2* __restrict__ x, const double* __restrict__ s,
+                           int inv, float* __restrict__ out) {
+    const double f = inv ? 1.0 / *s : *s;
+    const long total = L * ns * npx;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long li = k / npx;            // l * ns + i
+        const int p = (int)(k - li * npx);
+        const double2 v = x[k];
+        out[(2 * li) * npx + p] = (float)(v.x * f);
+        out[(2 * li + 1) * npx + p] = (float)(v.y * f);
+    }
+}
+
+// z = x + f (c_{2i} + i c_{2i+1}), f = 1 / *s (inv) or *s.
+__global__ void k_cnn_unpack_add(long L, int ns, int npx, const float* __restrict__ c, const double2* __restrict__ x,
+                                 const double* __restrict__ s, int inv, double2* __restrict__ z) {
+    const double f = inv ? 1.0 / *s : *s;
+    const long total = L * ns * npx;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const long li = k / npx;
+        const int p = (int)(k - li * npx);
+        const double2 v = x[k];
+        z[k] = make_double2(v.x + f * (double)c[(2 * li) * npx + p], v.y + f * (double)c[(2 * li + 1) * npx + p]);
+    }
+}
+
+// Adam on FP32 parameters: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+__global__ void k_adam(long n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const float gk = g[k];
+        const float mk = b1 * m[k] + (1.0f - b1) * gk;
+        const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+        m[k] = mk;
+        v[k] = vk;
+        w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    }
+}
+
+// Vector helpers of the data-consistency CG (natural layout, FP64).
+// out = a + f b, or f b when a is null (f = *fp * fm, or fm when fp is null).
+// out may be a or b (each element is read before it is written).
+__global__ void k_dc_axpy(long n, const double2* a, const double2* b, const double* __restrict__ fp, double fm,
+                          double2* out) {
+    const double f = fp ? *fp * fm : fm;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        out[k] = a ? cadd(a[k], cscale(b[k], f)) : cscale(b[k], f);
+}
+
+// Per-block partials of Re <a, b>.
+__global__ void k_dc_dot(long n, const double2* __restrict__ a, const double2* __restrict__ b,
+                         double* __restrict__ part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double2 u = a[k], v = b[k];
+        s += u.x * v.x + u.y * v.y;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// One-block scalar step of the data-consistency CG from the partials:
+//   mode 0: out[0] = sum(pa)                         (|r|^2)
+//   mode 1: out[0] = *rr / sum(pa)                   (alpha = rr / <p, M p>; 0 if rr = 0)
+//   mode 2: out[0] = sum(pa) / *rr, then *rr = sum(pa)   (beta; |r|^2 advanced)
+//   mode 3: out[0] = sqrt(sum(pa) / count)           (data scale)
+__global__ void k_dc_scalar(int mode, const double* __restrict__ pa, int np, double* rr, double count,
+                            double* out) {
+    __shared__ double red[16];
+    const double s = sum_partials(pa, np, red);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            out[0] = s;
+        } else if (mode == 1) {
+            const double r = *rr;
+            out[0] = (r > 0.0 && s > 0.0) ? r / s : 0.0;
+        } else if (mode == 2) {
+            const double r = *rr;
+            out[0] = r > 0.0 ? s / r : 0.0;
+            *rr = s;
+        } else {
+            out[0] = sqrt(s / count);
+        }
+    }
+}
+
+// g = 2 g / *den (the loss gradient 2 (x - xt) / ||xt||^2 from g = x - xt).
+__global__ void k_dc_grad0(long n, double2* __restrict__ g, const double* __restrict__ den) {
+    const double f = 2.0 / *den;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        g[k] = cscale(g[k], f);
+}
+
+// Per-block partials of |ax - y|^2 (ax FP64, y the complex64 measurement).
+__global__ void k_dc_resid(long n, const double2* __restrict__ ax, const float2* __restrict__ y,
+                           double* __restrict__ part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double dx = ax[k].x - (double)y[k].x, dy = ax[k].y - (double)y[k].y;
+        s += dx * dx + dy * dy;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}

@@ -31,7 +31,10 @@ ABI_SYMBOLS = (
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
     "smsm_kernel_timer_start", "smsm_kernel_timer_read", "smsm_batch_create", "smsm_batch_launch",
-    "smsm_batch_destroy", "smsm_batch_streams",
+    "smsm_batch_destroy", "smsm_batch_streams", "smsm_learned_create", "smsm_learned_destroy",
+    "smsm_learned_param_count", "smsm_learned_get_params", "smsm_learned_set_params", "smsm_learned_cnn_forward",
+    "smsm_learned_cnn_backward", "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
+    "smsm_learned_residual",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
 
@@ -107,6 +110,24 @@ def lib() -> ctypes.CDLL:
         L.smsm_batch_destroy.restype = st
         L.smsm_batch_streams.argtypes = [vp]
         L.smsm_batch_streams.restype = st
+        pf, pd = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+        L.smsm_learned_create.argtypes = [vp, st, st, st, ctypes.c_double, pf, pvp]
+        L.smsm_learned_destroy.argtypes = [vp]
+        L.smsm_learned_param_count.argtypes = [vp]
+        L.smsm_learned_param_count.restype = ctypes.c_long
+        L.smsm_learned_get_params.argtypes = [vp, pf]
+        L.smsm_learned_set_params.argtypes = [vp, pf]
+        L.smsm_learned_cnn_forward.argtypes = [vp, vp, vp, vp]
+        L.smsm_learned_cnn_backward.argtypes = [vp, vp, vp, vp, pf, vp]
+        L.smsm_learned_solve.argtypes = [vp, vp, vp, vp]
+        L.smsm_learned_gradients.argtypes = [vp, vp, vp, pd, pf, vp]
+        L.smsm_learned_train_step.argtypes = [vp, vp, vp, ctypes.c_double, pd, vp]
+        L.smsm_learned_residual.argtypes = [vp, vp, vp, pd, vp]
+        for name in ("smsm_learned_create", "smsm_learned_destroy", "smsm_learned_get_params",
+                     "smsm_learned_set_params", "smsm_learned_cnn_forward", "smsm_learned_cnn_backward",
+                     "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
+                     "smsm_learned_residual"):
+            getattr(L, name).restype = st
         _lib = L
     return _lib
 
@@ -455,3 +476,171 @@ def smsm_batch_destroy(batch: Batch):
 
 def smsm_batch_streams(batch: Batch) -> int:
     return batch.n_streams
+
+
+def flatten_params(params) -> "np.ndarray":
+    """[(w [co][ci][3][3], b [co]), ...] -> the flat float32 layout of the C ABI."""
+    return np.concatenate([np.concatenate([np.asarray(w, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                           for w, b in params]).astype(np.float32)
+
+
+def unflatten_params(flat, c_io: int, width: int, depth: int = 5) -> list:
+    chans = [c_io] + [width] * (depth - 1) + [c_io]
+    out, off = [], 0
+    for k in range(depth):
+        ci, co = chans[k], chans[k + 1]
+        w = flat[off:off + co * ci * 9].reshape(co, ci, 3, 3)
+        off += co * ci * 9
+        b = flat[off:off + co]
+        off += co
+        out.append((w, b))
+    return out
+
+
+class Learned:
+    """The learned unrolled solver on a plan (smsm_learned_*): a residual CNN
+    prior over each slice's 2 Ns k-space channels inside n_unroll
+    data-consistency iterations."""
+
+    def __init__(self, plan: Plan, params, width: int = 64, n_unroll: int = 5, n_cg: int = 10, mu: float = 1.0):
+        flat = flatten_params(params)
+        h = ctypes.c_void_p()
+        _check(lib().smsm_learned_create(plan._h, int(width), int(n_unroll), int(n_cg), float(mu),
+                                         flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h)),
+               "smsm_learned_create")
+        self._h = h
+        self.plan = plan
+        self.width, self.n_unroll, self.n_cg, self.mu = width, n_unroll, n_cg, mu
+        self.c_io = 2 * plan.shape_x[1]
+        self.shape_c = (plan.shape_x[0], self.c_io, plan.shape_x[2], plan.shape_x[3])
+
+    def param_count(self) -> int:
+        return int(lib().smsm_learned_param_count(self._h))
+
+    def get_params(self) -> "np.ndarray":
+        out = np.empty(self.param_count(), np.float32)
+        _check(lib().smsm_learned_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "smsm_learned_get_params")
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, np.float32)
+        _check(lib().smsm_learned_set_params(self._h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "smsm_learned_set_params")
+
+    def cnn_forward(self, inp, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape_c, dtype=torch.float32, device=inp.device)
+        _check(lib().smsm_learned_cnn_forward(self._h, _dev_ptr(inp, torch.float32, self.shape_c, "in"),
+                                              _dev_ptr(out, torch.float32, self.shape_c, "out"),
+                                              _stream_ptr(stream)), "smsm_learned_cnn_forward")
+        return out
+
+    def cnn_backward(self, inp, gout, stream=None):
+        import torch
+        gin = torch.empty(self.shape_c, dtype=torch.float32, device=inp.device)
+        grads = np.empty(self.param_count(), np.float32)
+        _check(lib().smsm_learned_cnn_backward(self._h, _dev_ptr(inp, torch.float32, self.shape_c, "in"),
+                                               _dev_ptr(gout, torch.float32, self.shape_c, "gout"),
+                                               _dev_ptr(gin, torch.float32, self.shape_c, "gin"),
+                                               grads.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               _stream_ptr(stream)), "smsm_learned_cnn_backward")
+        return gin, grads
+
+    def solve(self, y, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.plan.shape_x, dtype=torch.complex128, device=y.device)
+        _check(lib().smsm_learned_solve(self._h, _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"),
+                                        _dev_ptr(out, torch.complex128, self.plan.shape_x, "x"),
+                                        _stream_ptr(stream)), "smsm_learned_solve")
+        return out
+
+    def gradients(self, y, xt, stream=None):
+        import torch
+        loss = ctypes.c_double()
+        grads = np.empty(self.param_count(), np.float32)
+        _check(lib().smsm_learned_gradients(self._h, _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"),
+                                            _dev_ptr(xt, torch.complex128, self.plan.shape_x, "xt"),
+                                            ctypes.byref(loss), grads.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                            _stream_ptr(stream)), "smsm_learned_gradients")
+        return loss.value, grads
+
+    def train_step(self, y, xt, lr: float, stream=None) -> float:
+        import torch
+        loss = ctypes.c_double()
+        _check(lib().smsm_learned_train_step(self._h, _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"),
+                                             _dev_ptr(xt, torch.complex128, self.plan.shape_x, "xt"),
+                                             float(lr), ctypes.byref(loss), _stream_ptr(stream)),
+               "smsm_learned_train_step")
+        return loss.value
+
+    def residual(self, x, y, stream=None) -> float:
+        import torch
+        r = ctypes.c_double()
+        _check(lib().smsm_learned_residual(self._h, _dev_ptr(x, torch.complex128, self.plan.shape_x, "x"),
+                                           _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"), ctypes.byref(r),
+                                           _stream_ptr(stream)), "smsm_learned_residual")
+        return r.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().smsm_learned_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def smsm_learned_create(plan: Plan, params, width=64, n_unroll=5, n_cg=10, mu=1.0) -> Learned:
+    return Learned(plan, params, width, n_unroll, n_cg, mu)
+
+
+def smsm_learned_destroy(net: Learned):
+    net.close()
+
+
+def smsm_learned_param_count(net: Learned) -> int:
+    return net.param_count()
+
+
+def smsm_learned_get_params(net: Learned):
+    return net.get_params()
+
+
+def smsm_learned_set_params(net: Learned, flat):
+    net.set_params(flat)
+
+
+def smsm_learned_cnn_forward(net: Learned, inp, out=None, stream=None):
+    return net.cnn_forward(inp, out, stream)
+
+
+def smsm_learned_cnn_backward(net: Learned, inp, gout, stream=None):
+    return net.cnn_backward(inp, gout, stream)
+
+
+def smsm_learned_solve(net: Learned, y, out=None, stream=None):
+    return net.solve(y, out, stream)
+
+
+def smsm_learned_gradients(net: Learned, y, xt, stream=None):
+    return net.gradients(y, xt, stream)
+
+
+def smsm_learned_train_step(net: Learned, y, xt, lr: float, stream=None) -> float:
+    return net.train_step(y, xt, lr, stream)
+
+
+def smsm_learned_residual(net: Learned, x, y, stream=None) -> float:
+    return net.residual(x, y, stream)

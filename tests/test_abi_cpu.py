@@ -114,3 +114,40 @@ def test_batch_timer_and_image_entry_points_reject_bad_arguments():
     assert lib.smsm_batch_launch(None, None) == pkg.SMSM_E_INVALID
     assert lib.smsm_batch_destroy(None) == pkg.SMSM_OK
     assert lib.smsm_batch_streams(None) == 0
+
+
+@needs_lib
+def test_learned_entry_points_reject_bad_arguments():
+    lib = smsm.lib()
+    out = ctypes.c_void_p()
+    params = np.zeros(16, np.float32)
+    pf = params.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert lib.smsm_learned_create(None, 64, 5, 10, 1.0, pf, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    fake = ctypes.c_void_p(0x1000)            # never dereferenced: validation fails first
+    assert lib.smsm_learned_create(fake, 64, 5, 10, 1.0, None, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_create(fake, 60, 5, 10, 1.0, pf, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_create(fake, 64, 0, 10, 1.0, pf, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_create(fake, 64, 5, 10, 0.0, pf, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_create(fake, 64, 5, 10, 1.0, pf, None) == pkg.SMSM_E_INVALID
+    assert out.value is None
+    assert lib.smsm_learned_destroy(None) == pkg.SMSM_OK
+    assert lib.smsm_learned_param_count(None) == 0
+    assert lib.smsm_learned_get_params(None, pf) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_set_params(None, pf) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_cnn_forward(None, None, None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_cnn_backward(None, None, None, None, pf, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_solve(None, None, None, None) == pkg.SMSM_E_INVALID
+    d = ctypes.c_double()
+    assert lib.smsm_learned_gradients(None, None, None, ctypes.byref(d), pf, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_train_step(None, None, None, 1e-3, ctypes.byref(d), None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_learned_residual(None, None, None, ctypes.byref(d), None) == pkg.SMSM_E_INVALID
+
+
+def test_learned_parameter_layout_round_trip():
+    import smsm_inputs as si
+    params = si.cnn_init(1, 8, width=16)
+    flat = smsm.flatten_params(params)
+    assert flat.size == 8 * 16 * 9 + 16 + 3 * (16 * 16 * 9 + 16) + 16 * 8 * 9 + 8
+    back = smsm.unflatten_params(flat, 8, 16)
+    for (w, b), (w2, b2) in zip(params, back):
+        assert np.array_equal(w, w2) and np.array_equal(b, b2)

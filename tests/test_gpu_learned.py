@@ -1,0 +1,123 @@
+"""GPU parity of the learned unrolled solver (smsm_learned_*) against the FP64
+oracle in oracle/learned_oracle.py, and what training the network gains.
+
+The network runs in FP32 (weights and accumulation), so its outputs and
+gradients are held to FP32-sized relative errors; the data-consistency
+solves run in FP64."""
+import numpy as np
+import pytest
+
+import smsm_inputs as si
+from oracle import learned_oracle as lo
+from oracle import smsm_oracle as o
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_01893_amd  # noqa: F401  (fails loudly if the library is missing)
+    return torch, torch.device("cuda:0")
+
+
+def make_case(g, seed, wid):
+    case = si.make_case(g, seed, wid)
+    x_true, y = o.simulate(case, g.n_slices, g.snr)
+    return case, x_true, y.astype(np.complex64)
+
+
+def plan_for(torch, dev, g, case, params=None):
+    from paper_1901_01893_amd import smsm
+    coils = torch.from_numpy(case["coils"]).to(dev)
+    if params is None:
+        params = smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg, flags=smsm.SMSM_FLAG_X_C128)
+    return smsm.Plan(g.n, g.n, g.n_slices, g.n_shots, g.n_coils, g.filt, coils, case["masks"], case["shifts"],
+                     params)
+
+
+def oracle_aha(case):
+    coils = case["coils"].astype(np.complex128)
+    masks = case["masks"].astype(np.float64)
+    theta = o.caipi_phase(case["coils"].shape[-2], case["shifts"])
+    return lambda v: o.adjoint(o.forward(v, coils, masks, theta), coils, masks, theta), (coils, masks, theta)
+
+
+def f64_params(params):
+    return [(w.astype(np.float64), b.astype(np.float64)) for w, b in params]
+
+
+# 32 x 32 is the smallest matrix with 4 shots (folded length n / Ns >= 8)
+G32 = si.Geometry(n=32, n_slices=2, n_shots=4, n_coils=4, filt=3, lam=1e-3, n_irls=4, n_cg=6, phase_order=2,
+                  snr=30.0)
+
+
+def test_cnn_forward_backward_match_oracle(torch_dev):
+    """Width 64 (the configured network) on a 32 x 32 slice group."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, _, _ = make_case(G32, 0, 90)
+    params = si.cnn_init(3, 8, width=64, out_scale=1.0)
+    print("[learned] cnn fwd/bwd width 64, 32x32, L=2, Ns=4", flush=True)
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=64) as net:
+        rng = np.random.default_rng(5)
+        inp = rng.standard_normal(net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        p64 = f64_params(params)
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), p64)
+        assert rel(out, ref) < 1e-5
+        rgin, rgrads = lo.cnn_backward(acts, p64, gout.astype(np.float64))
+        assert rel(gin.cpu().numpy(), rgin) < 1e-5
+        got = smsm.unflatten_params(grads, 8, 64)
+        for k in range(5):
+            assert rel(got[k][0], rgrads[k][0]) < 1e-5, k
+            assert rel(got[k][1], rgrads[k][1]) < 1e-5, k
+
+
+def test_unrolled_solve_and_residual_match_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, _, y = make_case(G32, 1, 91)
+    params = si.cnn_init(4, 8, width=16, out_scale=0.5)
+    aha, (coils, masks, theta) = oracle_aha(case)
+    b = o.adjoint(y.astype(np.complex128), coils, masks, theta)
+    ref, _ = lo.unrolled_forward(b, aha, f64_params(params), mu=0.5, n_unroll=5, n_cg=10)
+    print("[learned] unrolled solve width 16, 32x32, 5 x 10 CG", flush=True)
+    with plan_for(torch, dev, G32, case) as plan, \
+            smsm.Learned(plan, params, width=16, n_unroll=5, n_cg=10, mu=0.5) as net:
+        yd = torch.from_numpy(y).to(dev)
+        x = net.solve(yd)
+        got = x.cpu().numpy()
+        err = o.nrmse(got, ref)
+        print(f"[learned] NRMSE vs oracle = {err:.3e}", flush=True)
+        assert err < 1e-5
+        res = net.residual(x, yd)
+        ref_res = np.linalg.norm((o.forward(got, coils, masks, theta) - y.astype(np.complex128)).ravel())
+        assert abs(res - ref_res) < 1e-10 * ref_res
+
+
+def test_unrolled_gradients_match_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, x_true, y = make_case(G32, 2, 92)
+    params = si.cnn_init(5, 8, width=16, out_scale=0.5)
+    aha, (coils, masks, theta) = oracle_aha(case)
+    b = o.adjoint(y.astype(np.complex128), coils, masks, theta)
+    target = x_true
+    loss_ref, grads_ref = lo.unrolled_loss_and_grads(b, aha, f64_params(params), 0.8, 3, 8, target)
+    print("[learned] gradients width 16, 32x32, 3 x 8 CG", flush=True)
+    with plan_for(torch, dev, G32, case) as plan, \
+            smsm.Learned(plan, params, width=16, n_unroll=3, n_cg=8, mu=0.8) as net:
+        loss, grads = net.gradients(torch.from_numpy(y).to(dev), torch.from_numpy(target).to(dev))
+        assert abs(loss - loss_ref) < 1e-5 * loss_ref
+        got = smsm.unflatten_params(grads, 8, 16)
+        for k in range(5):
+            assert rel(got[k][0], grads_ref[k][0]) < 1e-4, k
+            assert rel(got[k][1], grads_ref[k][1]) < 1e-4, k
+        # the parameters did not move
+        assert np.array_equal(net.get_params(), smsm.flatten_params(params))
