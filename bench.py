@@ -111,6 +111,60 @@ def batched_measurement(torch, dev, n_streams, reps, directions=5):
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 
 
+def learned_measurement(torch, dev, plan, g, workload, n_train=16, n_eval=2, steps=200, mu=0.05, lr=1e-3):
+    """The learned form on the timed workload: a width-64 network (5 unrolled
+    iterations of 10 data-consistency CG steps) trained on the GPU for `steps`
+    Adam steps against the plain solver's reconstructions of n_train seeded
+    instances, then timed and compared on n_eval held-out instances with the
+    same iterations without the network (C = 0) and with the plain solver."""
+    import smsm_inputs as si
+    from paper_1901_01893_amd import smsm
+    wid = si.WORKLOAD_IDS[workload]
+    case0 = si.make_case(g, 1000, wid)
+    data = []
+    for s in range(1000, 1000 + n_train + n_eval):
+        case = si.make_case(g, s, wid)
+        if not np.array_equal(case["coils"], case0["coils"]):
+            return {"skipped": "coil maps differ between seeds"}
+        y = synth_inputs(torch, dev, plan, g, case, 1)[0]
+        xt = plan.solve(y).to(torch.complex128)
+        torch.cuda.synchronize()
+        data.append((y, xt))
+    params = si.cnn_init(1, 2 * g.n_shots, width=64, out_scale=0.1)
+    zero = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
+    with smsm.Learned(plan, params, width=64, n_unroll=5, n_cg=10, mu=mu) as net, \
+            smsm.Learned(plan, zero, width=64, n_unroll=5, n_cg=10, mu=mu) as net0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = [net.train_step(*data[k % n_train], lr) for k in range(steps)]
+        torch.cuda.synchronize()
+        t_train = (time.perf_counter() - t0) / steps
+        def err(n, yd, xt):
+            return float(torch.linalg.vector_norm(n.solve(yd) - xt) / torch.linalg.vector_norm(xt))
+        held = data[n_train:]
+        e_net = float(np.mean([err(net, yd, xt) for yd, xt in held]))
+        e_dc = float(np.mean([err(net0, yd, xt) for yd, xt in held]))
+        ratios = [net.residual(net.solve(yd), yd) / net.residual(xt, yd) for yd, xt in held]
+        x = net.solve(held[0][0])
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            net.solve(held[0][0], x)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / reps
+    return {"network": "5 x (residual k-space CNN 2Ns-64-64-64-64-2Ns, 3x3, ReLU, FP32 + 10 FP64 CG "
+                       f"data-consistency steps, mu={mu})",
+            "training": f"{steps} Adam steps (lr {lr}) on {n_train} seeded instances, targets from the plain solver",
+            "train_ms_per_step": round(t_train * 1e3, 2), "loss_first_last": [round(float(losses[0]), 4),
+                                                                              round(float(losses[-1]), 4)],
+            "slice_groups_per_s": round(1.0 / t_solve, 3), "ms_per_solve": round(t_solve * 1e3, 3),
+            "heldout_rel_error_vs_plain": round(e_net, 4),
+            "heldout_rel_error_vs_plain_without_network": round(e_dc, 4),
+            "residual_ratio_vs_plain": [round(r, 3) for r in ratios],
+            "fallback_to_plain_if_ratio_above": 1.5}
+
+
 def time_kernel(torch, plan, name, reps):
     stream = torch.cuda.current_stream()
     plan.launch_kernel(name, 2)
@@ -194,6 +248,7 @@ def main():
                     help="profiling mode: one solve, a calibration copy, then REPS launches of this kernel")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-form measurement")
     ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -289,6 +344,8 @@ def main():
            "solve_status": smsm.status_string(status)}
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, dev, args.batch_streams, 3)
+    if not args.no_learned:
+        out["learned"] = learned_measurement(torch, dev, plan, g, args.workload)
 
     if not args.no_cpu_baseline and args.gpus == 1:
         from oracle import smsm_oracle as o
