@@ -111,6 +111,33 @@ def batched_measurement(torch, dev, n_streams, reps, directions=5):
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 
 
+def with_flags(smsm, params, extra):
+    p = smsm.Params.from_buffer_copy(params)
+    p.flags = params.flags | extra
+    return p
+
+
+def mixed_measurement(torch, plan, ys, x, reps=10):
+    """The mixed-precision form (SMSM_FLAG_REG_F32) on the same plan and
+    inputs: slice-groups/s over `reps` solves after two warm-up solves."""
+    from paper_1901_01893_amd import smsm
+    base = smsm.Params.from_buffer_copy(plan.params)
+    plan.set_params(with_flags(smsm, base, smsm.SMSM_FLAG_REG_F32))
+    try:
+        for k in range(2):
+            plan.solve(ys[k % len(ys)], x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            plan.solve(ys[k % len(ys)], x)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+    finally:
+        plan.set_params(base)
+    return {"form": "regulariser image-domain Hankel kernel stored complex64 (widened on load); all arithmetic FP64",
+            "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3)}
+
+
 def learned_measurement(torch, dev, plan, g, workload, n_train=16, n_eval=2, steps=200, mu=0.05, lr=1e-3):
     """The learned form on the timed workload: a width-64 network (5 unrolled
     iterations of 10 data-consistency CG steps) trained on the GPU for `steps`
@@ -249,6 +276,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision-form measurement")
     ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -344,6 +372,8 @@ def main():
            "solve_status": smsm.status_string(status)}
     if not args.no_batched:
         out["batched"] = batched_measurement(torch, dev, args.batch_streams, 3)
+    if not args.no_mixed:
+        out["mixed"] = mixed_measurement(torch, plan, ys, x)
     if not args.no_learned:
         out["learned"] = learned_measurement(torch, dev, plan, g, args.workload)
 
@@ -353,8 +383,15 @@ def main():
         y_or = y_or.astype(np.complex64)
         ref_path = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}_seed0.npy")
         if os.path.exists(ref_path):
+            ref = np.load(ref_path)
             plan.solve(torch.from_numpy(y_or).to(dev), x)
-            out["nrmse_vs_oracle"] = o.nrmse(x.cpu().numpy(), np.load(ref_path))
+            out["nrmse_vs_oracle"] = o.nrmse(x.cpu().numpy(), ref)
+            if "mixed" in out:
+                base = smsm.Params.from_buffer_copy(plan.params)
+                plan.set_params(with_flags(smsm, base, smsm.SMSM_FLAG_REG_F32))
+                plan.solve(torch.from_numpy(y_or).to(dev), x)
+                plan.set_params(base)
+                out["mixed"]["nrmse_vs_oracle"] = o.nrmse(x.cpu().numpy(), ref)
         out["cpu_baseline"] = cpu_baseline(g, case, y_or.astype(np.complex128))
     plan.close()
     print(json.dumps(out))

@@ -55,6 +55,7 @@ struct smsm_plan {
     int npmax = 0;           // partial sums per slice (max over producers)
     size_t lds_rows = 0, lds_col = 0, lds_gram = 0, lds_gram_lines = 0;
     bool have_weights = false;
+    bool khat_f32 = false;   // Khat was last built as complex64 (SMSM_FLAG_REG_F32)
     void* arena = nullptr;
     size_t bytes = 0;
     // device buffers
@@ -160,24 +161,31 @@ smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, hipStream_t 
 struct ColFastInst {
     int M, L, Ns;
     const void* fn;
+    const void* fn_f32;   // the instance reading Khat as complex64
 };
-#define COLFAST(M_, L_) {M_, L_, 4, (const void*)&k_col_fast<M_, L_, 4, 2>}
+#define COLFAST(M_, L_) {M_, L_, 4, (const void*)&k_col_fast<M_, L_, 4, 2>, (const void*)&k_col_fast<M_, L_, 4, 2, true>}
 const ColFastInst kColFast[] = {COLFAST(16, 2), COLFAST(16, 3), COLFAST(32, 2),
                                 COLFAST(32, 3), COLFAST(64, 2), COLFAST(64, 3)};
 #undef COLFAST
 
-template <int M_, int L_>
-void launch_colfast(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
+template <int M_, int L_, bool KF32>
+void launch_colfast_k(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
     if (P->kt_n < P->kt_cap && P->kt_seen++ % P->kt_stride == 0) {
         const int n = P->kt_n++;
-        hipExtLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st,
+        hipExtLaunchKernelGGL((k_col_fast<M_, L_, 4, 2, KF32>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st,
                               P->kt_ev[2 * n], P->kt_ev[2 * n + 1], 0, g, in, out, P->ST, P->theta, P->tw2,
                               P->twM, P->Khat, use_reg, pc, P->prow);
     } else {
-        hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in,
+        hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2, KF32>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in,
                            out, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
     }
+}
+template <int M_, int L_>
+void launch_colfast(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
+    // the complex64 table only matters where the regulariser term is applied
+    if (use_reg && P->khat_f32) launch_colfast_k<M_, L_, true>(P, in, out, use_reg, pc, st);
+    else launch_colfast_k<M_, L_, false>(P, in, out, use_reg, pc, st);
 }
 
 // Column pass (hybrid in -> hybrid out).  For MODE == COL_NORMAL, `pc` may
@@ -326,8 +334,9 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
                        P->tw1, P->Dhat);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
+        P->khat_f32 = (P->prm.flags & SMSM_FLAG_REG_F32) != 0;
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * (g.Ns + 1) / 2), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
-                           P->tw2, P->Khat);
+                           P->tw2, P->Khat, P->khat_f32 ? 1 : 0);
         LAUNCH_CHECK();
     }
     P->have_weights = true;
@@ -705,8 +714,11 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         for (const Opt& o : opts)
             if (hipFuncSetAttribute(o.f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)o.bytes) != hipSuccess)
                 ok = false;
-        if (P->col_fast >= 0 && hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                    (int)P->lds_colfast) != hipSuccess)
+        if (P->col_fast >= 0 && (hipFuncSetAttribute(kColFast[P->col_fast].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)P->lds_colfast) != hipSuccess ||
+                                 hipFuncSetAttribute(kColFast[P->col_fast].fn_f32,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)P->lds_colfast) != hipSuccess))
             ok = false;
     }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;
@@ -1138,7 +1150,7 @@ smsm_status smsm_images_sos(smsm_plan* P, const void* x_dev, void* img_dev, void
 namespace {
 
 // Algorithmic FP64 flops and compulsory bytes of one launch (see smsm.h).
-void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
+void kernel_cost(const Geo& g, int id, bool khat_f32, double* flops, double* bytes) {
     const double n1 = g.n1, n2 = g.n2, B = g.B, L = g.L, Ns = g.Ns, Nc = g.Nc, M = g.M, nc = g.nc, e = g.e;
     const double vec = B * n1 * n2 * 16.0;               // one c128 vector
     const double ds = band_ds(g.Ns, g.nc);
@@ -1157,7 +1169,7 @@ void kernel_cost(const Geo& g, int id, double* flops, double* bytes) {
                 + B * n2 * 12.0;                                  // x += alpha p, p = r + beta p, Re <p, q>
             f = n1 * per_col;
             b = 6.0 * vec + L * Nc * n1 * n2 * 16.0                // r, p, x in; p, q, x out; coil maps (c128)
-                + L * Ns * (Ns + 1) / 2.0 * n1 * n2 * 16.0;        // image-domain Hankel kernel (pairs j <= i)
+                + L * Ns * (Ns + 1) / 2.0 * n1 * n2 * (khat_f32 ? 8.0 : 16.0);   // image-domain Hankel kernel (pairs j <= i)
             break;
         }
         case SMSM_KERNEL_ROWS_INV:
@@ -1195,7 +1207,7 @@ extern "C" {
 
 smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* bytes) {
     if (!P || !flops || !bytes || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
-    kernel_cost(P->g, id, flops, bytes);
+    kernel_cost(P->g, id, P->khat_f32, flops, bytes);
     return SMSM_OK;
 }
 

@@ -119,11 +119,13 @@ __host__ __device__ inline int colfast_lds_total(const Geo& g) { return 2 * g.B 
 // pairs j <= i are stored, pair p = i (i + 1) / 2 + j (khat_pair), as
 // Khat[l][p][x][n].  grid (n1, L Ns (Ns + 1) / 2), block 256: the taps' x
 // transform A[d2] (products formed in parallel, summed in d1 order), then one
-// output n per thread from shared-memory twiddles.
+// output n per thread from shared-memory twiddles.  f32: the table is written
+// as complex64 (same element index, half the bytes), read back widened.
 SMSM_HD inline int khat_pair(int j, int i) { return i * (i + 1) / 2 + j; }   // j <= i
 __global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __restrict__ Kc,
                                                       const double2* __restrict__ tw1,
-                                                      const double2* __restrict__ tw2, double2* __restrict__ Khat) {
+                                                      const double2* __restrict__ tw2, double2* __restrict__ Khat,
+                                                      int f32) {
     __shared__ double2 A[BAND_MAX_NC];
     __shared__ double2 PR[BAND_MAX_NC * BAND_MAX_NC];
     __shared__ double2 T2[256];
@@ -148,7 +150,9 @@ __global__ void __launch_bounds__(256) k_hankel_image(Geo g, const double2* __re
     for (int n = threadIdx.x; n < n2; n += blockDim.x) {
         double2 k = cmk(0.0, 0.0);
         for (int d2 = 0; d2 < nc; ++d2) k = cfma(A[d2], T2[((d2 - e) * (n - n2 / 2)) & (n2 - 1)], k);
-        Khat[((size_t)blockIdx.y * n1 + x) * n2 + n] = k;
+        const size_t o = ((size_t)blockIdx.y * n1 + x) * n2 + n;
+        if (f32) reinterpret_cast<float2*>(Khat)[o] = make_float2((float)k.x, (float)k.y);   // complex64 form
+        else Khat[o] = k;
     }
 }
 
@@ -184,8 +188,9 @@ struct ColCg {
 // Also writes prow[b][j][x] (the input's rows within 2e of the ky edges, j as
 // in k_band_extract) for the band kernel.
 // Template: M = n2/Ns (folded length), L slices, NS shots, CG coil groups
-// (waves per shot).  blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
-template <int M, int L, int NS, int CG>
+// (waves per shot), KF32: Khat stored complex64 (the mixed-precision form).
+// blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
+template <int M, int L, int NS, int CG, bool KF32 = false>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
            const double2* __restrict__ theta, const double2* __restrict__ tw2, const double2* __restrict__ twM,
@@ -341,7 +346,8 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
                     const int pr = j <= i ? khat_pair(j, i) : khat_pair(i, j);
-                    double2 kv = Khat[((size_t)(s * (NS * (NS + 1) / 2) + pr) * n1 + x1) * N2 + n];
+                    const size_t ko = ((size_t)(s * (NS * (NS + 1) / 2) + pr) * n1 + x1) * N2 + n;
+                    double2 kv = KF32 ? c64to128(reinterpret_cast<const float2*>(Khat)[ko]) : Khat[ko];
                     kv.y = j <= i ? kv.y : -kv.y;
                     const double2 taj = cscale(TW2[(j * n) & (N2 - 1)], sgn_pow(n));
                     rg = cfma(kv, cmulc(U[(s * NS + j) * N2 + n], taj), rg);

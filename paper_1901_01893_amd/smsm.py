@@ -23,6 +23,7 @@ SMSM_E_NOMEM = -3
 SMSM_E_DEVICE = -4
 SMSM_E_NUMERIC = -5
 SMSM_FLAG_X_C128 = 0x1
+SMSM_FLAG_REG_F32 = 0x2
 
 # Every entry point of include/smsm.h.
 ABI_SYMBOLS = (
