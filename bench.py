@@ -138,7 +138,7 @@ def mixed_measurement(torch, plan, ys, x, reps=10):
             "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3)}
 
 
-def learned_measurement(torch, dev, plan, g, workload, n_train=16, n_eval=2, steps=200, mu=0.05, lr=1e-3):
+def learned_measurement(torch, dev, plan, g, workload, n_train=64, n_eval=4, steps=300, mu=0.05, lr=3e-4):
     """The learned form on the timed workload: a width-64 network (5 unrolled
     iterations of 10 data-consistency CG steps) trained on the GPU for `steps`
     Adam steps against the plain solver's reconstructions of n_train seeded
