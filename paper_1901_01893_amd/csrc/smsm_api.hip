@@ -1280,6 +1280,7 @@ struct smsm_learned {
     double2 *b = nullptr, *x = nullptr, *z = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr;
     double2 *g = nullptr, *wv = nullptr, *ax = nullptr, *xs = nullptr;
     double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] rr, [2] alpha, [3] beta, [8] loss num, [9] den
+    float *wpart = nullptr, *wbpart = nullptr;  // weight-gradient chunk partials (k_wgrad_part)
 };
 
 namespace {
@@ -1320,9 +1321,21 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
     const float* g = gout;
     float* bufs[2] = {Lr->ga, Lr->gbuf};
     for (int k = D - 1; k >= 0; --k) {
-        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(Lr->cin[k] * Lr->cout[k]), dim3(CNN_THREADS), 0, st, Lr->L,
-                           Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g, Lr->grads + Lr->woff[k],
-                           Lr->grads + Lr->boff[k], accumulate);
+        if (Lr->cin[k] % WG_TILE == 0 && Lr->cout[k] % WG_TILE == 0) {
+            const int nchunk = Lr->L * wg_chunks(Lr->H, Lr->W);
+            hipLaunchKernelGGL(k_wgrad_part, dim3(nchunk, Lr->cout[k] / WG_TILE, Lr->cin[k] / WG_TILE),
+                               dim3(CNN_THREADS), 0, st, Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g,
+                               Lr->wpart, Lr->wbpart);
+            LAUNCH_CHECK();
+            const int nout = Lr->cout[k] * Lr->cin[k] * 9 + Lr->cout[k];
+            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + CNN_THREADS - 1) / CNN_THREADS), dim3(CNN_THREADS), 0, st,
+                               nchunk, Lr->cin[k], Lr->cout[k], Lr->wpart, Lr->wbpart, Lr->grads + Lr->woff[k],
+                               Lr->grads + Lr->boff[k], accumulate);
+        } else {
+            hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(Lr->cin[k] * Lr->cout[k]), dim3(CNN_THREADS), 0, st, Lr->L,
+                               Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g, Lr->grads + Lr->woff[k],
+                               Lr->grads + Lr->boff[k], accumulate);
+        }
         LAUNCH_CHECK();
         float* dst = k > 0 ? bufs[k & 1] : gin;
         smsm_status s = lconv(Lr, Lr->cout[k], Lr->cin[k], g, Lr->params + Lr->woff[k], nullptr, dst, 0, true, st);
@@ -1505,6 +1518,13 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     for (int k = 0; k < 9; ++k) ov[k] = cv.take<double2>(n);
     const size_t oax = cv.take<double2>(ny), oxs = cv.take<double2>(n * n_unroll);
     const size_t opart = cv.take<double>(kVecBlocks), oscal = cv.take<double>(16);
+    size_t maxcc = 0, maxco = 0;
+    for (int k = 0; k < smsm_learned::kDepth; ++k) {
+        maxcc = std::max(maxcc, (size_t)Lr->cin[k] * Lr->cout[k]);
+        maxco = std::max(maxco, (size_t)Lr->cout[k]);
+    }
+    const size_t nchunk = (size_t)Lr->L * wg_chunks(Lr->H, Lr->W);
+    const size_t owp = cv.take<float>(nchunk * maxcc * 9), owb = cv.take<float>(nchunk * maxco);
     if (hipMalloc(&Lr->arena, cv.off) != hipSuccess) {
         delete Lr;
         return SMSM_E_NOMEM;
@@ -1524,6 +1544,8 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     Lr->xs = (double2*)(base + oxs);
     Lr->part = (double*)(base + opart);
     Lr->scal = (double*)(base + oscal);
+    Lr->wpart = (float*)(base + owp);
+    Lr->wbpart = (float*)(base + owb);
     bool ok = hipMemcpy(Lr->params, params_host, off * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(Lr->am, 0, off * sizeof(float)) == hipSuccess;
     ok = ok && hipMemset(Lr->av, 0, off * sizeof(float)) == hipSuccess;

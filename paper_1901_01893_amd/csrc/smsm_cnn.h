@@ -235,3 +235,118 @@ __global__ void k_dc_resid(long n, const double2* __restrict__ ax, const float2*
     s = block_sum(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
+
+// Weight gradients in two deterministic stages for channel counts that are
+// multiples of 8.  Stage 1: one workgroup per (pixel chunk, 8 output
+// channels, 8 input channels); a chunk is WG_ROWS(W) whole rows of one image
+// (WG_PX pixels).  The chunk's output gradients and its input rows with a
+// one-pixel zero halo are staged in shared memory; thread (wave w, lane) owns
+// the pair o = lane / 8, c = lane % 8 and its 9 taps over the w-th quarter of
+// the chunk's pixels, taken in order with the 3 x 3 input window slid along
+// the row (one gradient and three input reads per pixel; the 64 lanes of a
+// wave read the same pixel: shared-memory broadcasts); the 4 waves' sums are
+// added in order and stored as
+//   part[chunk][o][c][t]   and, for the first input-channel block, the
+//   bias partials bpart[chunk][o].
+// Stage 2 (k_wgrad_sum) adds the chunks in order.
+#define WG_PX 512
+#define WG_TILE 8
+__host__ __device__ inline int wg_rows(int H, int W) {
+    const int r = WG_PX / W;
+    return r < 1 ? 1 : (r > H ? H : r);
+}
+__host__ __device__ inline int wg_chunks(int H, int W) {
+    const int r = wg_rows(H, W);
+    return (H + r - 1) / r;
+}
+// staged input floats per channel: (rows + 2) x (W + 2); W <= 256
+#define WG_IN_MAX (((WG_PX / 256) + 2) * 258 > 34 * 34 ? ((WG_PX / 256) + 2) * 258 : 34 * 34)
+
+__global__ void __launch_bounds__(CNN_THREADS)
+k_wgrad_part(int ci, int co, int H, int W, const float* __restrict__ in, const float* __restrict__ gout,
+             float* __restrict__ part, float* __restrict__ bpart) {
+    __shared__ float gs[WG_TILE][WG_PX];
+    __shared__ float xs[WG_TILE][WG_IN_MAX];
+    __shared__ float red[4][64][10];
+    const int R = wg_rows(H, W), nch = wg_chunks(H, W);
+    const int chunk = blockIdx.x, n = chunk / nch, r0 = (chunk - n * nch) * R;
+    const int rows = (r0 + R <= H) ? R : H - r0;
+    const int o0 = blockIdx.y * WG_TILE, c0 = blockIdx.z * WG_TILE;
+    const int npx = H * W, W2 = W + 2;
+    const int lw = __builtin_ctz((unsigned)W);        // W is a power of two
+    const int tid = threadIdx.x;
+    // stage: gout rows r0 .. r0 + rows - 1 of the 8 output channels
+    for (int o = 0; o < WG_TILE; ++o)
+        for (int q = tid; q < R * W; q += CNN_THREADS)
+            gs[o][q] = q < rows * W ? gout[((size_t)n * co + o0 + o) * npx + r0 * W + q] : 0.0f;
+    // stage: input rows r0 - 1 .. r0 + rows with a zero halo, 8 input channels
+    for (int c = 0; c < WG_TILE; ++c)
+        for (int rr = 0; rr < R + 2; ++rr) {
+            const int i = r0 - 1 + rr;
+            for (int jj = tid; jj < W2; jj += CNN_THREADS) {
+                const int j = jj - 1;
+                const bool ok = i >= 0 && i < H && j >= 0 && j < W;
+                xs[c][rr * W2 + jj] = ok ? in[((size_t)n * ci + c0 + c) * npx + i * W + j] : 0.0f;
+            }
+        }
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    const int o = lane >> 3, c = lane & 7;
+    float acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
+    const int P = rows * W, qb = (P * w) / 4, qe = (P * (w + 1)) / 4;
+    float win[3][3];
+    for (int q = qb; q < qe; ++q) {
+        const int i = q >> lw, j = q & (W - 1);
+        const float* xp = &xs[c][i * W2 + j];          // top-left of the 3 x 3 window
+        if (q == qb || j == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) win[a][d] = xp[a * W2 + d];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                win[a][0] = win[a][1];
+                win[a][1] = win[a][2];
+                win[a][2] = xp[a * W2 + 2];
+            }
+        }
+        const float gv = gs[o][q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc[3 * a + d] = fmaf(gv, win[a][d], acc[3 * a + d]);
+        acc[9] += gv;
+    }
+#pragma unroll
+    for (int t = 0; t < 10; ++t) red[w][lane][t] = acc[t];
+    __syncthreads();
+    for (int k = tid; k < 64 * 10; k += CNN_THREADS) {
+        const int pl = k / 10, t = k - pl * 10;
+        const float s = ((red[0][pl][t] + red[1][pl][t]) + red[2][pl][t]) + red[3][pl][t];
+        const int oo = pl >> 3, cc = pl & 7;
+        if (t < 9) part[(((size_t)chunk * co + o0 + oo) * ci + c0 + cc) * 9 + t] = s;
+        else if (blockIdx.z == 0 && cc == 0) bpart[(size_t)chunk * co + o0 + oo] = s;
+    }
+}
+
+// gw[o][c][t] (+)= sum over chunks in order of part[chunk][o][c][t];
+// gb[o] (+)= sum of bpart[chunk][o].
+__global__ void k_wgrad_sum(int nchunk, int ci, int co, const float* __restrict__ part,
+                            const float* __restrict__ bpart, float* __restrict__ gw, float* __restrict__ gb,
+                            int accumulate) {
+    const int nw = co * ci * 9;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nw + co; k += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        if (k < nw) {
+            for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * nw + k];
+            gw[k] = accumulate ? gw[k] + s : s;
+        } else {
+            const int o = k - nw;
+            for (int ch = 0; ch < nchunk; ++ch) s += bpart[(size_t)ch * co + o];
+            gb[o] = accumulate ? gb[o] + s : s;
+        }
+    }
+}
