@@ -287,7 +287,8 @@ smsm_status smsm_kernel_timer_read(smsm_plan* plan, double* total_ms, int* launc
  * Parameters (host layout, float32): per layer, weights [co][ci][3][3] then
  * bias [co], layers in order.  The object holds the parameters, gradients,
  * Adam moments and a workspace for the plan's geometry, and uses the plan's
- * buffers: calls on one plan (solver or learned) must not overlap.
+ * buffers: the plan must outlive the object, and calls on one plan (solver
+ * or learned) must not overlap.
  * Requires 2 Ns to be a multiple of 4 (SMSM_E_UNSUPPORTED otherwise).
  * Vectors: y_dev c64 [Ns][Nc][n2][n1]; x_dev, xt_dev c128 [L][Ns][n2][n1]. */
 typedef struct smsm_learned smsm_learned;
