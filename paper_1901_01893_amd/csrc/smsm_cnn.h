@@ -275,20 +275,46 @@ k_wgrad_part(int ci, int co, int H, int W, const float* __restrict__ in, const f
     const int npx = H * W, W2 = W + 2;
     const int lw = __builtin_ctz((unsigned)W);        // W is a power of two
     const int tid = threadIdx.x;
-    // stage: gout rows r0 .. r0 + rows - 1 of the 8 output channels
-    for (int o = 0; o < WG_TILE; ++o)
-        for (int q = tid; q < R * W; q += CNN_THREADS)
-            gs[o][q] = q < rows * W ? gout[((size_t)n * co + o0 + o) * npx + r0 * W + q] : 0.0f;
-    // stage: input rows r0 - 1 .. r0 + rows with a zero halo, 8 input channels
-    for (int c = 0; c < WG_TILE; ++c)
-        for (int rr = 0; rr < R + 2; ++rr) {
-            const int i = r0 - 1 + rr;
-            for (int jj = tid; jj < W2; jj += CNN_THREADS) {
-                const int j = jj - 1;
-                const bool ok = i >= 0 && i < H && j >= 0 && j < W;
-                xs[c][rr * W2 + jj] = ok ? in[((size_t)n * ci + c0 + c) * npx + i * W + j] : 0.0f;
-            }
+    // stage: gout rows r0 .. r0 + rows - 1 of the 8 output channels (all
+    // loads of a thread issued before its stores)
+    {
+        constexpr int NG = WG_TILE * WG_PX / CNN_THREADS;
+        float v[NG];
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+            const int k = tid + u * CNN_THREADS, o = k / WG_PX, q = k - o * WG_PX;
+            v[u] = q < rows * W ? gout[((size_t)n * co + o0 + o) * npx + r0 * W + q] : 0.0f;
         }
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+            const int k = tid + u * CNN_THREADS, o = k / WG_PX, q = k - o * WG_PX;
+            if (q < R * W) gs[o][q] = v[u];
+        }
+    }
+    // stage: input rows r0 - 1 .. r0 + rows with a zero halo, 8 input
+    // channels.  Flat index k -> (channel, row, column) by multiply-high with
+    // ceil(2^32 / d): exact for k < 2^32 / d (here k < 8 * 34 * 34, d <= 258).
+    {
+        const int S = (R + 2) * W2;
+        const unsigned mS = 0xFFFFFFFFu / (unsigned)S + 1u, mW = 0xFFFFFFFFu / (unsigned)W2 + 1u;
+        constexpr int NX = (WG_TILE * WG_IN_MAX + CNN_THREADS - 1) / CNN_THREADS;
+        float v[NX];
+#pragma unroll
+        for (int u = 0; u < NX; ++u) {
+            const unsigned k = tid + u * CNN_THREADS;
+            const int c = (int)__umulhi(k, mS), q = (int)k - c * S;
+            const int rr = (int)__umulhi((unsigned)q, mW), jj = q - rr * W2;
+            const int i = r0 - 1 + rr, j = jj - 1;
+            const bool ok = c < WG_TILE && i >= 0 && i < H && j >= 0 && j < W;
+            v[u] = ok ? in[((size_t)n * ci + c0 + c) * npx + i * W + j] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < NX; ++u) {
+            const unsigned k = tid + u * CNN_THREADS;
+            const int c = (int)__umulhi(k, mS), q = (int)k - c * S;
+            if (c < WG_TILE) xs[c][q] = v[u];
+        }
+    }
     __syncthreads();
     const int lane = tid & 63, w = tid >> 6;
     const int o = lane >> 3, c = lane & 7;
