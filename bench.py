@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form measurement")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision-form measurement")
+    ap.add_argument("--profile-learned", type=int, default=0, metavar="STEPS",
+                    help="run only STEPS training steps and STEPS solves of the learned form (for a kernel trace)")
     ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -298,6 +300,19 @@ def main():
     ys = synth_inputs(torch, dev, plan, g, case, 1 if args.profile_kernel else N_DRAWS)
     y = ys[0]
     x = torch.empty(plan.shape_x, dtype=torch.complex64, device=dev)
+    if args.profile_learned:
+        import smsm_inputs as si
+        net = smsm.Learned(plan, si.cnn_init(1, 2 * g.n_shots, width=64), width=64, n_unroll=5, n_cg=10, mu=0.05)
+        xt = plan.solve(y).to(torch.complex128)
+        for _ in range(args.profile_learned):
+            net.train_step(y, xt, 3e-4)
+        for _ in range(args.profile_learned):
+            net.solve(y)
+        torch.cuda.synchronize()
+        net.close()
+        plan.close()
+        print(json.dumps({"profile_learned": args.profile_learned, "workload": args.workload}))
+        return
     if args.profile_kernel:
         # Kernel-level profiling: fill the plan's buffers with one solve, run a
         # plain device copy of known size (calibrates the HBM byte counters),
