@@ -60,7 +60,8 @@ BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (128, 3, 4, 7), (
 
 def batched_measurement(torch, dev, n_streams, reps, directions=5):
     """Slice-groups/s of a batch (every group of BATCH_GEOMS with `directions`
-    inputs each, seeded noise draws, one plan per group) as plain sequential
+    inputs each: diffusion directions with reseeded shot phases, U(0.3, 1)
+    attenuation and fresh noise; one plan per group) as plain sequential
     solves and as one graph on n_streams streams (0: chosen by the library's
     autotuner); the graph's outputs must equal the plain ones bit for bit."""
     import smsm_inputs as si
@@ -75,7 +76,9 @@ def batched_measurement(torch, dev, n_streams, reps, directions=5):
         plan = smsm.Plan(n, n, L, Ns, 32, r, coils, case["masks"], case["shifts"],
                          smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
         plans.append(plan)
-        for y in synth_inputs(torch, dev, plan, g, case, directions):
+        for d in range(directions):
+            # a diffusion direction: shot phases reseeded, magnitude attenuated by U(0.3, 1)
+            y = synth_inputs(torch, dev, plan, g, si.direction_case(g, case, d, 30 + k), 1)[0]
             entries.append((plan, y))
     # directions interleaved across groups: (g0 d0, g1 d0, ..., g0 d1, ...)
     order = [entries[k * directions + d] for d in range(directions) for k in range(len(plans))]
@@ -105,7 +108,7 @@ def batched_measurement(torch, dev, n_streams, reps, directions=5):
             plan.close()
     n = len(order)
     return {"groups": [f"{a}x{a} MB{b} Ns{c} r{d}" for a, b, c, d in BATCH_GEOMS], "coils": 32,
-            "directions_per_group": directions, "solves": n, "iterations": "15 IRLS x 15 CG",
+            "directions_per_group": directions, "inputs": "per direction: shot phases reseeded, magnitude x U(0.3, 1), fresh noise", "solves": n, "iterations": "15 IRLS x 15 CG",
             "streams": n_streams, "streams_chosen_by": "autotuner" if autotuned else "caller", "reps": reps,
             "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
