@@ -137,7 +137,8 @@ def mixed_measurement(torch, plan, ys, x, reps=10):
         t = (time.perf_counter() - t0) / reps
     finally:
         plan.set_params(base)
-    return {"form": "regulariser image-domain Hankel kernel stored complex64 (widened on load); all arithmetic FP64",
+    return {"form": "regulariser tables (image-domain Hankel kernel, band row and corner tables) stored complex64, "
+                    "widened on load; all arithmetic FP64",
             "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3)}
 
 

@@ -84,11 +84,12 @@ typedef struct {
 
 /* x written by smsm_solve is complex128 instead of complex64. */
 #define SMSM_FLAG_X_C128 0x1u
-/* Mixed-precision form: the regulariser's image-domain Hankel kernel (the
- * per-pixel shot-pair taps every column pass reads) is stored complex64 and
- * widened to FP64 on load; everything else stays FP64.  Takes effect when
- * the weights are next built (each IRLS step, smsm_set_weights); the error
- * against the FP64 oracle is reported per instance by the tests. */
+/* Mixed-precision form: the regulariser's tables that every CG iteration
+ * reads (the image-domain Hankel kernel of the column pass, the band
+ * kernel's transformed row tables and corner tables) are stored complex64
+ * and widened to FP64 on load; everything else stays FP64.  Takes effect
+ * when the weights are next built (each IRLS step, smsm_set_weights); the
+ * error against the FP64 oracle is reported per instance by the tests. */
 #define SMSM_FLAG_REG_F32 0x2u
 
 /*

@@ -55,7 +55,7 @@ struct smsm_plan {
     int npmax = 0;           // partial sums per slice (max over producers)
     size_t lds_rows = 0, lds_col = 0, lds_gram = 0, lds_gram_lines = 0;
     bool have_weights = false;
-    bool khat_f32 = false;   // Khat was last built as complex64 (SMSM_FLAG_REG_F32)
+    bool khat_f32 = false;   // Khat, Dhat and Dx were last built as complex64 (SMSM_FLAG_REG_F32)
     void* arena = nullptr;
     size_t bytes = 0;
     // device buffers
@@ -82,6 +82,7 @@ struct smsm_plan {
     size_t lds_colfast = 0;
     size_t lds_band = 0;
     BandFn band = nullptr;   // band-correction kernel for (2r-1, Ns)
+    BandFn band_f32 = nullptr;   // the same reading complex64 tables (SMSM_FLAG_REG_F32)
 };
 
 namespace {
@@ -256,7 +257,8 @@ smsm_status band_corr(smsm_plan* P, hipStream_t st) {
     a.ccorner = P->ccorner;
     a.part = P->bpart;
     void* args[] = {&a};
-    if (hipLaunchKernel((const void*)P->band, dim3(band_items(g), g.L), dim3(64 * g.Ns), args, P->lds_band, st) !=
+    if (hipLaunchKernel((const void*)(P->khat_f32 ? P->band_f32 : P->band), dim3(band_items(g), g.L), dim3(64 * g.Ns),
+                        args, P->lds_band, st) !=
         hipSuccess)
         return SMSM_E_DEVICE;
     LAUNCH_CHECK();
@@ -327,14 +329,15 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     const Geo& g = P->g;
     const long total = (long)g.L * (4 * g.e + 4 * g.e * g.e + 1) * g.Ns * g.Ns * g.nc * g.nc;
     const int blocks = (int)std::min<long>(8192, (total + kThreads - 1) / kThreads);
+    // the format every reader of these tables follows until the next build
+    P->khat_f32 = (P->prm.flags & SMSM_FLAG_REG_F32) != 0;
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
-                       P->Kc, P->Dside, P->Dx);
+                       P->Kc, P->Dside, P->Dx, P->khat_f32 ? 1 : 0);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_band_rowhat, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g, P->Dside,
-                       P->tw1, P->Dhat);
+                       P->tw1, P->Dhat, P->khat_f32 ? 1 : 0);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
-        P->khat_f32 = (P->prm.flags & SMSM_FLAG_REG_F32) != 0;
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * (g.Ns + 1) / 2), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
                            P->tw2, P->Khat, P->khat_f32 ? 1 : 0);
         LAUNCH_CHECK();
@@ -546,6 +549,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->npmax = std::max(P->ntile, 2 * kPadBlocks);
     P->lds_band = band_lds_bytes(g);
     P->band = band_fn(g.nc, Ns);
+    P->band_f32 = band_fn(g.nc, Ns, true);
     if (!P->band) {
         delete P;
         return SMSM_E_UNSUPPORTED;
@@ -710,6 +714,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                             {(const void*)&k_gram_q<16>, P->lds_gram}, {(const void*)&k_gram_q<32>, P->lds_gram},
                             {(const void*)&k_gram_q<64>, P->lds_gram}, {(const void*)&k_gram_q<128>, P->lds_gram},
                             {(const void*)&k_gram_q<256>, P->lds_gram}, {(const void*)P->band, P->lds_band},
+                            {(const void*)P->band_f32, P->lds_band},
                             {(const void*)&k_gram_lines, P->lds_gram_lines}};
         for (const Opt& o : opts)
             if (hipFuncSetAttribute(o.f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)o.bytes) != hipSuccess)
@@ -1179,8 +1184,9 @@ void kernel_cost(const Geo& g, int id, bool khat_f32, double* flops, double* byt
             break;
         case SMSM_KERNEL_BAND_CORR: {
             f = 8.0 * B * (2.0 * e * n2 * nc * nc + 2.0 * e * n1 * nc + 4.0 * e * e * nc * nc) * Ns;
-            b = L * (2.0 * e + 4.0 * e * e) * Ns * Ns * nc * nc * 16.0     // column-side and corner tables
-                + L * 2.0 * e * Ns * nc * Ns * n1 * 16.0                    // transformed row tables
+            b = L * 2.0 * e * Ns * Ns * nc * nc * 16.0                     // column-side tables
+                + L * 4.0 * e * e * Ns * Ns * nc * nc * (khat_f32 ? 8.0 : 16.0)   // corner tables
+                + L * 2.0 * e * Ns * nc * Ns * n1 * (khat_f32 ? 8.0 : 16.0)      // transformed row tables
                 + B * 4.0 * e * n2 * 16.0 + B * 2.0 * e * nc * n1 * 16.0    // band columns, rows of p
                 + B * (ds * 2.0 * e * n2 + 2.0 * e * n1 + 4.0 * e * e) * 16.0;   // corrections out
             break;

@@ -280,8 +280,10 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
 //   Dx[l][corner pixel][i][d2][d1][i'] = (lam/2) sum_{b' in I2 x I1, b'+d in [0,r)^2} W[(i, b'+d), (i', b')]
 // and the taps of the circular term (used in the image domain)
 //   Kc[l][i][i'][d2][d1] = (lam/2) sum_{b'} W[(i, b'+d), (i', b')].
+// f32: Dx is written as complex64 (same element index), the mixed-precision form.
 __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_lam,
-                              double2* __restrict__ Kc, double2* __restrict__ Dside, double2* __restrict__ Dx) {
+                              double2* __restrict__ Kc, double2* __restrict__ Dside, double2* __restrict__ Dx,
+                              int f32) {
     const int nc = g.nc, r = g.r, Ns = g.Ns, K = g.K, e = g.e, nsd = 4 * e + 4 * e * e + 1;
     const long total = (long)g.L * nsd * Ns * Ns * nc * nc;
     for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
@@ -321,9 +323,12 @@ __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_
             Kc[((((size_t)l * Ns + i) * Ns + ip) * nc + d2) * nc + d1] = cscale(acc, half_lam);
         else if (sd < 4 * e)
             Dside[(((((size_t)l * 4 * e + sd) * Ns + i) * nc + d2) * nc + d1) * Ns + ip] = cscale(acc, -half_lam);
-        else
-            Dx[(((((size_t)l * 4 * e * e + sd - 4 * e) * Ns + i) * nc + d2) * nc + d1) * Ns + ip] =
-                cscale(acc, half_lam);
+        else {
+            const size_t o = (((((size_t)l * 4 * e * e + sd - 4 * e) * Ns + i) * nc + d2) * nc + d1) * Ns + ip;
+            const double2 v = cscale(acc, half_lam);
+            if (f32) reinterpret_cast<float2*>(Dx)[o] = make_float2((float)v.x, (float)v.y);
+            else Dx[o] = v;
+        }
     }
 }
 
@@ -421,7 +426,9 @@ SMSM_DEV void band_col_sum(const double2* __restrict__ Pw, int PP, const double2
     }
 }
 
-template <int NC, int NS>
+// TF32: Dhat and Dx are stored complex64 (the mixed-precision form) and
+// widened to FP64 on load.
+template <int NC, int NS, bool TF32 = false>
 __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
     extern __shared__ double2 sm[];
     __shared__ double red[16];
@@ -498,7 +505,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
         const int ip = w;
         if (x < n1) {
             const double2 pout = a.prow[((size_t)(l * NS + ip) * 4 * e + band_pcol(ky, n2, e)) * n1 + x];
-            const double2* dh = a.Dhat + ((size_t)(l * 2 * e + line) * NS * NC * NS) * n1 + x;
+            const size_t dh0 = ((size_t)(l * 2 * e + line) * NS * NC * NS) * n1 + x;
             double2 s = cmk(0.0, 0.0);
             // one input shot per round, its 2 NC loads issued as one batch
             // (two shots per round need more registers than the column items
@@ -512,7 +519,8 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
                     const double2* pri = a.prow + (size_t)(l * NS + i) * 4 * e * n1 + x;
 #pragma unroll
                     for (int d2 = 0; d2 < NC; ++d2) {
-                        dv[u][d2] = dh[(((size_t)i * NC + d2) * NS + ip) * n1];
+                        const size_t o = dh0 + (((size_t)i * NC + d2) * NS + ip) * n1;
+                        dv[u][d2] = TF32 ? c64to128(reinterpret_cast<const float2*>(a.Dhat)[o]) : a.Dhat[o];
                         pv[u][d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
                     }
                 }
@@ -530,7 +538,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
         const int corner = cp / (e * e), px = cp - corner * e * e;
         const int rr = px / e, cc = px - rr * e;
         const int q2 = ((corner & 1) ? n2 - e : 0) + rr, q1 = ((corner & 2) ? n1 - e : 0) + cc;
-        const double2* Dc = a.Dx + ((size_t)l * 4 * e * e + cp) * NS * NC * NC * NS;
+        const size_t dc0 = ((size_t)l * 4 * e * e + cp) * NS * NC * NC * NS;
         const int cq = band_pcol(q1, n1, e);
         double2 pq[NS];
 #pragma unroll
@@ -548,7 +556,10 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
             const int kx = (q1 - e + d1) & (n1 - 1), ky = (q2 - e + d2) & (n2 - 1);
             pv[it] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
 #pragma unroll
-            for (int ip = 0; ip < NS; ++ip) dc[it][ip] = Dc[(size_t)t * NS + ip];
+            for (int ip = 0; ip < NS; ++ip) {
+                const size_t o = dc0 + (size_t)t * NS + ip;
+                dc[it][ip] = TF32 ? c64to128(reinterpret_cast<const float2*>(a.Dx)[o]) : a.Dx[o];
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -580,26 +591,27 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
 // Band kernel for (2r-1, Ns); null when the pair is outside what the plan
 // accepts (Ns r^2 <= 256, 2r-1 <= BAND_MAX_NC).
 typedef void (*BandFn)(BandArgs);
-template <int NS>
+template <int NS, bool TF32>
 inline BandFn band_fn_ns(int nc) {
     switch (nc) {
-        case 3: return &k_band_hyb<3, NS>;
-        case 5: return &k_band_hyb<5, NS>;
-        case 7: return &k_band_hyb<7, NS>;
-        case 9: return &k_band_hyb<9, NS>;
-        case 11: return NS <= 4 ? &k_band_hyb<11, (NS <= 4 ? NS : 4)> : nullptr;
-        case 13: return NS <= 4 ? &k_band_hyb<13, (NS <= 4 ? NS : 4)> : nullptr;
-        case 15: return NS <= 4 ? &k_band_hyb<15, (NS <= 4 ? NS : 4)> : nullptr;
-        case 17: return NS <= 2 ? &k_band_hyb<17, (NS <= 2 ? NS : 2)> : nullptr;
+        case 3: return &k_band_hyb<3, NS, TF32>;
+        case 5: return &k_band_hyb<5, NS, TF32>;
+        case 7: return &k_band_hyb<7, NS, TF32>;
+        case 9: return &k_band_hyb<9, NS, TF32>;
+        case 11: return NS <= 4 ? &k_band_hyb<11, (NS <= 4 ? NS : 4), TF32> : nullptr;
+        case 13: return NS <= 4 ? &k_band_hyb<13, (NS <= 4 ? NS : 4), TF32> : nullptr;
+        case 15: return NS <= 4 ? &k_band_hyb<15, (NS <= 4 ? NS : 4), TF32> : nullptr;
+        case 17: return NS <= 2 ? &k_band_hyb<17, (NS <= 2 ? NS : 2), TF32> : nullptr;
         default: return nullptr;
     }
 }
-inline BandFn band_fn(int nc, int ns) {
+// tf32: the instance reading complex64 tables
+inline BandFn band_fn(int nc, int ns, bool tf32 = false) {
     switch (ns) {
-        case 1: return band_fn_ns<1>(nc);
-        case 2: return band_fn_ns<2>(nc);
-        case 4: return band_fn_ns<4>(nc);
-        case 8: return band_fn_ns<8>(nc);
+        case 1: return tf32 ? band_fn_ns<1, true>(nc) : band_fn_ns<1, false>(nc);
+        case 2: return tf32 ? band_fn_ns<2, true>(nc) : band_fn_ns<2, false>(nc);
+        case 4: return tf32 ? band_fn_ns<4, true>(nc) : band_fn_ns<4, false>(nc);
+        case 8: return tf32 ? band_fn_ns<8, true>(nc) : band_fn_ns<8, false>(nc);
         default: return nullptr;
     }
 }
@@ -608,8 +620,10 @@ inline BandFn band_fn(int nc, int ns) {
 // e^{-2 pi i (d1 - e)(x - n1/2)/n1}, rows 0..e-1 top and e..2e-1 bottom
 // (side tables 0 and 1).  One workgroup per (l, row, i, d2) with its taps and
 // the kx twiddles in shared memory; thread = x, all i'.
+// f32: written as complex64 (same element index), the mixed-precision form.
 __global__ void __launch_bounds__(256) k_band_rowhat(Geo g, const double2* __restrict__ Dside,
-                                                     const double2* __restrict__ tw1, double2* __restrict__ Dhat) {
+                                                     const double2* __restrict__ tw1, double2* __restrict__ Dhat,
+                                                     int f32) {
     __shared__ double2 T1[256];
     __shared__ double2 DR[BAND_MAX_NC * 8];   // [d1][i'], Ns <= 8
     const int n1 = g.n1, Ns = g.Ns, nc = g.nc, e = g.e;
@@ -620,12 +634,13 @@ __global__ void __launch_bounds__(256) k_band_rowhat(Geo g, const double2* __res
     for (int t = threadIdx.x; t < n1; t += blockDim.x) T1[t] = tw1[t];
     for (int t = threadIdx.x; t < nc * Ns; t += blockDim.x) DR[t] = dr[t];
     __syncthreads();
-    double2* out = Dhat + (size_t)lrid * Ns * n1;
+    const size_t out0 = (size_t)lrid * Ns * n1;
     for (int x = threadIdx.x; x < n1; x += blockDim.x) {
         for (int ip = 0; ip < Ns; ++ip) {
             double2 s = cmk(0.0, 0.0);
             for (int d1 = 0; d1 < nc; ++d1) s = cfma(DR[d1 * Ns + ip], T1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
-            out[(size_t)ip * n1 + x] = s;
+            if (f32) reinterpret_cast<float2*>(Dhat)[out0 + (size_t)ip * n1 + x] = make_float2((float)s.x, (float)s.y);
+            else Dhat[out0 + (size_t)ip * n1 + x] = s;
         }
     }
 }

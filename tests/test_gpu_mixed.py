@@ -1,5 +1,5 @@
-"""Mixed-precision form (SMSM_FLAG_REG_F32: the regulariser's image-domain
-Hankel kernel stored complex64, all arithmetic FP64): NRMSE against the FP64
+"""Mixed-precision form (SMSM_FLAG_REG_F32: the regulariser's tables stored
+complex64, all arithmetic FP64): NRMSE against the FP64
 oracle per seeded instance, and on the 256 x 256 slice group against the
 oracle's stored solution.  The bar is the solve's NRMSE <= 1e-5."""
 import os
