@@ -99,11 +99,13 @@ def cnn_backward(acts, params, gout):
 
 def pack(x, s):
     """Complex [L][Ns][H][W] -> real [L][2 Ns][H][W]: channel 2i is Re x_i / s,
-    channel 2i + 1 is Im x_i / s."""
+    channel 2i + 1 is Im x_i / s (s = 0, all-zero data: the channels are 0,
+    and the prior's term s C(.) vanishes anyway)."""
     L, ns, h, w = x.shape
+    f = 1.0 / s if s > 0 else 0.0
     out = np.empty((L, 2 * ns, h, w))
-    out[:, 0::2] = x.real / s
-    out[:, 1::2] = x.imag / s
+    out[:, 0::2] = x.real * f
+    out[:, 1::2] = x.imag * f
     return out
 
 
@@ -151,9 +153,9 @@ def unrolled_loss_and_grads(b, apply_aha, params, mu: float, n_unroll: int, n_cg
         gz = mu * wv
         # z = x + s * unpack(C(pack(x, s))): the network sees x / s and its output is scaled by s
         _, acts = cnn_forward(pack(xs[k], s), params)
-        gc = pack(gz, 1.0 / s)                    # d loss / d channels of the output: s * (Re gz, Im gz)
+        gc = pack(gz, 1.0 / s) if s > 0 else np.zeros_like(acts[0])   # d loss / d output channels: s (Re gz, Im gz)
         gin, grads = cnn_backward(acts, params, gc)
         for j, (gw, gb) in enumerate(grads):
             total[j] = (total[j][0] + gw, total[j][1] + gb)
-        g = gz + unpack(gin, 1.0 / s)             # residual path + d channels / d x = 1 / s
+        g = gz + (unpack(gin, 1.0 / s) if s > 0 else 0.0)   # residual path + d channels / d x = 1 / s
     return loss, total

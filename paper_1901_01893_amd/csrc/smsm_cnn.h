@@ -127,10 +127,11 @@ __global__ void k_relu_bwd(long n, float* __restrict__ g, const float* __restric
 }
 
 // Complex k-space [L][Ns][npx] (FP64) -> channels [L][2 Ns][npx] (FP32):
-// channel 2i = f Re x_i, 2i + 1 = f Im x_i with f = 1 / *s (inv) or *s.
+// channel 2i = f Re x_i, 2i + 1 = f Im x_i with f = 1 / *s (inv) or *s
+// (1 / 0 taken as 0: all-zero data, where the prior's term s C(.) is 0).
 __global__ void k_cnn_pack(long L, int ns, int npx, const double2* __restrict__ x, const double* __restrict__ s,
                            int inv, float* __restrict__ out) {
-    const double f = inv ? 1.0 / *s : *s;
+    const double sv = *s, f = inv ? (sv > 0.0 ? 1.0 / sv : 0.0) : sv;
     const long total = L * ns * npx;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
         const long li = k / npx;            // l * ns + i
@@ -141,10 +142,10 @@ __global__ void k_cnn_pack(long L, int ns, int npx, const double2* __restrict__ 
     }
 }
 
-// z = x + f (c_{2i} + i c_{2i+1}), f = 1 / *s (inv) or *s.
+// z = x + f (c_{2i} + i c_{2i+1}), f = 1 / *s (inv) or *s (1 / 0 taken as 0).
 __global__ void k_cnn_unpack_add(long L, int ns, int npx, const float* __restrict__ c, const double2* __restrict__ x,
                                  const double* __restrict__ s, int inv, double2* __restrict__ z) {
-    const double f = inv ? 1.0 / *s : *s;
+    const double sv = *s, f = inv ? (sv > 0.0 ? 1.0 / sv : 0.0) : sv;
     const long total = L * ns * npx;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
         const long li = k / npx;

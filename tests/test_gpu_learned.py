@@ -166,3 +166,15 @@ def test_training_gains_over_the_iterations_without_the_network(torch_dev):
             r_l, r_p = net.residual(net.solve(yd), yd), net.residual(xt, yd)
             print(f"[learned] residual learned / plain = {r_l / r_p:.3f}", flush=True)
             assert np.isfinite(r_l) and r_p > 0
+
+
+def test_zero_data_gives_exactly_zero(torch_dev):
+    """y = 0: A^H y = 0 and the data scale s = 0, so the prior's term s C(.)
+    vanishes and x = 0 solves every data-consistency step exactly."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, _, y = make_case(G32, 3, 93)
+    params = [(w, np.full_like(b, 0.1)) for w, b in si.cnn_init(6, 8, width=16)]
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=16, n_unroll=2, n_cg=4) as net:
+        x = net.solve(torch.zeros(plan.shape_y, dtype=torch.complex64, device=dev)).cpu().numpy()
+    assert np.all(x == 0)

@@ -119,3 +119,12 @@ def test_pack_unpack_round_trip():
     assert c.shape == (2, 6, 4, 5)
     assert np.allclose(c[:, 2], x[:, 1].real / 2.5) and np.allclose(c[:, 3], x[:, 1].imag / 2.5)
     assert np.allclose(lo.unpack(c, 2.5), x, rtol=1e-15, atol=0)
+
+
+def test_zero_data_gives_zero():
+    """b = 0: x = 0 solves every data-consistency step exactly, whatever the
+    network (its term is scaled by s = 0)."""
+    m, apply, b = tiny_system(23)
+    params = tiny_params(60)           # nonzero biases: C(0) != 0
+    x, _ = lo.unrolled_forward(np.zeros_like(b), apply, params, mu=0.5, n_unroll=3, n_cg=20)
+    assert np.all(x == 0)
