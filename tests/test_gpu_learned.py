@@ -178,3 +178,30 @@ def test_zero_data_gives_exactly_zero(torch_dev):
     with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=16, n_unroll=2, n_cg=4) as net:
         x = net.solve(torch.zeros(plan.shape_y, dtype=torch.complex64, device=dev)).cpu().numpy()
     assert np.all(x == 0)
+
+
+def test_cnn_two_shots_matches_oracle(torch_dev):
+    """Two shots (4 channels in and out): the 4-channel convolution instances
+    and the per-channel-pair weight-gradient kernel of the first and last
+    layers."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g = si.Geometry(n=32, n_slices=2, n_shots=2, n_coils=4, filt=3, lam=1e-3, n_irls=2, n_cg=3, phase_order=2,
+                    snr=30.0)
+    case, _, _ = make_case(g, 4, 94)
+    params = si.cnn_init(7, 4, width=16, out_scale=1.0)
+    with plan_for(torch, dev, g, case) as plan, smsm.Learned(plan, params, width=16) as net:
+        rng = np.random.default_rng(8)
+        inp = rng.standard_normal(net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        p64 = f64_params(params)
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), p64)
+        assert rel(out, ref) < 1e-5
+        rgin, rgrads = lo.cnn_backward(acts, p64, gout.astype(np.float64))
+        assert rel(gin.cpu().numpy(), rgin) < 1e-5
+        got = smsm.unflatten_params(grads, 4, 16)
+        for k in range(5):
+            assert rel(got[k][0], rgrads[k][0]) < 1e-5, k
+            assert rel(got[k][1], rgrads[k][1]) < 1e-5, k
