@@ -308,6 +308,12 @@ long smsm_learned_param_count(const smsm_learned* net);
 smsm_status smsm_learned_get_params(smsm_learned* net, float* params_host);
 smsm_status smsm_learned_set_params(smsm_learned* net, const float* params_host);
 
+/* on != 0: the convolutions read a BF16 copy of the weights (rounded to
+ * nearest even from the FP32 parameters, refreshed after every change; FP32
+ * accumulation, FP32 biases), gradients are taken with respect to those
+ * weights and applied to the FP32 parameters.  Default off.  Synchronous. */
+smsm_status smsm_learned_set_bf16(smsm_learned* net, int on);
+
 /* The network alone: out = C(in), in_dev and out_dev float [L][2Ns][n2][n1]. */
 smsm_status smsm_learned_cnn_forward(smsm_learned* net, const void* in_dev, void* out_dev, void* stream);
 /* Gradients of sum(gout * C(in)): gin_dev (same layout) and all parameter

@@ -159,3 +159,17 @@ def unrolled_loss_and_grads(b, apply_aha, params, mu: float, n_unroll: int, n_cg
             total[j] = (total[j][0] + gw, total[j][1] + gb)
         g = gz + (unpack(gin, 1.0 / s) if s > 0 else 0.0)   # residual path + d channels / d x = 1 / s
     return loss, total
+
+
+def bf16_round(w):
+    """FP32 values rounded to BF16 (8-bit significand) to nearest, ties to
+    even, returned as FP64: the weights the BF16 form of the network uses."""
+    bits = np.asarray(w, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_params(params):
+    """The network's parameters as the BF16 form uses them: weights rounded,
+    biases kept."""
+    return [(bf16_round(w), np.asarray(b, dtype=np.float64)) for w, b in params]

@@ -1287,23 +1287,42 @@ struct smsm_learned {
     double2 *g = nullptr, *wv = nullptr, *ax = nullptr, *xs = nullptr;
     double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] rr, [2] alpha, [3] beta, [8] loss num, [9] den
     float *wpart = nullptr, *wbpart = nullptr;  // weight-gradient chunk partials (k_wgrad_part)
+    bool bf16 = false;                 // convolutions read the BF16 copy of the weights
+    unsigned short* wb = nullptr;      // BF16 copy of params (refreshed after every change)
 };
 
 namespace {
 
 long lvec(const smsm_learned* Lr) { return (long)Lr->L * (Lr->nc / 2) * Lr->H * Lr->W; }
 
-smsm_status lconv(smsm_learned* Lr, int ci, int co, const float* in, const float* w, const float* bias, float* out,
+template <int COB, bool WB16>
+void lconv_k(smsm_learned* Lr, dim3 grid, int ci, int co, const float* in, const void* w, const float* bias,
+             float* out, int relu, bool bwd, hipStream_t st) {
+    if (bwd) hipLaunchKernelGGL((k_conv3x3<COB, 1, WB16>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+    else hipLaunchKernelGGL((k_conv3x3<COB, 0, WB16>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+}
+// One convolution of layer weights at offset woff (FP32 or, with bf16, the
+// BF16 copy); biases stay FP32.
+smsm_status lconv(smsm_learned* Lr, int ci, int co, const float* in, size_t woff, const float* bias, float* out,
                   int relu, bool bwd, hipStream_t st) {
     const int npx = Lr->H * Lr->W;
     const dim3 grid((npx + CNN_THREADS - 1) / CNN_THREADS, co % 8 == 0 ? co / 8 : co / 4, Lr->L);
+    const void* w = Lr->bf16 ? (const void*)(Lr->wb + woff) : (const void*)(Lr->params + woff);
     if (co % 8 == 0) {
-        if (bwd) hipLaunchKernelGGL((k_conv3x3<8, 1>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
-        else hipLaunchKernelGGL((k_conv3x3<8, 0>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+        if (Lr->bf16) lconv_k<8, true>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
+        else lconv_k<8, false>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
     } else {
-        if (bwd) hipLaunchKernelGGL((k_conv3x3<4, 1>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
-        else hipLaunchKernelGGL((k_conv3x3<4, 0>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+        if (Lr->bf16) lconv_k<4, true>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
+        else lconv_k<4, false>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
     }
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// Refresh the BF16 copy of the parameters (when the network uses it).
+smsm_status lrefresh_bf16(smsm_learned* Lr, hipStream_t st) {
+    if (!Lr->bf16) return SMSM_OK;
+    hipLaunchKernelGGL(k_to_bf16, vec_grid(), dim3(kThreads), 0, st, (long)Lr->nparam, Lr->params, Lr->wb);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -1311,7 +1330,7 @@ smsm_status lconv(smsm_learned* Lr, int ci, int co, const float* in, const float
 // act[0] -> act[1..5] (ReLU after layers 0..3).
 smsm_status lcnn_forward(smsm_learned* Lr, hipStream_t st) {
     for (int k = 0; k < smsm_learned::kDepth; ++k) {
-        smsm_status s = lconv(Lr, Lr->cin[k], Lr->cout[k], Lr->act[k], Lr->params + Lr->woff[k],
+        smsm_status s = lconv(Lr, Lr->cin[k], Lr->cout[k], Lr->act[k], Lr->woff[k],
                               Lr->params + Lr->boff[k], Lr->act[k + 1], k < smsm_learned::kDepth - 1, false, st);
         if (s) return s;
     }
@@ -1344,7 +1363,7 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
         }
         LAUNCH_CHECK();
         float* dst = k > 0 ? bufs[k & 1] : gin;
-        smsm_status s = lconv(Lr, Lr->cout[k], Lr->cin[k], g, Lr->params + Lr->woff[k], nullptr, dst, 0, true, st);
+        smsm_status s = lconv(Lr, Lr->cout[k], Lr->cin[k], g, Lr->woff[k], nullptr, dst, 0, true, st);
         if (s) return s;
         if (k > 0) {
             hipLaunchKernelGGL(k_relu_bwd, vec_grid(), dim3(kThreads), 0, st, nh, dst, Lr->act[k]);
@@ -1531,6 +1550,7 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     }
     const size_t nchunk = (size_t)Lr->L * wg_chunks(Lr->H, Lr->W);
     const size_t owp = cv.take<float>(nchunk * maxcc * 9), owb = cv.take<float>(nchunk * maxco);
+    const size_t ow16 = cv.take<unsigned short>(off);
     if (hipMalloc(&Lr->arena, cv.off) != hipSuccess) {
         delete Lr;
         return SMSM_E_NOMEM;
@@ -1552,6 +1572,7 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     Lr->scal = (double*)(base + oscal);
     Lr->wpart = (float*)(base + owp);
     Lr->wbpart = (float*)(base + owb);
+    Lr->wb = (unsigned short*)(base + ow16);
     bool ok = hipMemcpy(Lr->params, params_host, off * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(Lr->am, 0, off * sizeof(float)) == hipSuccess;
     ok = ok && hipMemset(Lr->av, 0, off * sizeof(float)) == hipSuccess;
@@ -1587,7 +1608,19 @@ smsm_status smsm_learned_set_params(smsm_learned* Lr, const float* host) {
     Lr->adam_t = 0;
     const bool ok = hipMemset(Lr->am, 0, Lr->nparam * sizeof(float)) == hipSuccess &&
                     hipMemset(Lr->av, 0, Lr->nparam * sizeof(float)) == hipSuccess;
-    return ok ? SMSM_OK : SMSM_E_DEVICE;
+    if (!ok) return SMSM_E_DEVICE;
+    smsm_status s = lrefresh_bf16(Lr, nullptr);
+    if (s) return s;
+    return hipDeviceSynchronize() == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+smsm_status smsm_learned_set_bf16(smsm_learned* Lr, int on) {
+    if (!Lr) return SMSM_E_INVALID;
+    if (hipSetDevice(Lr->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
+    Lr->bf16 = on != 0;
+    smsm_status s = lrefresh_bf16(Lr, nullptr);
+    if (s) return s;
+    return hipDeviceSynchronize() == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
 }
 
 smsm_status smsm_learned_cnn_forward(smsm_learned* Lr, const void* in_dev, void* out_dev, void* stream) {
@@ -1662,7 +1695,7 @@ smsm_status smsm_learned_train_step(smsm_learned* Lr, const void* y_dev, const v
     hipLaunchKernelGGL(k_adam, vec_grid(), dim3(kThreads), 0, S(stream), (long)Lr->nparam, Lr->params, Lr->grads,
                        Lr->am, Lr->av, (float)lr, b1, b2, 1e-8f, c1, c2);
     LAUNCH_CHECK();
-    return SMSM_OK;
+    return lrefresh_bf16(Lr, S(stream));
 }
 
 smsm_status smsm_learned_residual(smsm_learned* Lr, const void* x_dev, const void* y_dev, double* res, void* stream) {

@@ -35,7 +35,7 @@ ABI_SYMBOLS = (
     "smsm_batch_destroy", "smsm_batch_streams", "smsm_learned_create", "smsm_learned_destroy",
     "smsm_learned_param_count", "smsm_learned_get_params", "smsm_learned_set_params", "smsm_learned_cnn_forward",
     "smsm_learned_cnn_backward", "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
-    "smsm_learned_residual",
+    "smsm_learned_residual", "smsm_learned_set_bf16",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
 
@@ -124,10 +124,11 @@ def lib() -> ctypes.CDLL:
         L.smsm_learned_gradients.argtypes = [vp, vp, vp, pd, pf, vp]
         L.smsm_learned_train_step.argtypes = [vp, vp, vp, ctypes.c_double, pd, vp]
         L.smsm_learned_residual.argtypes = [vp, vp, vp, pd, vp]
+        L.smsm_learned_set_bf16.argtypes = [vp, st]
         for name in ("smsm_learned_create", "smsm_learned_destroy", "smsm_learned_get_params",
                      "smsm_learned_set_params", "smsm_learned_cnn_forward", "smsm_learned_cnn_backward",
                      "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
-                     "smsm_learned_residual"):
+                     "smsm_learned_residual", "smsm_learned_set_bf16"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -529,6 +530,9 @@ class Learned:
         _check(lib().smsm_learned_set_params(self._h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
                "smsm_learned_set_params")
 
+    def set_bf16(self, on: bool = True):
+        _check(lib().smsm_learned_set_bf16(self._h, 1 if on else 0), "smsm_learned_set_bf16")
+
     def cnn_forward(self, inp, out=None, stream=None):
         import torch
         if out is None:
@@ -645,3 +649,7 @@ def smsm_learned_train_step(net: Learned, y, xt, lr: float, stream=None) -> floa
 
 def smsm_learned_residual(net: Learned, x, y, stream=None) -> float:
     return net.residual(x, y, stream)
+
+
+def smsm_learned_set_bf16(net: Learned, on: bool = True):
+    net.set_bf16(on)

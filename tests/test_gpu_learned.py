@@ -205,3 +205,39 @@ def test_cnn_two_shots_matches_oracle(torch_dev):
         for k in range(5):
             assert rel(got[k][0], rgrads[k][0]) < 1e-5, k
             assert rel(got[k][1], rgrads[k][1]) < 1e-5, k
+
+
+def test_bf16_weights_match_oracle(torch_dev):
+    """BF16 weights (rounded to nearest even), FP32 accumulation: network
+    outputs and gradients, and the unrolled gradients, against the oracle
+    run on the same rounded weights."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, x_true, y = make_case(G32, 5, 95)
+    params = si.cnn_init(9, 8, width=64, out_scale=1.0)
+    pb = lo.bf16_params(params)
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=64, n_unroll=3, n_cg=8,
+                                                              mu=0.8) as net:
+        net.set_bf16(True)
+        rng = np.random.default_rng(9)
+        inp = rng.standard_normal(net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), pb)
+        assert rel(out, ref) < 1e-5
+        assert rel(out, lo.cnn_forward(inp.astype(np.float64), f64_params(params))[0]) > 1e-4   # rounding is real
+        rgin, rgrads = lo.cnn_backward(acts, pb, gout.astype(np.float64))
+        assert rel(gin.cpu().numpy(), rgin) < 1e-5
+        got = smsm.unflatten_params(grads, 8, 64)
+        for k in range(5):
+            assert rel(got[k][0], rgrads[k][0]) < 1e-5, k
+        aha, (coils, masks, theta) = oracle_aha(case)
+        b = o.adjoint(y.astype(np.complex128), coils, masks, theta)
+        loss_ref, grads_ref = lo.unrolled_loss_and_grads(b, aha, pb, 0.8, 3, 8, x_true)
+        loss, grads = net.gradients(torch.from_numpy(y).to(dev), torch.from_numpy(x_true).to(dev))
+        assert abs(loss - loss_ref) < 1e-5 * loss_ref
+        got = smsm.unflatten_params(grads, 8, 64)
+        for k in range(5):
+            assert rel(got[k][0], grads_ref[k][0]) < 1e-4, k
+            assert rel(got[k][1], grads_ref[k][1]) < 1e-4, k

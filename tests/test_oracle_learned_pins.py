@@ -128,3 +128,18 @@ def test_zero_data_gives_zero():
     params = tiny_params(60)           # nonzero biases: C(0) != 0
     x, _ = lo.unrolled_forward(np.zeros_like(b), apply, params, mu=0.5, n_unroll=3, n_cg=20)
     assert np.all(x == 0)
+
+
+def test_bf16_rounding_closed_forms():
+    # exactly representable values are unchanged
+    v = np.array([1.0, -2.5, 0.15625, 3.0 * 2 ** -20, 0.0], dtype=np.float32)
+    assert np.array_equal(lo.bf16_round(v), v.astype(np.float64))
+    # ties to even at the 8-bit significand: 1 + 2^-8 -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert lo.bf16_round(np.float32(1 + 2 ** -8)) == 1.0
+    assert lo.bf16_round(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6
+    # above a tie rounds up, below rounds down
+    assert lo.bf16_round(np.float32(1 + 2 ** -8 + 2 ** -20)) == 1 + 2 ** -7
+    assert lo.bf16_round(np.float32(1 + 2 ** -8 - 2 ** -20)) == 1.0
+    # relative error at most the unit roundoff of an 8-bit significand, 2^-8
+    x = np.random.default_rng(3).standard_normal(10000).astype(np.float32)
+    assert np.max(np.abs(lo.bf16_round(x) - x) / np.abs(x)) <= 2.0 ** -8
