@@ -165,7 +165,6 @@ def learned_measurement(torch, dev, plan, g, workload, n_train=64, n_eval=4, ste
     zero = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
     with smsm.Learned(plan, params, width=64, n_unroll=5, n_cg=10, mu=mu) as net, \
             smsm.Learned(plan, zero, width=64, n_unroll=5, n_cg=10, mu=mu) as net0:
-        net.set_bf16(True)          # BF16 weights, FP32 accumulation and master weights
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         losses = [net.train_step(*data[k % n_train], lr) for k in range(steps)]
@@ -185,7 +184,7 @@ def learned_measurement(torch, dev, plan, g, workload, n_train=64, n_eval=4, ste
             net.solve(held[0][0], x)
         torch.cuda.synchronize()
         t_solve = (time.perf_counter() - t0) / reps
-    return {"network": "5 x (residual k-space CNN 2Ns-64-64-64-64-2Ns, 3x3, ReLU, BF16 weights, FP32 "
+    return {"network": "5 x (residual k-space CNN 2Ns-64-64-64-64-2Ns, 3x3, ReLU, FP32 weights and "
                        f"accumulation + 10 FP64 CG data-consistency steps, mu={mu})",
             "training": f"{steps} Adam steps (lr {lr}) on {n_train} seeded instances, targets from the plain solver",
             "train_ms_per_step": round(t_train * 1e3, 2), "loss_first_last": [round(float(losses[0]), 4),
