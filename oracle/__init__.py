@@ -1,4 +1,6 @@
-"""FP64 CPU oracle for the SMS-MUSSELS IRLS solve.
+"""FP64 CPU oracles of SMS-MUSSELS: the IRLS solve (smsm_oracle), the
+augmented-Lagrangian solve (al_oracle) and the learned unrolled solver
+(learned_oracle).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
 baseline leg of the benchmark; never by the GPU library.

@@ -30,8 +30,14 @@ What it computes (Mani et al., "SMS MUSSELS", arXiv 1901.01893):
 Pins: every operator above, the weights, one CG step, the lam = 0 solve and
 the monotone decrease of the smoothed objective are checked against
 definitions, closed forms and brute force in tests/test_oracle_pins.py.  The
-whole fixed-iteration solve at the workload sizes is parity unpinned beyond
-those parts: its own iteration is the reference.
+whole solve is pinned in tests/test_oracle_solve_pins.py: it equals a dense
+brute-force IRLS written from the readings (to rounding, 2e-15), its fixed
+point at a fixed eps zeroes the smoothed objective's gradient, it recovers
+noiseless low-rank data that least squares cannot, and run long it reaches
+the minimiser of Eq. 10 that the augmented-Lagrangian oracle certifies by the
+subgradient optimality condition; ten planted mistakes each fail one of
+these.  At the workload sizes the fixed-count iteration is its own reference
+beyond those pins.
 
 Readings taken where the paper is silent (every one listed in the design
 notes): centred unitary DFT; CAIPI phase exp(-2 pi i s_l (j2 - N2/2)) on the
