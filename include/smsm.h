@@ -34,6 +34,12 @@
  *
  * Pointers named *_dev are device pointers of the device that was current
  * when the plan was created; host pointers are read during the call only.
+ * Memory: the plan holds only what smsm_plan_create derives (the coil maps,
+ * transform and phase tables, the status word).  Every buffer a solve or an
+ * operator chain writes (the CG vectors, the Gram, weight and band tables,
+ * partial sums) lives in a caller-owned workspace of smsm_workspace_bytes()
+ * bytes bound with smsm_set_workspace; no entry point that runs kernels
+ * allocates device memory.
  * Every entry point that takes a stream enqueues its work on that stream
  * (NULL = the default stream) and returns without waiting; kernel faults
  * show at the caller's next synchronisation.  A plan is not re-entrant: use
@@ -59,7 +65,8 @@ typedef enum {
     SMSM_E_UNSUPPORTED = -2,  /* valid but not implemented (e.g. a sampling pattern) */
     SMSM_E_NOMEM = -3,        /* device allocation failed in plan creation */
     SMSM_E_DEVICE = -4,       /* a HIP runtime call failed */
-    SMSM_E_NUMERIC = -5       /* NaN/Inf met in the CG recurrences (smsm_plan_status) */
+    SMSM_E_NUMERIC = -5,      /* NaN/Inf met in the CG recurrences (smsm_plan_status) */
+    SMSM_E_NOT_CONVERGED = -6 /* the weights iteration hit ns_max_iter (smsm_plan_status) */
 } smsm_status;
 
 typedef struct {
@@ -99,8 +106,10 @@ typedef struct {
  * 1 where shot i acquires ky line j2; this build supports the interleaved
  * pattern of Eq. 2 only (j2 % Ns == i) and returns SMSM_E_UNSUPPORTED for
  * any other.  caipi_shift: host [L] shift of each slice as a fraction of
- * the FOV (NULL = l/L).  All device memory the plan needs is allocated here
- * and released by smsm_plan_destroy.  On failure *out is NULL.
+ * the FOV (NULL = l/L).  The plan's own device memory (coil maps widened to
+ * complex128, transform and phase tables: smsm_plan_device_bytes) is
+ * allocated here and released by smsm_plan_destroy; the plan has no
+ * workspace until smsm_set_workspace binds one.  On failure *out is NULL.
  */
 smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* params,
                              const void* coil_maps_dev, const uint8_t* shot_mask,
@@ -109,8 +118,25 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
 /* Release the plan and its device memory (synchronises the device first). NULL is a no-op. */
 smsm_status smsm_plan_destroy(smsm_plan* plan);
 
-/* Bytes of device memory the plan holds. */
+/* Bytes of device memory the plan holds (not counting the workspace). */
 size_t smsm_plan_device_bytes(const smsm_plan* plan);
+
+/* Bytes of device workspace a plan needs: about 7 c128 vectors of
+ * [L][Ns][n2][n1], the folded data, the image-domain Hankel kernel and the
+ * band, Gram and weight tables (about 250 MB for 256 x 256, 3 slices, 4
+ * shots, 32 coils, 7 x 7 filter).  0 for a null plan. */
+size_t smsm_workspace_bytes(const smsm_plan* plan);
+
+/* Bind caller-owned device memory (e.g. a torch tensor) as the plan's
+ * workspace: ws_dev on the plan's device, 256-byte aligned, bytes >=
+ * smsm_workspace_bytes(plan); NULL unbinds.  The library neither frees nor
+ * clears it; its contents between calls are the library's (weights loaded by
+ * smsm_set_weights live there and are forgotten when another workspace is
+ * bound).  The caller keeps it allocated while the plan may use it, and while
+ * a batch built on the plan exists.  Entry points that run kernels return
+ * SMSM_E_INVALID while no workspace is bound.  Errors: SMSM_E_INVALID for a
+ * null plan, a short or misaligned buffer. */
+smsm_status smsm_set_workspace(smsm_plan* plan, void* ws_dev, size_t bytes);
 
 /* Replace the solver parameters of an existing plan (same geometry). */
 smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params);
@@ -118,14 +144,18 @@ smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params);
 /*
  * The IRLS solve.  y_dev: c64 [Ns][Nc][n2][n1]; x_dev: c64 (or c128 with
  * SMSM_FLAG_X_C128) [L][Ns][n2][n1]; y and x must not overlap.  All work is
- * asynchronous on `stream`; no device memory is allocated.
+ * asynchronous on `stream` and runs in the bound workspace (SMSM_E_INVALID
+ * without one); no device memory is allocated.
  */
 smsm_status smsm_solve(smsm_plan* plan, const void* y_dev, void* x_dev, void* stream);
 
 /*
- * Numeric status of the last solve: SMSM_E_NUMERIC if a CG step met a
- * non-finite or non-positive curvature, else SMSM_OK.  Synchronises the
- * device and clears the flag.
+ * Numeric status since the last call: SMSM_E_NUMERIC if a CG step met a
+ * non-finite or non-positive curvature (NaN or Inf in y, for instance),
+ * else SMSM_E_NOT_CONVERGED if a weights iteration of a solve or of
+ * smsm_weights left a slice above the tolerance after ns_max_iter steps
+ * (its W is then the last iterate), else SMSM_OK.  Synchronises the device
+ * and clears both flags.
  */
 smsm_status smsm_plan_status(smsm_plan* plan);
 
@@ -144,11 +174,11 @@ const char* smsm_status_string(smsm_status s);
  * several times (e.g. the diffusion directions of one slice group): its solves
  * share its scratch memory, so they all run in entry order on the stream of
  * its first entry, while distinct plans are dealt round-robin to the streams.
- * Ownership: the plans stay alive and unused by other calls while the batch
- * exists; y_devs/x_devs (layouts as for smsm_solve; every x distinct) are
+ * Ownership: the plans stay alive, with the workspaces bound at capture, and
+ * unused by other calls while the batch exists; y_devs/x_devs (layouts as for smsm_solve; every x distinct) are
  * baked into the graph, so the caller keeps them allocated and refills y_devs
  * before each launch.  Per-launch kernel timing must be off on every plan.
- * Errors: SMSM_E_INVALID (null plan or buffer, n < 1,
+ * Errors: SMSM_E_INVALID (null plan or buffer, a plan without a workspace, n < 1,
  * n_streams outside [1, 64], plans on different devices, timing on),
  * SMSM_E_NOMEM, SMSM_E_DEVICE (stream, capture or instantiation failure), or
  * the first error a captured solve returned.
@@ -191,8 +221,9 @@ smsm_status smsm_gram(smsm_plan* plan, const void* x_dev, void* g_dev, void* str
 /* W_l = (G_l + eps_l I)^(-1/2): G c128 [L][K][K] -> W c128 [L][K][K], by a
  * scaled coupled Newton-Schulz iteration run until ||I - Z Y||_F < 1e-10 or
  * for ns_max_iter steps (condition numbers up to about 1e8 converge within
- * the default cap).  eps: host [L]; eps_l <= 0 gives W_l = 0 (unregularised
- * slice).  Synchronises `stream`. */
+ * the default cap; a slice still above the tolerance at the cap sets the
+ * SMSM_E_NOT_CONVERGED flag of smsm_plan_status).  eps: host [L]; eps_l <= 0
+ * gives W_l = 0 (unregularised slice).  Synchronises `stream`. */
 smsm_status smsm_weights(smsm_plan* plan, const void* g_dev, const double* eps,
                          void* w_dev, void* stream);
 
@@ -287,9 +318,10 @@ smsm_status smsm_kernel_timer_read(smsm_plan* plan, double* total_ms, int* launc
  *
  * Parameters (host layout, float32): per layer, weights [co][ci][3][3] then
  * bias [co], layers in order.  The object holds the parameters, gradients,
- * Adam moments and a workspace for the plan's geometry, and uses the plan's
- * buffers: the plan must outlive the object, and calls on one plan (solver
- * or learned) must not overlap.
+ * Adam moments and buffers for the plan's geometry, and uses the plan's
+ * workspace: the plan must outlive the object and have a workspace bound
+ * when the object solves (SMSM_E_INVALID otherwise), and calls on one plan
+ * (solver or learned) must not overlap.
  * Requires 2 Ns to be a multiple of 4 (SMSM_E_UNSUPPORTED otherwise).
  * Vectors: y_dev c64 [Ns][Nc][n2][n1]; x_dev, xt_dev c128 [L][Ns][n2][n1]. */
 typedef struct smsm_learned smsm_learned;

@@ -35,6 +35,12 @@ int ilog2(int v) {
     return l;
 }
 
+// Offsets (bytes from the workspace base) of the buffers a solve writes.
+struct WsLayout {
+    size_t x, b, r, p, q, h1, h2, ytil, G, W, Y0, Y1, Z0, Z1, T, Kc, Khat, Dside, Dx, crow, ccol, ccorner, Dhat,
+        pcol, prow, gpart, gC, grow, gcol, gcor, pr, pq, part0, part1, sigma, eps, wscale, epsin, nsmu, done, cgs;
+};
+
 }  // namespace
 
 struct smsm_plan {
@@ -56,12 +62,17 @@ struct smsm_plan {
     size_t lds_rows = 0, lds_col = 0, lds_gram = 0, lds_gram_lines = 0;
     bool have_weights = false;
     bool khat_f32 = false;   // Khat, Dhat and Dx were last built as complex64 (SMSM_FLAG_REG_F32)
-    void* arena = nullptr;
+    void* arena = nullptr;   // plan-owned: what creation derives (coil maps, tables, status word)
     size_t bytes = 0;
-    // device buffers
+    void* ws = nullptr;      // caller-owned workspace (every buffer a solve writes), or null
+    size_t ws_bytes = 0;     // bytes the workspace must hold
+    WsLayout wo{};           // offsets of the scratch buffers in the workspace
+    // device buffers (plan arena)
     double2* ST = nullptr;                    // coils [L][Nc][n1][n2], complex128
     double2 *tw1 = nullptr, *tw2 = nullptr, *twM = nullptr;
     double2 *theta = nullptr, *tau = nullptr;
+    int* flags = nullptr;    // numeric status: [0] CG curvature non-finite or <= 0, [1] weights not converged
+    // device buffers (workspace)
     double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
@@ -71,7 +82,7 @@ struct smsm_plan {
     double *pr = nullptr, *pq = nullptr, *bpart = nullptr, *part0 = nullptr, *part1 = nullptr, *sigma = nullptr, *eps = nullptr;
     double *wscale = nullptr, *epsin = nullptr, *nsmu = nullptr;
     double* cgs = nullptr;   // CG scalars: |r|^2 of the last three residuals [0..2]; the last step length [8]
-    int *done = nullptr, *flags = nullptr;
+    int* done = nullptr;
 
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
@@ -439,7 +450,8 @@ smsm_status chain_weights(smsm_plan* P, const double2* G, const double* src, dou
     }
     const long tot = (long)g.L * g.K * g.K;
     hipLaunchKernelGGL(k_ns_finish, dim3((int)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, g.K,
-                       KP, g.L, P->Z0, P->Z1, P->done + (size_t)(nit + 1) * g.L, P->wscale, P->W);
+                       KP, g.L, P->Z0, P->Z1, P->done + (size_t)(nit + 1) * g.L, P->done + (size_t)nit * g.L,
+                       P->wscale, P->W, P->flags);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
@@ -472,6 +484,37 @@ smsm_status chain_lmax(smsm_plan* P, const double2* G, double* lmax, hipStream_t
     return SMSM_OK;
 }
 
+// Point the plan's scratch buffers into the workspace at `base` (null: none).
+void bind_workspace(smsm_plan* P, void* base) {
+    P->ws = base;
+    char* c = static_cast<char*>(base);
+    const WsLayout& w = P->wo;
+    auto d2 = [&](size_t o) { return c ? (double2*)(c + o) : nullptr; };
+    auto d1 = [&](size_t o) { return c ? (double*)(c + o) : nullptr; };
+    P->x = d2(w.x); P->b = d2(w.b); P->r = d2(w.r); P->p = d2(w.p); P->q = d2(w.q);
+    P->h1 = d2(w.h1); P->h2 = d2(w.h2); P->ytil = d2(w.ytil);
+    P->G = d2(w.G); P->W = d2(w.W); P->Y0 = d2(w.Y0); P->Y1 = d2(w.Y1);
+    P->Z0 = d2(w.Z0); P->Z1 = d2(w.Z1); P->T = d2(w.T);
+    P->Kc = d2(w.Kc); P->Khat = d2(w.Khat); P->Dside = d2(w.Dside); P->Dx = d2(w.Dx);
+    P->crow = d2(w.crow); P->ccol = d2(w.ccol); P->ccorner = d2(w.ccorner); P->Dhat = d2(w.Dhat);
+    P->pcol = d2(w.pcol); P->prow = d2(w.prow);
+    P->gpart = d2(w.gpart); P->gC = d2(w.gC); P->grow = d2(w.grow); P->gcol = d2(w.gcol); P->gcor = d2(w.gcor);
+    P->pr = d1(w.pr); P->pq = d1(w.pq); P->part0 = d1(w.part0); P->part1 = d1(w.part1);
+    P->bpart = c ? P->pq + P->npc : nullptr;   // band partials follow the column-pass partials
+    P->sigma = d1(w.sigma); P->eps = d1(w.eps); P->wscale = d1(w.wscale); P->epsin = d1(w.epsin);
+    P->nsmu = d1(w.nsmu);
+    P->done = c ? (int*)(c + w.done) : nullptr;
+    P->cgs = d1(w.cgs);
+    // the weight tables of an earlier workspace are not in this one
+    P->have_weights = false;
+}
+
+// Entry points that run kernels on the plan's scratch need a bound workspace.
+smsm_status ready(smsm_plan* P) {
+    if (!P || !P->ws) return SMSM_E_INVALID;
+    return hipSetDevice(P->dev) == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+}
+
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     const char* pa = static_cast<const char*>(a);
     const char* pb = static_cast<const char*>(b);
@@ -490,6 +533,7 @@ const char* smsm_status_string(smsm_status s) {
         case SMSM_E_NOMEM: return "device allocation failed";
         case SMSM_E_DEVICE: return "HIP runtime error";
         case SMSM_E_NUMERIC: return "non-finite or non-positive CG curvature";
+        case SMSM_E_NOT_CONVERGED: return "weights iteration did not converge within ns_max_iter";
     }
     return "unknown status";
 }
@@ -568,7 +612,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
             P->lds_colfast <= (size_t)max_lds)
             P->col_fast = k;
 
-    // device memory layout
+    // device memory: the plan arena holds what creation derives; every buffer
+    // a solve or operator chain writes lives in the caller's workspace
     const size_t nvec = (size_t)L * Ns * n2 * n1;
     const size_t KK = (size_t)L * g.K * g.K;
     const size_t KKP = (size_t)L * P->KP * P->KP;
@@ -579,36 +624,40 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oST = cv.take<double2>((size_t)L * Nc * n1 * n2);
     const size_t otw1 = cv.take<double2>(n1), otw2 = cv.take<double2>(n2), otwM = cv.take<double2>(g.M);
     const size_t oth = cv.take<double2>((size_t)L * n2), otau = cv.take<double2>((size_t)Ns * n2);
-    const size_t ox = cv.take<double2>(nvec), ob = cv.take<double2>(nvec), orr = cv.take<double2>(nvec);
-    const size_t op = cv.take<double2>(nvec), oq = cv.take<double2>(nvec);
-    const size_t oh1 = cv.take<double2>(nvec), oh2 = cv.take<double2>(nvec);
-    const size_t oyt = cv.take<double2>((size_t)Ns * Nc * n1 * g.M);
-    const size_t oG = cv.take<double2>(KK), oW = cv.take<double2>(KK);
-    const size_t oY0 = cv.take<double2>(KKP), oY1 = cv.take<double2>(KKP);
-    const size_t oZ0 = cv.take<double2>(KKP), oZ1 = cv.take<double2>(KKP), oT = cv.take<double2>(KKP);
-    const size_t oKc = cv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
-    const size_t oKh = cv.take<double2>((size_t)L * Ns * (Ns + 1) / 2 * n1 * n2);   // Hermitian pairs j <= i
-    const size_t oD = cv.take<double2>(ntab);
-    const size_t oDx = cv.take<double2>(ntab * g.e);
-    const size_t ocrow = cv.take<double2>((size_t)g.B * 2 * g.e * n1);
-    const size_t occol = cv.take<double2>(nds * g.B * 2 * g.e * n2);
-    const size_t ocorner = cv.take<double2>((size_t)g.B * 4 * g.e * g.e);
-    const size_t oDhat = cv.take<double2>((size_t)L * 2 * g.e * Ns * g.nc * Ns * n1);
-    const size_t opcol = cv.take<double2>((size_t)g.B * 4 * g.e * n2);
-    const size_t oprow = cv.take<double2>((size_t)g.B * 4 * g.e * n1);
     const size_t ofx = cv.take<double2>((size_t)n1 * P->np_band), ofinv = cv.take<double2>((size_t)n1 * HYB_MAX_E2);
-    const size_t ogp = cv.take<double2>((size_t)L * g.npairs * n1 * g.nc), ogC = cv.take<double2>(nper);
-    const size_t ogr = cv.take<double2>(nper * 2 * g.e), ogc = cv.take<double2>(nper * 2 * g.e);
-    const size_t ogk = cv.take<double2>(nper * 4 * g.e * g.e);
+    const size_t oflags = cv.take<int>(4);
     P->npc = P->col_fast >= 0 ? n1 : kVecBlocks;
+    Carver wv;
+    WsLayout& w = P->wo;
+    w.x = wv.take<double2>(nvec); w.b = wv.take<double2>(nvec); w.r = wv.take<double2>(nvec);
+    w.p = wv.take<double2>(nvec); w.q = wv.take<double2>(nvec);
+    w.h1 = wv.take<double2>(nvec); w.h2 = wv.take<double2>(nvec);
+    w.ytil = wv.take<double2>((size_t)Ns * Nc * n1 * g.M);
+    w.G = wv.take<double2>(KK); w.W = wv.take<double2>(KK);
+    w.Y0 = wv.take<double2>(KKP); w.Y1 = wv.take<double2>(KKP);
+    w.Z0 = wv.take<double2>(KKP); w.Z1 = wv.take<double2>(KKP); w.T = wv.take<double2>(KKP);
+    w.Kc = wv.take<double2>((size_t)L * Ns * Ns * g.nc * g.nc);
+    w.Khat = wv.take<double2>((size_t)L * Ns * (Ns + 1) / 2 * n1 * n2);   // Hermitian pairs j <= i
+    w.Dside = wv.take<double2>(ntab);
+    w.Dx = wv.take<double2>(ntab * g.e);
+    w.crow = wv.take<double2>((size_t)g.B * 2 * g.e * n1);
+    w.ccol = wv.take<double2>(nds * g.B * 2 * g.e * n2);
+    w.ccorner = wv.take<double2>((size_t)g.B * 4 * g.e * g.e);
+    w.Dhat = wv.take<double2>((size_t)L * 2 * g.e * Ns * g.nc * Ns * n1);
+    w.pcol = wv.take<double2>((size_t)g.B * 4 * g.e * n2);
+    w.prow = wv.take<double2>((size_t)g.B * 4 * g.e * n1);
+    w.gpart = wv.take<double2>((size_t)L * g.npairs * n1 * g.nc); w.gC = wv.take<double2>(nper);
+    w.grow = wv.take<double2>(nper * 2 * g.e); w.gcol = wv.take<double2>(nper * 2 * g.e);
+    w.gcor = wv.take<double2>(nper * 4 * g.e * g.e);
     // partial sums: |r|^2 ring [3][npr]; Re <p, N p> [npc column pass | band]
-    const size_t opr = cv.take<double>(3 * (size_t)P->npr);
-    const size_t opq = cv.take<double>((size_t)P->npc + (size_t)band_items(g) * L);
-    const size_t onp0 = cv.take<double>((size_t)L * P->npmax), onp1 = cv.take<double>((size_t)L * P->npmax);
-    const size_t osig = cv.take<double>(L), oeps = cv.take<double>(L), ows = cv.take<double>(L);
-    const size_t oei = cv.take<double>(L), onsmu = cv.take<double>((size_t)P->ns_iters * L);
-    const size_t odone = cv.take<int>((size_t)(P->ns_iters + 2) * L), oflags = cv.take<int>(4);
-    const size_t ocgs = cv.take<double>(16);
+    w.pr = wv.take<double>(3 * (size_t)P->npr);
+    w.pq = wv.take<double>((size_t)P->npc + (size_t)band_items(g) * L);
+    w.part0 = wv.take<double>((size_t)L * P->npmax); w.part1 = wv.take<double>((size_t)L * P->npmax);
+    w.sigma = wv.take<double>(L); w.eps = wv.take<double>(L); w.wscale = wv.take<double>(L);
+    w.epsin = wv.take<double>(L); w.nsmu = wv.take<double>((size_t)P->ns_iters * L);
+    w.done = wv.take<int>((size_t)(P->ns_iters + 2) * L);
+    w.cgs = wv.take<double>(16);
+    P->ws_bytes = (wv.off + 255) & ~size_t(255);
 
     P->bytes = cv.off;
     if (hipMalloc(&P->arena, P->bytes) != hipSuccess) { delete P; return SMSM_E_NOMEM; }
@@ -616,33 +665,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->ST = (double2*)(base + oST);
     P->tw1 = (double2*)(base + otw1); P->tw2 = (double2*)(base + otw2); P->twM = (double2*)(base + otwM);
     P->theta = (double2*)(base + oth); P->tau = (double2*)(base + otau);
-    P->x = (double2*)(base + ox); P->b = (double2*)(base + ob); P->r = (double2*)(base + orr);
-    P->p = (double2*)(base + op); P->q = (double2*)(base + oq);
-    P->h1 = (double2*)(base + oh1); P->h2 = (double2*)(base + oh2); P->ytil = (double2*)(base + oyt);
-    P->G = (double2*)(base + oG); P->W = (double2*)(base + oW);
-    P->Y0 = (double2*)(base + oY0); P->Y1 = (double2*)(base + oY1);
-    P->Z0 = (double2*)(base + oZ0); P->Z1 = (double2*)(base + oZ1); P->T = (double2*)(base + oT);
-    P->Kc = (double2*)(base + oKc); P->Khat = (double2*)(base + oKh); P->Dside = (double2*)(base + oD); P->Dx = (double2*)(base + oDx);
-    P->crow = (double2*)(base + ocrow); P->ccol = (double2*)(base + occol); P->ccorner = (double2*)(base + ocorner);
-    P->Dhat = (double2*)(base + oDhat); P->pcol = (double2*)(base + opcol); P->prow = (double2*)(base + oprow);
     P->fx = (double2*)(base + ofx); P->finv = (double2*)(base + ofinv);
-    P->gpart = (double2*)(base + ogp); P->gC = (double2*)(base + ogC);
-    P->grow = (double2*)(base + ogr); P->gcol = (double2*)(base + ogc); P->gcor = (double2*)(base + ogk);
-    P->pr = (double*)(base + opr); P->pq = (double*)(base + opq); P->part0 = (double*)(base + onp0);
-    P->bpart = P->pq + P->npc;   // band partials follow the column-pass partials
-    P->part1 = (double*)(base + onp1);
-    P->sigma = (double*)(base + osig); P->eps = (double*)(base + oeps); P->wscale = (double*)(base + ows);
-    P->epsin = (double*)(base + oei); P->nsmu = (double*)(base + onsmu);
-    P->done = (int*)(base + odone); P->flags = (int*)(base + oflags);
-    P->cgs = (double*)(base + ocgs);
-    {   // every carved pointer must be set before any launch
-        const void* carved[] = {P->ST, P->tw1, P->tw2, P->twM, P->theta, P->tau, P->x, P->b, P->r, P->p, P->q,
-                                P->h1, P->h2, P->ytil, P->G, P->W, P->Kc, P->Khat, P->Dside, P->Dx, P->Dhat,
-                                P->crow, P->ccol, P->ccorner, P->pcol, P->prow, P->fx, P->finv, P->pr, P->pq,
-                                P->bpart, P->part0, P->part1, P->cgs};
-        for (const void* c : carved)
-            if (!c) { (void)hipFree(P->arena); delete P; return SMSM_E_DEVICE; }
-    }
+    P->flags = (int*)(base + oflags);
 
     // host tables: twiddles, CAIPI phases, shot modulation
     std::vector<double2> t1, t2, tM, th((size_t)L * n2), ta((size_t)Ns * n2);
@@ -698,9 +722,6 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         ok = hipGetLastError() == hipSuccess;
     }
     if (ok) {
-        hipLaunchKernelGGL(k_zero_c128, dim3(512), dim3(kThreads), 0, st, (long)(L * Ns * Ns * g.nc * g.nc), P->Kc);
-        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)ntab, P->Dside);
-        hipLaunchKernelGGL(k_zero_c128, dim3(2048), dim3(kThreads), 0, st, (long)(ntab * g.e), P->Dx);
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kThreads), 0, st, 4L, P->flags);
 
         ok = hipGetLastError() == hipSuccess;
@@ -748,6 +769,16 @@ smsm_status smsm_plan_destroy(smsm_plan* plan) {
 
 size_t smsm_plan_device_bytes(const smsm_plan* plan) { return plan ? plan->bytes : 0; }
 
+size_t smsm_workspace_bytes(const smsm_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+smsm_status smsm_set_workspace(smsm_plan* plan, void* ws_dev, size_t bytes) {
+    if (!plan) return SMSM_E_INVALID;
+    if (ws_dev && (bytes < plan->ws_bytes || (reinterpret_cast<uintptr_t>(ws_dev) & 255u) != 0))
+        return SMSM_E_INVALID;
+    bind_workspace(plan, ws_dev);
+    return SMSM_OK;
+}
+
 smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params) {
     if (!plan) return SMSM_E_INVALID;
     smsm_status s = check_params(params);
@@ -761,6 +792,7 @@ smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params) {
 
 smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
     if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     const Geo& g = P->g;
     const size_t nvec = (size_t)g.L * g.Ns * g.n2 * g.n1;
     const size_t ny = (size_t)g.Ns * g.Nc * g.n2 * g.n1 * sizeof(float2);
@@ -841,15 +873,16 @@ smsm_status smsm_plan_status(smsm_plan* P) {
     if (!P) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
-    int h = 0;
-    if (hipMemcpy(&h, P->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SMSM_E_DEVICE;
-    const int zero = 0;
-    if (hipMemcpy(P->flags, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return SMSM_E_DEVICE;
-    return h ? SMSM_E_NUMERIC : SMSM_OK;
+    int h[2] = {0, 0};
+    if (hipMemcpy(h, P->flags, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return SMSM_E_DEVICE;
+    const int zero[2] = {0, 0};
+    if (hipMemcpy(P->flags, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return SMSM_E_DEVICE;
+    return h[0] ? SMSM_E_NUMERIC : (h[1] ? SMSM_E_NOT_CONVERGED : SMSM_OK);
 }
 
 smsm_status smsm_apply_A(smsm_plan* P, const void* x_dev, void* y_dev, void* stream) {
     if (!P || !x_dev || !y_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     const Geo& g = P->g;
     hipStream_t st = S(stream);
@@ -867,6 +900,7 @@ smsm_status smsm_apply_A(smsm_plan* P, const void* x_dev, void* y_dev, void* str
 
 smsm_status smsm_apply_AH(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
     if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     smsm_status s = chain_AH_hyb(P, (const float2*)y_dev, P->h2, st);
@@ -876,18 +910,21 @@ smsm_status smsm_apply_AH(smsm_plan* P, const void* y_dev, void* x_dev, void* st
 
 smsm_status smsm_apply_AHA(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, false, S(stream));
 }
 
 smsm_status smsm_gram(smsm_plan* P, const void* x_dev, void* g_dev, void* stream) {
     if (!P || !x_dev || !g_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_gram(P, (const double2*)x_dev, nullptr, (double2*)g_dev, S(stream));
 }
 
 smsm_status smsm_weights(smsm_plan* P, const void* g_dev, const double* eps, void* w_dev, void* stream) {
     if (!P || !g_dev || !eps || !w_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     const Geo& g = P->g;
     hipStream_t st = S(stream);
@@ -903,12 +940,14 @@ smsm_status smsm_weights(smsm_plan* P, const void* g_dev, const double* eps, voi
 
 smsm_status smsm_lambda_max(smsm_plan* P, const void* g_dev, void* lmax_dev, void* stream) {
     if (!P || !g_dev || !lmax_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_lmax(P, (const double2*)g_dev, (double*)lmax_dev, S(stream));
 }
 
 smsm_status smsm_set_weights(smsm_plan* P, const void* w_dev, void* stream) {
     if (!P || !w_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     const Geo& g = P->g;
     hipStream_t st = S(stream);
@@ -920,6 +959,7 @@ smsm_status smsm_set_weights(smsm_plan* P, const void* w_dev, void* stream) {
 
 smsm_status smsm_apply_reg(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_REG, true, S(stream));
@@ -927,6 +967,7 @@ smsm_status smsm_apply_reg(smsm_plan* P, const void* x_dev, void* out_dev, void*
 
 smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, void* stream) {
     if (!P || !x_dev || !out_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (!P->have_weights) return SMSM_E_INVALID;
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     return chain_normal(P, (const double2*)x_dev, (double2*)out_dev, COL_NORMAL, true, S(stream));
@@ -1024,6 +1065,7 @@ static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* con
     int distinct = 0;
     for (int k = 0; k < n; ++k) {
         if (!plans[k] || !y_devs[k] || !x_devs[k]) return SMSM_E_INVALID;
+        if (!plans[k]->ws) return SMSM_E_INVALID;            // the graph bakes in the bound workspace
         if (plans[k]->dev != plans[0]->dev) return SMSM_E_INVALID;
         if (plans[k]->kt_cap > 0) return SMSM_E_INVALID;      // no per-launch timing inside a graph
         owner[k] = -1;
@@ -1132,6 +1174,7 @@ smsm_status smsm_kernel_timer_read(smsm_plan* P, double* total_ms, int* launches
 
 smsm_status smsm_images_sos(smsm_plan* P, const void* x_dev, void* img_dev, void* stream) {
     if (!P || !x_dev || !img_dev) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     const Geo& g = P->g;
     hipStream_t st = S(stream);
@@ -1219,6 +1262,7 @@ smsm_status smsm_kernel_cost(const smsm_plan* P, int id, double* flops, double* 
 
 smsm_status smsm_launch_kernel(smsm_plan* P, int id, int reps, void* stream) {
     if (!P || reps < 0 || id < 0 || id > SMSM_KERNEL_BAND_EXTRACT) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
     if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     const bool reg = P->prm.lambda > 0.0 && P->have_weights;
@@ -1654,6 +1698,7 @@ smsm_status smsm_learned_cnn_backward(smsm_learned* Lr, const void* in_dev, cons
 
 smsm_status smsm_learned_solve(smsm_learned* Lr, const void* y_dev, void* x_dev, void* stream) {
     if (!Lr || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (!Lr->P->ws) return SMSM_E_INVALID;   // the plan's workspace carries the CG vectors
     if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     smsm_status s = lsetup(Lr, y_dev, st);
@@ -1667,6 +1712,7 @@ smsm_status smsm_learned_solve(smsm_learned* Lr, const void* y_dev, void* x_dev,
 smsm_status smsm_learned_gradients(smsm_learned* Lr, const void* y_dev, const void* xt_dev, double* loss,
                                    float* grads_host, void* stream) {
     if (!Lr || !y_dev || !xt_dev || !loss) return SMSM_E_INVALID;
+    if (!Lr->P->ws) return SMSM_E_INVALID;   // the plan's workspace carries the CG vectors
     if (hipSetDevice(Lr->dev) != hipSuccess) return SMSM_E_DEVICE;
     hipStream_t st = S(stream);
     smsm_status s = lsetup(Lr, y_dev, st);

@@ -248,13 +248,16 @@ __global__ void k_ns_start(int K, int KP, int L, const double* __restrict__ src,
 // W_l = wscale_l * Z_l (unpadded K x K), Z_l from the buffer the last
 // executed iteration wrote.
 __global__ void k_ns_finish(int K, int KP, int L, const double2* __restrict__ Z0, const double2* __restrict__ Z1,
-                            const int* __restrict__ last, const double* __restrict__ wscale,
-                            double2* __restrict__ W) {
+                            const int* __restrict__ last, const int* __restrict__ conv,
+                            const double* __restrict__ wscale, double2* __restrict__ W, int* __restrict__ flags) {
     const long total = (long)L * K * K;
     const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int l = (int)(idx / ((long)K * K));
     const int rem = (int)(idx - (long)l * K * K);
+    // conv[l]: slice l met the tolerance within the iteration cap (or is
+    // unregularised); otherwise the plan's status word records it
+    if (rem == 0 && !conv[l]) flags[1] = 1;
     const int i = rem / K, j = rem - i * K;
     const size_t o = (size_t)l * KP * KP + (size_t)i * KP + j;
     W[idx] = cscale((last[l] ? Z1 : Z0)[o], wscale[l]);

@@ -93,8 +93,9 @@ k_band_extract(int n1, int n2, int e, int np, const double2* __restrict__ pt, co
 //           of every workgroup forms alpha = *rr / sum(pq[0..npq)) before
 //           its own vector loads and shares it through shared memory (the
 //           same fixed-order sum everywhere, so all workgroups agree);
-//           rr == 0 (exact solution) gives alpha = 0, non-positive or
-//           non-finite curvature gives alpha = 0 and sets flags[0]; the
+//           rr == 0 (exact solution) gives alpha = 0, a non-finite |r|^2
+//           or a non-positive or non-finite curvature gives alpha = 0 and
+//           sets flags[0]; the
 //           first workgroup stores alpha in *alpha_out.
 // Thread layout: lane = ky (LY = min(64, n2) lanes per x, 64 / LY x per
 // step), so the natural band-column corrections of a lane's ky (shares
@@ -146,7 +147,9 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     if (MODE == 2 && wave == 0) {
         const double pq = wave_sum_partials(a.pq, a.npq, lane), rr = *a.rr;
         const double al = rr / pq;
-        const bool bad = rr > 0.0 && (!(pq > 0.0) || !isfinite(al));
+        // a non-finite |r|^2 (NaN or Inf reached the residual) is flagged, not
+        // taken for an exact solution
+        const bool bad = !isfinite(rr) || (rr > 0.0 && (!(pq > 0.0) || !isfinite(al)));
         const double alpha0 = (rr > 0.0 && !bad) ? al : 0.0;
         if (lane == 0) {
             alpha_sh = alpha0;

@@ -22,12 +22,14 @@ SMSM_E_UNSUPPORTED = -2
 SMSM_E_NOMEM = -3
 SMSM_E_DEVICE = -4
 SMSM_E_NUMERIC = -5
+SMSM_E_NOT_CONVERGED = -6
 SMSM_FLAG_X_C128 = 0x1
 SMSM_FLAG_REG_F32 = 0x2
 
 # Every entry point of include/smsm.h.
 ABI_SYMBOLS = (
-    "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_plan_set_params",
+    "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_workspace_bytes",
+    "smsm_set_workspace", "smsm_plan_set_params",
     "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
@@ -77,6 +79,10 @@ def lib() -> ctypes.CDLL:
         L.smsm_plan_destroy.restype = st
         L.smsm_plan_device_bytes.argtypes = [vp]
         L.smsm_plan_device_bytes.restype = ctypes.c_size_t
+        L.smsm_workspace_bytes.argtypes = [vp]
+        L.smsm_workspace_bytes.restype = ctypes.c_size_t
+        L.smsm_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
+        L.smsm_set_workspace.restype = st
         L.smsm_plan_set_params.argtypes = [vp, ctypes.POINTER(Params)]
         L.smsm_plan_set_params.restype = st
         L.smsm_solve.argtypes = [vp, vp, vp, vp]
@@ -165,11 +171,15 @@ def make_params(lam=1e-3, n_irls=10, n_cg=10, eps_frac=0.1, eps_decay=1.5, eps_f
 
 
 class Plan:
-    """A solver plan for one geometry (wraps smsm_plan_create / destroy)."""
+    """A solver plan for one geometry (wraps smsm_plan_create / destroy).
+
+    workspace: "auto" allocates a torch uint8 tensor of workspace_bytes() on
+    the coils' device and binds it (smsm_set_workspace); None leaves the plan
+    without one (bind it later with set_workspace)."""
 
     def __init__(self, n1: int, n2: int, n_slices: int, n_shots: int, n_coils: int, filt: int,
                  coils, masks: np.ndarray, shifts: Optional[Sequence[float]] = None,
-                 params: Optional[Params] = None, stream=None):
+                 params: Optional[Params] = None, stream=None, workspace="auto"):
         import torch
         self.geom = Geometry(n1, n2, n_slices, n_shots, n_coils, filt)
         self.params = params if params is not None else make_params()
@@ -195,6 +205,11 @@ class Plan:
             _stream_ptr(stream), ctypes.byref(out))
         _check(st, "smsm_plan_create")
         self._h = out
+        self._ws = None
+        if isinstance(workspace, str) and workspace == "auto":
+            self.set_workspace(torch.empty(self.workspace_bytes(), dtype=torch.uint8, device=coils.device))
+        elif workspace is not None:
+            self.set_workspace(workspace)
 
     # -- lifecycle ----------------------------------------------------------
     def close(self):
@@ -214,9 +229,25 @@ class Plan:
     def __exit__(self, *a):
         self.close()
 
-    @property
     def device_bytes(self) -> int:
+        """Device memory the plan holds (not counting its workspace)."""
         return int(lib().smsm_plan_device_bytes(self._h))
+
+    def workspace_bytes(self) -> int:
+        return int(lib().smsm_workspace_bytes(self._h))
+
+    def set_workspace(self, ws):
+        """Bind a contiguous device tensor of at least workspace_bytes() bytes
+        (kept referenced here while bound); None unbinds."""
+        if ws is None:
+            _check(lib().smsm_set_workspace(self._h, None, 0), "smsm_set_workspace")
+            self._ws = None
+            return
+        if not ws.is_cuda or not ws.is_contiguous():
+            raise ValueError("workspace: a contiguous device tensor")
+        nbytes = ws.numel() * ws.element_size()
+        _check(lib().smsm_set_workspace(self._h, ctypes.c_void_p(ws.data_ptr()), nbytes), "smsm_set_workspace")
+        self._ws = ws
 
     def set_params(self, params: Params):
         _check(lib().smsm_plan_set_params(self._h, ctypes.byref(params)), "smsm_plan_set_params")
@@ -336,90 +367,31 @@ class Plan:
         return f.value, b.value
 
 
-# Flat names mirroring the C ABI.
-def smsm_plan_create(n1, n2, n_slices, n_shots, n_coils, filt, coils, masks, shifts=None, params=None,
-                     stream=None) -> Plan:
-    return Plan(n1, n2, n_slices, n_shots, n_coils, filt, coils, masks, shifts, params, stream)
-
-
-def smsm_plan_destroy(plan: Plan):
-    plan.close()
-
-
-def smsm_solve(plan: Plan, y, out=None, stream=None):
-    return plan.solve(y, out, stream)
-
-
-def smsm_plan_status(plan: Plan) -> int:
-    return plan.status()
-
-
-def smsm_apply_A(plan: Plan, x, out=None, stream=None):
-    return plan.apply_A(x, out, stream)
-
-
-def smsm_apply_AH(plan: Plan, y, out=None, stream=None):
-    return plan.apply_AH(y, out, stream)
-
-
-def smsm_apply_AHA(plan: Plan, x, out=None, stream=None):
-    return plan.apply_AHA(x, out, stream)
-
-
-def smsm_gram(plan: Plan, x, out=None, stream=None):
-    return plan.gram(x, out, stream)
-
-
-def smsm_weights(plan: Plan, G, eps, out=None, stream=None):
-    return plan.weights(G, eps, out, stream)
-
-
-def smsm_lambda_max(plan: Plan, G, stream=None):
-    return plan.lambda_max(G, stream)
-
-
-def smsm_set_weights(plan: Plan, W, stream=None):
-    plan.set_weights(W, stream)
-
-
-def smsm_apply_reg(plan: Plan, x, out=None, stream=None):
-    return plan.apply_reg(x, out, stream)
-
-
-def smsm_apply_normal(plan: Plan, x, out=None, stream=None):
-    return plan.apply_normal(x, out, stream)
-
-
-def smsm_launch_kernel(plan: Plan, name: str, reps: int = 1, stream=None):
-    plan.launch_kernel(name, reps, stream)
-
-
-def smsm_kernel_cost(plan: Plan, name: str):
-    return plan.kernel_cost(name)
-
-
-def smsm_images_sos(plan: Plan, x, out=None, stream=None):
-    return plan.images_sos(x, out, stream)
-
-
-def smsm_kernel_timer_start(plan: Plan, name: str, capacity: int, stride: int = 1):
-    plan.kernel_timer_start(name, capacity, stride)
-
-
-def smsm_kernel_timer_read(plan: Plan):
-    return plan.kernel_timer_read()
-
-
-def smsm_plan_device_bytes(plan: Plan) -> int:
-    return plan.device_bytes()
-
-
-def smsm_plan_set_params(plan: Plan, params: Params):
-    plan.set_params(params)
-
-
-def smsm_status_string(status: int) -> str:
-    return status_string(status)
+# Flat names mirroring the C ABI: each is the marshalling method itself, taking
+# the plan first (smsm_solve(plan, y) is plan.solve(y)).
+smsm_plan_create = Plan
+smsm_plan_destroy = Plan.close
+smsm_plan_device_bytes = Plan.device_bytes
+smsm_workspace_bytes = Plan.workspace_bytes
+smsm_set_workspace = Plan.set_workspace
+smsm_plan_set_params = Plan.set_params
+smsm_solve = Plan.solve
+smsm_plan_status = Plan.status
+smsm_apply_A = Plan.apply_A
+smsm_apply_AH = Plan.apply_AH
+smsm_apply_AHA = Plan.apply_AHA
+smsm_gram = Plan.gram
+smsm_weights = Plan.weights
+smsm_lambda_max = Plan.lambda_max
+smsm_set_weights = Plan.set_weights
+smsm_apply_reg = Plan.apply_reg
+smsm_apply_normal = Plan.apply_normal
+smsm_images_sos = Plan.images_sos
+smsm_launch_kernel = Plan.launch_kernel
+smsm_kernel_cost = Plan.kernel_cost
+smsm_kernel_timer_start = Plan.kernel_timer_start
+smsm_kernel_timer_read = Plan.kernel_timer_read
+smsm_status_string = status_string
 
 
 class Batch:
@@ -464,20 +436,10 @@ class Batch:
             pass
 
 
-def smsm_batch_create(plans, ys, xs, n_streams: int = 2) -> Batch:
-    return Batch(plans, ys, xs, n_streams)
-
-
-def smsm_batch_launch(batch: Batch, stream=None):
-    batch.launch(stream)
-
-
-def smsm_batch_destroy(batch: Batch):
-    batch.close()
-
-
-def smsm_batch_streams(batch: Batch) -> int:
-    return batch.n_streams
+smsm_batch_create = Batch
+smsm_batch_launch = Batch.launch
+smsm_batch_destroy = Batch.close
+smsm_batch_streams = Batch.n_streams.fget
 
 
 def flatten_params(params) -> "np.ndarray":
@@ -607,49 +569,15 @@ class Learned:
         self.close()
 
 
-def smsm_learned_create(plan: Plan, params, width=64, n_unroll=5, n_cg=10, mu=1.0) -> Learned:
-    return Learned(plan, params, width, n_unroll, n_cg, mu)
-
-
-def smsm_learned_destroy(net: Learned):
-    net.close()
-
-
-def smsm_learned_param_count(net: Learned) -> int:
-    return net.param_count()
-
-
-def smsm_learned_get_params(net: Learned):
-    return net.get_params()
-
-
-def smsm_learned_set_params(net: Learned, flat):
-    net.set_params(flat)
-
-
-def smsm_learned_cnn_forward(net: Learned, inp, out=None, stream=None):
-    return net.cnn_forward(inp, out, stream)
-
-
-def smsm_learned_cnn_backward(net: Learned, inp, gout, stream=None):
-    return net.cnn_backward(inp, gout, stream)
-
-
-def smsm_learned_solve(net: Learned, y, out=None, stream=None):
-    return net.solve(y, out, stream)
-
-
-def smsm_learned_gradients(net: Learned, y, xt, stream=None):
-    return net.gradients(y, xt, stream)
-
-
-def smsm_learned_train_step(net: Learned, y, xt, lr: float, stream=None) -> float:
-    return net.train_step(y, xt, lr, stream)
-
-
-def smsm_learned_residual(net: Learned, x, y, stream=None) -> float:
-    return net.residual(x, y, stream)
-
-
-def smsm_learned_set_bf16(net: Learned, on: bool = True):
-    net.set_bf16(on)
+smsm_learned_create = Learned
+smsm_learned_destroy = Learned.close
+smsm_learned_param_count = Learned.param_count
+smsm_learned_get_params = Learned.get_params
+smsm_learned_set_params = Learned.set_params
+smsm_learned_cnn_forward = Learned.cnn_forward
+smsm_learned_cnn_backward = Learned.cnn_backward
+smsm_learned_solve = Learned.solve
+smsm_learned_gradients = Learned.gradients
+smsm_learned_train_step = Learned.train_step
+smsm_learned_residual = Learned.residual
+smsm_learned_set_bf16 = Learned.set_bf16

@@ -34,6 +34,20 @@ def test_binding_has_a_function_per_declared_symbol():
         assert callable(getattr(smsm, name, None)), name
 
 
+def test_flat_names_are_the_marshalling_methods():
+    # each flat name is the class method (or constructor) that marshals the
+    # call, so no name can drift from what the class does
+    owners = {"plan": smsm.Plan, "batch": smsm.Batch, "learned": smsm.Learned}
+    for name in declared_symbols():
+        f = getattr(smsm, name)
+        if name == "smsm_status_string":
+            assert f is smsm.status_string
+            continue
+        kind = "batch" if name.startswith("smsm_batch") else "learned" if name.startswith("smsm_learned") else "plan"
+        cls = owners[kind]
+        assert f is cls or any(f is getattr(v, "fget", v) for v in vars(cls).values()), name
+
+
 @needs_lib
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(smsm.LIB_PATH)
@@ -43,8 +57,8 @@ def test_library_exports_every_declared_symbol():
 
 @needs_lib
 def test_status_strings():
-    for code in (0, -1, -2, -3, -4, -5):
-        assert pkg.status_string(code)
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert pkg.status_string(code) != "unknown status"
     assert pkg.status_string(-99) == "unknown status"
 
 
@@ -91,6 +105,8 @@ def test_entry_points_reject_null_plan():
     assert lib.smsm_set_weights(None, None, None) == pkg.SMSM_E_INVALID
     assert lib.smsm_plan_destroy(None) == pkg.SMSM_OK
     assert lib.smsm_plan_device_bytes(None) == 0
+    assert lib.smsm_workspace_bytes(None) == 0
+    assert lib.smsm_set_workspace(None, None, 0) == pkg.SMSM_E_INVALID
 
 
 @needs_lib

@@ -1,7 +1,8 @@
 """Batches of slice groups under one graph (smsm_batch_*): every solve of a
 batch equals the plain solve of its plan bit for bit, on every replay, with
-eager work between the replays; a plan that appears several times (several
-inputs of one slice group) runs its solves in order."""
+eager work between the replays, and the oracle's solve to 1e-10; a plan that
+appears several times (several inputs of one slice group) runs its solves in
+order."""
 import numpy as np
 import pytest
 
@@ -27,6 +28,9 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
+ORACLE_TOL = 1e-10
+
+
 def make_plan(torch, dev, g, seed):
     from paper_1901_01893_amd import smsm
     case = si.make_case(g, seed, 200 + seed)
@@ -34,7 +38,15 @@ def make_plan(torch, dev, g, seed):
     coils = torch.from_numpy(case["coils"]).to(dev)
     plan = smsm.Plan(g.n, g.n, g.n_slices, g.n_shots, g.n_coils, g.filt, coils, case["masks"], case["shifts"],
                      smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg, flags=smsm.SMSM_FLAG_X_C128))
+    plan.case, plan.g = case, g
     return plan, torch.from_numpy(y.astype(np.complex64)).to(dev)
+
+
+def oracle_of(plan, y):
+    """The oracle's solve of the plan's geometry for the device input y."""
+    g, case = plan.g, plan.case
+    return o.solve(y.cpu().numpy().astype(np.complex128), case["coils"], case["masks"], case["shifts"],
+                   o.SolveParams(lam=g.lam, r=g.filt, n_irls=g.n_irls, n_cg=g.n_cg))
 
 
 def test_batch_matches_plain_solves_bitwise(torch_dev):
@@ -48,6 +60,7 @@ def test_batch_matches_plain_solves_bitwise(torch_dev):
             ys.append(y)
             refs.append(plan.solve(y).clone())
         torch.cuda.synchronize()
+        oracles = [oracle_of(pl, y) for pl, y in zip(plans, ys)]
         xs = [torch.zeros_like(r) for r in refs]
         batch = smsm.Batch(plans, ys, xs, n_streams=2)
         try:
@@ -59,6 +72,9 @@ def test_batch_matches_plain_solves_bitwise(torch_dev):
                 torch.cuda.synchronize()
                 for k in range(len(plans)):
                     assert torch.equal(xs[k], refs[k]), (rep, k)
+                    err = o.nrmse(xs[k].cpu().numpy(), oracles[k])
+                    print(f"[batch] replay {rep} entry {k}: NRMSE vs oracle {err:.2e}", flush=True)
+                    assert err < ORACLE_TOL, (rep, k, err)
                 # eager work between the replays: a plain solve on one of the plans
                 j = rep % len(plans)
                 assert torch.equal(plans[j].solve(ys[j]), refs[j])
@@ -81,6 +97,7 @@ def test_batch_runs_a_repeated_plan_in_order(torch_dev):
         y_a2 = (0.5 * y_a).contiguous()
         refs = [plan_a.solve(y_a).clone(), plan_b.solve(y_b).clone(), plan_a.solve(y_a2).clone()]
         torch.cuda.synchronize()
+        oracles = [oracle_of(plan_a, y_a), oracle_of(plan_b, y_b), oracle_of(plan_a, y_a2)]
         xs = [torch.zeros_like(r) for r in refs]
         batch = smsm.Batch([plan_a, plan_b, plan_a], [y_a, y_b, y_a2], xs, n_streams=2)
         try:
@@ -92,6 +109,7 @@ def test_batch_runs_a_repeated_plan_in_order(torch_dev):
                 torch.cuda.synchronize()
                 for k in range(3):
                     assert torch.equal(xs[k], refs[k]), (rep, k)
+                    assert o.nrmse(xs[k].cpu().numpy(), oracles[k]) < ORACLE_TOL, (rep, k)
         finally:
             batch.close()
     finally:
@@ -121,6 +139,7 @@ def test_autotuned_batch_matches_plain_solves(torch_dev):
             torch.cuda.synchronize()
             for k in range(len(plans)):
                 assert torch.equal(xs[k], refs[k]), k
+                assert o.nrmse(xs[k].cpu().numpy(), oracle_of(plans[k], ys[k])) < ORACLE_TOL, k
         finally:
             batch.close()
     finally:

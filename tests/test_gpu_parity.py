@@ -1,7 +1,8 @@
 """GPU parity: every C-ABI entry point against the FP64 oracle on the same
 seeded inputs.  The HIP path computes in FP64, so operator-level tolerances
-are ~1e-12 relative; the solve is held to NRMSE <= 1e-5 (the target for the
-whole IRLS iteration) and is expected to land far below it."""
+are ~1e-12 relative; complex128 solves are held to NRMSE <= 1e-11 against the
+oracle (measured ~2e-13), complex64 results to 1e-7 (their rounding floor is
+~3e-8), far inside the 1e-5 the FP32 target would allow."""
 import os
 
 import numpy as np
@@ -14,7 +15,8 @@ from tests.helpers import case_for, oracle_params, rel
 pytestmark = pytest.mark.gpu
 
 OP_TOL = 1e-11       # operator-level relative error (FP64 kernels vs FP64 oracle)
-SOLVE_TOL = 1e-5     # NRMSE of the IRLS solution vs the oracle
+SOLVE_TOL = 1e-11    # NRMSE of a complex128 IRLS solution vs the oracle
+C64_TOL = 1e-7       # NRMSE of a complex64 result (solution or stored reference) vs FP64
 
 
 @pytest.fixture(scope="module")
@@ -173,7 +175,7 @@ def test_solve_c64_output_and_determinism(torch_dev):
     assert a.dtype == np.complex64
     assert np.array_equal(a, b)                      # fixed-order reductions: bitwise repeatable
     ref = o.solve(y.astype(np.complex128), case["coils"], case["masks"], case["shifts"], oracle_params(g))
-    assert o.nrmse(a, ref) < SOLVE_TOL
+    assert o.nrmse(a, ref) < C64_TOL
     plan.close()
 
 
@@ -265,5 +267,38 @@ def test_solve_sg256_matches_stored_oracle(torch_dev):
     err = o.nrmse(x, ref)
     print(f"[solve sg256 seed=0] NRMSE vs oracle = {err:.3e}", flush=True)
     assert plan.status() == smsm.SMSM_OK
-    assert err < SOLVE_TOL
+    assert err < C64_TOL                 # the stored reference is complex64 (rounding ~2.6e-8)
+    plan.close()
+
+
+def test_nan_in_data_sets_numeric_status(torch_dev):
+    """A NaN on an acquired line reaches the CG curvature: the solve finishes
+    (every loop is bounded) and smsm_plan_status reports SMSM_E_NUMERIC once."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, x_true, y = case_for("small", 7)
+    y = y.copy()
+    y[1, 2, 5, 9] = np.nan                      # shot 1 acquires ky = 5 (5 mod 4 = 1)
+    assert case["masks"][1, 5] == 1
+    plan = make_plan(torch, dev, g, case, smsm.make_params(lam=g.lam, n_irls=2, n_cg=3))
+    plan.solve(to_dev(torch, dev, y))
+    assert plan.status() == smsm.SMSM_E_NUMERIC
+    assert plan.status() == smsm.SMSM_OK        # reading clears the flags
+    plan.close()
+
+
+def test_weights_iteration_cap_reports_not_converged(torch_dev):
+    """Newton-Schulz stopped by a cap of one step leaves the weights above
+    tolerance: the status says so (the default cap converges: OK)."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, x_true, y = case_for("small", 8)
+    yd = to_dev(torch, dev, y)
+    plan = make_plan(torch, dev, g, case, smsm.make_params(lam=g.lam, n_irls=2, n_cg=2, ns_max_iter=1))
+    plan.solve(yd)
+    assert plan.status() == smsm.SMSM_E_NOT_CONVERGED
+    plan.close()
+    plan = make_plan(torch, dev, g, case, smsm.make_params(lam=g.lam, n_irls=2, n_cg=2))
+    plan.solve(yd)
+    assert plan.status() == smsm.SMSM_OK
     plan.close()
