@@ -66,7 +66,8 @@ typedef enum {
     SMSM_E_NOMEM = -3,        /* device allocation failed in plan creation */
     SMSM_E_DEVICE = -4,       /* a HIP runtime call failed */
     SMSM_E_NUMERIC = -5,      /* NaN/Inf met in the CG recurrences (smsm_plan_status) */
-    SMSM_E_NOT_CONVERGED = -6 /* the weights iteration hit ns_max_iter (smsm_plan_status) */
+    SMSM_E_NOT_CONVERGED = -6,/* the weights iteration hit ns_max_iter (smsm_plan_status) */
+    SMSM_E_SCRATCH = -7       /* workspace above SMSM_NOALLOC_SCRATCH_BYTES (smsm_solve_noalloc) */
 } smsm_status;
 
 typedef struct {
@@ -148,6 +149,26 @@ smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params);
  * without one); no device memory is allocated.
  */
 smsm_status smsm_solve(smsm_plan* plan, const void* y_dev, void* x_dev, void* stream);
+
+/* Size of the static device scratch of smsm_solve_noalloc: 64 MiB. */
+#define SMSM_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * The IRLS solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * exactly smsm_solve (same kernels, same order, same result bit for bit),
+ * run in a static device array of SMSM_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends, instead of the
+ * bound workspace (which may be absent and is left untouched).  No device
+ * memory is allocated or freed.  Every call on one device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (any plans, any streams) race and must be serialised by the caller.
+ * Errors: SMSM_E_INVALID for null arguments; SMSM_E_SCRATCH when
+ * smsm_workspace_bytes(plan) exceeds the array (enough for 64 x 64 and most
+ * 128 x 128 geometries, not for 256 x 256 with 32 coils); SMSM_E_DEVICE if
+ * the array's address cannot be taken; else as smsm_solve.
+ */
+smsm_status smsm_solve_noalloc(smsm_plan* plan, const void* y_dev, void* x_dev, void* stream);
 
 /*
  * Numeric status since the last call: SMSM_E_NUMERIC if a CG step met a

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -534,6 +535,7 @@ const char* smsm_status_string(smsm_status s) {
         case SMSM_E_DEVICE: return "HIP runtime error";
         case SMSM_E_NUMERIC: return "non-finite or non-positive CG curvature";
         case SMSM_E_NOT_CONVERGED: return "weights iteration did not converge within ns_max_iter";
+        case SMSM_E_SCRATCH: return "workspace larger than the static scratch of smsm_solve_noalloc";
     }
     return "unknown status";
 }
@@ -867,6 +869,54 @@ smsm_status smsm_solve(smsm_plan* P, const void* y_dev, void* x_dev, void* strea
         hipLaunchKernelGGL(k_to_c64, vec_grid(), dim3(kThreads), 0, st, nvec_l, P->q, (float2*)x_dev);
     LAUNCH_CHECK();
     return SMSM_OK;
+}
+
+}  // extern "C"
+
+// ---- the solve without allocation: a static device array as the workspace --
+// One array per device (each device that loads the library holds its own copy
+// until the process ends).  Host code must not pass `scratch` itself to a
+// kernel: its device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[SMSM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's scratch (the current device must be `dev`).
+smsm_status scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kScratchDevices) return SMSM_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SMSM_E_DEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SMSM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+smsm_status smsm_solve_noalloc(smsm_plan* P, const void* y_dev, void* x_dev, void* stream) {
+    if (!P || !y_dev || !x_dev) return SMSM_E_INVALID;
+    if (P->ws_bytes > (size_t)SMSM_NOALLOC_SCRATCH_BYTES) return SMSM_E_SCRATCH;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    void* base = nullptr;
+    smsm_status s = scratch_address(P->dev, &base);
+    if (s) return s;
+    // the solve runs in the scratch (every buffer it reads it writes first, so
+    // nothing needs clearing); the plan's own binding comes back afterwards
+    void* own = P->ws;
+    const bool own_weights = P->have_weights;
+    bind_workspace(P, base);
+    s = smsm_solve(P, y_dev, x_dev, stream);
+    bind_workspace(P, own);
+    P->have_weights = own_weights;
+    return s;
 }
 
 smsm_status smsm_plan_status(smsm_plan* P) {

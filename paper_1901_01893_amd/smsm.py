@@ -23,6 +23,8 @@ SMSM_E_NOMEM = -3
 SMSM_E_DEVICE = -4
 SMSM_E_NUMERIC = -5
 SMSM_E_NOT_CONVERGED = -6
+SMSM_E_SCRATCH = -7
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SMSM_FLAG_X_C128 = 0x1
 SMSM_FLAG_REG_F32 = 0x2
 
@@ -30,7 +32,7 @@ SMSM_FLAG_REG_F32 = 0x2
 ABI_SYMBOLS = (
     "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_workspace_bytes",
     "smsm_set_workspace", "smsm_plan_set_params",
-    "smsm_solve", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
+    "smsm_solve", "smsm_solve_noalloc", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
     "smsm_kernel_timer_start", "smsm_kernel_timer_read", "smsm_batch_create", "smsm_batch_launch",
@@ -87,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.smsm_plan_set_params.restype = st
         L.smsm_solve.argtypes = [vp, vp, vp, vp]
         L.smsm_solve.restype = st
+        L.smsm_solve_noalloc.argtypes = [vp, vp, vp, vp]
+        L.smsm_solve_noalloc.restype = st
         L.smsm_plan_status.argtypes = [vp]
         L.smsm_plan_status.restype = st
         L.smsm_status_string.argtypes = [st]
@@ -266,6 +270,18 @@ class Plan:
         _check(lib().smsm_solve(self._h, yp, xp, _stream_ptr(stream)), "smsm_solve")
         return out
 
+    def solve_noalloc(self, y, out, stream=None):
+        """The same solve run in the library's static device scratch (no
+        allocation anywhere; `out` must be given).  Calls that overlap on one
+        device race."""
+        import torch
+        c128 = bool(self.params.flags & SMSM_FLAG_X_C128)
+        dt = torch.complex128 if c128 else torch.complex64
+        yp = _dev_ptr(y, torch.complex64, self.shape_y, "y")
+        xp = _dev_ptr(out, dt, self.shape_x, "x")
+        _check(lib().smsm_solve_noalloc(self._h, yp, xp, _stream_ptr(stream)), "smsm_solve_noalloc")
+        return out
+
     def status(self) -> int:
         return int(lib().smsm_plan_status(self._h))
 
@@ -376,6 +392,7 @@ smsm_workspace_bytes = Plan.workspace_bytes
 smsm_set_workspace = Plan.set_workspace
 smsm_plan_set_params = Plan.set_params
 smsm_solve = Plan.solve
+smsm_solve_noalloc = Plan.solve_noalloc
 smsm_plan_status = Plan.status
 smsm_apply_A = Plan.apply_A
 smsm_apply_AH = Plan.apply_AH

@@ -93,6 +93,7 @@ def test_every_flat_binding_once(torch_dev):
     yd = to_dev(torch, dev, y)
     x = call("smsm_solve", plan, yd)
     assert call("smsm_plan_status", plan) == smsm.SMSM_OK
+    assert torch.equal(call("smsm_solve_noalloc", plan, yd, torch.empty_like(x)), x)
     assert call("smsm_status_string", smsm.SMSM_E_NUMERIC)
     ya = call("smsm_apply_A", plan, x)
     assert ya.shape == plan.shape_y
