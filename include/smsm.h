@@ -124,7 +124,7 @@ size_t smsm_plan_device_bytes(const smsm_plan* plan);
 
 /* Bytes of device workspace a plan needs: about 7 c128 vectors of
  * [L][Ns][n2][n1], the folded data, the image-domain Hankel kernel and the
- * band, Gram and weight tables (about 250 MB for 256 x 256, 3 slices, 4
+ * band, Gram and weight tables (about 240 MB for 256 x 256, 3 slices, 4
  * shots, 32 coils, 7 x 7 filter).  0 for a null plan. */
 size_t smsm_workspace_bytes(const smsm_plan* plan);
 
