@@ -361,10 +361,18 @@ long smsm_learned_param_count(const smsm_learned* net);
 smsm_status smsm_learned_get_params(smsm_learned* net, float* params_host);
 smsm_status smsm_learned_set_params(smsm_learned* net, const float* params_host);
 
-/* on != 0: the convolutions read a BF16 copy of the weights (rounded to
- * nearest even from the FP32 parameters, refreshed after every change; FP32
- * accumulation, FP32 biases), gradients are taken with respect to those
- * weights and applied to the FP32 parameters.  Default off.  Synchronous. */
+/* Weight format of the network's convolutions.  on = 0 (default): FP32
+ * weights and accumulation on the vector ALU.  on = 1: BF16 weights (rounded
+ * to nearest even from the FP32 parameters, refreshed after every change) on
+ * the BF16 matrix cores, FP32 activations entering each product in three
+ * BF16 parts (products exact to FP32), FP32 accumulation.  on = 2: the BF16
+ * network on the matrix cores: BF16 weights, every convolution input (the
+ * network input and the hidden activations, stored as BF16 values) and the
+ * gradient entering each backward-data convolution rounded to BF16, FP32
+ * accumulation and biases; weight gradients from the FP32 output gradients
+ * and the stored activations.  Gradients are taken with respect to the BF16
+ * weights and applied to the FP32 parameters.  Errors: SMSM_E_INVALID for a
+ * null object or on outside 0..2.  Synchronous. */
 smsm_status smsm_learned_set_bf16(smsm_learned* net, int on);
 
 /* The network alone: out = C(in), in_dev and out_dev float [L][2Ns][n2][n1]. */

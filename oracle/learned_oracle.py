@@ -28,11 +28,17 @@ data-consistency solve as the exact inverse: for x = M^-1 (b + mu z),
 M = A^H A + mu I (Hermitian), the gradient of a real loss with respect to z
 is mu M^-1 g_x, with M^-1 again taken as n_cg CG steps, here from zero.
 
+Two BF16 forms: BF16 weights with exact products (bf16_params), and the
+BF16 network (act_bf16: every convolution input rounded to BF16, the
+rounding passed straight through in the backward pass).
+
 Pins (tests/test_oracle_learned_pins.py): the convolution against
 scipy.signal.correlate2d, every analytic gradient against central finite
 differences (with exact solves, where the backward pass is exact), the
-data-consistency step against a dense solve, and the untrained limit (zero
-network: the iteration converges to the SENSE least-squares solution).
+data-consistency step against a dense solve, the untrained limit (zero
+network: the iteration converges to the SENSE least-squares solution), and
+the BF16 network reducing to the plain one on data whose every rounded
+quantity is already a BF16 value, with BF16-valued activations otherwise.
 """
 import numpy as np
 
@@ -69,26 +75,36 @@ def conv3x3_backward(x, w, gout):
 
 # ---- the network ------------------------------------------------------------
 
-def cnn_forward(x, params):
+def cnn_forward(x, params, act_bf16=False):
     """params = [(w0, b0), ..., (w4, b4)]; ReLU after every layer but the last.
-    Returns the output and the input of every layer (for the backward pass)."""
-    acts = [x]
-    h = x
+    Returns the output and the input of every layer (for the backward pass).
+    act_bf16: the BF16 network, whose every convolution input (the network
+    input and the hidden activations after their ReLU) is rounded to BF16."""
+    h = bf16_round(x) if act_bf16 else x
+    acts = [h]
     for k, (w, b) in enumerate(params):
         h = conv3x3(h, w, b)
         if k < len(params) - 1:
             h = np.maximum(h, 0.0)
+            if act_bf16:
+                h = bf16_round(h)
             acts.append(h)
     return h, acts
 
 
-def cnn_backward(acts, params, gout):
-    """Gradients with respect to the network input and every (w, b)."""
+def cnn_backward(acts, params, gout, act_bf16=False):
+    """Gradients with respect to the network input and every (w, b).
+    act_bf16: the BF16 network's backward pass (rounding passed straight
+    through): the gradient entering each transposed convolution is rounded
+    to BF16 as that convolution's input, while the weight and bias gradients
+    take the unrounded output gradient and the layer's (rounded) input."""
     grads = [None] * len(params)
     g = gout
     for k in range(len(params) - 1, -1, -1):
         w, _ = params[k]
         gx, gw, gb = conv3x3_backward(acts[k], w, g)
+        if act_bf16:
+            gx = conv3x3_backward(acts[k], w, bf16_round(g))[0]
         grads[k] = (gw, gb)
         # ReLU of the layer below: the stored activation is its output
         g = gx * (acts[k] > 0.0) if k > 0 else gx
@@ -124,14 +140,14 @@ def dc_solve(apply_aha, b, z, mu: float, n_cg: int, x0=None):
     return so.cg(lambda v: apply_aha(v) + mu * v, b + mu * z, z if x0 is None else x0, n_cg)
 
 
-def unrolled_forward(b, apply_aha, params, mu: float, n_unroll: int, n_cg: int):
+def unrolled_forward(b, apply_aha, params, mu: float, n_unroll: int, n_cg: int, act_bf16=False):
     """x_K and the iterates x_0 .. x_{K-1} (x_0 = b = A^H y)."""
     s = data_scale(b)
     x = b.copy()
     xs = []
     for _ in range(n_unroll):
         xs.append(x)
-        c, _ = cnn_forward(pack(x, s), params)
+        c, _ = cnn_forward(pack(x, s), params, act_bf16)
         z = x + unpack(c, s)
         x = dc_solve(apply_aha, b, z, mu, n_cg)
     return x, xs
@@ -141,10 +157,11 @@ def loss_value(x, x_target) -> float:
     return float(np.sum(np.abs(x - x_target) ** 2) / np.sum(np.abs(x_target) ** 2))
 
 
-def unrolled_loss_and_grads(b, apply_aha, params, mu: float, n_unroll: int, n_cg: int, x_target):
+def unrolled_loss_and_grads(b, apply_aha, params, mu: float, n_unroll: int, n_cg: int, x_target,
+                            act_bf16=False):
     """Loss and its gradients with respect to every (w, b) of the network."""
     s = data_scale(b)
-    xK, xs = unrolled_forward(b, apply_aha, params, mu, n_unroll, n_cg)
+    xK, xs = unrolled_forward(b, apply_aha, params, mu, n_unroll, n_cg, act_bf16)
     loss = loss_value(xK, x_target)
     g = 2.0 * (xK - x_target) / np.sum(np.abs(x_target) ** 2)    # d loss / d Re x + i d loss / d Im x
     total = [(np.zeros_like(w, dtype=np.float64), np.zeros_like(bb, dtype=np.float64)) for w, bb in params]
@@ -152,9 +169,9 @@ def unrolled_loss_and_grads(b, apply_aha, params, mu: float, n_unroll: int, n_cg
         wv = so.cg(lambda v: apply_aha(v) + mu * v, g, np.zeros_like(g), n_cg)
         gz = mu * wv
         # z = x + s * unpack(C(pack(x, s))): the network sees x / s and its output is scaled by s
-        _, acts = cnn_forward(pack(xs[k], s), params)
+        _, acts = cnn_forward(pack(xs[k], s), params, act_bf16)
         gc = pack(gz, 1.0 / s) if s > 0 else np.zeros_like(acts[0])   # d loss / d output channels: s (Re gz, Im gz)
-        gin, grads = cnn_backward(acts, params, gc)
+        gin, grads = cnn_backward(acts, params, gc, act_bf16)
         for j, (gw, gb) in enumerate(grads):
             total[j] = (total[j][0] + gw, total[j][1] + gb)
         g = gz + (unpack(gin, 1.0 / s) if s > 0 else 0.0)   # residual path + d channels / d x = 1 / s

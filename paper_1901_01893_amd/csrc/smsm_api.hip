@@ -7,6 +7,7 @@
 #include "smsm_gram.h"
 #include "smsm_hyb.h"
 #include "smsm_cnn.h"
+#include "smsm_cnn_mfma.h"
 #include "smsm.h"
 
 #include <hip/hip_ext.h>
@@ -1381,51 +1382,86 @@ struct smsm_learned {
     double2 *g = nullptr, *wv = nullptr, *ax = nullptr, *xs = nullptr;
     double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] rr, [2] alpha, [3] beta, [8] loss num, [9] den
     float *wpart = nullptr, *wbpart = nullptr;  // weight-gradient chunk partials (k_wgrad_part)
-    bool bf16 = false;                 // convolutions read the BF16 copy of the weights
-    unsigned short* wb = nullptr;      // BF16 copy of params (refreshed after every change)
+    // 0: FP32 weights on the vector ALU; BF16 weights on the matrix cores with
+    // 1: exact products (FP32 activations in three BF16 parts), 2: the BF16
+    // network (convolution inputs and hidden activations rounded to BF16)
+    int bf16 = 0;
+    // packed BF16 weights per layer, [0] forward P[o][t][c], [1] backward-data
+    // P[c][t][o] (taps flipped), refreshed after every change of the parameters
+    unsigned short* wpk[kDepth][2] = {};
+    int pk_rows[kDepth][2] = {}, pk_cols[kDepth][2] = {};
 };
 
 namespace {
 
 long lvec(const smsm_learned* Lr) { return (long)Lr->L * (Lr->nc / 2) * Lr->H * Lr->W; }
 
-template <int COB, bool WB16>
-void lconv_k(smsm_learned* Lr, dim3 grid, int ci, int co, const float* in, const void* w, const float* bias,
+template <int COB>
+void lconv_k(smsm_learned* Lr, dim3 grid, int ci, int co, const float* in, const float* w, const float* bias,
              float* out, int relu, bool bwd, hipStream_t st) {
-    if (bwd) hipLaunchKernelGGL((k_conv3x3<COB, 1, WB16>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
-    else hipLaunchKernelGGL((k_conv3x3<COB, 0, WB16>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+    if (bwd) hipLaunchKernelGGL((k_conv3x3<COB, 1>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
+    else hipLaunchKernelGGL((k_conv3x3<COB, 0>), grid, dim3(CNN_THREADS), 0, st, ci, co, Lr->H, Lr->W, in, w, bias, out, relu);
 }
-// One convolution of layer weights at offset woff (FP32 or, with bf16, the
-// BF16 copy); biases stay FP32.
-smsm_status lconv(smsm_learned* Lr, int ci, int co, const float* in, size_t woff, const float* bias, float* out,
-                  int relu, bool bwd, hipStream_t st) {
+// Layer k's convolution (bwd: its backward-data transpose, no bias): FP32
+// weights on the vector ALU, or BF16 weights on the matrix cores.
+smsm_status lconv(smsm_learned* Lr, int k, bool bwd, const float* in, float* out, int relu, hipStream_t st) {
+    const int ci = bwd ? Lr->cout[k] : Lr->cin[k], co = bwd ? Lr->cin[k] : Lr->cout[k];
+    const float* bias = bwd ? nullptr : Lr->params + Lr->boff[k];
+    if (Lr->bf16) {
+        const int d = bwd ? 1 : 0, rows = Lr->pk_rows[k][d];
+        const dim3 grid(((Lr->H + CM_TR - 1) / CM_TR) * ((Lr->W + CM_TC - 1) / CM_TC), 1, Lr->L);
+        const int cols = Lr->pk_cols[k][d], rnd = (Lr->bf16 == 2 && relu) ? 1 : 0;
+        const unsigned short* P = Lr->wpk[k][d];
+        const int H = Lr->H, W = Lr->W;
+        if (Lr->bf16 == 2) {
+            if (rows % 64 == 0)
+                hipLaunchKernelGGL((k_conv3x3_mfma<4, 1>), dim3(grid.x, rows / 64, grid.z), dim3(256), 0, st, ci, co,
+                                   cols, H, W, in, P, bias, out, relu, rnd);
+            else
+                hipLaunchKernelGGL((k_conv3x3_mfma<1, 1>), dim3(grid.x, rows / 16, grid.z), dim3(256), 0, st, ci, co,
+                                   cols, H, W, in, P, bias, out, relu, rnd);
+        } else {
+            if (rows % 64 == 0)
+                hipLaunchKernelGGL((k_conv3x3_mfma<4, 3>), dim3(grid.x, rows / 64, grid.z), dim3(256), 0, st, ci, co,
+                                   cols, H, W, in, P, bias, out, relu, 0);
+            else
+                hipLaunchKernelGGL((k_conv3x3_mfma<1, 3>), dim3(grid.x, rows / 16, grid.z), dim3(256), 0, st, ci, co,
+                                   cols, H, W, in, P, bias, out, relu, 0);
+        }
+        LAUNCH_CHECK();
+        return SMSM_OK;
+    }
     const int npx = Lr->H * Lr->W;
     const dim3 grid((npx + CNN_THREADS - 1) / CNN_THREADS, co % 8 == 0 ? co / 8 : co / 4, Lr->L);
-    const void* w = Lr->bf16 ? (const void*)(Lr->wb + woff) : (const void*)(Lr->params + woff);
-    if (co % 8 == 0) {
-        if (Lr->bf16) lconv_k<8, true>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
-        else lconv_k<8, false>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
-    } else {
-        if (Lr->bf16) lconv_k<4, true>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
-        else lconv_k<4, false>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
-    }
+    const float* w = Lr->params + Lr->woff[k];
+    if (co % 8 == 0) lconv_k<8>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
+    else lconv_k<4>(Lr, grid, ci, co, in, w, bias, out, relu, bwd, st);
     LAUNCH_CHECK();
     return SMSM_OK;
 }
 
-// Refresh the BF16 copy of the parameters (when the network uses it).
+// Refresh the packed BF16 weights of every layer (when the network uses them).
 smsm_status lrefresh_bf16(smsm_learned* Lr, hipStream_t st) {
     if (!Lr->bf16) return SMSM_OK;
-    hipLaunchKernelGGL(k_to_bf16, vec_grid(), dim3(kThreads), 0, st, (long)Lr->nparam, Lr->params, Lr->wb);
-    LAUNCH_CHECK();
+    for (int k = 0; k < smsm_learned::kDepth; ++k)
+        for (int d = 0; d < 2; ++d) {
+            hipLaunchKernelGGL(k_conv_wpack, dim3(256), dim3(kThreads), 0, st, Lr->cin[k], Lr->cout[k],
+                               Lr->params + Lr->woff[k], d, Lr->pk_rows[k][d], Lr->pk_cols[k][d], Lr->wpk[k][d]);
+            LAUNCH_CHECK();
+        }
     return SMSM_OK;
 }
 
-// act[0] -> act[1..5] (ReLU after layers 0..3).
+// act[0] -> act[1..5] (ReLU after layers 0..3).  The BF16 network first
+// rounds its input act[0] to BF16 values (in place).
 smsm_status lcnn_forward(smsm_learned* Lr, hipStream_t st) {
+    if (Lr->bf16 == 2) {
+        hipLaunchKernelGGL(k_round_bf16, vec_grid(), dim3(kThreads), 0, st, (long)Lr->L * Lr->nc * Lr->H * Lr->W,
+                           Lr->act[0]);
+        LAUNCH_CHECK();
+    }
     for (int k = 0; k < smsm_learned::kDepth; ++k) {
-        smsm_status s = lconv(Lr, Lr->cin[k], Lr->cout[k], Lr->act[k], Lr->woff[k],
-                              Lr->params + Lr->boff[k], Lr->act[k + 1], k < smsm_learned::kDepth - 1, false, st);
+        smsm_status s = lconv(Lr, k, false, Lr->act[k], Lr->act[k + 1], k < smsm_learned::kDepth - 1, st);
         if (s) return s;
     }
     return SMSM_OK;
@@ -1457,7 +1493,7 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
         }
         LAUNCH_CHECK();
         float* dst = k > 0 ? bufs[k & 1] : gin;
-        smsm_status s = lconv(Lr, Lr->cout[k], Lr->cin[k], g, Lr->woff[k], nullptr, dst, 0, true, st);
+        smsm_status s = lconv(Lr, k, true, g, dst, 0, st);
         if (s) return s;
         if (k > 0) {
             hipLaunchKernelGGL(k_relu_bwd, vec_grid(), dim3(kThreads), 0, st, nh, dst, Lr->act[k]);
@@ -1644,7 +1680,15 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     }
     const size_t nchunk = (size_t)Lr->L * wg_chunks(Lr->H, Lr->W);
     const size_t owp = cv.take<float>(nchunk * maxcc * 9), owb = cv.take<float>(nchunk * maxco);
-    const size_t ow16 = cv.take<unsigned short>(off);
+    size_t opk[smsm_learned::kDepth][2];
+    for (int k = 0; k < smsm_learned::kDepth; ++k) {
+        Lr->pk_rows[k][0] = cm_round(Lr->cout[k], 16);
+        Lr->pk_cols[k][0] = cm_round(Lr->cin[k], CM_CK);
+        Lr->pk_rows[k][1] = cm_round(Lr->cin[k], 16);
+        Lr->pk_cols[k][1] = cm_round(Lr->cout[k], CM_CK);
+        for (int d = 0; d < 2; ++d)
+            opk[k][d] = cv.take<unsigned short>((size_t)Lr->pk_rows[k][d] * 9 * Lr->pk_cols[k][d]);
+    }
     if (hipMalloc(&Lr->arena, cv.off) != hipSuccess) {
         delete Lr;
         return SMSM_E_NOMEM;
@@ -1666,7 +1710,8 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     Lr->scal = (double*)(base + oscal);
     Lr->wpart = (float*)(base + owp);
     Lr->wbpart = (float*)(base + owb);
-    Lr->wb = (unsigned short*)(base + ow16);
+    for (int k = 0; k < smsm_learned::kDepth; ++k)
+        for (int d = 0; d < 2; ++d) Lr->wpk[k][d] = (unsigned short*)(base + opk[k][d]);
     bool ok = hipMemcpy(Lr->params, params_host, off * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(Lr->am, 0, off * sizeof(float)) == hipSuccess;
     ok = ok && hipMemset(Lr->av, 0, off * sizeof(float)) == hipSuccess;
@@ -1709,9 +1754,9 @@ smsm_status smsm_learned_set_params(smsm_learned* Lr, const float* host) {
 }
 
 smsm_status smsm_learned_set_bf16(smsm_learned* Lr, int on) {
-    if (!Lr) return SMSM_E_INVALID;
+    if (!Lr || on < 0 || on > 2) return SMSM_E_INVALID;
     if (hipSetDevice(Lr->dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return SMSM_E_DEVICE;
-    Lr->bf16 = on != 0;
+    Lr->bf16 = on;
     smsm_status s = lrefresh_bf16(Lr, nullptr);
     if (s) return s;
     return hipDeviceSynchronize() == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;

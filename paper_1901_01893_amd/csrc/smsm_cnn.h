@@ -3,9 +3,10 @@
 //   z = x + s C(x / s),   x <- (A^H A + mu I)^-1 (A^H y + mu z),
 // C a real CNN over the 2 Ns channels (real and imaginary part of each shot's
 // k-space) of every slice: five 3 x 3 layers with ReLU after the first four;
-// s = sqrt(mean |A^H y|^2).  The network runs in FP32 (FP32 weights and
-// accumulation, fixed summation order); the data-consistency solves run in
-// FP64 on the solver's normal operator.
+// s = sqrt(mean |A^H y|^2).  The network runs with FP32 weights on the
+// vector ALU or with BF16 weights on the matrix cores (smsm_cnn_mfma.h), FP32
+// accumulation and a fixed summation order either way; the data-consistency
+// solves run in FP64 on the solver's normal operator.
 //
 // Layouts: activations [N][C][H][W] float (N = slices), weights
 // [Co][Ci][3][3] then bias [Co] per layer, layers back to back.
@@ -23,12 +24,11 @@
 // Ci here.  One thread per pixel and COB consecutive output channels; the
 // weights of a (channel block, input channel) are wave-uniform and read
 // through the scalar cache.  Sums run over input channels, then taps (row
-// major), in order.  grid (ceil(H W / 256), co / COB, N), block 256.
-// WB16: the weights are BF16 (the upper 16 bits of the FP32 pattern) and
-// widened exactly to FP32 on load; the accumulation is FP32 either way.
-template <int COB, int BWD, bool WB16 = false>
+// major), in order.  grid (ceil(H W / 256), co / COB, N), block 256.  (The
+// network's BF16-weight form runs on the matrix cores: smsm_cnn_mfma.h.)
+template <int COB, int BWD>
 __global__ void __launch_bounds__(CNN_THREADS)
-k_conv3x3(int ci, int co, int H, int W, const float* __restrict__ in, const void* __restrict__ wv,
+k_conv3x3(int ci, int co, int H, int W, const float* __restrict__ in, const float* __restrict__ wv,
           const float* __restrict__ bias, float* __restrict__ out, int relu) {
     const int npx = H * W;
     const int p = blockIdx.x * CNN_THREADS + threadIdx.x;
@@ -54,17 +54,9 @@ k_conv3x3(int ci, int co, int H, int W, const float* __restrict__ in, const void
         for (int u = 0; u < COB; ++u) {
             // forward: w[o0+u][c][t]; backward: w[c][o0+u][8-t]
             const size_t wo = BWD ? ((size_t)c * co + o0 + u) * 9 : ((size_t)(o0 + u) * ci + c) * 9;
-            if (WB16) {
-                const unsigned short* wp = static_cast<const unsigned short*>(wv) + wo;
+            const CNN_CONST float* wp = (const CNN_CONST float*)(uintptr_t)(wv + wo);
 #pragma unroll
-                for (int t = 0; t < 9; ++t)
-                    acc[u] = fmaf(__uint_as_float((unsigned)wp[BWD ? 8 - t : t] << 16), v[t], acc[u]);
-            } else {
-                const CNN_CONST float* wp =
-                    (const CNN_CONST float*)(uintptr_t)(static_cast<const float*>(wv) + wo);
-#pragma unroll
-                for (int t = 0; t < 9; ++t) acc[u] = fmaf(wp[BWD ? 8 - t : t], v[t], acc[u]);
-            }
+            for (int t = 0; t < 9; ++t) acc[u] = fmaf(wp[BWD ? 8 - t : t], v[t], acc[u]);
         }
     }
     if (live) {
@@ -162,15 +154,6 @@ __global__ void k_cnn_unpack_add(long L, int ns, int npx, const float* __restric
         const int p = (int)(k - li * npx);
         const double2 v = x[k];
         z[k] = make_double2(v.x + f * (double)c[(2 * li) * npx + p], v.y + f * (double)c[(2 * li + 1) * npx + p]);
-    }
-}
-
-// BF16 copy of FP32 values, rounded to nearest, ties to even (the upper 16
-// bits of the FP32 pattern after adding 0x7FFF plus the lowest kept bit).
-__global__ void k_to_bf16(long n, const float* __restrict__ w, unsigned short* __restrict__ out) {
-    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const unsigned b = __float_as_uint(w[k]);
-        out[k] = (unsigned short)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
     }
 }
 

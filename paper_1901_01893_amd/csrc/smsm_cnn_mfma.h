@@ -1,0 +1,218 @@
+// 3 x 3 convolutions of the learned prior on the BF16 matrix cores (gfx950
+// v_mfma_f32_16x16x32_bf16), BF16 weights and FP32 accumulation, in two
+// forms: exact products (FP32 activations split into three BF16 parts,
+// x = hi + mid + lo exact to ~2^-27 of x, so each product w x is formed to
+// FP32 accuracy from three BF16 products), or the BF16 network (every
+// convolution input rounded to BF16: one product).
+//
+// Implicit GEMM: out[o][p] = bias[o] + sum_{t, c} W[o][t][c] in[c][p + off_t].
+// A workgroup (4 waves) takes an output tile of CM_TR rows x CM_TC columns of
+// one image and 16 NOB output channels; wave w takes tile row w (CM_TC = 64
+// pixels = 4 blocks of 16).  The input tile with its one-pixel halo is staged
+// in shared memory in chunks of CM_CK = 16 channels as BF16 planes,
+// position-major with the channels contiguous (16-byte fragment reads; the
+// position stride of 24 BF16 puts the 16 lanes of a fragment read on
+// distinct banks), and the chunk's weights (16 NOB rows of 9 taps x 16
+// channels, row stride 152 BF16, again bank-distinct for a fragment read)
+// beside it.  One MFMA step (K = 32) covers two taps of the chunk:
+// lane group g = l / 16 takes tap 2 s + g / 2 and channels 8 (g % 2) .. + 7,
+// so the 9 taps take 5 steps (the tenth tap has zero weights).  Per step a
+// wave reads its weight fragments (16 bytes per lane per 16-channel block),
+// then per pixel block the planes' fragments, and issues one MFMA per plane
+// and output-channel block.  MFMA operand layout (16x16x32): lane l
+// holds A[m = l % 16][k = 8 (l / 16) + j] and B[k = 8 (l / 16) + j][n = l % 16],
+// j < 8, and receives C[m = 4 (l / 16) + j][n = l % 16], j < 4.  The sums run
+// in a fixed order (chunks, steps, planes), so results are deterministic.
+#pragma once
+#include "smsm_device.h"
+
+typedef __bf16 cm_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float cm_f32x4 __attribute__((ext_vector_type(4)));
+
+#define CM_TR 4                                   // output rows per workgroup (one per wave)
+#define CM_TC 64                                  // output columns per workgroup
+#define CM_CK 16                                  // input channels per staged chunk
+#define CM_PSTR 24                                // BF16 per staged position (16 channels + 8 spread)
+#define CM_POS ((CM_TR + 2) * (CM_TC + 2))        // staged positions (tile and halo)
+#define CM_WSTR (9 * CM_CK + 8)                   // BF16 per staged weight row (9 taps x 16 channels + 8 spread)
+
+SMSM_HD inline int cm_round(int v, int m) { return (v + m - 1) / m * m; }
+
+// BF16 bits of an FP32 value, round to nearest, ties to even.
+SMSM_DEV unsigned cm_bf16_bits(float v) {
+    const unsigned b = __float_as_uint(v);
+    return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+
+// Packed BF16 weights of one layer (w [co][ci][3][3], FP32) for
+//   fwd (bwd = 0): P[o][t][c] = w[o][c][t],      o < rows = co rounded up to 16, c < cols = ci rounded up to 16;
+//   bwd-data (1):  P[c][t][o] = w[o][c][8 - t],  c < rows = ci rounded up to 16, o < cols = co rounded up to 16;
+// zero in the padding.  The BF16 rounding is that of the network's BF16 copy.
+__global__ void k_conv_wpack(int ci, int co, const float* __restrict__ w, int bwd, int rows, int cols,
+                             unsigned short* __restrict__ P) {
+    const long total = (long)rows * 9 * cols;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < total; k += (long)gridDim.x * blockDim.x) {
+        const int col = (int)(k % cols);
+        const long rt = k / cols;
+        const int t = (int)(rt % 9), row = (int)(rt / 9);
+        const int o = bwd ? col : row, c = bwd ? row : col;
+        float v = 0.0f;
+        if (o < co && c < ci) v = w[((size_t)o * ci + c) * 9 + (bwd ? 8 - t : t)];
+        P[k] = (unsigned short)cm_bf16_bits(v);
+    }
+}
+
+// One convolution (forward with packed fwd weights, or the backward-data
+// transpose with packed bwd weights and no bias): ci input channels, co
+// output channels, `cols` = ci rounded up to 16 (the packed row length),
+// images [N][ci][H][W] -> [N][co][H][W].  PLANES = 3: the input in three BF16
+// parts (products exact to FP32); PLANES = 1: the input rounded to BF16 (the
+// BF16 network), and round_out != 0 stores each output rounded to a BF16
+// value (the network's hidden activations).  grid (ceil(H / CM_TR)
+// ceil(W / CM_TC), rows / (16 NOB), N), block 256.
+template <int NOB, int PLANES>
+__global__ void __launch_bounds__(256, 3)
+k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__ in,
+               const unsigned short* __restrict__ P, const float* __restrict__ bias, float* __restrict__ out,
+               int relu, int round_out) {
+    __shared__ __attribute__((aligned(16))) unsigned short xs[PLANES][CM_POS * CM_PSTR];
+    __shared__ __attribute__((aligned(16))) unsigned short wsm[16 * NOB * CM_WSTR];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, l16 = lane & 15;
+    const int tiles_x = (W + CM_TC - 1) / CM_TC;
+    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
+    const int r0 = ty * CM_TR, c0 = tx * CM_TC, n = blockIdx.z;
+    const int o0 = blockIdx.y * 16 * NOB;
+    const size_t npx = (size_t)H * W;
+    const float* src = in + (size_t)n * ci * npx;
+    const int half = (g & 1) * 8;               // this lane group's channels within the chunk
+
+    cm_f32x4 acc[NOB][4];
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) acc[ob][pb] = cm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // staging items of this thread: (channel octet, position), positions
+    // consecutive across lanes; their addresses are the same for every chunk.
+    // The raw values of the next chunk are loaded while the current chunk's
+    // products run.
+    constexpr int NIT = (CM_POS * (CM_CK / 8) + 255) / 256;
+    int s_off[NIT];      // element offset of the item's first channel at chunk 0 (-1: zero or none)
+    int s_lds[NIT];      // its shared-memory slot (-1: none)
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+        const int item = tid + 256 * u;
+        const int oc = item / CM_POS, pos = item - oc * CM_POS;
+        const int pr = pos / (CM_TC + 2), pc = pos - pr * (CM_TC + 2);
+        const int i = r0 - 1 + pr, j = c0 - 1 + pc;
+        const bool live = item < CM_POS * (CM_CK / 8);
+        const bool inside = live && i >= 0 && i < H && j >= 0 && j < W;
+        s_off[u] = inside ? (int)((size_t)oc * 8 * npx + (size_t)i * W + j) : -1;
+        s_lds[u] = live ? pos * CM_PSTR + oc * 8 : -1;
+    }
+    float raw[NIT][8];
+    auto load_chunk = [&](int cc) {
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int c8 = cc + (s_lds[u] >= 0 ? (s_lds[u] % CM_PSTR) : 0);   // first channel of the octet
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                raw[u][q] = (s_off[u] >= 0 && c8 + q < ci) ? src[(size_t)s_off[u] + (size_t)(cc + q) * npx] : 0.0f;
+        }
+    };
+    // the chunk's weights: rows o0 .. o0 + 16 NOB - 1, 9 taps x 16 channels
+    // each, 16 bytes per item
+    constexpr int NW = (16 * NOB * 9 * 2 + 255) / 256;
+    load_chunk(0);
+    for (int cc = 0; cc < cols; cc += CM_CK) {
+        uint4 wraw[NW];
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int item = tid + 256 * u;
+            const int row = item / 18, rem = item - row * 18;
+            if (item < 16 * NOB * 18)
+                wraw[u] = *reinterpret_cast<const uint4*>(P + ((size_t)(o0 + row) * 9 + rem / 2) * cols + cc + 8 * (rem & 1));
+        }
+        __syncthreads();   // the previous chunk's fragments are read
+#pragma unroll
+        for (int u = 0; u < NW; ++u) {
+            const int item = tid + 256 * u;
+            const int row = item / 18, rem = item - row * 18;
+            if (item < 16 * NOB * 18)
+                *reinterpret_cast<uint4*>(&wsm[row * CM_WSTR + (rem / 2) * CM_CK + 8 * (rem & 1)]) = wraw[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            if (s_lds[u] < 0) continue;
+            unsigned part[PLANES][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float a0 = raw[u][2 * q], a1 = raw[u][2 * q + 1];
+#pragma unroll
+                for (int pl = 0; pl < PLANES; ++pl) {
+                    const unsigned h0 = cm_bf16_bits(a0), h1 = cm_bf16_bits(a1);
+                    part[pl][q] = h0 | (h1 << 16);
+                    a0 -= __uint_as_float(h0 << 16);   // exact: the remainder of a round to nearest
+                    a1 -= __uint_as_float(h1 << 16);
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < PLANES; ++pl)
+                *reinterpret_cast<uint4*>(&xs[pl][s_lds[u]]) = make_uint4(part[pl][0], part[pl][1], part[pl][2], part[pl][3]);
+        }
+        __syncthreads();
+        if (cc + CM_CK < cols) load_chunk(cc + CM_CK);
+#pragma unroll 1
+        for (int st = 0; st < 5; ++st) {
+            const int t = 2 * st + (g >> 1);                 // this lane group's tap (9: none)
+            const int tt = t < 9 ? t : 8;
+            const int dy = tt / 3, dx = tt - 3 * (tt / 3);
+            cm_bf16x8 a[NOB];
+#pragma unroll
+            for (int ob = 0; ob < NOB; ++ob) {
+                const cm_bf16x8 w8 = *reinterpret_cast<const cm_bf16x8*>(&wsm[(ob * 16 + l16) * CM_WSTR + tt * CM_CK + half]);
+                a[ob] = t < 9 ? w8 : cm_bf16x8{};
+            }
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int so = ((wave + dy) * (CM_TC + 2) + pb * 16 + l16 + dx) * CM_PSTR + half;
+#pragma unroll
+                for (int pl = 0; pl < PLANES; ++pl) {
+                    const cm_bf16x8 b = *reinterpret_cast<const cm_bf16x8*>(&xs[pl][so]);
+#pragma unroll
+                    for (int ob = 0; ob < NOB; ++ob)
+                        acc[ob][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ob], b, acc[ob][pb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: lane holds C[o = ob 16 + 4 g + j][pixel = pb 16 + l16] of tile row `wave`
+    const int row = r0 + wave;
+    if (row >= H) return;
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = o0 + ob * 16 + 4 * g + j;
+            if (o >= co) continue;
+            const float bo = bias ? bias[o] : 0.0f;
+            float* dst = out + ((size_t)n * co + o) * npx + (size_t)row * W;
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) {
+                const int col = c0 + pb * 16 + l16;
+                if (col < W) {
+                    float v = acc[ob][pb][j] + bo;
+                    if (relu && v < 0.0f) v = 0.0f;
+                    if (round_out) v = __uint_as_float(cm_bf16_bits(v) << 16);
+                    dst[col] = v;
+                }
+            }
+        }
+}
+
+// x <- x rounded to a BF16 value (in place; the BF16 network's input).
+__global__ void k_round_bf16(long n, float* __restrict__ x) {
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        x[k] = __uint_as_float(cm_bf16_bits(x[k]) << 16);
+}

@@ -509,8 +509,10 @@ class Learned:
         _check(lib().smsm_learned_set_params(self._h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
                "smsm_learned_set_params")
 
-    def set_bf16(self, on: bool = True):
-        _check(lib().smsm_learned_set_bf16(self._h, 1 if on else 0), "smsm_learned_set_bf16")
+    def set_bf16(self, mode: int = 1):
+        """0: FP32 weights; 1: BF16 weights, exact products; 2: the BF16
+        network (convolution inputs rounded to BF16 too).  True means 1."""
+        _check(lib().smsm_learned_set_bf16(self._h, int(mode)), "smsm_learned_set_bf16")
 
     def cnn_forward(self, inp, out=None, stream=None):
         import torch

@@ -241,3 +241,124 @@ def test_bf16_weights_match_oracle(torch_dev):
         for k in range(5):
             assert rel(got[k][0], grads_ref[k][0]) < 1e-4, k
             assert rel(got[k][1], grads_ref[k][1]) < 1e-4, k
+
+
+def test_bf16_network_is_exact_on_bf16_values(torch_dev):
+    """The BF16 network on a network whose activations and gradients are
+    all short dyadic numbers (each output channel reads one input channel at
+    one tap with weight +-1; integer inputs and output gradients): every
+    rounding is forced, so output, input gradient and parameter gradients
+    equal the oracle's bit for bit."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    from tests.test_oracle_learned_pins import bf16_exact_network
+    case, _, _ = make_case(G32, 7, 98)
+    params = [(w.astype(np.float32), b.astype(np.float32)) for w, b in bf16_exact_network(31)]
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=8, n_unroll=1, n_cg=1,
+                                                              mu=0.5) as net:
+        net.set_bf16(2)
+        rng = np.random.default_rng(13)
+        inp = rng.integers(-4, 5, size=net.shape_c).astype(np.float32)
+        gout = rng.integers(-3, 4, size=net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        p64 = f64_params(params)
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), p64, act_bf16=True)
+        rgin, rgrads = lo.cnn_backward(acts, p64, gout.astype(np.float64), act_bf16=True)
+        assert np.array_equal(out, ref)
+        assert np.array_equal(gin.cpu().numpy(), rgin)
+        got = smsm.unflatten_params(grads, 8, 8)
+        for k in range(5):
+            assert np.array_equal(got[k][0], rgrads[k][0]) and np.array_equal(got[k][1], rgrads[k][1]), k
+
+
+# The BF16 network rounds every hidden activation to BF16: the GPU forms it by
+# FP32 accumulation in the matrix cores' order, the oracle in FP64, so a
+# fraction of about sqrt(K) 2^-24 / 2^-8 (4e-4 at K = 576 terms) of the
+# activations round to the neighbouring BF16 value, each moving by 2^-8;
+# through four hidden layers that is ~2e-4 in norm (measured 2.2e-4).  The
+# backward pass rounds the gradient entering each of its five convolutions
+# as well and passes the differing ReLU masks on, about ten times that
+# (measured 2.6e-3).  Both sides' roundings are correct roundings of nearly
+# equal values; the exact test above fixes the structure bit for bit.
+BF16NET_TOL = 5e-4
+BF16NET_GRAD_TOL = 5e-3
+# Unrolled through three data-consistency iterations the first layer's
+# weight gradient gathers every flip upstream (measured 1.5e-2).
+BF16NET_UNROLL_TOL = 5e-2
+
+
+def test_bf16_network_matches_oracle(torch_dev):
+    """The BF16 network (every convolution input rounded to BF16, one BF16
+    product per term on the matrix cores): outputs and gradients of the
+    width-64 network, and the unrolled loss and gradients, against the
+    oracle's BF16 network on the same rounded weights (tolerances above)."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, x_true, y = make_case(G32, 6, 97)
+    params = si.cnn_init(10, 8, width=64, out_scale=1.0)
+    pb = lo.bf16_params(params)
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=64, n_unroll=3, n_cg=8,
+                                                              mu=0.8) as net:
+        net.set_bf16(2)
+        rng = np.random.default_rng(10)
+        inp = rng.standard_normal(net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), pb, act_bf16=True)
+        rgin, rgrads = lo.cnn_backward(acts, pb, gout.astype(np.float64), act_bf16=True)
+        print(f"[bf16 network] out {rel(out, ref):.2e} gin {rel(gin.cpu().numpy(), rgin):.2e}", flush=True)
+        assert rel(out, ref) < BF16NET_TOL
+        assert rel(out, lo.cnn_forward(inp.astype(np.float64), pb)[0]) > 4 * BF16NET_TOL   # the rounding is real
+        assert rel(gin.cpu().numpy(), rgin) < BF16NET_GRAD_TOL
+        got = smsm.unflatten_params(grads, 8, 64)
+        for k in range(5):
+            assert rel(got[k][0], rgrads[k][0]) < BF16NET_GRAD_TOL, k
+            assert rel(got[k][1], rgrads[k][1]) < BF16NET_GRAD_TOL, k
+        aha, (coils, masks, theta) = oracle_aha(case)
+        b = o.adjoint(y.astype(np.complex128), coils, masks, theta)
+        loss_ref, grads_ref = lo.unrolled_loss_and_grads(b, aha, pb, 0.8, 3, 8, x_true, act_bf16=True)
+        loss, grads = net.gradients(torch.from_numpy(y).to(dev), torch.from_numpy(x_true).to(dev))
+        print(f"[bf16 network] loss {abs(loss - loss_ref) / loss_ref:.2e}", flush=True)
+        assert abs(loss - loss_ref) < BF16NET_TOL * loss_ref
+        got = smsm.unflatten_params(grads, 8, 64)
+        errs = [(rel(got[k][0], grads_ref[k][0]), rel(got[k][1], grads_ref[k][1])) for k in range(5)]
+        print("[bf16 network] unrolled gradients " + " ".join(f"{a:.1e}/{b:.1e}" for a, b in errs), flush=True)
+        for k, (ew, eb) in enumerate(errs):
+            assert ew < BF16NET_UNROLL_TOL and eb < BF16NET_UNROLL_TOL, k
+
+
+@pytest.mark.parametrize("bf16", [0, 1, 2])
+def test_cnn_wide_images_match_oracle(torch_dev, bf16):
+    """256-wide images (the workload's width: the weight-gradient kernel's
+    two-row chunks and 258-wide halo staging, four 64-column tiles of the
+    matrix-core convolution), one slice, 8-channel layers: outputs, input
+    gradient and parameter gradients against the oracle, FP32 and BF16 weights."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g = si.Geometry(n=256, n_slices=1, n_shots=4, n_coils=2, filt=3, lam=1e-3, n_irls=1, n_cg=1, phase_order=2,
+                    snr=30.0)
+    case = si.make_case(g, 1, 96)
+    params = si.cnn_init(11, 8, width=8, out_scale=1.0)
+    ref_params = lo.bf16_params(params) if bf16 else f64_params(params)
+    act_bf16 = bf16 == 2
+    with plan_for(torch, dev, g, case) as plan, smsm.Learned(plan, params, width=8, n_unroll=1, n_cg=1,
+                                                             mu=0.5) as net:
+        net.set_bf16(bf16)
+        rng = np.random.default_rng(12)
+        inp = rng.standard_normal(net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        out = net.cnn_forward(torch.from_numpy(inp).to(dev)).cpu().numpy()
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        ref, acts = lo.cnn_forward(inp.astype(np.float64), ref_params, act_bf16)
+        rgin, rgrads = lo.cnn_backward(acts, ref_params, gout.astype(np.float64), act_bf16)
+        print(f"[cnn 256 wide bf16={bf16}] out {rel(out, ref):.2e} gin {rel(gin.cpu().numpy(), rgin):.2e}",
+              flush=True)
+        tol = BF16NET_GRAD_TOL if act_bf16 else 1e-5
+        assert rel(out, ref) < (BF16NET_TOL if act_bf16 else 1e-5)
+        assert rel(gin.cpu().numpy(), rgin) < tol
+        got = smsm.unflatten_params(grads, 8, 8)
+        for k in range(5):
+            assert rel(got[k][0], rgrads[k][0]) < tol, k
+            assert rel(got[k][1], rgrads[k][1]) < tol, k

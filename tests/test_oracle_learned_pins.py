@@ -143,3 +143,54 @@ def test_bf16_rounding_closed_forms():
     # relative error at most the unit roundoff of an 8-bit significand, 2^-8
     x = np.random.default_rng(3).standard_normal(10000).astype(np.float32)
     assert np.max(np.abs(lo.bf16_round(x) - x) / np.abs(x)) <= 2.0 ** -8
+
+
+def bf16_exact_network(seed, c=8, depth=5):
+    """A network whose activations and gradients stay short dyadic numbers
+    (BF16 values): each output channel reads one input channel (a
+    permutation) at one tap with weight +-1, biases in quarters."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for _ in range(depth):
+        w = np.zeros((c, c, 3, 3))
+        perm = rng.permutation(c)
+        for o in range(c):
+            a, d = rng.integers(0, 3, size=2)
+            w[o, perm[o], a, d] = rng.choice([-1.0, 1.0])
+        params.append((w, rng.integers(-2, 3, size=c) * 0.25))
+    return params
+
+
+def test_bf16_network_reduces_to_plain_on_bf16_exact_data():
+    """Where every rounded quantity is already a BF16 value the BF16 network
+    is the plain network: same output, input gradient and parameter
+    gradients, exactly."""
+    params = bf16_exact_network(21)
+    rng = np.random.default_rng(22)
+    x = rng.integers(-4, 5, size=(2, 8, 7, 6)).astype(np.float64)
+    gout = rng.integers(-3, 4, size=(2, 8, 7, 6)).astype(np.float64)
+    out, acts = lo.cnn_forward(x, params)
+    out_b, acts_b = lo.cnn_forward(x, params, act_bf16=True)
+    assert np.array_equal(out, out_b)
+    gin, grads = lo.cnn_backward(acts, params, gout)
+    gin_b, grads_b = lo.cnn_backward(acts_b, params, gout, act_bf16=True)
+    assert np.array_equal(gin, gin_b)
+    for (gw, gb), (gw2, gb2) in zip(grads, grads_b):
+        assert np.array_equal(gw, gw2) and np.array_equal(gb, gb2)
+
+
+def test_bf16_network_activations_are_bf16_values():
+    """On general data every convolution input of the BF16 network is a BF16
+    value (its FP32 pattern has zero low 16 bits) and the rounding changes
+    the output by the BF16 unit roundoff's order, no more."""
+    rng = np.random.default_rng(23)
+    params = [(rng.standard_normal((8, 8, 3, 3)) * 0.3, rng.standard_normal(8) * 0.1) for _ in range(5)]
+    x = rng.standard_normal((1, 8, 9, 9))
+    out, _ = lo.cnn_forward(x, params)
+    out_b, acts_b = lo.cnn_forward(x, params, act_bf16=True)
+    for a in acts_b:
+        f = a.astype(np.float32)
+        assert np.array_equal(f.astype(np.float64), a)
+        assert np.all((f.view(np.uint32) & 0xFFFF) == 0)
+    d = np.linalg.norm(out_b - out) / np.linalg.norm(out)
+    assert 1e-4 < d < 2.0 ** -6
