@@ -142,58 +142,141 @@ def mixed_measurement(torch, plan, ys, x, reps=10):
             "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3)}
 
 
-def learned_measurement(torch, dev, plan, g, workload, n_train=64, n_eval=4, steps=300, mu=0.05, lr=3e-4):
-    """The learned form on the timed workload: a width-64 network (5 unrolled
-    iterations of 10 data-consistency CG steps) trained on the GPU for `steps`
-    Adam steps against the plain solver's reconstructions of n_train seeded
-    instances, then timed and compared on n_eval held-out instances with the
-    same iterations without the network (C = 0) and with the plain solver."""
+def host_truth(g, wid, seed, coils):
+    """Host half of a seeded instance: the truth k-space x_true = F(rho phi)
+    of the seeded phantoms and shot phases (smsm_inputs) and the masks."""
     import smsm_inputs as si
+    case = si.make_case(g, seed, wid, noise=False, coils=coils)
+    m = case["rho"].astype(np.float64)[:, None] * case["phase"].astype(np.complex128)
+    return centred_fft2(m), case["masks"]
+
+
+def device_instance(torch, dev, plan, g, wid, seed, truth):
+    """One seeded instance of the workload, y resident on the device, from
+    its host half `truth` (host_truth): clean data by the library's own A and
+    complex Gaussian noise of the same distribution drawn on the device from
+    a generator seeded by the seed (drawing 8.4 M complex normals on the host
+    would take longer than the solve).  Returns y (complex64)."""
+    x_true, masks = truth
+    clean = plan.apply_A(torch.from_numpy(x_true).to(dev))
+    mask = torch.from_numpy(masks.astype(np.float64)).to(dev)[:, None, :, None]
+    acquired = mask.expand_as(clean.real) > 0
+    rms = torch.sqrt(torch.mean(torch.abs(clean[acquired]) ** 2))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1_000_003 * wid + seed)
+    noise = torch.randn(tuple(clean.shape), dtype=torch.complex128, device=dev, generator=gen)
+    return (clean + mask * (rms / g.snr) * noise).to(torch.complex64).contiguous()
+
+
+def instances(torch, dev, plan, g, wid, seeds, coils, workers=6):
+    """device_instance over `seeds` in order, the host halves of the next
+    instances prepared by a thread pool while the device works."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as pool:
+        futs = [pool.submit(host_truth, g, wid, sd, coils) for sd in seeds[:2 * workers]]
+        for k, sd in enumerate(seeds):
+            if k + 2 * workers < len(seeds):
+                futs.append(pool.submit(host_truth, g, wid, seeds[k + 2 * workers], coils))
+            yield device_instance(torch, dev, plan, g, wid, sd, futs[k].result())
+            futs[k] = None
+
+
+LEARNED_TRAIN_SEEDS = 10000   # training instances 10000, 10001, ...
+LEARNED_EVAL_SEEDS = 20000    # held-out instances 20000, 20001, ...
+FALLBACK_RATIO = 1.5
+
+
+def learned_measurement(torch, dev, plan, g, workload, n_train=2000, n_eval=200, mu=0.05, lr=3e-4, bf16=2):
+    """The learned form on the timed workload: the width-64 BF16 network (5
+    unrolled iterations of 10 data-consistency CG steps) trained on the GPU
+    with one Adam step per seeded instance (n_train instances, streamed:
+    each is generated, solved by the plain solver for its target and trained
+    on once), then evaluated on n_eval held-out instances against the plain
+    solver, against the same iterations without the network, and with the
+    plain solver as fallback when its residual exceeds FALLBACK_RATIO x the
+    plain solver's; on the stored FP64 oracle solutions of the workload
+    (complex64) the plain and learned solutions are compared with the oracle."""
+    import smsm_inputs as si
+    from oracle import smsm_oracle as o
     from paper_1901_01893_amd import smsm
     wid = si.WORKLOAD_IDS[workload]
-    case0 = si.make_case(g, 1000, wid)
-    data = []
-    for s in range(1000, 1000 + n_train + n_eval):
-        case = si.make_case(g, s, wid)
-        if not np.array_equal(case["coils"], case0["coils"]):
-            return {"skipped": "coil maps differ between seeds"}
-        y = synth_inputs(torch, dev, plan, g, case, 1)[0]
-        xt = plan.solve(y).to(torch.complex128)
-        torch.cuda.synchronize()
-        data.append((y, xt))
+    coils = si.make_case(g, 0, wid)["coils"]
     params = si.cnn_init(1, 2 * g.n_shots, width=64, out_scale=0.1)
     zero = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
+    xp = torch.empty(plan.shape_x, dtype=torch.complex64, device=dev)
+    rel = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
     with smsm.Learned(plan, params, width=64, n_unroll=5, n_cg=10, mu=mu) as net, \
             smsm.Learned(plan, zero, width=64, n_unroll=5, n_cg=10, mu=mu) as net0:
-        torch.cuda.synchronize()
+        net.set_bf16(bf16)
+        net0.set_bf16(bf16)
+        losses, t_step = [], 0.0
         t0 = time.perf_counter()
-        losses = [net.train_step(*data[k % n_train], lr) for k in range(steps)]
+        for k, y in enumerate(instances(torch, dev, plan, g, wid,
+                                        list(range(LEARNED_TRAIN_SEEDS, LEARNED_TRAIN_SEEDS + n_train)), coils)):
+            plan.solve(y, xp)
+            xt = xp.to(torch.complex128)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            losses.append(net.train_step(y, xt, lr))
+            t_step += time.perf_counter() - ts
+            if k % 500 == 0:
+                print(f"[bench] learned: trained on {k + 1} of {n_train} instances", file=sys.stderr, flush=True)
+        t_train_total = time.perf_counter() - t0
+        e_net, e_dc, e_fb, ratios, n_fb = [], [], [], [], 0
+        for y in instances(torch, dev, plan, g, wid, list(range(LEARNED_EVAL_SEEDS, LEARNED_EVAL_SEEDS + n_eval)),
+                           coils):
+            plan.solve(y, xp)
+            xpl = xp.to(torch.complex128)
+            x, fell, r_l, r_p = net.solve_fallback(y, FALLBACK_RATIO)
+            xl = net.solve(y)
+            e_net.append(rel(xl, xpl))
+            e_dc.append(rel(net0.solve(y), xpl))
+            e_fb.append(rel(x, xpl))
+            ratios.append(r_l / r_p)
+            n_fb += int(fell)
+        # against the FP64 oracle on its stored solutions of this workload
+        oracle_cmp = []
+        for seed in (0, 1000, 1001, 1002, 1003):
+            path = os.path.join(ROOT, "tests", "golden", f"oracle_{workload}_seed{seed}.npy")
+            if not os.path.exists(path):
+                continue
+            case = si.make_case(g, seed, wid)
+            _, y_or = o.simulate(case, g.n_slices, g.snr)
+            yd = torch.from_numpy(y_or.astype(np.complex64)).to(dev)
+            ref = torch.from_numpy(np.load(path).astype(np.complex128)).to(dev)
+            plan.solve(yd, xp)
+            x, fell, _, _ = net.solve_fallback(yd, FALLBACK_RATIO)
+            oracle_cmp.append({"seed": seed, "plain": rel(xp.to(torch.complex128), ref),
+                               "learned": rel(net.solve(yd), ref), "learned_with_fallback": rel(x, ref),
+                               "fell_back": bool(fell)})
+        y = device_instance(torch, dev, plan, g, wid, LEARNED_EVAL_SEEDS,
+                            host_truth(g, wid, LEARNED_EVAL_SEEDS, coils))
+        xo = net.solve(y)
         torch.cuda.synchronize()
-        t_train = (time.perf_counter() - t0) / steps
-        def err(n, yd, xt):
-            return float(torch.linalg.vector_norm(n.solve(yd) - xt) / torch.linalg.vector_norm(xt))
-        held = data[n_train:]
-        e_net = float(np.mean([err(net, yd, xt) for yd, xt in held]))
-        e_dc = float(np.mean([err(net0, yd, xt) for yd, xt in held]))
-        ratios = [net.residual(net.solve(yd), yd) / net.residual(xt, yd) for yd, xt in held]
-        x = net.solve(held[0][0])
-        torch.cuda.synchronize()
-        reps = 5
+        reps = 10
         t0 = time.perf_counter()
         for _ in range(reps):
-            net.solve(held[0][0], x)
+            net.solve(y, xo)
         torch.cuda.synchronize()
         t_solve = (time.perf_counter() - t0) / reps
-    return {"network": "5 x (residual k-space CNN 2Ns-64-64-64-64-2Ns, 3x3, ReLU, FP32 weights and "
-                       f"accumulation + 10 FP64 CG data-consistency steps, mu={mu})",
-            "training": f"{steps} Adam steps (lr {lr}) on {n_train} seeded instances, targets from the plain solver",
-            "train_ms_per_step": round(t_train * 1e3, 2), "loss_first_last": [round(float(losses[0]), 4),
-                                                                              round(float(losses[-1]), 4)],
+    mode = {0: "FP32 weights", 1: "BF16 weights, exact products",
+            2: "BF16 network (BF16 weights and convolution inputs)"}[bf16]
+    return {"network": "5 x (residual k-space CNN 2Ns-64-64-64-64-2Ns, 3x3, ReLU, "
+                       f"{mode}, FP32 accumulation on the matrix cores + 10 FP64 CG data-consistency steps, mu={mu})",
+            "training": f"one Adam step (lr {lr}) on each of {n_train} seeded instances (seeds "
+                        f"{LEARNED_TRAIN_SEEDS}..), targets from the plain solver",
+            "train_instances": n_train, "train_ms_per_step": round(t_step / max(n_train, 1) * 1e3, 2),
+            "train_total_s": round(t_train_total, 1),
+            "loss_first_last100": [round(float(np.mean(losses[:100])), 4), round(float(np.mean(losses[-100:])), 4)],
             "slice_groups_per_s": round(1.0 / t_solve, 3), "ms_per_solve": round(t_solve * 1e3, 3),
-            "heldout_rel_error_vs_plain": round(e_net, 4),
-            "heldout_rel_error_vs_plain_without_network": round(e_dc, 4),
-            "residual_ratio_vs_plain": [round(r, 3) for r in ratios],
-            "fallback_to_plain_if_ratio_above": 1.5}
+            "eval_instances": n_eval,
+            "heldout_rel_error_vs_plain": round(float(np.mean(e_net)), 4),
+            "heldout_rel_error_vs_plain_without_network": round(float(np.mean(e_dc)), 4),
+            "heldout_rel_error_vs_plain_with_fallback": round(float(np.mean(e_fb)), 4),
+            "residual_ratio_vs_plain": {"mean": round(float(np.mean(ratios)), 3),
+                                        "max": round(float(np.max(ratios)), 3)},
+            "fallback_ratio": FALLBACK_RATIO, "fallback_rate": round(n_fb / max(n_eval, 1), 4),
+            "vs_stored_oracle": oracle_cmp}
 
 
 def time_kernel(torch, plan, name, reps):
@@ -370,6 +453,8 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form measurement")
+    ap.add_argument("--learned-train", type=int, default=2000, help="training instances of the learned form")
+    ap.add_argument("--learned-eval", type=int, default=200, help="held-out instances of the learned form")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision-form measurement")
     ap.add_argument("--profile-learned", type=int, default=0, metavar="STEPS",
                     help="run only STEPS training steps and STEPS solves of the learned form (for a kernel trace)")
@@ -397,6 +482,7 @@ def main():
     if args.profile_learned:
         import smsm_inputs as si
         net = smsm.Learned(plan, si.cnn_init(1, 2 * g.n_shots, width=64), width=64, n_unroll=5, n_cg=10, mu=0.05)
+        net.set_bf16(2)
         xt = plan.solve(y).to(torch.complex128)
         for _ in range(args.profile_learned):
             net.train_step(y, xt, 3e-4)
@@ -479,7 +565,8 @@ def main():
     if not args.no_mixed:
         out["mixed"] = mixed_measurement(torch, plan, ys, x)
     if not args.no_learned:
-        out["learned"] = learned_measurement(torch, dev, plan, g, args.workload)
+        out["learned"] = learned_measurement(torch, dev, plan, g, args.workload, n_train=args.learned_train,
+                                             n_eval=args.learned_eval)
 
     if not args.no_cpu_baseline and args.gpus == 1:
         from oracle import smsm_oracle as o

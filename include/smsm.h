@@ -397,6 +397,19 @@ smsm_status smsm_learned_train_step(smsm_learned* net, const void* y_dev, const 
 smsm_status smsm_learned_residual(smsm_learned* net, const void* x_dev, const void* y_dev, double* res,
                                   void* stream);
 
+/* The learned solve with the plain IRLS solve as its fallback: x = the
+ * learned solve of y and r_l = ||A x - y||.  The reference residual r_p is
+ * res_ref when res_ref > 0 (e.g. the plain solver's residual on an earlier
+ * input of the slice group), else that of the plain solve of y, run here with
+ * the plan's parameters.  When r_l > ratio * r_p, x is replaced by the plain
+ * solve (run here if it has not been) and *fell_back = 1, else 0.
+ * res_out[0] = r_l, res_out[1] = r_p.  x_dev c128 [L][Ns][n2][n1].  The plain
+ * solve uses the plan's workspace and one of the object's vectors.  Errors:
+ * SMSM_E_INVALID for null arguments or ratio <= 0; else as the solves.
+ * Synchronous. */
+smsm_status smsm_learned_solve_fallback(smsm_learned* net, const void* y_dev, void* x_dev, double ratio,
+                                        double res_ref, double* res_out, int* fell_back, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

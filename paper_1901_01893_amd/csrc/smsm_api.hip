@@ -1839,6 +1839,43 @@ smsm_status smsm_learned_train_step(smsm_learned* Lr, const void* y_dev, const v
     return lrefresh_bf16(Lr, S(stream));
 }
 
+// The plain IRLS solve of y into the object's vector wv (complex128 output
+// for that call whatever the plan's output flag).
+static smsm_status plain_into(smsm_learned* Lr, const void* y_dev, void* stream) {
+    smsm_plan* P = Lr->P;
+    const uint32_t flags = P->prm.flags;
+    P->prm.flags = flags | SMSM_FLAG_X_C128;
+    const smsm_status s = smsm_solve(P, y_dev, Lr->wv, stream);
+    P->prm.flags = flags;
+    return s;
+}
+
+smsm_status smsm_learned_solve_fallback(smsm_learned* Lr, const void* y_dev, void* x_dev, double ratio,
+                                        double res_ref, double* res_out, int* fell_back, void* stream) {
+    if (!Lr || !y_dev || !x_dev || !res_out || !fell_back || !(ratio > 0.0)) return SMSM_E_INVALID;
+    smsm_status s = smsm_learned_solve(Lr, y_dev, x_dev, stream);
+    if (s) return s;
+    double r_l = 0.0, r_p = res_ref;
+    if ((s = smsm_learned_residual(Lr, x_dev, y_dev, &r_l, stream))) return s;
+    bool have_plain = false;
+    if (!(r_p > 0.0)) {
+        if ((s = plain_into(Lr, y_dev, stream))) return s;
+        if ((s = smsm_learned_residual(Lr, Lr->wv, y_dev, &r_p, stream))) return s;
+        have_plain = true;
+    }
+    *fell_back = r_l > ratio * r_p ? 1 : 0;
+    if (*fell_back) {
+        if (!have_plain && (s = plain_into(Lr, y_dev, stream))) return s;
+        hipStream_t st = S(stream);
+        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), Lr->wv, (double2*)x_dev);
+        LAUNCH_CHECK();
+        if (hipStreamSynchronize(st) != hipSuccess) return SMSM_E_DEVICE;
+    }
+    res_out[0] = r_l;
+    res_out[1] = r_p;
+    return SMSM_OK;
+}
+
 smsm_status smsm_learned_residual(smsm_learned* Lr, const void* x_dev, const void* y_dev, double* res, void* stream) {
     if (!Lr || !x_dev || !y_dev || !res) return SMSM_E_INVALID;
     hipStream_t st = S(stream);

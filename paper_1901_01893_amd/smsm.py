@@ -39,7 +39,7 @@ ABI_SYMBOLS = (
     "smsm_batch_destroy", "smsm_batch_streams", "smsm_learned_create", "smsm_learned_destroy",
     "smsm_learned_param_count", "smsm_learned_get_params", "smsm_learned_set_params", "smsm_learned_cnn_forward",
     "smsm_learned_cnn_backward", "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
-    "smsm_learned_residual", "smsm_learned_set_bf16",
+    "smsm_learned_residual", "smsm_learned_solve_fallback", "smsm_learned_set_bf16",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
 
@@ -134,11 +134,13 @@ def lib() -> ctypes.CDLL:
         L.smsm_learned_gradients.argtypes = [vp, vp, vp, pd, pf, vp]
         L.smsm_learned_train_step.argtypes = [vp, vp, vp, ctypes.c_double, pd, vp]
         L.smsm_learned_residual.argtypes = [vp, vp, vp, pd, vp]
+        L.smsm_learned_solve_fallback.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, pd,
+                                                  ctypes.POINTER(ctypes.c_int), vp]
         L.smsm_learned_set_bf16.argtypes = [vp, st]
         for name in ("smsm_learned_create", "smsm_learned_destroy", "smsm_learned_get_params",
                      "smsm_learned_set_params", "smsm_learned_cnn_forward", "smsm_learned_cnn_backward",
                      "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
-                     "smsm_learned_residual", "smsm_learned_set_bf16"):
+                     "smsm_learned_residual", "smsm_learned_solve_fallback", "smsm_learned_set_bf16"):
             getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -570,6 +572,22 @@ class Learned:
                                            _stream_ptr(stream)), "smsm_learned_residual")
         return r.value
 
+    def solve_fallback(self, y, ratio: float = 1.5, res_ref: float = 0.0, out=None, stream=None):
+        """The learned solve, replaced by the plain IRLS solve when its
+        data-consistency residual exceeds ratio x the reference (res_ref, or
+        the plain solve's own when res_ref <= 0).  Returns (x, fell_back,
+        learned residual, reference residual)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.plan.shape_x, dtype=torch.complex128, device=y.device)
+        res = (ctypes.c_double * 2)()
+        fb = ctypes.c_int()
+        _check(lib().smsm_learned_solve_fallback(self._h, _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"),
+                                                 _dev_ptr(out, torch.complex128, self.plan.shape_x, "x"),
+                                                 float(ratio), float(res_ref), res, ctypes.byref(fb),
+                                                 _stream_ptr(stream)), "smsm_learned_solve_fallback")
+        return out, bool(fb.value), res[0], res[1]
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().smsm_learned_destroy(self._h)
@@ -599,4 +617,5 @@ smsm_learned_solve = Learned.solve
 smsm_learned_gradients = Learned.gradients
 smsm_learned_train_step = Learned.train_step
 smsm_learned_residual = Learned.residual
+smsm_learned_solve_fallback = Learned.solve_fallback
 smsm_learned_set_bf16 = Learned.set_bf16

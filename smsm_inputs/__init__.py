@@ -129,16 +129,19 @@ def caipi_shifts(n_slices: int) -> np.ndarray:
     return np.arange(n_slices, dtype=np.float64) / n_slices
 
 
-def make_case(geom: Geometry, seed: int, workload_id: int = 0) -> dict:
+def make_case(geom: Geometry, seed: int, workload_id: int = 0, noise: bool = True, coils=None) -> dict:
     """All random ingredients of one slice group, rounded to GPU precision.
 
     Returns a dict with
       rho    float32   [L][n][n]      magnitude phantoms
       phase  complex64 [L][Ns][n][n]  shot phases (unit modulus)
       coils  complex64 [L][Nc][n][n]  sensitivities
-      noise  complex64 [Ns][Nc][n][n] unit-variance complex noise
+      noise  complex64 [Ns][Nc][n][n] unit-variance complex noise (absent when noise=False,
+                                      for a consumer that draws it elsewhere)
       masks  uint8     [Ns][n]        ky sampling per shot
       shifts float64   [L]            CAIPI shift fractions
+    `coils`: the geometry's maps when already computed (they depend on the
+    geometry only); the phantoms and phases do not depend on either option.
     """
     g = geom
     ss = np.random.SeedSequence([int(workload_id), int(seed)])
@@ -148,17 +151,18 @@ def make_case(geom: Geometry, seed: int, workload_id: int = 0) -> dict:
     rho = np.stack([ellipse_phantom(r_ph, g.n) for _ in range(g.n_slices)])
     phase = np.stack([shot_phases(r_phase, g.n, g.n_shots, g.phase_order)
                       for _ in range(g.n_slices)])
-    coils = coil_maps(g.n, g.n_slices, g.n_coils)
-    shape = (g.n_shots, g.n_coils, g.n, g.n)
-    noise = (r_noise.standard_normal(shape) + 1j * r_noise.standard_normal(shape)) / np.sqrt(2.0)
-    return {
+    out = {
         "rho": rho.astype(np.float32),
         "phase": phase.astype(np.complex64),
-        "coils": coils.astype(np.complex64),
-        "noise": noise.astype(np.complex64),
+        "coils": (coil_maps(g.n, g.n_slices, g.n_coils) if coils is None else coils).astype(np.complex64),
         "masks": shot_masks(g.n, g.n_shots),
         "shifts": caipi_shifts(g.n_slices),
     }
+    if noise:
+        shape = (g.n_shots, g.n_coils, g.n, g.n)
+        nz = (r_noise.standard_normal(shape) + 1j * r_noise.standard_normal(shape)) / np.sqrt(2.0)
+        out["noise"] = nz.astype(np.complex64)
+    return out
 
 
 def random_complex(seed: int, shape, scale: float = 1.0) -> np.ndarray:

@@ -158,6 +158,10 @@ def test_learned_entry_points_reject_bad_arguments():
     assert lib.smsm_learned_train_step(None, None, None, 1e-3, ctypes.byref(d), None) == pkg.SMSM_E_INVALID
     assert lib.smsm_learned_residual(None, None, None, ctypes.byref(d), None) == pkg.SMSM_E_INVALID
     assert lib.smsm_learned_set_bf16(None, 1) == pkg.SMSM_E_INVALID
+    r2 = (ctypes.c_double * 2)()
+    fb = ctypes.c_int()
+    assert lib.smsm_learned_solve_fallback(None, None, None, 1.5, 0.0, r2, ctypes.byref(fb), None) == \
+        pkg.SMSM_E_INVALID
 
 
 def test_learned_parameter_layout_round_trip():

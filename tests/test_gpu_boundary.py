@@ -133,6 +133,8 @@ def test_every_flat_binding_once(torch_dev):
     call("smsm_learned_gradients", net, yd, xl)
     call("smsm_learned_train_step", net, yd, xl, 1e-4)
     assert call("smsm_learned_residual", net, xl, yd) >= 0.0
+    xf, fell, r_l, r_p = call("smsm_learned_solve_fallback", net, yd, 1.5)
+    assert r_l > 0 and r_p > 0 and fell == (r_l > 1.5 * r_p)
     call("smsm_learned_destroy", net)
     call("smsm_plan_destroy", plan)
     assert called == set(smsm.ABI_SYMBOLS), set(smsm.ABI_SYMBOLS) - called

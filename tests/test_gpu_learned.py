@@ -362,3 +362,27 @@ def test_cnn_wide_images_match_oracle(torch_dev, bf16):
         for k in range(5):
             assert rel(got[k][0], rgrads[k][0]) < tol, k
             assert rel(got[k][1], rgrads[k][1]) < tol, k
+
+
+def test_fallback_to_the_plain_solver_both_branches(torch_dev):
+    """smsm_learned_solve_fallback: with a ratio no residual can meet the
+    output is the plain IRLS solve (bit for bit), with one every residual
+    meets it is the learned solve; the residuals are those of the outputs."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    case, _, y = make_case(G32, 8, 99)
+    yd = torch.from_numpy(y).to(dev)
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, si.cnn_init(4, 8, width=8), width=8,
+                                                              n_unroll=2, n_cg=4, mu=0.5) as net:
+        x_plain = plan.solve(yd)                   # complex128 output (the plan's flag)
+        x_learned = net.solve(yd)
+        torch.cuda.synchronize()
+        x, fell, r_l, r_p = net.solve_fallback(yd, ratio=1e-9)
+        assert fell and torch.equal(x, x_plain)
+        assert abs(r_l - net.residual(x_learned, yd)) <= 1e-12 * r_l
+        assert abs(r_p - net.residual(x_plain, yd)) <= 1e-12 * r_p
+        x, fell, r_l2, _ = net.solve_fallback(yd, ratio=1e9)
+        assert not fell and torch.equal(x, x_learned) and r_l2 == r_l
+        # a caller's reference residual replaces the plain solve's
+        x, fell, _, r_ref = net.solve_fallback(yd, ratio=1.5, res_ref=0.5 * r_l)
+        assert fell and r_ref == 0.5 * r_l and torch.equal(x, x_plain)
