@@ -410,6 +410,68 @@ smsm_status smsm_learned_residual(smsm_learned* net, const void* x_dev, const vo
 smsm_status smsm_learned_solve_fallback(smsm_learned* net, const void* y_dev, void* x_dev, double ratio,
                                         double res_ref, double* res_out, int* fell_back, void* stream);
 
+/* ---- augmented-Lagrangian solve -----------------------------------------
+ *
+ * The paper's own solver of Eq. 10 (Theory, the paragraph after Eq. 10;
+ * Methods, "Reconstruction"; its steps are left to a cited paper, so they are
+ * taken from the method): split Z_l = H_l(x_l) with scaled duals U_l and
+ * repeat n_outer times
+ *     x   <- n_cg CG steps, warm-started, on
+ *            (A^H A + (beta/2) c) x = A^H y + (beta/2) sum_l H_l^H(Z_l - U_l)
+ *     Z_l <- singular-value soft thresholding of M_l = H_l(x_l) + U_l at
+ *            tau = lambda / beta,   U_l <- M_l - Z_l
+ * from x0 = A^H y, Z_l = H_l(x0), U_l = 0 (c = H_l^H H_l, the number of valid
+ * patches holding a sample).  The thresholding is M_l f(M_l^H M_l) with
+ * f(s^2) = max(1 - tau/s, 0), formed from the K x K Gram on the FP64 matrix
+ * cores (a scaled Newton-Schulz sign iteration for the projector on the
+ * singular values above tau, then the coupled iteration of the weights);
+ * singular values within about 1e-14 ||M^H M - tau^2 I||_F / tau^2 of tau
+ * relative may be placed on either side, where f is that close to zero.
+ * A Newton-Schulz step that does not converge sets the SMSM_E_NOT_CONVERGED
+ * flag of smsm_plan_status. */
+typedef struct smsm_al smsm_al;
+
+typedef struct {
+    double  lambda;   /* lambda of Eq. 10, > 0 (the plan's own lambda is not used) */
+    double  beta;     /* penalty weight of the split, > 0 */
+    int32_t n_outer;  /* outer iterations, >= 1 */
+    int32_t n_cg;     /* CG steps of each x-step, >= 0 */
+    int32_t n_sign;   /* steps of the sign iteration (0: as many as the 1e-14 resolution needs, about 43) */
+    uint32_t flags;   /* SMSM_FLAG_X_C128: x written complex128 */
+} smsm_al_params;
+
+/* Create the solver's state on a plan (same device): the duals in two
+ * buffers of [L][K][stride] complex128 (stride = smsm_al_dual_stride >= the
+ * (n1-r+1)(n2-r+1) patch anchors; about 1.2 GB for 256 x 256, 3 slices, 4
+ * shots, 7 x 7), six vectors of [L][Ns][n2][n1] complex128, Gram partials and
+ * K x K matrices, allocated here (smsm_al_device_bytes) and released by
+ * smsm_al_destroy.  The plan must outlive it.  Errors: SMSM_E_INVALID for
+ * null arguments or parameters out of range, SMSM_E_NOMEM, SMSM_E_DEVICE. */
+smsm_status smsm_al_create(smsm_plan* plan, const smsm_al_params* params, smsm_al** out);
+
+/* Release the state (synchronises the device first).  NULL is a no-op. */
+smsm_status smsm_al_destroy(smsm_al* al);
+
+/* Device bytes the state holds. */
+size_t smsm_al_device_bytes(const smsm_al* al);
+
+/* The solve: y_dev c64 [Ns][Nc][n2][n1] -> x_dev c64 (c128 with
+ * SMSM_FLAG_X_C128) [L][Ns][n2][n1].  Runs the operator chains in the plan's
+ * workspace (SMSM_E_INVALID without one); allocates nothing; asynchronous on
+ * `stream`.  The state and the plan must not be used concurrently. */
+smsm_status smsm_al_solve(smsm_al* al, const void* y_dev, void* x_dev, void* stream);
+
+/* Copy the scaled duals U_l of the last solve into u_dev: c128
+ * [L][K][stride], entry [l][k][p] = U_l[p][k] for patch anchor
+ * p = p2 (n1-r+1) + p1 < (n1-r+1)(n2-r+1) and column k = (i r + b2) r + b1
+ * (zero for p beyond the anchors).  At a solution, Y_l = (beta/lambda) U_l
+ * certifies optimality for Eq. 10: A^H(A x - y) + (lambda/2) sum_l H_l^H(Y_l) = 0,
+ * ||Y_l||_2 <= 1 and Re<Y_l, H_l(x_l)> = ||H_l(x_l)||_*.  Asynchronous. */
+smsm_status smsm_al_dual(smsm_al* al, void* u_dev, void* stream);
+
+/* Row stride (entries) of the dual layout; 0 for a null state. */
+long smsm_al_dual_stride(const smsm_al* al);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include "smsm_hyb.h"
 #include "smsm_cnn.h"
 #include "smsm_cnn_mfma.h"
+#include "smsm_al.h"
 #include "smsm.h"
 
 #include <hip/hip_ext.h>
@@ -1895,3 +1896,361 @@ smsm_status smsm_learned_residual(smsm_learned* Lr, const void* x_dev, const voi
 }
 
 }  // extern "C"
+
+// ---- augmented-Lagrangian solve ------------------------------------------
+
+struct smsm_al {
+    smsm_plan* P = nullptr;
+    int dev = 0;
+    AlGeo a{};
+    double lam = 0.0, beta = 0.0, tau = 0.0;
+    int n_outer = 0, n_cg = 0, n_sign = 0, nit_w = 0;
+    uint32_t flags = 0;
+    int chunk = 0, nchunk = 0, ntile = 0, npmax = 0;
+    void* arena = nullptr;
+    size_t bytes = 0;
+    double2 *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr;
+    double2 *hzu = nullptr, *hu = nullptr;   // H^H(Z - U) and H^H(U), [L][Ns][n2][n1]
+    double2* U[2] = {};                      // scaled duals [L][K][NPP]; U[cur] after a solve
+    int cur = 0;
+    double2* gpart = nullptr;                // Gram partials [L][nchunk][pairs][64][64]
+    double2 *G = nullptr, *Q = nullptr, *X[2] = {}, *T = nullptr, *Pr = nullptr, *C = nullptr;
+    double2 *Y[2] = {}, *Z[2] = {}, *Wp = nullptr, *F = nullptr;   // [L][KP][KP]
+    double *dpart0 = nullptr, *dpart1 = nullptr;   // dense partials [L][npmax]
+    double* smu = nullptr;    // mu^2 of the sign iteration's steps
+    double* ones = nullptr;   // [L] ones (unscaled products)
+    int* zeros = nullptr;     // [L] zeros (never-converged flags of the sign steps)
+    double *nsmu = nullptr, *wscale = nullptr, *tau2 = nullptr;
+    int* done = nullptr;      // coupled iteration: [(nit_w + 2) L]
+    double *part = nullptr, *scal = nullptr;   // CG partials [kVecBlocks], scalars
+};
+
+namespace {
+
+constexpr int kAlChunks = 16;          // patch chunks of the Gram partials
+constexpr double kAlSignLo = 1e-14;    // sign iteration: resolution relative to ||G - tau^2 I||_F
+constexpr double kAlMuMax = 1.6;       // largest scale of a sign step (p(1.6) = 0.352 > 0)
+constexpr int kAlNsIters = 30;         // cap of the coupled iteration for Gt^(-1/2)
+
+// Scales mu_k of the sign iteration X <- p(mu_k X), p(t) = 1.5 t - 0.5 t^3,
+// for a spectrum |X| within [lo, 1]: mu maximises the lower end, min(p(mu lo),
+// p(mu)) (p is increasing up to 1 and decreasing beyond), capped at
+// kAlMuMax; then plain steps until the lower end is 1 to rounding, and one
+// more.  The upper end stays 1 (p(mu t) peaks at t = 1/mu with value 1).
+std::vector<double> al_sign_schedule(double lo) {
+    auto pf = [](double t) { return 1.5 * t - 0.5 * t * t * t; };
+    std::vector<double> mu;
+    while (1.0 - lo > 1e-16 && mu.size() < 200) {
+        double m = 1.0;
+        if (lo < 0.5) {
+            if (pf(kAlMuMax * lo) < pf(kAlMuMax)) {
+                m = kAlMuMax;
+            } else {
+                double u = 1.0, v = kAlMuMax;
+                for (int it = 0; it < 80; ++it) {
+                    const double c = 0.5 * (u + v);
+                    if (pf(c * lo) < pf(c)) u = c;
+                    else v = c;
+                }
+                m = 0.5 * (u + v);
+            }
+        }
+        lo = std::min(pf(m * lo), pf(m));
+        mu.push_back(m);
+    }
+    mu.push_back(1.0);
+    return mu;
+}
+
+smsm_status al_launch_gemm_norm(smsm_al* A, const double2* a0, const double2* b0, double2* c0, hipStream_t st) {
+    HgArgs u{};
+    u.A0 = a0; u.B0 = b0; u.C0 = c0;
+    u.part_in = A->ones;
+    u.np_in = 1;
+    u.part_out = A->dpart1;
+    hipLaunchKernelGGL(k_zgemm<HG_NORM>, dim3(A->ntile, 1, A->a.L), dim3(64 * HW), 0, st, A->a.K, A->a.KP, u);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// F = f(M^H M) of the split M = H(x) + U[cur] (see smsm_al.h).
+smsm_status al_threshold(smsm_al* A, hipStream_t st) {
+    const AlGeo& a = A->a;
+    const int npair = a.KB * (a.KB + 1) / 2;
+    hipLaunchKernelGGL(k_al_gram, dim3(npair, A->nchunk, a.L), dim3(kThreads), 0, st, a, A->x, A->U[A->cur],
+                       A->chunk, A->gpart);
+    LAUNCH_CHECK();
+    const dim3 dg(kPadBlocks, a.L);
+    hipLaunchKernelGGL(k_al_gram_sum, dg, dim3(kThreads), 0, st, a, A->gpart, A->nchunk, A->tau * A->tau, A->G,
+                       A->Q, A->dpart0);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_al_sign_start, dg, dim3(kThreads), 0, st, a.KP, A->Q, A->dpart0, kPadBlocks, A->X[0]);
+    LAUNCH_CHECK();
+    int xc = 0;
+    for (int k = 0; k < A->n_sign; ++k) {
+        HgArgs t{};
+        t.A0 = A->X[xc]; t.B0 = A->X[xc]; t.C0 = A->T;
+        t.done_cur = A->zeros;
+        t.part_out = A->dpart0;
+        t.mu = A->smu + k;
+        t.mu_stride = 0;
+        hipLaunchKernelGGL(k_zgemm<HG_NS>, dim3(A->ntile, 1, a.L), dim3(64 * HW), 0, st, a.K, a.KP, t);
+        LAUNCH_CHECK();
+        smsm_status s = al_launch_gemm_norm(A, A->X[xc], A->T, A->X[xc ^ 1], st);
+        if (s) return s;
+        xc ^= 1;
+    }
+    hipLaunchKernelGGL(k_al_proj, dg, dim3(kThreads), 0, st, a.K, a.KP, A->X[xc], A->Pr);
+    LAUNCH_CHECK();
+    smsm_status s = al_launch_gemm_norm(A, A->G, A->Pr, A->C, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_al_gtilde, dg, dim3(kThreads), 0, st, a.K, a.KP, A->C, A->Pr, A->tau * A->tau, A->Y[0],
+                       A->dpart0);
+    LAUNCH_CHECK();
+    const int nit = A->nit_w;
+    hipLaunchKernelGGL(k_ns_start, dg, dim3(kThreads), 0, st, a.K, a.KP, a.L, A->tau2, 1.0, A->dpart0, kPadBlocks,
+                       A->Y[0], A->Z[0], A->wscale, A->done, nit, A->nsmu);
+    LAUNCH_CHECK();
+    for (int k = 0; k < nit; ++k) {
+        const int c0 = k & 1, c1 = c0 ^ 1;
+        HgArgs t{};
+        t.A0 = A->Z[c0]; t.B0 = A->Y[c0]; t.C0 = A->T;
+        t.done_cur = A->done + (size_t)k * a.L;
+        t.part_out = A->dpart0;
+        t.mu = A->nsmu + (size_t)k * a.L;
+        t.mu_stride = 1;
+        hipLaunchKernelGGL(k_zgemm<HG_NS>, dim3(A->ntile, 1, a.L), dim3(64 * HW), 0, st, a.K, a.KP, t);
+        LAUNCH_CHECK();
+        HgArgs u{};
+        u.A0 = A->Y[c0]; u.B0 = A->T; u.C0 = A->Y[c1];
+        u.A1 = A->T; u.B1 = A->Z[c0]; u.C1 = A->Z[c1];
+        u.done_cur = A->done + (size_t)k * a.L;
+        u.done_next = A->done + (size_t)(k + 1) * a.L;
+        u.last = A->done + (size_t)(nit + 1) * a.L;
+        u.par = c1;
+        u.tol2 = kNsTol * kNsTol;
+        u.part_in = A->dpart0;
+        u.np_in = A->ntile;
+        hipLaunchKernelGGL(k_zgemm<HG_PAIR>, dim3(A->ntile, 1, 2 * a.L), dim3(64 * HW), 0, st, a.K, a.KP, u);
+        LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_al_pick, dg, dim3(kThreads), 0, st, a.K, a.KP, A->Z[0], A->Z[1],
+                       A->done + (size_t)(nit + 1) * a.L, A->done + (size_t)nit * a.L, A->wscale, A->Wp,
+                       A->P->flags);
+    LAUNCH_CHECK();
+    if ((s = al_launch_gemm_norm(A, A->Pr, A->Wp, A->C, st))) return s;
+    hipLaunchKernelGGL(k_al_f, dg, dim3(kThreads), 0, st, a.K, a.KP, A->C, A->Pr, A->tau, A->F);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+long al_nvec(const smsm_al* A) { return (long)A->a.L * A->a.Ns * A->a.n2 * A->a.n1; }
+
+smsm_status al_dot(smsm_al* A, const double2* u, const double2* v, hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_dot, vec_grid(), dim3(kThreads), 0, st, al_nvec(A), u, v, A->part);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+smsm_status al_scalar(smsm_al* A, int mode, double* rr, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(kThreads), 0, st, mode, A->part, kVecBlocks, rr, 0.0, out);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+smsm_status al_axpy(smsm_al* A, const double2* u, const double2* v, const double* fp, double fm, double2* out,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_dc_axpy, vec_grid(), dim3(kThreads), 0, st, al_nvec(A), u, v, fp, fm, out);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// out = (A^H A + (beta/2) c) v
+smsm_status al_normal(smsm_al* A, const double2* v, double2* out, hipStream_t st) {
+    smsm_status s = chain_normal(A->P, v, out, COL_NORMAL, false, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_al_diag, vec_grid(), dim3(kThreads), 0, st, A->a, v, 0.5 * A->beta, out);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+// n_cg CG steps on the x-step's system from the current x (the oracle's
+// recurrence: r = rhs - N x, p = r, alpha = |r|^2 / <p, N p>, beta = |r'|^2 / |r|^2).
+smsm_status al_cg(smsm_al* A, hipStream_t st) {
+    double* sc = A->scal;
+    smsm_status s;
+    if ((s = al_normal(A, A->x, A->q, st))) return s;
+    if ((s = al_axpy(A, A->rhs, A->q, nullptr, -1.0, A->r, st))) return s;
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, al_nvec(A), A->r, A->p);
+    LAUNCH_CHECK();
+    if ((s = al_dot(A, A->r, A->r, st)) || (s = al_scalar(A, 0, nullptr, sc + 1, st))) return s;
+    for (int j = 0; j < A->n_cg; ++j) {
+        if ((s = al_normal(A, A->p, A->q, st))) return s;
+        if ((s = al_dot(A, A->p, A->q, st)) || (s = al_scalar(A, 1, sc + 1, sc + 2, st))) return s;
+        if ((s = al_axpy(A, A->x, A->p, sc + 2, 1.0, A->x, st))) return s;
+        if ((s = al_axpy(A, A->r, A->q, sc + 2, -1.0, A->r, st))) return s;
+        if ((s = al_dot(A, A->r, A->r, st)) || (s = al_scalar(A, 2, sc + 1, sc + 3, st))) return s;
+        if ((s = al_axpy(A, A->r, A->p, sc + 3, 1.0, A->p, st))) return s;
+    }
+    return SMSM_OK;
+}
+
+void al_release(smsm_al* A) {
+    if (!A) return;
+    if (A->arena && hipSetDevice(A->dev) == hipSuccess) (void)hipFree(A->arena);
+    delete A;
+}
+
+}  // namespace
+
+extern "C" {
+
+smsm_status smsm_al_create(smsm_plan* P, const smsm_al_params* prm, smsm_al** out) {
+    if (!out) return SMSM_E_INVALID;
+    *out = nullptr;
+    if (!P || !prm || !(prm->lambda > 0.0) || !(prm->beta > 0.0) || prm->n_outer < 1 || prm->n_cg < 0 ||
+        prm->n_sign < 0 || prm->n_sign > 200 || (prm->flags & ~SMSM_FLAG_X_C128))
+        return SMSM_E_INVALID;
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const Geo& g = P->g;
+    smsm_al* A = new (std::nothrow) smsm_al;
+    if (!A) return SMSM_E_NOMEM;
+    A->P = P;
+    A->dev = P->dev;
+    AlGeo& a = A->a;
+    a.n1 = g.n1; a.n2 = g.n2; a.L = g.L; a.Ns = g.Ns; a.r = g.r; a.K = g.K; a.KP = dense_stride(g.K);
+    a.P1 = g.n1 - g.r + 1; a.P2 = g.n2 - g.r + 1; a.NP = a.P1 * a.P2;
+    a.NPP = (a.NP + AL_PT - 1) / AL_PT * AL_PT;
+    a.KB = (g.K + AL_BK - 1) / AL_BK;
+    A->lam = prm->lambda;
+    A->beta = prm->beta;
+    A->tau = prm->lambda / prm->beta;
+    A->n_outer = prm->n_outer;
+    A->n_cg = prm->n_cg;
+    A->flags = prm->flags;
+    A->nit_w = kAlNsIters;
+    std::vector<double> smu = al_sign_schedule(kAlSignLo);
+    if (prm->n_sign > 0) smu.resize(prm->n_sign, 1.0);
+    A->n_sign = (int)smu.size();
+    for (double& m : smu) m = m * m;   // k_zgemm<HG_NS> takes mu^2 (its T = sqrt(m) (1.5 I - 0.5 m X^2))
+    A->nchunk = std::min(kAlChunks, (a.NP + AL_SL - 1) / AL_SL);
+    A->chunk = ((a.NP + A->nchunk - 1) / A->nchunk + AL_SL - 1) / AL_SL * AL_SL;
+    A->nchunk = (a.NP + A->chunk - 1) / A->chunk;
+    A->ntile = dense_tiles(g.K);
+    A->npmax = std::max(A->ntile, kPadBlocks);
+    const size_t nvec = (size_t)g.L * g.Ns * g.n2 * g.n1;
+    const size_t nu = (size_t)g.L * g.K * a.NPP;
+    const size_t nd = (size_t)g.L * a.KP * a.KP;
+    const int npair = a.KB * (a.KB + 1) / 2;
+    Carver cv;
+    size_t ov[8];
+    for (int k = 0; k < 8; ++k) ov[k] = cv.take<double2>(nvec);
+    const size_t ou0 = cv.take<double2>(nu), ou1 = cv.take<double2>(nu);
+    const size_t ogp = cv.take<double2>((size_t)g.L * A->nchunk * npair * AL_BK * AL_BK);
+    size_t od[13];
+    for (int k = 0; k < 13; ++k) od[k] = cv.take<double2>(nd);
+    const size_t op0 = cv.take<double>((size_t)g.L * A->npmax), op1 = cv.take<double>((size_t)g.L * A->npmax);
+    const size_t osmu = cv.take<double>(smu.size()), oones = cv.take<double>(g.L), ozeros = cv.take<int>(g.L);
+    const size_t onsmu = cv.take<double>((size_t)A->nit_w * g.L), ows = cv.take<double>(g.L),
+                 otau2 = cv.take<double>(g.L);
+    const size_t odone = cv.take<int>((size_t)(A->nit_w + 2) * g.L);
+    const size_t opart = cv.take<double>(kVecBlocks), oscal = cv.take<double>(16);
+    A->bytes = cv.off;
+    if (hipMalloc(&A->arena, cv.off) != hipSuccess) {
+        delete A;
+        return SMSM_E_NOMEM;
+    }
+    char* base = static_cast<char*>(A->arena);
+    double2** vecs[8] = {&A->b, &A->x, &A->r, &A->p, &A->q, &A->rhs, &A->hzu, &A->hu};
+    for (int k = 0; k < 8; ++k) *vecs[k] = (double2*)(base + ov[k]);
+    A->U[0] = (double2*)(base + ou0);
+    A->U[1] = (double2*)(base + ou1);
+    A->gpart = (double2*)(base + ogp);
+    double2** dn[13] = {&A->G, &A->Q, &A->X[0], &A->X[1], &A->T, &A->Pr, &A->C,
+                        &A->Y[0], &A->Y[1], &A->Z[0], &A->Z[1], &A->Wp, &A->F};
+    for (int k = 0; k < 13; ++k) *dn[k] = (double2*)(base + od[k]);
+    A->dpart0 = (double*)(base + op0);
+    A->dpart1 = (double*)(base + op1);
+    A->smu = (double*)(base + osmu);
+    A->ones = (double*)(base + oones);
+    A->zeros = (int*)(base + ozeros);
+    A->nsmu = (double*)(base + onsmu);
+    A->wscale = (double*)(base + ows);
+    A->tau2 = (double*)(base + otau2);
+    A->done = (int*)(base + odone);
+    A->part = (double*)(base + opart);
+    A->scal = (double*)(base + oscal);
+    std::vector<double> ones(g.L, 1.0), t2(g.L, A->tau * A->tau);
+    std::vector<int> zeros(g.L, 0);
+    bool ok = hipMemcpy(A->smu, smu.data(), smu.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(A->ones, ones.data(), g.L * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(A->zeros, zeros.data(), g.L * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(A->tau2, t2.data(), g.L * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+    // the dense buffers' padding stays zero from here on (every kernel writes zeros there)
+    ok = ok && hipMemset(base + ov[0], 0, osmu - ov[0]) == hipSuccess;
+    ok = ok && hipMemset(A->scal, 0, 16 * sizeof(double)) == hipSuccess;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        al_release(A);
+        return SMSM_E_DEVICE;
+    }
+    *out = A;
+    return SMSM_OK;
+}
+
+smsm_status smsm_al_destroy(smsm_al* A) {
+    if (A && hipSetDevice(A->dev) == hipSuccess) (void)hipDeviceSynchronize();
+    al_release(A);
+    return SMSM_OK;
+}
+
+size_t smsm_al_device_bytes(const smsm_al* A) { return A ? A->bytes : 0; }
+
+smsm_status smsm_al_solve(smsm_al* A, const void* y_dev, void* x_dev, void* stream) {
+    if (!A || !y_dev || !x_dev) return SMSM_E_INVALID;
+    smsm_plan* P = A->P;
+    if (!P->ws) return SMSM_E_INVALID;   // the plan's workspace carries the operator chains' buffers
+    if (hipSetDevice(A->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    const AlGeo& a = A->a;
+    const long n = al_nvec(A);
+    smsm_status s = chain_AH_hyb(P, (const float2*)y_dev, P->h2, st);
+    if (s) return s;
+    if ((s = rows_fwd(P, P->h2, A->b, st))) return s;                          // b = A^H y
+    hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, n, A->b, A->x);   // x0 = b
+    LAUNCH_CHECK();
+    A->cur = 0;
+    hipLaunchKernelGGL(k_zero_c128, vec_grid(), dim3(kThreads), 0, st, (long)a.L * a.K * a.NPP, A->U[0]);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_al_init, vec_grid(), dim3(kThreads), 0, st, a, A->x, A->hu, A->hzu);
+    LAUNCH_CHECK();
+    const int KB = a.KB;
+    for (int it = 0; it < A->n_outer; ++it) {
+        if ((s = al_axpy(A, A->b, A->hzu, nullptr, 0.5 * A->beta, A->rhs, st))) return s;   // b + (beta/2) H^H(Z - U)
+        if ((s = al_cg(A, st))) return s;
+        if ((s = al_threshold(A, st))) return s;
+        hipLaunchKernelGGL(k_al_update, dim3(a.NPP / AL_PT * KB, 1, a.L), dim3(kThreads), 0, st, a, A->x,
+                           A->U[A->cur], A->F, A->U[A->cur ^ 1]);
+        LAUNCH_CHECK();
+        A->cur ^= 1;
+        hipLaunchKernelGGL(k_al_gather, dim3(1024), dim3(kThreads), 0, st, a, A->x, A->U[A->cur], A->hu, A->hzu);
+        LAUNCH_CHECK();
+    }
+    if (A->flags & SMSM_FLAG_X_C128)
+        hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, n, A->x, (double2*)x_dev);
+    else
+        hipLaunchKernelGGL(k_to_c64, vec_grid(), dim3(kThreads), 0, st, n, A->x, (float2*)x_dev);
+    LAUNCH_CHECK();
+    return SMSM_OK;
+}
+
+smsm_status smsm_al_dual(smsm_al* A, void* u_dev, void* stream) {
+    if (!A || !u_dev) return SMSM_E_INVALID;
+    if (hipSetDevice(A->dev) != hipSuccess) return SMSM_E_DEVICE;
+    const AlGeo& a = A->a;
+    return hipMemcpyAsync(u_dev, A->U[A->cur], (size_t)a.L * a.K * a.NPP * sizeof(double2), hipMemcpyDeviceToDevice,
+                          S(stream)) == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+}
+
+long smsm_al_dual_stride(const smsm_al* A) { return A ? (long)A->a.NPP : 0; }
+
+}  // extern "C"
+

@@ -40,6 +40,8 @@ ABI_SYMBOLS = (
     "smsm_learned_param_count", "smsm_learned_get_params", "smsm_learned_set_params", "smsm_learned_cnn_forward",
     "smsm_learned_cnn_backward", "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
     "smsm_learned_residual", "smsm_learned_solve_fallback", "smsm_learned_set_bf16",
+    "smsm_al_create", "smsm_al_destroy", "smsm_al_device_bytes", "smsm_al_solve", "smsm_al_dual",
+    "smsm_al_dual_stride",
 )
 KERNEL_IDS = {"col_normal": 0, "rows_inv": 1, "rows_fwd": 2, "band_corr": 3, "cg_update": 4, "band_extract": 5}
 
@@ -54,6 +56,11 @@ class Params(ctypes.Structure):
                 ("eps_frac", ctypes.c_double), ("eps_decay", ctypes.c_double),
                 ("eps_floor_frac", ctypes.c_double), ("ns_max_iter", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class ALParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("beta", ctypes.c_double), ("n_outer", ctypes.c_int32),
+                ("n_cg", ctypes.c_int32), ("n_sign", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class SmsmError(RuntimeError):
@@ -142,6 +149,18 @@ def lib() -> ctypes.CDLL:
                      "smsm_learned_solve", "smsm_learned_gradients", "smsm_learned_train_step",
                      "smsm_learned_residual", "smsm_learned_solve_fallback", "smsm_learned_set_bf16"):
             getattr(L, name).restype = st
+        L.smsm_al_create.argtypes = [vp, ctypes.POINTER(ALParams), pvp]
+        L.smsm_al_create.restype = st
+        L.smsm_al_destroy.argtypes = [vp]
+        L.smsm_al_destroy.restype = st
+        L.smsm_al_device_bytes.argtypes = [vp]
+        L.smsm_al_device_bytes.restype = ctypes.c_size_t
+        L.smsm_al_solve.argtypes = [vp, vp, vp, vp]
+        L.smsm_al_solve.restype = st
+        L.smsm_al_dual.argtypes = [vp, vp, vp]
+        L.smsm_al_dual.restype = st
+        L.smsm_al_dual_stride.argtypes = [vp]
+        L.smsm_al_dual_stride.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -212,6 +231,7 @@ class Plan:
         _check(st, "smsm_plan_create")
         self._h = out
         self._ws = None
+        self.device = coils.device
         if isinstance(workspace, str) and workspace == "auto":
             self.set_workspace(torch.empty(self.workspace_bytes(), dtype=torch.uint8, device=coils.device))
         elif workspace is not None:
@@ -619,3 +639,73 @@ smsm_learned_train_step = Learned.train_step
 smsm_learned_residual = Learned.residual
 smsm_learned_solve_fallback = Learned.solve_fallback
 smsm_learned_set_bf16 = Learned.set_bf16
+
+
+class AL:
+    """The augmented-Lagrangian solve of Eq. 10 on a plan (smsm_al_*): the
+    split Z = H(x) with scaled duals U, singular-value thresholding at
+    lam / beta, n_outer outer iterations of n_cg CG steps each."""
+
+    def __init__(self, plan: Plan, lam: float, beta: float, n_outer: int = 30, n_cg: int = 5, n_sign: int = 0,
+                 c128: bool = True):
+        p = ALParams(float(lam), float(beta), int(n_outer), int(n_cg), int(n_sign),
+                     SMSM_FLAG_X_C128 if c128 else 0)
+        h = ctypes.c_void_p()
+        _check(lib().smsm_al_create(plan._h, ctypes.byref(p), ctypes.byref(h)), "smsm_al_create")
+        self._h = h
+        self.plan = plan
+        self.lam, self.beta, self.n_outer, self.n_cg, self.c128 = lam, beta, n_outer, n_cg, c128
+        L, Ns, n2, n1 = plan.shape_x
+        r = plan.geom.filt
+        self.n_anchor = (n2 - r + 1) * (n1 - r + 1)
+        self.shape_dual = (L, Ns * r * r, int(lib().smsm_al_dual_stride(h)))
+
+    def device_bytes(self) -> int:
+        return int(lib().smsm_al_device_bytes(self._h))
+
+    def solve(self, y, out=None, stream=None):
+        import torch
+        dt = torch.complex128 if self.c128 else torch.complex64
+        if out is None:
+            out = torch.empty(self.plan.shape_x, dtype=dt, device=y.device)
+        _check(lib().smsm_al_solve(self._h, _dev_ptr(y, torch.complex64, self.plan.shape_y, "y"),
+                                   _dev_ptr(out, dt, self.plan.shape_x, "x"), _stream_ptr(stream)), "smsm_al_solve")
+        return out
+
+    def dual(self, out=None, stream=None):
+        """The scaled duals of the last solve, [L][K][stride] complex128
+        (entry [l][k][p] = U_l[p][k] for p < n_anchor, zero beyond)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.shape_dual, dtype=torch.complex128, device=self.plan.device)
+        _check(lib().smsm_al_dual(self._h, _dev_ptr(out, torch.complex128, self.shape_dual, "u"),
+                                  _stream_ptr(stream)), "smsm_al_dual")
+        return out
+
+    def dual_stride(self) -> int:
+        return int(lib().smsm_al_dual_stride(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().smsm_al_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+smsm_al_create = AL
+smsm_al_destroy = AL.close
+smsm_al_device_bytes = AL.device_bytes
+smsm_al_solve = AL.solve
+smsm_al_dual = AL.dual
+smsm_al_dual_stride = AL.dual_stride

@@ -37,13 +37,13 @@ def test_binding_has_a_function_per_declared_symbol():
 def test_flat_names_are_the_marshalling_methods():
     # each flat name is the class method (or constructor) that marshals the
     # call, so no name can drift from what the class does
-    owners = {"plan": smsm.Plan, "batch": smsm.Batch, "learned": smsm.Learned}
+    owners = {"plan": smsm.Plan, "batch": smsm.Batch, "learned": smsm.Learned, "al": smsm.AL}
     for name in declared_symbols():
         f = getattr(smsm, name)
         if name == "smsm_status_string":
             assert f is smsm.status_string
             continue
-        kind = "batch" if name.startswith("smsm_batch") else "learned" if name.startswith("smsm_learned") else "plan"
+        kind = next((k for k in ("batch", "learned", "al") if name.startswith(f"smsm_{k}_")), "plan")
         cls = owners[kind]
         assert f is cls or any(f is getattr(v, "fget", v) for v in vars(cls).values()), name
 
@@ -162,6 +162,28 @@ def test_learned_entry_points_reject_bad_arguments():
     fb = ctypes.c_int()
     assert lib.smsm_learned_solve_fallback(None, None, None, 1.5, 0.0, r2, ctypes.byref(fb), None) == \
         pkg.SMSM_E_INVALID
+
+
+@needs_lib
+def test_al_entry_points_reject_bad_arguments():
+    lib = smsm.lib()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)            # never dereferenced: validation fails first
+    good = smsm.ALParams(1e-3, 1e-4, 10, 5, 0, 0)
+    assert lib.smsm_al_create(None, ctypes.byref(good), ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_al_create(fake, None, ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert lib.smsm_al_create(fake, ctypes.byref(good), None) == pkg.SMSM_E_INVALID
+    for bad in (smsm.ALParams(0.0, 1e-4, 10, 5, 0, 0), smsm.ALParams(1e-3, 0.0, 10, 5, 0, 0),
+                smsm.ALParams(1e-3, float("nan"), 10, 5, 0, 0), smsm.ALParams(1e-3, 1e-4, 0, 5, 0, 0),
+                smsm.ALParams(1e-3, 1e-4, 10, -1, 0, 0), smsm.ALParams(1e-3, 1e-4, 10, 5, -1, 0),
+                smsm.ALParams(1e-3, 1e-4, 10, 5, 201, 0), smsm.ALParams(1e-3, 1e-4, 10, 5, 0, 0x2)):
+        assert lib.smsm_al_create(fake, ctypes.byref(bad), ctypes.byref(out)) == pkg.SMSM_E_INVALID
+    assert out.value is None
+    assert lib.smsm_al_destroy(None) == pkg.SMSM_OK
+    assert lib.smsm_al_device_bytes(None) == 0
+    assert lib.smsm_al_dual_stride(None) == 0
+    assert lib.smsm_al_solve(None, None, None, None) == pkg.SMSM_E_INVALID
+    assert lib.smsm_al_dual(None, None, None) == pkg.SMSM_E_INVALID
 
 
 def test_learned_parameter_layout_round_trip():

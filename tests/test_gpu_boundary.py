@@ -136,5 +136,12 @@ def test_every_flat_binding_once(torch_dev):
     xf, fell, r_l, r_p = call("smsm_learned_solve_fallback", net, yd, 1.5)
     assert r_l > 0 and r_p > 0 and fell == (r_l > 1.5 * r_p)
     call("smsm_learned_destroy", net)
+    solver = call("smsm_al_create", plan, 1e-3, 1e-4, 2, 2)
+    assert call("smsm_al_device_bytes", solver) > 0
+    assert call("smsm_al_dual_stride", solver) >= solver.n_anchor
+    xa = call("smsm_al_solve", solver, yd)
+    assert xa.shape == plan.shape_x
+    assert call("smsm_al_dual", solver).shape == solver.shape_dual
+    call("smsm_al_destroy", solver)
     call("smsm_plan_destroy", plan)
     assert called == set(smsm.ABI_SYMBOLS), set(smsm.ABI_SYMBOLS) - called
