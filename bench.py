@@ -320,6 +320,72 @@ def learned_measurement(torch, dev, plan, g, workload, n_train=2000, n_eval=200,
             "vs_stored_oracle": oracle_cmp}
 
 
+# AL penalty per workload: tau = lambda / beta keeps about a quarter of the
+# singular values of H(A^H y) above the threshold (0.4 .. 43 at 64 x 64,
+# 0.9 .. 241 at 256 x 256)
+AL_BETA = {"small": 1e-4, "sg256": 2e-5}
+AL_OUTER, AL_CG = 30, 5
+
+
+def al_measurement(torch, dev, plan, g, workload, case, reps=3):
+    """The augmented-Lagrangian solve of Eq. 10 (smsm_al_*) on the timed
+    workload: AL_OUTER outer iterations of AL_CG CG steps at the workload's
+    lambda, slice-groups/s over `reps` solves after one warm-up; the objective
+    of Eq. 10 (evaluated by the oracle on the host) at its result and at the
+    IRLS solve's of the same input; and its parity with the oracle's AL on the
+    small workload (10 outer iterations of 5 CG steps)."""
+    import smsm_inputs as si
+    from oracle import al_oracle as al
+    from oracle import smsm_oracle as o
+    from paper_1901_01893_amd import smsm
+    lam, beta = g.lam, AL_BETA[workload]
+    _, y_or = o.simulate(case, g.n_slices, g.snr)
+    y_or = y_or.astype(np.complex64)
+    yd = torch.from_numpy(y_or).to(dev)
+    with smsm.AL(plan, lam, beta, AL_OUTER, AL_CG) as s:
+        x = s.solve(yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.solve(yd, x)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        status = plan.status()
+        state_mb = s.device_bytes() / 1e6
+        x_al = x.cpu().numpy()
+    base = smsm.Params.from_buffer_copy(plan.params)
+    try:
+        plan.set_params(with_flags(smsm, base, smsm.SMSM_FLAG_X_C128))
+        x_irls = plan.solve(yd).cpu().numpy()
+    finally:
+        plan.set_params(base)
+    theta = o.caipi_phase(g.n, case["shifts"])
+    y64 = y_or.astype(np.complex128)
+    j_al = o.objective(x_al, y64, case["coils"], case["masks"], theta, lam, g.filt)
+    j_irls = o.objective(x_irls, y64, case["coils"], case["masks"], theta, lam, g.filt)
+    # parity with the oracle's AL on the small workload
+    gs = si.WORKLOADS["small"]
+    cs = si.make_case(gs, 3, 300)
+    _, ys = o.simulate(cs, gs.n_slices, gs.snr)
+    ys = ys.astype(np.complex64)
+    with smsm.Plan(gs.n, gs.n, gs.n_slices, gs.n_shots, gs.n_coils, gs.filt, torch.from_numpy(cs["coils"]).to(dev),
+                   cs["masks"], cs["shifts"], smsm.make_params(lam=gs.lam, n_irls=1, n_cg=1)) as ps, \
+            smsm.AL(ps, gs.lam, AL_BETA["small"], 10, 5) as ss:
+        xs = ss.solve(torch.from_numpy(ys).to(dev)).cpu().numpy()
+    xr = al.solve_al(ys.astype(np.complex128), cs["coils"], cs["masks"], cs["shifts"],
+                     al.ALParams(lam=gs.lam, r=gs.filt, beta=AL_BETA["small"], n_outer=10, n_cg=5))
+    return {"form": "augmented Lagrangian (split Z = H(x), scaled duals, singular-value thresholding at "
+                    "lambda / beta from the K x K Gram by Newton-Schulz matrix functions on the FP64 matrix "
+                    "cores), FP64",
+            "lambda": lam, "beta": beta, "outer_iterations": AL_OUTER, "cg_per_outer": AL_CG,
+            "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 2),
+            "ms_per_outer_iteration": round(t * 1e3 / AL_OUTER, 3), "state_mb": round(state_mb, 1),
+            "status": smsm.status_string(status),
+            "objective_eq10": {"al": j_al, "irls": j_irls, "al_over_irls": j_al / j_irls},
+            "rel_diff_al_vs_irls": float(np.linalg.norm(x_al - x_irls) / np.linalg.norm(x_irls)),
+            "nrmse_vs_oracle_al_small": o.nrmse(xs, xr)}
+
+
 def time_kernel(torch, plan, name, reps):
     stream = torch.cuda.current_stream()
     plan.launch_kernel(name, 2)
@@ -497,8 +563,11 @@ def main():
     ap.add_argument("--learned-train", type=int, default=2000, help="training instances of the learned form")
     ap.add_argument("--learned-eval", type=int, default=200, help="held-out instances of the learned form")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision-form measurement")
+    ap.add_argument("--no-al", action="store_true", help="skip the augmented-Lagrangian measurement")
     ap.add_argument("--profile-learned", type=int, default=0, metavar="STEPS",
                     help="run only STEPS training steps and STEPS solves of the learned form (for a kernel trace)")
+    ap.add_argument("--profile-al", type=int, default=0, metavar="SOLVES",
+                    help="run only SOLVES augmented-Lagrangian solves of the workload (for a kernel trace)")
     ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -520,6 +589,15 @@ def main():
     ys = synth_inputs(torch, dev, plan, g, case, 1 if args.profile_kernel else N_DRAWS)
     y = ys[0]
     x = torch.empty(plan.shape_x, dtype=torch.complex64, device=dev)
+    if args.profile_al:
+        with smsm.AL(plan, g.lam, AL_BETA[args.workload], AL_OUTER, AL_CG) as s:
+            xa = s.solve(y)
+            for _ in range(args.profile_al - 1):
+                s.solve(y, xa)
+            torch.cuda.synchronize()
+        plan.close()
+        print(json.dumps({"profile_al": args.profile_al, "workload": args.workload}))
+        return
     if args.profile_learned:
         import smsm_inputs as si
         net = smsm.Learned(plan, si.cnn_init(1, 2 * g.n_shots, width=64), width=64, n_unroll=5, n_cg=10, mu=0.05)
@@ -605,6 +683,8 @@ def main():
         out["batched"] = batched_measurement(torch, dev, args.batch_streams, 3)
     if not args.no_mixed:
         out["mixed"] = mixed_measurement(torch, dev, plan, g, args.workload, ys, x)
+    if not args.no_al and args.workload in AL_BETA:
+        out["al"] = al_measurement(torch, dev, plan, g, args.workload, case)
     if not args.no_learned:
         out["learned"] = learned_measurement(torch, dev, plan, g, args.workload, n_train=args.learned_train,
                                              n_eval=args.learned_eval)

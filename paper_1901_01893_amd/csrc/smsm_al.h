@@ -65,7 +65,7 @@ SMSM_DEV int al_col_off(const AlGeo& a, int k) {
 // diagonal) are staged in shared memory, the
 // next slab's loads in flight during the current slab's products.
 // part[l][chunk][pair][64][64] (tiles outside K written as zero).
-__global__ void __launch_bounds__(256) k_al_gram(AlGeo a, const double2* __restrict__ x,
+__global__ void __launch_bounds__(256, 2) k_al_gram(AlGeo a, const double2* __restrict__ x,
                                                  const double2* __restrict__ U, int chunk,
                                                  double2* __restrict__ part) {
     __shared__ double2 sa[AL_SL][AL_STR];
@@ -297,7 +297,7 @@ __global__ void k_al_f(int K, int KP, const double2* __restrict__ C, const doubl
 // 16 w of the block against the tile's 64 patches (4 tiles of
 // v_mfma_f64_16x16x4f64); chunks of 16 j of M^T and F staged in shared memory,
 // the next chunk's loads in flight during the current chunk's products.
-__global__ void __launch_bounds__(256) k_al_update(AlGeo a, const double2* __restrict__ x,
+__global__ void __launch_bounds__(256, 2) k_al_update(AlGeo a, const double2* __restrict__ x,
                                                    const double2* __restrict__ Uin, const double2* __restrict__ F,
                                                    double2* __restrict__ Uout) {
     __shared__ double2 sm[16][AL_STR];   // M^T chunk [j][p]

@@ -107,6 +107,28 @@ def test_al_solve_matches_oracle(torch_dev, name):
     assert e_x < SOLVE_TOL and e_u < SOLVE_TOL
 
 
+# the 256 x 256 slice group (32 coils, MB3, 4 shots, 7 x 7): tau = lam / beta = 50
+# keeps about a quarter of the singular values of H(A^H y) (0.9 .. 241)
+SG256_LAM, SG256_BETA = 1e-3, 2e-5
+
+
+def test_al_solve_sg256_matches_oracle(torch_dev):
+    """The 256 x 256 slice group, two outer iterations of three CG steps
+    (the oracle takes about 20 s on the host): iterate and duals."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, _, y = case_for("sg256", 0)
+    with make_plan(torch, dev, g, case) as plan, smsm.AL(plan, SG256_LAM, SG256_BETA, 2, 3) as s:
+        x = s.solve(torch.from_numpy(y).to(dev)).cpu().numpy()
+        u = gpu_duals(s, s.n_anchor)
+        assert plan.status() == smsm.SMSM_OK
+    xr, ur = oracle_al(g, case, y, SG256_LAM, SG256_BETA, 2, 3)
+    e_x = rel(x, xr)
+    e_u = max(rel(u[l], ur[l]) for l in range(g.n_slices))
+    print(f"[al sg256] NRMSE x {e_x:.2e}, duals {e_u:.2e}", flush=True)
+    assert e_x < SOLVE_TOL and e_u < SOLVE_TOL
+
+
 def test_al_solve_is_deterministic_and_complex64_output(torch_dev):
     torch, dev = torch_dev
     from paper_1901_01893_amd import smsm
