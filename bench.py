@@ -53,63 +53,102 @@ def synth_inputs(torch, dev, plan, g, case, n_draws=1):
     return ys
 
 
-# Batched form: uneven slice groups (32 coils, 15 x 15 iterations), power-of-two
-# matrix sizes; (n, MB, shots, filter).  8 shots need a filter of at most 5 x 5.
-BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (128, 3, 4, 7), (128, 2, 2, 7), (128, 2, 8, 5))
+# Batched form: ten uneven slice groups (32 coils, 15 x 15 iterations) of
+# power-of-two matrix sizes standing in for 192/224/256, shots {2, 4, 8}, MB
+# {2, 3}; (n, MB, shots, filter).  8 shots need a filter of at most 5 x 5, and
+# at 256 x 256 more shared memory than a workgroup has (generic column pass).
+BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (256, 3, 2, 7), (256, 3, 4, 5),
+               (128, 3, 4, 7), (128, 2, 2, 7), (128, 2, 8, 5), (128, 3, 8, 5), (128, 3, 2, 7))
 
 
-def batched_measurement(torch, dev, n_streams, reps, directions=5):
-    """Slice-groups/s of a batch (every group of BATCH_GEOMS with `directions`
-    inputs each: diffusion directions with reseeded shot phases, U(0.3, 1)
-    attenuation and fresh noise; one plan per group) as plain sequential
-    solves and as one graph on n_streams streams (0: chosen by the library's
-    autotuner); the graph's outputs must equal the plain ones bit for bit."""
+def direction_truth(g, case, d, wid):
+    """Host half of one diffusion direction of a slice group: its truth
+    k-space (smsm_inputs.direction_case without noise)."""
+    import smsm_inputs as si
+    dc = si.direction_case(g, case, d, wid, noise=False)
+    return centred_fft2(dc["rho"].astype(np.float64)[:, None] * dc["phase"].astype(np.complex128))
+
+
+def direction_input(torch, dev, plan, g, case, x_true, d, wid):
+    """y = A x_true + noise of one direction: A applied by the library, the
+    complex Gaussian noise (SNR of the geometry) drawn on the device from a
+    generator seeded by (wid, d)."""
+    clean = plan.apply_A(torch.from_numpy(x_true).to(dev))
+    mask = torch.from_numpy(case["masks"].astype(np.float64)).to(dev)[:, None, :, None]
+    rms = torch.sqrt(torch.mean(torch.abs(clean[mask.expand_as(clean.real) > 0]) ** 2))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7919 * wid + d)
+    noise = torch.randn(tuple(clean.shape), dtype=torch.complex128, device=dev, generator=gen)
+    return (clean + mask * (rms / g.snr) * noise).to(torch.complex64).contiguous()
+
+
+def batched_measurement(torch, dev, n_streams, reps, directions=30):
+    """Slice-groups/s of a batch, every group of BATCH_GEOMS with `directions`
+    inputs (diffusion directions: shot phases reseeded, U(0.3, 1) attenuation,
+    fresh noise; one plan per group, shared by its directions), as plain
+    sequential solves and as one graph on n_streams streams; n_streams = 0
+    lets the library's autotuner choose the count on one direction per group,
+    and the full batch is captured with that count.  The graph's outputs must
+    equal the plain ones bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
     import smsm_inputs as si
     from paper_1901_01893_amd import smsm
     autotuned = n_streams == 0
     plans, entries = [], []
-    for k, (n, L, Ns, r) in enumerate(BATCH_GEOMS):
-        g = si.Geometry(n=n, n_slices=L, n_shots=Ns, n_coils=32, filt=r, lam=1e-3, n_irls=15, n_cg=15,
-                        phase_order=3, snr=20.0)
-        case = si.make_case(g, k, 30)
-        coils = torch.from_numpy(case["coils"]).to(dev)
-        plan = smsm.Plan(n, n, L, Ns, 32, r, coils, case["masks"], case["shifts"],
-                         smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
-        plans.append(plan)
-        for d in range(directions):
-            # a diffusion direction: shot phases reseeded, magnitude attenuated by U(0.3, 1)
-            y = synth_inputs(torch, dev, plan, g, si.direction_case(g, case, d, 30 + k), 1)[0]
-            entries.append((plan, y))
-    # directions interleaved across groups: (g0 d0, g1 d0, ..., g0 d1, ...)
-    order = [entries[k * directions + d] for d in range(directions) for k in range(len(plans))]
-    ys = [y for _, y in order]
-    xs_plain = [torch.empty(pl.shape_x, dtype=torch.complex64, device=dev) for pl, _ in order]
-    xs_graph = [torch.empty_like(x) for x in xs_plain]
-    batch = smsm.Batch([pl for pl, _ in order], ys, xs_graph, n_streams=n_streams)
-    n_streams = batch.n_streams
     try:
-        def plain():
-            for (plan, y), x in zip(order, xs_plain):
-                plan.solve(y, x)
-        def timed(fn):
-            fn()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
+        with ThreadPoolExecutor(8) as pool:
+            for k, (n, L, Ns, r) in enumerate(BATCH_GEOMS):
+                g = si.Geometry(n=n, n_slices=L, n_shots=Ns, n_coils=32, filt=r, lam=1e-3, n_irls=15, n_cg=15,
+                                phase_order=3, snr=20.0)
+                case = si.make_case(g, k, 30, noise=False)
+                plan = smsm.Plan(n, n, L, Ns, 32, r, torch.from_numpy(case["coils"]).to(dev), case["masks"],
+                                 case["shifts"], smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
+                plans.append(plan)
+                truths = pool.map(lambda d: direction_truth(g, case, d, 30 + k), range(directions))
+                for d, xt in enumerate(truths):
+                    entries.append((plan, direction_input(torch, dev, plan, g, case, xt, d, 30 + k)))
+        torch.cuda.synchronize()
+        print(f"[bench] batched: {len(entries)} inputs of {len(plans)} slice groups ready", file=sys.stderr,
+              flush=True)
+        # directions interleaved across groups: (g0 d0, g1 d0, ..., g0 d1, ...)
+        order = [entries[k * directions + d] for d in range(directions) for k in range(len(plans))]
+        ys = [y for _, y in order]
+        xs_plain = [torch.empty(pl.shape_x, dtype=torch.complex64, device=dev) for pl, _ in order]
+        xs_graph = [torch.empty_like(x) for x in xs_plain]
+        if autotuned:
+            m = len(plans)
+            probe = smsm.Batch([pl for pl, _ in order[:m]], ys[:m], xs_graph[:m], n_streams=0)
+            n_streams = probe.n_streams
+            probe.close()
+        batch = smsm.Batch([pl for pl, _ in order], ys, xs_graph, n_streams=n_streams)
+        try:
+            def plain():
+                for (plan, y), x in zip(order, xs_plain):
+                    plan.solve(y, x)
+
+            def timed(fn):
                 fn()
-            torch.cuda.synchronize()
-            return (time.perf_counter() - t0) / reps
-        t_plain = timed(plain)
-        t_graph = timed(batch.launch)
-        equal = all(torch.equal(a, b) for a, b in zip(xs_plain, xs_graph))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t0) / reps
+            t_plain = timed(plain)
+            print(f"[bench] batched: plain {t_plain:.2f} s per pass", file=sys.stderr, flush=True)
+            t_graph = timed(batch.launch)
+            equal = all(torch.equal(a, b) for a, b in zip(xs_plain, xs_graph))
+        finally:
+            batch.close()
     finally:
-        batch.close()
         for plan in plans:
             plan.close()
     n = len(order)
     return {"groups": [f"{a}x{a} MB{b} Ns{c} r{d}" for a, b, c, d in BATCH_GEOMS], "coils": 32,
-            "directions_per_group": directions, "inputs": "per direction: shot phases reseeded, magnitude x U(0.3, 1), fresh noise", "solves": n, "iterations": "15 IRLS x 15 CG",
-            "streams": n_streams, "streams_chosen_by": "autotuner" if autotuned else "caller", "reps": reps,
+            "directions_per_group": directions,
+            "inputs": "per direction: shot phases reseeded, magnitude x U(0.3, 1), fresh noise",
+            "solves": n, "iterations": "15 IRLS x 15 CG", "streams": n_streams,
+            "streams_chosen_by": "autotuner (one direction per group)" if autotuned else "caller", "reps": reps,
             "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 
@@ -569,6 +608,7 @@ def main():
     ap.add_argument("--profile-al", type=int, default=0, metavar="SOLVES",
                     help="run only SOLVES augmented-Lagrangian solves of the workload (for a kernel trace)")
     ap.add_argument("--batch-streams", type=int, default=0, help="0: the library's autotuner picks the count")
+    ap.add_argument("--batch-directions", type=int, default=30, help="diffusion directions per slice group")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -680,7 +720,7 @@ def main():
            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in kern.items()},
            "solve_status": smsm.status_string(status)}
     if not args.no_batched:
-        out["batched"] = batched_measurement(torch, dev, args.batch_streams, 3)
+        out["batched"] = batched_measurement(torch, dev, args.batch_streams, 2, args.batch_directions)
     if not args.no_mixed:
         out["mixed"] = mixed_measurement(torch, dev, plan, g, args.workload, ys, x)
     if not args.no_al and args.workload in AL_BETA:

@@ -203,6 +203,11 @@ const char* smsm_status_string(smsm_status s);
  * n_streams outside [1, 64], plans on different devices, timing on),
  * SMSM_E_NOMEM, SMSM_E_DEVICE (stream, capture or instantiation failure), or
  * the first error a captured solve returned.
+ * The entries are captured in consecutive segments of at most 30 entries
+ * holding at most 5 of any one plan, one graph per segment, launched in order (a
+ * plan's solves form one dependency chain, which a segment keeps short; a
+ * single graph holding 30 solves of a plan, about 67,000 kernels deep, ended
+ * the process in its launch on this runtime).
  * n_streams = 0 autotunes the launch shape: a graph is captured for each
  * stream count in {1, 2, 3, 4, 6, 8} up to the number of distinct plans, each
  * is launched once untimed and twice timed (hipEvents on an internal stream),

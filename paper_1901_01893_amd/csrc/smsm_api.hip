@@ -30,6 +30,8 @@ constexpr int kNsDefaultIters = 16;  // Newton-Schulz iteration cap
 constexpr int kSqSteps = 30;         // squarings for the largest eigenvalue
 constexpr int kPadBlocks = 32;       // blocks per slice of the dense set-up kernels
 constexpr double kNsTol = 1e-10;     // ||I - Z Y||_F at which NS is converged
+constexpr int kBatchMaxRepeat = 5;   // entries of one plan per captured graph of a batch
+constexpr int kBatchMaxSegment = 30; // entries per captured graph of a batch
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
@@ -1029,15 +1031,15 @@ smsm_status smsm_apply_normal(smsm_plan* P, const void* x_dev, void* out_dev, vo
 struct smsm_batch {
     int dev = 0;
     int n_streams = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraph_t> graphs;         // consecutive segments of the entries, launched in order
+    std::vector<hipGraphExec_t> execs;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;
 };
 
 static void batch_release(smsm_batch* B) {
-    if (B->exec) (void)hipGraphExecDestroy(B->exec);
-    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (hipGraphExec_t e : B->execs) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t gr : B->graphs) (void)hipGraphDestroy(gr);
     for (hipEvent_t ev : B->events) (void)hipEventDestroy(ev);
     for (hipStream_t st : B->streams) (void)hipStreamDestroy(st);
     delete B;
@@ -1051,8 +1053,13 @@ static smsm_status batch_time(smsm_batch* B, hipStream_t st, float* ms) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return SMSM_E_DEVICE;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return SMSM_E_DEVICE; }
-    bool ok = hipGraphLaunch(B->exec, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
-    for (int k = 0; k < 2 && ok; ++k) ok = hipGraphLaunch(B->exec, st) == hipSuccess;
+    auto launch_all = [&]() {
+        for (hipGraphExec_t e : B->execs)
+            if (hipGraphLaunch(e, st) != hipSuccess) return false;
+        return true;
+    };
+    bool ok = launch_all() && hipEventRecord(e0, st) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k) ok = launch_all();
     ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
          hipEventElapsedTime(ms, e0, e1) == hipSuccess;
     (void)hipEventDestroy(e0);
@@ -1141,32 +1148,46 @@ static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* con
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { batch_release(B); return SMSM_E_DEVICE; }
         B->events.push_back(ev);
     }
+    // consecutive segments of at most kBatchMaxSegment entries in which no
+    // plan has more than kBatchMaxRepeat, each captured as its own graph (fork from and join into the
+    // first stream) and launched in order: a plan's solves run in sequence on
+    // one stream, so a segment bounds the length of the graph's dependency
+    // chains
     hipStream_t origin = B->streams[0];
-    if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        batch_release(B);
-        return SMSM_E_DEVICE;
-    }
-    bool ok = hipEventRecord(B->events[0], origin) == hipSuccess;
-    for (int k = 1; k < ns && ok; ++k) ok = hipStreamWaitEvent(B->streams[k], B->events[0], 0) == hipSuccess;
-    smsm_status s = ok ? SMSM_OK : SMSM_E_DEVICE;
-    for (int k = 0; k < n && s == SMSM_OK; ++k)
-        s = smsm_solve(plans[k], y_devs[k], x_devs[k], B->streams[owner[k] % ns]);
-    for (int k = 1; k < ns && s == SMSM_OK; ++k) {
-        if (hipEventRecord(B->events[k], B->streams[k]) != hipSuccess ||
-            hipStreamWaitEvent(origin, B->events[k], 0) != hipSuccess)
-            s = SMSM_E_DEVICE;
-    }
-    hipGraph_t graph = nullptr;
-    const bool ended = hipStreamEndCapture(origin, &graph) == hipSuccess;
-    B->graph = graph;
-    if (s != SMSM_OK || !ended || !graph) {
-        batch_release(B);
-        return s != SMSM_OK ? s : SMSM_E_DEVICE;
-    }
-    if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess) {
-        B->exec = nullptr;
-        batch_release(B);
-        return SMSM_E_DEVICE;
+    std::vector<int> count(distinct, 0);
+    int k0 = 0;
+    while (k0 < n) {
+        std::fill(count.begin(), count.end(), 0);
+        int k1 = k0;
+        while (k1 < n && k1 - k0 < kBatchMaxSegment && count[owner[k1]] < kBatchMaxRepeat) ++count[owner[k1++]];
+        if (hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            batch_release(B);
+            return SMSM_E_DEVICE;
+        }
+        bool ok = hipEventRecord(B->events[0], origin) == hipSuccess;
+        for (int k = 1; k < ns && ok; ++k) ok = hipStreamWaitEvent(B->streams[k], B->events[0], 0) == hipSuccess;
+        smsm_status s = ok ? SMSM_OK : SMSM_E_DEVICE;
+        for (int k = k0; k < k1 && s == SMSM_OK; ++k)
+            s = smsm_solve(plans[k], y_devs[k], x_devs[k], B->streams[owner[k] % ns]);
+        for (int k = 1; k < ns && s == SMSM_OK; ++k) {
+            if (hipEventRecord(B->events[k], B->streams[k]) != hipSuccess ||
+                hipStreamWaitEvent(origin, B->events[k], 0) != hipSuccess)
+                s = SMSM_E_DEVICE;
+        }
+        hipGraph_t graph = nullptr;
+        const bool ended = hipStreamEndCapture(origin, &graph) == hipSuccess;
+        if (graph) B->graphs.push_back(graph);
+        if (s != SMSM_OK || !ended || !graph) {
+            batch_release(B);
+            return s != SMSM_OK ? s : SMSM_E_DEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            batch_release(B);
+            return SMSM_E_DEVICE;
+        }
+        B->execs.push_back(exec);
+        k0 = k1;
     }
     *out = B;
     return SMSM_OK;
@@ -1175,7 +1196,9 @@ static smsm_status batch_capture(smsm_plan* const* plans, int n, const void* con
 smsm_status smsm_batch_launch(smsm_batch* B, void* stream) {
     if (!B) return SMSM_E_INVALID;
     if (hipSetDevice(B->dev) != hipSuccess) return SMSM_E_DEVICE;
-    return hipGraphLaunch(B->exec, S(stream)) == hipSuccess ? SMSM_OK : SMSM_E_DEVICE;
+    for (hipGraphExec_t e : B->execs)
+        if (hipGraphLaunch(e, S(stream)) != hipSuccess) return SMSM_E_DEVICE;
+    return SMSM_OK;
 }
 
 smsm_status smsm_batch_destroy(smsm_batch* B) {

@@ -189,20 +189,24 @@ def cnn_init(seed: int, c_io: int, width: int = 64, depth: int = 5, out_scale: f
     return params
 
 
-def direction_case(geom: Geometry, case: dict, direction: int, workload_id: int = 0) -> dict:
+def direction_case(geom: Geometry, case: dict, direction: int, workload_id: int = 0, noise: bool = True) -> dict:
     """One diffusion direction of a slice group: the same phantoms, coils,
     masks and shifts, the shot phases reseeded, the magnitude scaled by a
-    diffusion attenuation factor drawn from U(0.3, 1), and fresh noise."""
+    diffusion attenuation factor drawn from U(0.3, 1), and fresh noise
+    (absent when noise=False, for a consumer that draws it elsewhere; the
+    phases and attenuation do not depend on it)."""
     g = geom
     ss = np.random.SeedSequence([int(workload_id), 5000 + int(direction)])
     r_phase, r_noise, r_att = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
     att = r_att.uniform(0.3, 1.0)
     phase = np.stack([shot_phases(r_phase, g.n, g.n_shots, g.phase_order) for _ in range(g.n_slices)])
-    shape = (g.n_shots, g.n_coils, g.n, g.n)
-    noise = (r_noise.standard_normal(shape) + 1j * r_noise.standard_normal(shape)) / np.sqrt(2.0)
     out = dict(case)
     out["rho"] = (case["rho"].astype(np.float64) * att).astype(np.float32)
     out["phase"] = phase.astype(np.complex64)
-    out["noise"] = noise.astype(np.complex64)
+    out.pop("noise", None)
+    if noise:
+        shape = (g.n_shots, g.n_coils, g.n, g.n)
+        nz = (r_noise.standard_normal(shape) + 1j * r_noise.standard_normal(shape)) / np.sqrt(2.0)
+        out["noise"] = nz.astype(np.complex64)
     out["attenuation"] = float(att)
     return out

@@ -145,3 +145,35 @@ def test_autotuned_batch_matches_plain_solves(torch_dev):
     finally:
         for plan in plans:
             plan.close()
+
+
+def test_batch_of_many_directions_spans_several_graphs(torch_dev):
+    # seven inputs of one slice group and two of another: the first plan has
+    # more entries than one captured segment holds (five), so the batch runs
+    # as two graphs in order; every output equals its plain solve bit for bit
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    plan_a, y_a = make_plan(torch, dev, GEOMS[1], 20)
+    plan_b, y_b = make_plan(torch, dev, GEOMS[1], 21)
+    try:
+        ys = [(0.5 + 0.1 * k) * y_a for k in range(7)] + [y_b, 0.7 * y_b]
+        plans = [plan_a] * 7 + [plan_b] * 2
+        refs = [pl.solve(y).clone() for pl, y in zip(plans, ys)]
+        torch.cuda.synchronize()
+        xs = [torch.zeros_like(r) for r in refs]
+        batch = smsm.Batch(plans, ys, xs, n_streams=2)
+        try:
+            for rep in range(2):
+                for x in xs:
+                    x.zero_()
+                batch.launch()
+                torch.cuda.synchronize()
+                for k in range(len(plans)):
+                    assert torch.equal(xs[k], refs[k]), (rep, k)
+            assert o.nrmse(xs[6].cpu().numpy(), oracle_of(plan_a, ys[6])) < ORACLE_TOL
+        finally:
+            batch.close()
+    finally:
+        plan_a.close()
+        plan_b.close()
+

@@ -48,6 +48,16 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 110),
     "n128_L2_Ns8_r5": (si.Geometry(n=128, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 111),
+    # the other instances of the batched bench's ten groups: three slices with the
+    # generic column pass at 2 and 8 shots, and the fast column pass <64, 3> with a 5 x 5 filter
+    "n256_L3_Ns2_r7": (si.Geometry(n=256, n_slices=3, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 112),
+    "n256_L3_Ns4_r5": (si.Geometry(n=256, n_slices=3, n_shots=4, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 113),
+    "n128_L3_Ns8_r5": (si.Geometry(n=128, n_slices=3, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 114),
+    "n128_L3_Ns2_r7": (si.Geometry(n=128, n_slices=3, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 115),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
