@@ -292,41 +292,54 @@ __global__ void k_al_f(int K, int KP, const double2* __restrict__ C, const doubl
 
 // Dual update U_out = M - M F (M = H(x) + U_in), written [k][p].  The product
 // is taken transposed, T^T[k][p] = sum_j F[j][k] M[p][j], so that the
-// matrix cores' output tile runs along patches.  grid (NPP / AL_PT * KB, 1, L),
-// block 256: workgroup (patch tile, 64-row block of k), wave w the 16 rows
-// 16 w of the block against the tile's 64 patches (4 tiles of
-// v_mfma_f64_16x16x4f64); chunks of 16 j of M^T and F staged in shared memory,
-// the next chunk's loads in flight during the current chunk's products.
-__global__ void __launch_bounds__(256, 2) k_al_update(AlGeo a, const double2* __restrict__ x,
-                                                   const double2* __restrict__ Uin, const double2* __restrict__ F,
-                                                   double2* __restrict__ Uout) {
-    __shared__ double2 sm[16][AL_STR];   // M^T chunk [j][p]
-    __shared__ double2 sf[16][AL_STR];   // F chunk [j][k]
+// matrix cores' output tile runs along patches.  grid (NPP / AL_PT * KBU, 1, L)
+// with KBU = ceil(K / (16 NW)), block 64 NW: workgroup (patch tile, 16 NW rows
+// of k), wave w the 16 rows 16 w of the block against the tile's 64 patches
+// (4 tiles of v_mfma_f64_16x16x4f64); chunks of 16 j of M^T and F staged in
+// shared memory, the next chunk's loads in flight during the current chunk's
+// products.  More rows per workgroup stage each patch tile's M^T fewer times.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW, 8 / NW) k_al_update(AlGeo a, const double2* __restrict__ x,
+                                                               const double2* __restrict__ Uin,
+                                                               const double2* __restrict__ F,
+                                                               double2* __restrict__ Uout) {
+    constexpr int NT = 64 * NW, KR = 16 * NW;
+    constexpr int SM_IT = 16 * AL_PT / NT, SF_IT = 16 * KR / NT;   // staged entries per thread
+    __shared__ double2 sm[16][AL_STR];      // M^T chunk [j][p]
+    __shared__ double2 sf[16][KR + 1];      // F chunk [j][k]
     const int l = blockIdx.z;
-    const int tile = blockIdx.x / a.KB, kb = blockIdx.x - tile * a.KB;
-    const int p0 = tile * AL_PT, k0 = kb * AL_BK;
+    const int kbu = (a.K + KR - 1) / KR;
+    const int tile = blockIdx.x / kbu, kb = blockIdx.x - tile * kbu;
+    const int p0 = tile * AL_PT, k0 = kb * KR;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const double2* xl = x + (size_t)l * a.Ns * a.n2 * a.n1;
     const double2* Ul = Uin + (size_t)l * a.K * a.NPP;
     const double2* Fl = F + (size_t)l * a.KP * a.KP;
-    // staging: thread -> patch (or k) column tid & 63, rows (tid >> 6) + 4 s
-    const int col = tid & 63, jr = tid >> 6;
-    const int p = p0 + col;
-    const bool pok = p < a.NP;
-    int po = 0;
-    if (pok) {
-        const int p2 = p / a.P1;
-        po = p2 * a.n1 + (p - p2 * a.P1);
+    // staging of M^T: entry e = tid + s NT -> patch e & 63, row e >> 6
+    int po[SM_IT];
+    bool pok[SM_IT];
+#pragma unroll
+    for (int s = 0; s < SM_IT; ++s) {
+        const int p = p0 + ((tid + s * NT) & 63);
+        pok[s] = p < a.NP;
+        const int p2 = pok[s] ? p / a.P1 : 0;
+        po[s] = pok[s] ? p2 * a.n1 + (p - p2 * a.P1) : 0;
     }
-    const bool kcol_ok = k0 + col < a.K;
-    double2 vm[4], vf[4];
+    double2 vm[SM_IT], vf[SF_IT];
     auto load = [&](int j0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int j = j0 + jr + 4 * s;
+        for (int s = 0; s < SM_IT; ++s) {
+            const int e = tid + s * NT;
+            const int j = j0 + (e >> 6);
             const int off = al_col_off(a, j);
-            vm[s] = (pok && off >= 0) ? cadd(xl[off + po], Ul[(size_t)j * a.NPP + p]) : cmk(0.0, 0.0);
-            vf[s] = (kcol_ok && j < a.K) ? Fl[(size_t)j * a.KP + k0 + col] : cmk(0.0, 0.0);
+            vm[s] = (pok[s] && off >= 0) ? cadd(xl[off + po[s]], Ul[(size_t)j * a.NPP + p0 + (e & 63)])
+                                         : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int s = 0; s < SF_IT; ++s) {
+            const int e = tid + s * NT;
+            const int j = j0 + e / KR, kk = k0 + e % KR;
+            vf[s] = (kk < a.K && j < a.K) ? Fl[(size_t)j * a.KP + kk] : cmk(0.0, 0.0);
         }
     };
     const bool wok = k0 + 16 * w < a.K;
@@ -341,9 +354,14 @@ __global__ void __launch_bounds__(256, 2) k_al_update(AlGeo a, const double2* __
     for (int j0 = 0; j0 < a.K; j0 += 16) {
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            sm[jr + 4 * s][col] = vm[s];
-            sf[jr + 4 * s][col] = vf[s];
+        for (int s = 0; s < SM_IT; ++s) {
+            const int e = tid + s * NT;
+            sm[e >> 6][e & 63] = vm[s];
+        }
+#pragma unroll
+        for (int s = 0; s < SF_IT; ++s) {
+            const int e = tid + s * NT;
+            sf[e / KR][e % KR] = vf[s];
         }
         __syncthreads();
         if (j0 + 16 < a.K) load(j0 + 16);

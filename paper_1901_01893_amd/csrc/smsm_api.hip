@@ -1950,7 +1950,8 @@ struct smsm_al {
 
 namespace {
 
-constexpr int kAlChunks = 16;          // patch chunks of the Gram partials
+constexpr int kAlChunks = 64;          // patch chunks of the Gram partials
+constexpr int kAlUpdWaves = 8;         // dual update: waves (16 rows of K each) per workgroup
 constexpr double kAlSignLo = 1e-14;    // sign iteration: resolution relative to ||G - tau^2 I||_F
 constexpr double kAlMuMax = 1.6;       // largest scale of a sign step (p(1.6) = 0.352 > 0)
 constexpr int kAlNsIters = 30;         // cap of the coupled iteration for Gt^(-1/2)
@@ -2245,13 +2246,13 @@ smsm_status smsm_al_solve(smsm_al* A, const void* y_dev, void* x_dev, void* stre
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_al_init, vec_grid(), dim3(kThreads), 0, st, a, A->x, A->hu, A->hzu);
     LAUNCH_CHECK();
-    const int KB = a.KB;
+    const int kbu = (a.K + 16 * kAlUpdWaves - 1) / (16 * kAlUpdWaves);
     for (int it = 0; it < A->n_outer; ++it) {
         if ((s = al_axpy(A, A->b, A->hzu, nullptr, 0.5 * A->beta, A->rhs, st))) return s;   // b + (beta/2) H^H(Z - U)
         if ((s = al_cg(A, st))) return s;
         if ((s = al_threshold(A, st))) return s;
-        hipLaunchKernelGGL(k_al_update, dim3(a.NPP / AL_PT * KB, 1, a.L), dim3(kThreads), 0, st, a, A->x,
-                           A->U[A->cur], A->F, A->U[A->cur ^ 1]);
+        hipLaunchKernelGGL(k_al_update<kAlUpdWaves>, dim3(a.NPP / AL_PT * kbu, 1, a.L), dim3(64 * kAlUpdWaves), 0,
+                           st, a, A->x, A->U[A->cur], A->F, A->U[A->cur ^ 1]);
         LAUNCH_CHECK();
         A->cur ^= 1;
         hipLaunchKernelGGL(k_al_gather, dim3(1024), dim3(kThreads), 0, st, a, A->x, A->U[A->cur], A->hu, A->hzu);
