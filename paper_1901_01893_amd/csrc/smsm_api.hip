@@ -1500,7 +1500,17 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
     const float* g = gout;
     float* bufs[2] = {Lr->ga, Lr->gbuf};
     for (int k = D - 1; k >= 0; --k) {
-        if (Lr->cin[k] % WG_TILE == 0 && Lr->cout[k] % WG_TILE == 0) {
+        if (Lr->bf16 == 2) {
+            // the BF16 network: layer inputs are BF16 values, weight gradients on the matrix cores
+            const int nchunk = Lr->L * wgm_chunks(Lr->H, Lr->W);
+            hipLaunchKernelGGL(k_wgrad_mfma, dim3(nchunk, (Lr->cin[k] + 15) / 16), dim3(kThreads), 0, st,
+                               Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g, Lr->wpart, Lr->wbpart);
+            LAUNCH_CHECK();
+            const int nout = Lr->cout[k] * Lr->cin[k] * 9 + Lr->cout[k];
+            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + CNN_THREADS - 1) / CNN_THREADS), dim3(CNN_THREADS), 0, st,
+                               nchunk, Lr->cin[k], Lr->cout[k], Lr->wpart, Lr->wbpart, Lr->grads + Lr->woff[k],
+                               Lr->grads + Lr->boff[k], accumulate);
+        } else if (Lr->cin[k] % WG_TILE == 0 && Lr->cout[k] % WG_TILE == 0) {
             const int nchunk = Lr->L * wg_chunks(Lr->H, Lr->W);
             hipLaunchKernelGGL(k_wgrad_part, dim3(nchunk, Lr->cout[k] / WG_TILE, Lr->cin[k] / WG_TILE),
                                dim3(CNN_THREADS), 0, st, Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g,
@@ -1702,7 +1712,7 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
         maxcc = std::max(maxcc, (size_t)Lr->cin[k] * Lr->cout[k]);
         maxco = std::max(maxco, (size_t)Lr->cout[k]);
     }
-    const size_t nchunk = (size_t)Lr->L * wg_chunks(Lr->H, Lr->W);
+    const size_t nchunk = (size_t)Lr->L * std::max(wg_chunks(Lr->H, Lr->W), wgm_chunks(Lr->H, Lr->W));
     const size_t owp = cv.take<float>(nchunk * maxcc * 9), owb = cv.take<float>(nchunk * maxco);
     size_t opk[smsm_learned::kDepth][2];
     for (int k = 0; k < smsm_learned::kDepth; ++k) {

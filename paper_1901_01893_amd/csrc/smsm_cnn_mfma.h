@@ -211,6 +211,138 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
         }
 }
 
+// Weight gradients of one 3 x 3 layer of the BF16 network on the matrix
+// cores, per pixel chunk: dW[o][c][t] = sum_p g[o][p] in[c][p + off_t] and
+// db[o] = sum_p g[o][p] (the chunks are added in order by k_wgrad_sum).  The
+// layer input is BF16-valued (the BF16 network rounds every convolution
+// input) and the output gradient g FP32, split into three BF16 parts
+// (g = hi + mid + lo exactly), so every product is exact and the sums are
+// FP32 in the matrix cores' order.  The contraction runs over pixels: one
+// MFMA step (K = 32) takes 32 consecutive pixels of a row; lane l holds
+// A[o = l % 16][8 (l / 16) + j] = g[o][pixel] and B[8 (l / 16) + j][c = l % 16]
+// = in[c][pixel + off_t].  A chunk is WGM_ROWS rows x WGM_TC columns of one
+// image, walked in sub-tiles of WGM_SR rows; each sub-tile's input (16
+// channels, rows -1 .. WGM_SR, the tile's columns shifted by -1, 0 and +1:
+// three copies, so that every tap's fragment is an aligned 16-byte read) is
+// staged in shared memory as BF16, [copy][channel][row][column] with the
+// channel stride padded by 8 BF16 so that the 16 lanes of a fragment read
+// land on distinct banks.  Wave w takes output channels 16 w .. 16 w + 15.
+// grid (N wgm_chunks(H, W), ceil(ci / 16)), block 256.  Writes
+// part[chunk][o][c][t] for o < co, c < ci, and (input-channel block 0)
+// bpart[chunk][o].  W must be a multiple of 8.
+#define WGM_TC 64
+#define WGM_SR 4
+#define WGM_ROWS 16
+#define WGM_CSTR ((WGM_SR + 2) * WGM_TC + 8)   // BF16 per staged channel
+
+SMSM_HD inline int wgm_chunks(int H, int W) {
+    return ((H + WGM_ROWS - 1) / WGM_ROWS) * ((W + WGM_TC - 1) / WGM_TC);
+}
+
+__global__ void __launch_bounds__(256, 2)
+k_wgrad_mfma(int ci, int co, int H, int W, const float* __restrict__ in, const float* __restrict__ g,
+             float* __restrict__ part, float* __restrict__ bpart) {
+    __shared__ __attribute__((aligned(16))) unsigned short xs[3][16 * WGM_CSTR];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int gq = lane >> 4, l16 = lane & 15;
+    const int cpi = wgm_chunks(H, W);
+    const int chunk = blockIdx.x, n = chunk / cpi, cr = chunk - n * cpi;
+    const int tiles_x = (W + WGM_TC - 1) / WGM_TC;
+    const int ty = cr / tiles_x, tx = cr - ty * tiles_x;
+    const int yc = ty * WGM_ROWS, x0 = tx * WGM_TC;
+    const int c0 = blockIdx.y * 16;
+    const size_t npx = (size_t)H * W;
+    const float* src = in + (size_t)n * ci * npx;
+    const int o = 16 * w + l16;                          // this lane's row of A
+    const float* grow = g + ((size_t)n * co + (o < co ? o : 0)) * npx;
+    cm_f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = cm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    for (int sr = 0; sr < WGM_ROWS; sr += WGM_SR) {
+        const int y0 = yc + sr;
+        if (y0 >= H) break;                              // the same for the whole workgroup
+        __syncthreads();                                 // the previous sub-tile's fragments are read
+        // items (channel, row, 8-column block), each written as three shifted copies
+        for (int it = tid; it < 16 * (WGM_SR + 2) * (WGM_TC / 8); it += 256) {
+            const int b = it % (WGM_TC / 8), rc = it / (WGM_TC / 8);
+            const int r = rc % (WGM_SR + 2), c = rc / (WGM_SR + 2);
+            const int y = y0 - 1 + r, cg = c0 + c, xb = x0 + 8 * b;
+            const bool rok = cg < ci && y >= 0 && y < H;
+            const float* row = src + (size_t)(rok ? cg : 0) * npx + (size_t)(rok ? y : 0) * W;
+            float v[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                const int x = xb - 1 + q;
+                v[q] = (rok && x >= 0 && x < W) ? row[x] : 0.0f;
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {                // copy d holds in[..][x + d - 1]
+                unsigned pk[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    pk[q] = cm_bf16_bits(v[2 * q + d]) | (cm_bf16_bits(v[2 * q + 1 + d]) << 16);
+                *reinterpret_cast<uint4*>(&xs[d][c * WGM_CSTR + r * WGM_TC + 8 * b]) =
+                    make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int s = 0; s < 2 * WGM_SR; ++s) {
+            const int ry = s >> 1, xl = 32 * (s & 1) + 8 * gq;   // this lane's 8 pixels: row y0 + ry, columns x0 + xl ..
+            const int y = y0 + ry;
+            float gv[8];
+            if (o < co && y < H && x0 + xl < W) {
+                const float4* gp = reinterpret_cast<const float4*>(grow + (size_t)y * W + x0 + xl);
+                const float4 u0 = gp[0], u1 = gp[1];
+                gv[0] = u0.x; gv[1] = u0.y; gv[2] = u0.z; gv[3] = u0.w;
+                gv[4] = u1.x; gv[5] = u1.y; gv[6] = u1.z; gv[7] = u1.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) gv[q] = 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bsum += gv[q];
+            cm_bf16x8 a[3];
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                unsigned pk[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const unsigned h0 = cm_bf16_bits(gv[2 * q]), h1 = cm_bf16_bits(gv[2 * q + 1]);
+                    pk[q] = h0 | (h1 << 16);
+                    gv[2 * q] -= __uint_as_float(h0 << 16);        // exact: the remainder of a round to nearest
+                    gv[2 * q + 1] -= __uint_as_float(h1 << 16);
+                }
+                a[pl] = __builtin_bit_cast(cm_bf16x8, make_uint4(pk[0], pk[1], pk[2], pk[3]));
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t - 3 * (t / 3);
+                const cm_bf16x8 bfr =
+                    *reinterpret_cast<const cm_bf16x8*>(&xs[dx][l16 * WGM_CSTR + (ry + dy) * WGM_TC + xl]);
+#pragma unroll
+                for (int pl = 0; pl < 3; ++pl)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pl], bfr, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds C[o = 16 w + 4 gq + j][c = c0 + l16] of each tap
+    const int c = c0 + l16;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int oo = 16 * w + 4 * gq + j;
+        if (oo >= co || c >= ci) continue;
+        float* dst = part + (((size_t)chunk * co + oo) * ci + c) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[t] = acc[t][j];
+    }
+    // bias: the four lane groups of a row add in a fixed order
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (blockIdx.y == 0 && gq == 0 && o < co) bpart[(size_t)chunk * co + o] = bsum;
+}
+
 // x <- x rounded to a BF16 value (in place; the BF16 network's input).
 __global__ void k_round_bf16(long n, float* __restrict__ x) {
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)

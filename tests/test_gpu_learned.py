@@ -272,6 +272,37 @@ def test_bf16_network_is_exact_on_bf16_values(torch_dev):
             assert np.array_equal(got[k][0], rgrads[k][0]) and np.array_equal(got[k][1], rgrads[k][1]), k
 
 
+def test_bf16_network_weight_gradients_are_fp32_accurate(torch_dev):
+    """The forced-rounding network with FP32 output gradients that are not
+    BF16 values: every layer's weight and bias gradients come from the same
+    BF16 activations and the same gradients on both sides (each backward-data
+    sum has one term), so the matrix-core weight gradients (the FP32 gradient
+    in three BF16 parts, exact products, FP32 sums) must match the FP64 oracle
+    to FP32 accumulation accuracy (a part dropped from the split would be off
+    by 2^-9 or 2^-17); the input gradient stays exact."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    from tests.test_oracle_learned_pins import bf16_exact_network
+    case, _, _ = make_case(G32, 7, 98)
+    params = [(w.astype(np.float32), b.astype(np.float32)) for w, b in bf16_exact_network(32)]
+    with plan_for(torch, dev, G32, case) as plan, smsm.Learned(plan, params, width=8, n_unroll=1, n_cg=1,
+                                                              mu=0.5) as net:
+        net.set_bf16(2)
+        rng = np.random.default_rng(14)
+        inp = rng.integers(-4, 5, size=net.shape_c).astype(np.float32)
+        gout = rng.standard_normal(net.shape_c).astype(np.float32)
+        gin, grads = net.cnn_backward(torch.from_numpy(inp).to(dev), torch.from_numpy(gout).to(dev))
+        p64 = f64_params(params)
+        _, acts = lo.cnn_forward(inp.astype(np.float64), p64, act_bf16=True)
+        rgin, rgrads = lo.cnn_backward(acts, p64, gout.astype(np.float64), act_bf16=True)
+        assert np.array_equal(gin.cpu().numpy(), rgin)
+        got = smsm.unflatten_params(grads, 8, 8)
+        errs = [(rel(got[k][0], rgrads[k][0]), rel(got[k][1], rgrads[k][1])) for k in range(5)]
+        print(f"[bf16 wgrad] per-layer relative errors (weights, biases): {errs}", flush=True)
+        for k in range(5):
+            assert errs[k][0] < 2e-5 and errs[k][1] < 2e-5, (k, errs[k])
+
+
 # The BF16 network rounds every hidden activation to BF16: the GPU forms it by
 # FP32 accumulation in the matrix cores' order, the oracle in FP64, so a
 # fraction of about sqrt(K) 2^-24 / 2^-8 (4e-4 at K = 576 terms) of the
