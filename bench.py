@@ -87,14 +87,15 @@ def batched_measurement(torch, dev, n_streams, reps, directions=30):
     inputs (diffusion directions: shot phases reseeded, U(0.3, 1) attenuation,
     fresh noise; one plan per group, shared by its directions), as plain
     sequential solves and as one graph on n_streams streams; n_streams = 0
-    lets the library's autotuner choose the count on one direction per group,
-    and the full batch is captured with that count.  The graph's outputs must
+    lets the library's autotuners choose each plan's launch shapes and the
+    stream count (on one direction per group), and the full batch is captured
+    with that count.  The graph's outputs must
     equal the plain ones bit for bit."""
     from concurrent.futures import ThreadPoolExecutor
     import smsm_inputs as si
     from paper_1901_01893_amd import smsm
     autotuned = n_streams == 0
-    plans, entries = [], []
+    plans, entries, shapes = [], [], []
     try:
         with ThreadPoolExecutor(8) as pool:
             for k, (n, L, Ns, r) in enumerate(BATCH_GEOMS):
@@ -104,6 +105,7 @@ def batched_measurement(torch, dev, n_streams, reps, directions=30):
                 plan = smsm.Plan(n, n, L, Ns, 32, r, torch.from_numpy(case["coils"]).to(dev), case["masks"],
                                  case["shifts"], smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg))
                 plans.append(plan)
+                shapes.append(plan.autotune(10) if autotuned else None)
                 truths = pool.map(lambda d: direction_truth(g, case, d, 30 + k), range(directions))
                 for d, xt in enumerate(truths):
                     entries.append((plan, direction_input(torch, dev, plan, g, case, xt, d, 30 + k)))
@@ -148,7 +150,10 @@ def batched_measurement(torch, dev, n_streams, reps, directions=30):
             "directions_per_group": directions,
             "inputs": "per direction: shot phases reseeded, magnitude x U(0.3, 1), fresh noise",
             "solves": n, "iterations": "15 IRLS x 15 CG", "streams": n_streams,
-            "streams_chosen_by": "autotuner (one direction per group)" if autotuned else "caller", "reps": reps,
+            "streams_chosen_by": "autotuner (one direction per group)" if autotuned else "caller",
+            "launch_shapes": ([{"rows_per_workgroup": a, "columns_per_wave": b} for a, b in shapes]
+                              if autotuned else "defaults"),
+            "reps": reps,
             "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 

@@ -229,6 +229,21 @@ smsm_status smsm_batch_launch(smsm_batch* batch, void* stream);
  * (not the plans or buffers).  A null batch is a no-op. */
 smsm_status smsm_batch_destroy(smsm_batch* batch);
 
+/* Launch shapes by measurement: for the plan's geometry, each candidate
+ * number of rows per workgroup of the row transforms (2 .. 32 where the
+ * kernel can take it) and of image columns per wave of the hybrid vector pass
+ * (1, 2, 4 where they tile the image) is timed with hipEvents over `reps`
+ * launches of its kernels (smsm_launch_kernel, after one untimed launch) on
+ * the plan's buffers, whatever they hold, and the fastest is kept; the
+ * numeric flags the timed launches raise are cleared.  The row shape leaves
+ * every result bit for bit the same; the vector pass's shape sets the order
+ * of the |r|^2 partial sums, so solves change at rounding level.
+ * shape[0] = rows per workgroup, shape[1] = columns per wave (may be NULL).
+ * Capture a batch after tuning its plans (a batch keeps the shapes it was
+ * captured with).  Synchronous.  Errors: SMSM_E_INVALID for a null plan, reps
+ * outside [1, 1000] or no workspace; SMSM_E_DEVICE. */
+smsm_status smsm_plan_autotune(smsm_plan* plan, int reps, int* shape, void* stream);
+
 /* ---- operator entry points (one kernel chain each, asynchronous) ------- */
 
 /* y = A x (Fig. 1).  x_dev c128 [L][Ns][n2][n1] -> y_dev c128 [Ns][Nc][n2][n1]

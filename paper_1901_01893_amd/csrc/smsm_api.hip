@@ -58,6 +58,7 @@ struct smsm_plan {
     size_t lds_roww = 0;
     int npc = 0;             // partials of Re <p, column pass> (one per column workgroup, or kVecBlocks)
     int npr = 0;             // partials of |r|^2 (blocks of the hybrid vector pass)
+    int npr_max = 0;         // the largest npr of any vector-pass shape (size of the ring)
     int hyb_xw = 1;          // x steps per wave of the hybrid vector pass
     dim3 hyb_grid;
     int np_band = 0;         // padded width of the band-column extraction table
@@ -139,6 +140,37 @@ struct Carver {
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 dim3 vec_grid() { return dim3(kVecBlocks); }
+
+// Launch shapes a plan can take (smsm_plan_autotune picks among them).
+// Row transforms: TRw rows per workgroup; the kernel needs TRw a multiple of
+// (waves per workgroup) x (rows per wave) and TRw n1 <= 8 x threads.
+bool rows_shape_ok(const Geo& g, int trw) {
+    const int G = std::max(1, 64 / g.n1), blk = std::min(256, 64 * trw / G);
+    return trw >= 1 && g.n2 % trw == 0 && blk >= 64 && trw % ((blk / 64) * G) == 0 && trw * g.n1 <= 8 * blk;
+}
+void set_rows_shape(smsm_plan* P, int trw) {
+    const int n1 = P->g.n1;
+    P->TRw = trw;
+    P->rows_blk = std::min(256, 64 * trw / std::max(1, 64 / n1));
+    P->lds_roww = (size_t)trw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
+}
+// Vector pass: xw columns per wave, HYB_WAVES waves per workgroup, chunks of
+// min(n2, 64) ky; the blocks must tile the image exactly.
+int hyb_blocks(const Geo& g, int xw) {
+    const int LY = std::min(64, g.n2), XPS = 64 / LY, per = HYB_WAVES * xw * XPS;
+    if (g.n1 % per != 0) return 0;
+    return (g.n2 / LY) * (g.n1 / per) * g.B;
+}
+bool set_hyb_shape(smsm_plan* P, int xw) {
+    const Geo& g = P->g;
+    const int nb = hyb_blocks(g, xw);
+    if (nb <= 0 || (P->npr_max > 0 && nb > P->npr_max)) return false;
+    const int LY = std::min(64, g.n2), XPS = 64 / LY;
+    P->hyb_xw = xw;
+    P->hyb_grid = dim3((g.n2 / LY) * (g.n1 / (HYB_WAVES * xw * XPS)), g.B);
+    P->npr = nb;
+    return true;
+}
 
 // ---- kernel chains -------------------------------------------------------
 // kx inverse DFT, natural [B][n2][n1] -> hybrid [B][n1][n2].
@@ -583,16 +615,12 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
     P->lds_gram_lines = (size_t)(1 + g.nc) * std::max(n1, n2) * sizeof(double2);
-    P->TRw = (n1 == 16) ? 16 : (n1 == 32 ? 8 : 4);
-    P->rows_blk = std::min(256, 64 * P->TRw / std::max(1, 64 / n1));
-    P->lds_roww = (size_t)P->TRw * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
-    {
-        const int LY = std::min(64, n2), XPS = 64 / LY;
-        P->hyb_xw = std::min(4, n1 / (HYB_WAVES * XPS));
-        if (P->hyb_xw < 1) { delete P; return SMSM_E_UNSUPPORTED; }   // n1 < HYB_WAVES (64 / min(n2, 64))
-        P->hyb_grid = dim3((n2 / LY) * (n1 / (HYB_WAVES * P->hyb_xw * XPS)), g.B);
-        P->npr = (int)(P->hyb_grid.x * P->hyb_grid.y);
+    set_rows_shape(P, (n1 == 16) ? 16 : (n1 == 32 ? 8 : 4));
+    if (!set_hyb_shape(P, 4) && !set_hyb_shape(P, 2) && !set_hyb_shape(P, 1)) {
+        delete P;                                   // n1 < HYB_WAVES (64 / min(n2, 64))
+        return SMSM_E_UNSUPPORTED;
     }
+    P->npr_max = hyb_blocks(g, 1);                  // the |r|^2 ring is sized for every shape
     P->np_band = 16 * ((4 * g.e + 15) / 16);
     P->KP = dense_stride(g.K);
     P->ntile = dense_tiles(g.K);
@@ -656,7 +684,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     w.grow = wv.take<double2>(nper * 2 * g.e); w.gcol = wv.take<double2>(nper * 2 * g.e);
     w.gcor = wv.take<double2>(nper * 4 * g.e * g.e);
     // partial sums: |r|^2 ring [3][npr]; Re <p, N p> [npc column pass | band]
-    w.pr = wv.take<double>(3 * (size_t)P->npr);
+    w.pr = wv.take<double>(3 * (size_t)P->npr_max);
     w.pq = wv.take<double>((size_t)P->npc + (size_t)band_items(g) * L);
     w.part0 = wv.take<double>((size_t)L * P->npmax); w.part1 = wv.take<double>((size_t)L * P->npmax);
     w.sigma = wv.take<double>(L); w.eps = wv.take<double>(L); w.wscale = wv.take<double>(L);
@@ -1207,6 +1235,75 @@ smsm_status smsm_batch_destroy(smsm_batch* B) {
     (void)hipDeviceSynchronize();
     batch_release(B);
     return SMSM_OK;
+}
+
+smsm_status smsm_plan_autotune(smsm_plan* P, int reps, int* shape, void* stream) {
+    if (!P || reps < 1 || reps > 1000) return SMSM_E_INVALID;
+    if (!P->ws) return SMSM_E_INVALID;   // no workspace bound
+    if (hipSetDevice(P->dev) != hipSuccess) return SMSM_E_DEVICE;
+    hipStream_t st = S(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SMSM_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SMSM_E_DEVICE;
+    }
+    // ms for `reps` rounds of the kernels of `ids`, after one untimed round
+    auto timed = [&](const int* ids, int nid, float* ms) -> smsm_status {
+        for (int round = 0; round < 2; ++round) {
+            if (round == 1 && hipEventRecord(e0, st) != hipSuccess) return SMSM_E_DEVICE;
+            for (int k = 0; k < nid; ++k) {
+                smsm_status s = smsm_launch_kernel(P, ids[k], round == 0 ? 1 : reps, stream);
+                if (s) return s;
+            }
+        }
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return SMSM_E_DEVICE;
+        return SMSM_OK;
+    };
+    smsm_status s = SMSM_OK;
+    static const int kTrw[] = {2, 4, 8, 16, 32};
+    static const int kXw[] = {1, 2, 4};
+    const int rows_ids[] = {SMSM_KERNEL_ROWS_INV, SMSM_KERNEL_ROWS_FWD};
+    const int vec_ids[] = {SMSM_KERNEL_CG_UPDATE};
+    int best_trw = P->TRw, best_xw = P->hyb_xw;
+    float best = 0.0f;
+    bool any = false;
+    for (int trw : kTrw) {
+        if (s || !rows_shape_ok(P->g, trw)) continue;
+        set_rows_shape(P, trw);
+        float ms = 0.0f;
+        s = timed(rows_ids, 2, &ms);
+        if (!s && (!any || ms < best)) {
+            best = ms;
+            best_trw = trw;
+            any = true;
+        }
+    }
+    set_rows_shape(P, best_trw);
+    any = false;
+    for (int xw : kXw) {
+        if (s || !set_hyb_shape(P, xw)) continue;
+        float ms = 0.0f;
+        s = timed(vec_ids, 1, &ms);
+        if (!s && (!any || ms < best)) {
+            best = ms;
+            best_xw = xw;
+            any = true;
+        }
+    }
+    (void)set_hyb_shape(P, best_xw);
+    // the timed launches ran on whatever the buffers held: forget what they flagged
+    if (!s && (hipMemsetAsync(P->flags, 0, 4 * sizeof(int), st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+        s = SMSM_E_DEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!s && shape) {
+        shape[0] = P->TRw;
+        shape[1] = P->hyb_xw;
+    }
+    return s;
 }
 
 smsm_status smsm_kernel_timer_start(smsm_plan* P, int kernel_id, int capacity, int stride) {

@@ -31,7 +31,7 @@ SMSM_FLAG_REG_F32 = 0x2
 # Every entry point of include/smsm.h.
 ABI_SYMBOLS = (
     "smsm_plan_create", "smsm_plan_destroy", "smsm_plan_device_bytes", "smsm_workspace_bytes",
-    "smsm_set_workspace", "smsm_plan_set_params",
+    "smsm_set_workspace", "smsm_plan_set_params", "smsm_plan_autotune",
     "smsm_solve", "smsm_solve_noalloc", "smsm_plan_status", "smsm_status_string", "smsm_apply_A", "smsm_apply_AH",
     "smsm_apply_AHA", "smsm_gram", "smsm_weights", "smsm_lambda_max", "smsm_set_weights",
     "smsm_apply_reg", "smsm_apply_normal", "smsm_images_sos", "smsm_launch_kernel", "smsm_kernel_cost",
@@ -94,6 +94,8 @@ def lib() -> ctypes.CDLL:
         L.smsm_set_workspace.restype = st
         L.smsm_plan_set_params.argtypes = [vp, ctypes.POINTER(Params)]
         L.smsm_plan_set_params.restype = st
+        L.smsm_plan_autotune.argtypes = [vp, st, ctypes.POINTER(ctypes.c_int), vp]
+        L.smsm_plan_autotune.restype = st
         L.smsm_solve.argtypes = [vp, vp, vp, vp]
         L.smsm_solve.restype = st
         L.smsm_solve_noalloc.argtypes = [vp, vp, vp, vp]
@@ -279,6 +281,14 @@ class Plan:
         _check(lib().smsm_plan_set_params(self._h, ctypes.byref(params)), "smsm_plan_set_params")
         self.params = params
 
+    def autotune(self, reps: int = 20, stream=None):
+        """Choose the launch shapes by timing (smsm_plan_autotune); returns
+        (rows per workgroup of the row transforms, columns per wave of the
+        vector pass)."""
+        shape = (ctypes.c_int * 2)()
+        _check(lib().smsm_plan_autotune(self._h, int(reps), shape, _stream_ptr(stream)), "smsm_plan_autotune")
+        return shape[0], shape[1]
+
     # -- solve ----------------------------------------------------------------
     def solve(self, y, out=None, stream=None):
         """x = IRLS solve of Eq. 10 for y (c64 [Ns][Nc][n2][n1])."""
@@ -413,6 +423,7 @@ smsm_plan_device_bytes = Plan.device_bytes
 smsm_workspace_bytes = Plan.workspace_bytes
 smsm_set_workspace = Plan.set_workspace
 smsm_plan_set_params = Plan.set_params
+smsm_plan_autotune = Plan.autotune
 smsm_solve = Plan.solve
 smsm_solve_noalloc = Plan.solve_noalloc
 smsm_plan_status = Plan.status

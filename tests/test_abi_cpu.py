@@ -107,6 +107,8 @@ def test_entry_points_reject_null_plan():
     assert lib.smsm_plan_device_bytes(None) == 0
     assert lib.smsm_workspace_bytes(None) == 0
     assert lib.smsm_set_workspace(None, None, 0) == pkg.SMSM_E_INVALID
+    shape = (ctypes.c_int * 2)()
+    assert lib.smsm_plan_autotune(None, 10, shape, None) == pkg.SMSM_E_INVALID
 
 
 @needs_lib

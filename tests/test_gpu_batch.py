@@ -177,3 +177,40 @@ def test_batch_of_many_directions_spans_several_graphs(torch_dev):
         plan_a.close()
         plan_b.close()
 
+
+def test_autotuned_launch_shapes_keep_oracle_parity(torch_dev):
+    # smsm_plan_autotune on each benched kind of plan: the chosen shapes are
+    # valid, the row shape alone leaves solves bit for bit the same, and the
+    # tuned solves still match the oracle; a batch captured afterwards equals
+    # the tuned plain solves bit for bit
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    plans, ys, refs = [], [], []
+    try:
+        for k, g in enumerate(GEOMS):
+            plan, y = make_plan(torch, dev, g, 30 + k)
+            x0 = plan.solve(y).clone()
+            trw, xw = plan.autotune(5)
+            print(f"[autotune] {g.n}x{g.n} Ns{g.n_shots}: rows per workgroup {trw}, columns per wave {xw}", flush=True)
+            assert trw >= 1 and xw in (1, 2, 4)
+            x1 = plan.solve(y)
+            assert plan.status() == smsm.SMSM_OK
+            err = o.nrmse(x1.cpu().numpy(), oracle_of(plan, y))
+            assert err < ORACLE_TOL, (k, err)
+            assert o.nrmse(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-12
+            plans.append(plan)
+            ys.append(y)
+            refs.append(x1.clone())
+        xs = [torch.zeros_like(r) for r in refs]
+        batch = smsm.Batch(plans, ys, xs, n_streams=2)
+        try:
+            batch.launch()
+            torch.cuda.synchronize()
+            for k in range(len(plans)):
+                assert torch.equal(xs[k], refs[k]), k
+        finally:
+            batch.close()
+    finally:
+        for plan in plans:
+            plan.close()
+

@@ -90,6 +90,8 @@ def test_every_flat_binding_once(torch_dev):
     call("smsm_set_workspace", plan, ws)
     assert call("smsm_plan_device_bytes", plan) > 0
     call("smsm_plan_set_params", plan, p)
+    trw, xw = call("smsm_plan_autotune", plan, 3)
+    assert trw >= 1 and xw in (1, 2, 4)
     yd = to_dev(torch, dev, y)
     x = call("smsm_solve", plan, yd)
     assert call("smsm_plan_status", plan) == smsm.SMSM_OK
