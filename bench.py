@@ -54,11 +54,12 @@ def synth_inputs(torch, dev, plan, g, case, n_draws=1):
 
 
 # Batched form: ten uneven slice groups (32 coils, 15 x 15 iterations) of
-# power-of-two matrix sizes standing in for 192/224/256, shots {2, 4, 8}, MB
-# {2, 3}; (n, MB, shots, filter).  8 shots need a filter of at most 5 x 5, and
-# at 256 x 256 more shared memory than a workgroup has (generic column pass).
-BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 2, 4, 7), (256, 3, 2, 7), (256, 3, 4, 5),
-               (128, 3, 4, 7), (128, 2, 2, 7), (128, 2, 8, 5), (128, 3, 8, 5), (128, 3, 2, 7))
+# matrix sizes {192, 224, 256}, shots {2, 4, 8}, MB {2, 3}; (n, MB, shots,
+# filter).  8 shots need a filter of at most 5 x 5, and at 256 x 256 more
+# shared memory than a workgroup has (generic column pass).
+BATCH_GEOMS = ((256, 3, 4, 7), (256, 2, 2, 7), (256, 3, 2, 7), (256, 2, 4, 7),
+               (224, 3, 4, 7), (224, 2, 2, 7), (224, 2, 8, 5),
+               (192, 3, 4, 7), (192, 2, 8, 5), (192, 3, 2, 7))
 
 
 def direction_truth(g, case, d, wid):

@@ -71,8 +71,8 @@ typedef enum {
 } smsm_status;
 
 typedef struct {
-    int32_t n1;        /* kx / readout size; power of two, 16..256 */
-    int32_t n2;        /* ky / phase-encode size; power of two, 16..256 */
+    int32_t n1;        /* kx / readout size, 16..256: a power of two, or 3 or 7 times one, a multiple of 16 (e.g. 192, 224) */
+    int32_t n2;        /* ky / phase-encode size, the same set */
     int32_t n_slices;  /* L, simultaneously excited slices, 1..4 */
     int32_t n_shots;   /* Ns, interleaved shots, power of two 1..8, n2/Ns >= 8 */
     int32_t n_coils;   /* Nc, receive channels, >= 1 */

@@ -34,11 +34,23 @@ constexpr int kBatchMaxRepeat = 5;   // entries of one plan per captured graph o
 constexpr int kBatchMaxSegment = 30; // entries per captured graph of a batch
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-int ilog2(int v) {
+// log2 of the largest power of two dividing v (v > 0): the radix-2 part of a
+// transform length
+int pow2_log(int v) {
     int l = 0;
-    while ((1 << l) < v) ++l;
+    while (((v >> l) & 1) == 0) ++l;
     return l;
 }
+// transform lengths the kernels take: 16 .. 256, a power of two times 1, 3 or
+// 7, and a multiple of 16
+bool length_ok(int n) {
+    if (n < 16 || n > 256 || n % 16 != 0) return false;
+    const int q = n >> pow2_log(n);
+    return q == 1 || q == 3 || q == 7;
+}
+constexpr int kRowsAnyTR = 8;         // rows per workgroup of the row passes for lengths with an odd factor
+// ky chunk of the hybrid vector pass: the largest power of two dividing n2, at most 64
+int hyb_ly(const Geo& g) { return std::min(64, g.n2 & -g.n2); }
 
 // Offsets (bytes from the workspace base) of the buffers a solve writes.
 struct WsLayout {
@@ -157,7 +169,7 @@ void set_rows_shape(smsm_plan* P, int trw) {
 // Vector pass: xw columns per wave, HYB_WAVES waves per workgroup, chunks of
 // min(n2, 64) ky; the blocks must tile the image exactly.
 int hyb_blocks(const Geo& g, int xw) {
-    const int LY = std::min(64, g.n2), XPS = 64 / LY, per = HYB_WAVES * xw * XPS;
+    const int LY = hyb_ly(g), XPS = 64 / LY, per = HYB_WAVES * xw * XPS;
     if (g.n1 % per != 0) return 0;
     return (g.n2 / LY) * (g.n1 / per) * g.B;
 }
@@ -165,7 +177,7 @@ bool set_hyb_shape(smsm_plan* P, int xw) {
     const Geo& g = P->g;
     const int nb = hyb_blocks(g, xw);
     if (nb <= 0 || (P->npr_max > 0 && nb > P->npr_max)) return false;
-    const int LY = std::min(64, g.n2), XPS = 64 / LY;
+    const int LY = hyb_ly(g), XPS = 64 / LY;
     P->hyb_xw = xw;
     P->hyb_grid = dim3((g.n2 / LY) * (g.n1 / (HYB_WAVES * xw * XPS)), g.B);
     P->npr = nb;
@@ -176,6 +188,12 @@ bool set_hyb_shape(smsm_plan* P, int xw) {
 // kx inverse DFT, natural [B][n2][n1] -> hybrid [B][n1][n2].
 smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
     const Geo& g = P->g;
+    if (!is_pow2(g.n1)) {
+        hipLaunchKernelGGL(k_rows_any<true>, dim3(g.n2 / kRowsAnyTR, g.B), dim3(kThreads),
+                           (size_t)kRowsAnyTR * (g.n1 + 1) * sizeof(double2), st, g, in, out, P->tw1, kRowsAnyTR);
+        LAUNCH_CHECK();
+        return SMSM_OK;
+    }
     const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
     switch (g.n1) {
@@ -192,6 +210,12 @@ smsm_status rows_inv(smsm_plan* P, const double2* in, double2* out, hipStream_t 
 // kx forward DFT, hybrid -> natural.
 smsm_status rows_fwd(smsm_plan* P, const double2* in, double2* out, hipStream_t st) {
     const Geo& g = P->g;
+    if (!is_pow2(g.n1)) {
+        hipLaunchKernelGGL(k_rows_any<false>, dim3(g.n2 / kRowsAnyTR, g.B), dim3(kThreads),
+                           (size_t)kRowsAnyTR * (g.n1 + 1) * sizeof(double2), st, g, in, out, P->tw1, kRowsAnyTR);
+        LAUNCH_CHECK();
+        return SMSM_OK;
+    }
     const dim3 grid(g.n2 / P->TRw, g.B), blk(P->rows_blk);
     const size_t lds = P->lds_roww;
     switch (g.n1) {
@@ -343,7 +367,7 @@ smsm_status hyb_update(smsm_plan* P, HybArgs a, hipStream_t st) {
     a.npq = P->npc + (a.use_band ? band_items(P->g) * P->g.L : 0);
     if (!a.alpha_out) a.alpha_out = P->cgs + 8;
     a.flags = P->flags;
-    const void* fn = hyb_update_fn(a.mode, P->hyb_xw, P->g.n2 >= 64, a.use_band != 0);
+    const void* fn = hyb_update_fn(a.mode, P->hyb_xw, hyb_ly(P->g) == 64, a.use_band != 0);
     void* args[] = {&a};
     if (!fn || hipLaunchKernel(fn, P->hyb_grid, dim3(64 * HYB_WAVES), args, 0, st) != hipSuccess) return SMSM_E_DEVICE;
     LAUNCH_CHECK();
@@ -382,8 +406,12 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
     hipLaunchKernelGGL(k_band_tables, dim3(blocks), dim3(kThreads), 0, st, g, P->W, 0.5 * P->prm.lambda,
                        P->Kc, P->Dside, P->Dx, P->khat_f32 ? 1 : 0);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_band_rowhat, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g, P->Dside,
-                       P->tw1, P->Dhat, P->khat_f32 ? 1 : 0);
+    if (is_pow2(g.n1))
+        hipLaunchKernelGGL(k_band_rowhat<true>, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g,
+                           P->Dside, P->tw1, P->Dhat, P->khat_f32 ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_band_rowhat<false>, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g,
+                           P->Dside, P->tw1, P->Dhat, P->khat_f32 ? 1 : 0);
     LAUNCH_CHECK();
     if (P->col_fast >= 0) {
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * (g.Ns + 1) / 2), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
@@ -424,7 +452,9 @@ smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double
         vh = P->h1;
     }
     const size_t lds = P->lds_gram;
-    switch (g.n2) {
+    if (!is_pow2(g.n2)) {
+        hipLaunchKernelGGL(k_gram_q_any, dim3(g.n1), dim3(512), lds, st, g, vh, P->tw2, P->gpart);
+    } else switch (g.n2) {
         case 16: hipLaunchKernelGGL(k_gram_q<16>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
         case 32: hipLaunchKernelGGL(k_gram_q<32>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
         case 64: hipLaunchKernelGGL(k_gram_q<64>, dim3(g.n1), dim3(kThreads), lds, st, g, vh, P->tw2, P->gpart); break;
@@ -434,16 +464,30 @@ smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double
     LAUNCH_CHECK();
     const int wpb = kThreads / 64;
     const int nwc = g.L * g.npairs * g.nc;
-    hipLaunchKernelGGL(k_gram_c, dim3((nwc + wpb - 1) / wpb), dim3(kThreads), 0, st, g, P->gpart, P->tw1, P->gC);
+    if (is_pow2(g.n1))
+        hipLaunchKernelGGL(k_gram_c<true>, dim3((nwc + wpb - 1) / wpb), dim3(kThreads), 0, st, g, P->gpart, P->tw1,
+                           P->gC);
+    else
+        hipLaunchKernelGGL(k_gram_c<false>, dim3((nwc + wpb - 1) / wpb), dim3(kThreads), 0, st, g, P->gpart, P->tw1,
+                           P->gC);
     LAUNCH_CHECK();
     // natural band columns of v (contiguous in ky) for the column sums
     if ((s = band_extract(P, vh, false, st))) return s;
-    hipLaunchKernelGGL(k_gram_lines, dim3(2 * g.e * g.L * g.npairs, 2), dim3(kThreads), P->lds_gram_lines, st, g, v,
-                       P->pcol, P->grow, P->gcol);
+    const bool p2 = is_pow2(g.n1) && is_pow2(g.n2);
+    const dim3 gl(2 * g.e * g.L * g.npairs, 2);
+    if (p2)
+        hipLaunchKernelGGL(k_gram_lines<true>, gl, dim3(kThreads), P->lds_gram_lines, st, g, v, P->pcol, P->grow,
+                           P->gcol);
+    else
+        hipLaunchKernelGGL(k_gram_lines<false>, gl, dim3(kThreads), P->lds_gram_lines, st, g, v, P->pcol, P->grow,
+                           P->gcol);
     LAUNCH_CHECK();
     const long ncor = (long)nwc * g.nc * 4 * g.e * g.e;
-    hipLaunchKernelGGL(k_gram_corners, dim3((int)std::min<long>(4096, (ncor + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, g, v, P->gcor);
+    const dim3 gcg((int)std::min<long>(4096, (ncor + kThreads - 1) / kThreads));
+    if (p2)
+        hipLaunchKernelGGL(k_gram_corners<true>, gcg, dim3(kThreads), 0, st, g, v, P->gcor);
+    else
+        hipLaunchKernelGGL(k_gram_corners<false>, gcg, dim3(kThreads), 0, st, g, v, P->gcor);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gram_assemble, dim3(nwc * g.nc), dim3(64), 0, st, g, P->gC, P->grow, P->gcol, P->gcor, G);
     LAUNCH_CHECK();
@@ -587,7 +631,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const int n1 = geom->n1, n2 = geom->n2, L = geom->n_slices, Ns = geom->n_shots, Nc = geom->n_coils,
               r = geom->filt;
     if (n1 <= 0 || n2 <= 0 || L <= 0 || Ns <= 0 || Nc <= 0 || r <= 0) return SMSM_E_INVALID;
-    if (!is_pow2(n1) || !is_pow2(n2) || n1 < 16 || n2 < 16 || n1 > 256 || n2 > 256) return SMSM_E_UNSUPPORTED;
+    if (!length_ok(n1) || !length_ok(n2)) return SMSM_E_UNSUPPORTED;
     if (!is_pow2(Ns) || Ns > 8 || n2 / Ns < 8 || L > 4) return SMSM_E_UNSUPPORTED;
     if (r < 2 || 2 * r - 1 > std::min(n1, n2) / 2 || Ns * r * r > 256 || 2 * r - 1 > BAND_MAX_NC)
         return SMSM_E_UNSUPPORTED;
@@ -602,7 +646,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     Geo& g = P->g;
     g.n1 = n1; g.n2 = n2; g.L = L; g.Ns = Ns; g.Nc = Nc; g.r = r;
     g.K = Ns * r * r; g.nc = 2 * r - 1; g.e = r - 1; g.M = n2 / Ns;
-    g.logn1 = ilog2(n1); g.logn2 = ilog2(n2); g.logM = ilog2(g.M);
+    g.logn1 = pow2_log(n1); g.logn2 = pow2_log(n2); g.logM = pow2_log(g.M);
     g.B = L * Ns;
     g.nband = 2 * g.e * n1 + 2 * g.e * (n2 - 2 * g.e);
     g.npairs = Ns * (Ns + 1) / 2;
@@ -610,7 +654,8 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     P->ns_iters = params->ns_max_iter > 0 ? params->ns_max_iter : kNsDefaultIters;
 
     P->TR = std::max(1, std::min(n2, 2048 / n1));
-    P->TRy = std::min(g.M, P->TR);
+    while (P->TR & (P->TR - 1)) P->TR &= P->TR - 1;   // a power of two
+    P->TRy = std::min(g.M & -g.M, P->TR);              // divides the M folded lines
     P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
@@ -642,7 +687,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         return SMSM_E_UNSUPPORTED;
     }
     for (int k = 0; k < (int)(sizeof(kColFast) / sizeof(kColFast[0])); ++k)
-        if (kColFast[k].M == g.M && kColFast[k].L == L && kColFast[k].Ns == Ns &&
+        if (kColFast[k].M == g.M && kColFast[k].L == L && kColFast[k].Ns == Ns && is_pow2(n1) && is_pow2(n2) &&
             P->lds_colfast <= (size_t)max_lds)
             P->col_fast = k;
 
@@ -770,7 +815,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                             {(const void*)&k_gram_q<64>, P->lds_gram}, {(const void*)&k_gram_q<128>, P->lds_gram},
                             {(const void*)&k_gram_q<256>, P->lds_gram}, {(const void*)P->band, P->lds_band},
                             {(const void*)P->band_f32, P->lds_band},
-                            {(const void*)&k_gram_lines, P->lds_gram_lines}};
+                            {(const void*)&k_gram_lines<true>, P->lds_gram_lines},
+                            {(const void*)&k_gram_lines<false>, P->lds_gram_lines},
+                            {(const void*)&k_gram_q_any, P->lds_gram}};
         for (const Opt& o : opts)
             if (hipFuncSetAttribute(o.f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)o.bytes) != hipSuccess)
                 ok = false;
@@ -1271,7 +1318,7 @@ smsm_status smsm_plan_autotune(smsm_plan* P, int reps, int* shape, void* stream)
     float best = 0.0f;
     bool any = false;
     for (int trw : kTrw) {
-        if (s || !rows_shape_ok(P->g, trw)) continue;
+        if (s || !is_pow2(P->g.n1) || !rows_shape_ok(P->g, trw)) continue;
         set_rows_shape(P, trw);
         float ms = 0.0f;
         s = timed(rows_ids, 2, &ms);
@@ -1354,7 +1401,10 @@ smsm_status smsm_images_sos(smsm_plan* P, const void* x_dev, void* img_dev, void
     if (s) return s;
     const dim3 grid(g.n1, g.L);
     double* img = (double*)img_dev;
-    switch (g.n2) {
+    if (!is_pow2(g.n2)) {
+        hipLaunchKernelGGL(k_sos_any, grid, dim3(kThreads), (size_t)(g.Ns + 1) * g.n2 * sizeof(double2), st, g,
+                           P->h1, P->tw2, img);
+    } else switch (g.n2) {
         case 16: hipLaunchKernelGGL(k_sos_cols<16>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
         case 32: hipLaunchKernelGGL(k_sos_cols<32>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;
         case 64: hipLaunchKernelGGL(k_sos_cols<64>, grid, dim3(64), 0, st, g, P->h1, P->tw2, img); break;

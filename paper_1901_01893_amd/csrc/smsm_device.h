@@ -158,15 +158,95 @@ SMSM_DEV void sum_partials2(const double* __restrict__ a, int na, const double* 
     __syncthreads();
 }
 
+// v mod n for v in [-n, 2n) (one wrap either way), any length n > 0.
+SMSM_DEV int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// v mod n in [0, n) for any v (a mask when n is a power of two).
+SMSM_DEV int imod(int v, int n) {
+    if ((n & (n - 1)) == 0) return v & (n - 1);
+    const int m = v % n;
+    return m < 0 ? m + n : m;
+}
+
+// Outputs per thread of the final step of a transform whose length has an
+// odd factor (each launch keeps nb n <= FFT_MIX_PER_THREAD x threads).
+#define FFT_MIX_PER_THREAD 16
+
 // Batched in-place FFT in shared memory.
-// nb sequences of length n = 2^logn; sequence b occupies buf[b*stride + j].
-// Forward computes X[k] = sum_j x[j] e^{-2 pi i jk/n}; inverse uses e^{+...}
-// (both unnormalised).  tw[k] = e^{-2 pi i k/n} for k < n/2 (global or shared).
-// All threads of the block must call it; it starts and ends with a barrier.
+// nb sequences of length n = q 2^logn (q = 1, or an odd factor such as 3 or
+// 7); sequence b occupies buf[b*stride + j].  Forward computes
+// X[k] = sum_j x[j] e^{-2 pi i jk/n}; inverse uses e^{+...} (both
+// unnormalised).  tw[k] = e^{-2 pi i k/n}, k < n/2 for q = 1, k < n otherwise
+// (global or shared).  For q > 1, decimation in time over the odd factor: the
+// q interleaved sequences x[q m + r] (m < 2^logn) are transformed in place by
+// the radix-2 stages, then X[k] = sum_{r<q} w_n^{r k} Y_r[k mod 2^logn] is
+// formed in registers (at most FFT_MIX_PER_THREAD outputs per thread) and
+// written back.  All threads of the block must call it; it starts and ends
+// with a barrier.
 SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
                             const double2* __restrict__ tw, bool inverse) {
     const int tid = threadIdx.x, nt = blockDim.x;
     __syncthreads();
+    const int q = n >> logn;
+    if (q > 1) {
+        const int p = 1 << logn, hp = p >> 1;
+        for (int idx = tid; idx < nb * n; idx += nt) {
+            const int b = idx / n, jj = idx - b * n, m = jj / q, r = jj - m * q;
+            const int rm = logn ? (int)(__brev((unsigned)m) >> (32 - logn)) : 0;
+            if (m < rm) {
+                double2* s = buf + b * stride;
+                const double2 t = s[q * m + r];
+                s[q * m + r] = s[q * rm + r];
+                s[q * rm + r] = t;
+            }
+        }
+        __syncthreads();
+        for (int st = 0; st < logn; ++st) {
+            const int half = 1 << st;
+            for (int idx = tid; idx < nb * q * hp; idx += nt) {
+                const int b = idx / (q * hp), rem = idx - b * q * hp, r = rem / hp, k = rem - r * hp;
+                const int pos = k & (half - 1);
+                const int i0 = ((k >> st) << (st + 1)) + pos, i1 = i0 + half;
+                double2 w = tw[(pos << (logn - 1 - st)) * q];   // w_p^(.) = w_n^(q .)
+                if (inverse) w.y = -w.y;
+                double2* base = buf + b * stride;
+                const double2 a = base[q * i0 + r];
+                const double2 c = cmul(base[q * i1 + r], w);
+                base[q * i0 + r] = cadd(a, c);
+                base[q * i1 + r] = csub(a, c);
+            }
+            __syncthreads();
+        }
+        double2 out[FFT_MIX_PER_THREAD];
+#pragma unroll
+        for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
+            const int idx = tid + u * nt;
+            if (idx < nb * n) {
+                const int b = idx / n, k = idx - b * n, km = k & (p - 1);
+                const double2* base = buf + b * stride + q * km;
+                double2 acc = base[0];
+                int ph = 0;                                   // r k mod n
+                for (int r = 1; r < q; ++r) {
+                    ph += k;
+                    if (ph >= n) ph -= n;
+                    double2 w = tw[ph];
+                    if (inverse) w.y = -w.y;
+                    acc = cfma(base[r], w, acc);
+                }
+                out[u] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
+            const int idx = tid + u * nt;
+            if (idx < nb * n) {
+                const int b = idx / n, k = idx - b * n;
+                buf[b * stride + k] = out[u];
+            }
+        }
+        __syncthreads();
+        return;
+    }
     if (logn == 0) return;
     for (int idx = tid; idx < nb * n; idx += nt) {
         const int b = idx >> logn, j = idx & (n - 1);

@@ -102,10 +102,55 @@ k_gram_q(Geo g, const double2* __restrict__ h1, const double2* __restrict__ tw2,
     }
 }
 
+// Q as k_gram_q for n2 with an odd factor (3 or 7 times a power of two):
+// the B columns at x inverse-transformed in shared memory (fft_batch_lds),
+// then each (l, pair, d2) bin summed directly over n in order:
+//   Q = (-1)^(d2-e) sum_n conj(u_i[n]) u_i'[n] w^{((d2-e) n) mod n2}.
+// grid n1, block 512; shared memory (B + 1) n2 double2.
+__global__ void __launch_bounds__(512)
+k_gram_q_any(Geo g, const double2* __restrict__ h1, const double2* __restrict__ tw2, double2* __restrict__ Q) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, n2 = g.n2, B = g.B, Ns = g.Ns, nc = g.nc, e = g.e, npairs = g.npairs;
+    const int x = blockIdx.x;
+    double2* U = sm;                 // [B][n2]
+    double2* TW = sm + B * n2;       // [n2]
+    for (int k = threadIdx.x; k < n2; k += blockDim.x) TW[k] = tw2[k];
+    for (int idx = threadIdx.x; idx < B * n2; idx += blockDim.x) {
+        const int b = idx / n2, k = idx - b * n2;
+        U[idx] = cscale(h1[((size_t)b * n1 + x) * n2 + k], sgn_pow(k));
+    }
+    fft_batch_lds(U, n2, g.logn2, B, n2, TW, true);
+    const double isq = 1.0 / sqrt((double)n2);
+    for (int idx = threadIdx.x; idx < B * n2; idx += blockDim.x) {
+        const int n = idx % n2;
+        U[idx] = cscale(U[idx], isq * sgn_pow(n));
+    }
+    __syncthreads();
+    const int nt = g.L * npairs * nc;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int task = t / nc, d2 = t - task * nc;
+        const int l = task / npairs, pair = task - l * npairs;
+        int i, ip;
+        gram_pair(pair, Ns, i, ip);
+        const double2* ui = U + (l * Ns + i) * n2;
+        const double2* uj = U + (l * Ns + ip) * n2;
+        const int step = imod(d2 - e, n2);
+        double2 s = cmk(0.0, 0.0);
+        int ph = 0;
+        for (int n = 0; n < n2; ++n) {
+            s = cfma(cconjmul(ui[n], uj[n]), TW[ph], s);
+            ph += step;
+            if (ph >= n2) ph -= n2;
+        }
+        Q[(((size_t)l * npairs + pair) * n1 + x) * nc + d2] = cscale(s, sgn_pow(d2 - e));
+    }
+}
+
 // C[l][pair][d2][d1] = sum_x Q[l][pair][x][d2] e^{-2 pi i (d1-e)(x-n1/2)/n1}.
 // One wave per (l, pair, d2): the wave's Q column and the kx twiddles are
 // staged in shared memory in one batch, then lane = d1 + GS g sums the x of
 // group g (fixed order) and the groups are added in order.
+template <bool POW2>
 __global__ void __launch_bounds__(256)
 k_gram_c(Geo g, const double2* __restrict__ Q, const double2* __restrict__ tw1, double2* __restrict__ C) {
     __shared__ double2 qs[4][256];
@@ -132,7 +177,10 @@ k_gram_c(Geo g, const double2* __restrict__ Q, const double2* __restrict__ tw1, 
     double2 s = cmk(0.0, 0.0);
     if (d1 < nc) {
 #pragma unroll 8
-        for (int x = x0; x < x0 + xq; ++x) s = cfma(qs[wl][x], ts[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
+        for (int x = x0; x < x0 + xq; ++x) {
+            const int ph = (d1 - e) * (x - n1 / 2);
+            s = cfma(qs[wl][x], ts[POW2 ? ph & (n1 - 1) : imod(ph, n1)], s);
+        }
     }
     s = gram_reduce_groups(s, gs);
     if (qg == 0 && d1 < nc) C[((size_t)lp * nc + d2) * nc + d1] = s;
@@ -148,6 +196,7 @@ k_gram_c(Geo g, const double2* __restrict__ Q, const double2* __restrict__ tw1, 
 // free lag) is then summed by one thread from shared memory, in order.
 // Dynamic shared memory: (1 + 2r-1) max(n1, n2) double2.
 #define GRAM_STAGE 16
+template <bool POW2>
 __global__ void __launch_bounds__(256)
 k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ xcol, double2* __restrict__ rows,
              double2* __restrict__ cols) {
@@ -176,7 +225,8 @@ k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ x
             const int k0 = base + u * blockDim.x, k = k0 < tot ? k0 : tot - 1;
             const bool isa = k < n;
             const int f = isa ? 0 : (k - n) / n, q = isa ? k : (k - n) - f * n;
-            const int line_b = col ? band_pcol((q1a + f - e) & (n1 - 1), n1, e) : (q2a + f - e) & (n2 - 1);
+            const int line_b = col ? band_pcol(POW2 ? (q1a + f - e) & (n1 - 1) : wrap1(q1a + f - e, n1), n1, e)
+                                   : (POW2 ? (q2a + f - e) & (n2 - 1) : wrap1(q2a + f - e, n2));
             const double2* bp = isa ? base_i : base_j;
             v[u] = bp[(size_t)(isa ? line_a : line_b) * ls + q];
         }
@@ -199,8 +249,10 @@ k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ x
 #pragma unroll 2
         for (int q = 0; q < n; q += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                s4[u] = cfma(cmk(a4[2 * (q + u)], -a4[2 * (q + u) + 1]), bf[(q + u + fr - e) & (n - 1)], s4[u]);
+            for (int u = 0; u < 4; ++u) {
+                const int j = q + u + fr - e;
+                s4[u] = cfma(cmk(a4[2 * (q + u)], -a4[2 * (q + u) + 1]), bf[POW2 ? j & (n - 1) : wrap1(j, n)], s4[u]);
+            }
         }
         const double2 s = cadd(cadd(s4[0], s4[1]), cadd(s4[2], s4[3]));
         const int d2 = col ? fr : fx, d1 = col ? fx : fr;
@@ -209,6 +261,7 @@ k_gram_lines(Geo g, const double2* __restrict__ x, const double2* __restrict__ x
 }
 
 // Corner values cor[l][pair][d2][d1][qa][qb] = z_d[band row qa][band col qb].
+template <bool POW2>
 __global__ void k_gram_corners(Geo g, const double2* __restrict__ x, double2* __restrict__ cor) {
     const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e, e2 = 2 * g.e;
     const long total = (long)g.L * g.npairs * nc * nc * e2 * e2;
@@ -227,7 +280,8 @@ __global__ void k_gram_corners(Geo g, const double2* __restrict__ x, double2* __
         const double2* xi = x + ((size_t)l * Ns + i) * n2 * n1;
         const double2* xj = x + ((size_t)l * Ns + ip) * n2 * n1;
         cor[idx] = cconjmul(xi[(size_t)q2 * n1 + q1],
-                            xj[(size_t)((q2 + d2 - e) & (n2 - 1)) * n1 + ((q1 + d1 - e) & (n1 - 1))]);
+                            xj[(size_t)(POW2 ? (q2 + d2 - e) & (n2 - 1) : wrap1(q2 + d2 - e, n2)) * n1 +
+                               (POW2 ? (q1 + d1 - e) & (n1 - 1) : wrap1(q1 + d1 - e, n1))]);
     }
 }
 

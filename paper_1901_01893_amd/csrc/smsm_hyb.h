@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(64 * HYB_WAVES) k_hyb_update(HybArgs a) {
     __shared__ double2 cs[BAND ? HYB_MAX_E2 * 64 : 1];    // corrections [cl][ky in chunk]
     const Geo& g = a.g;
     const int n1 = g.n1, n2 = g.n2, e = g.e, e2 = 2 * g.e;
-    const int LY = n2 < 64 ? n2 : 64, XPS = 64 / LY, nkc = n2 / LY;
+    const int LY = min(64, n2 & -n2), XPS = 64 / LY, nkc = n2 / LY;   // ky chunk: largest power of two dividing n2, <= 64
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int kc = blockIdx.x % nkc, xb = blockIdx.x / nkc, b = blockIdx.y;

@@ -21,6 +21,8 @@
 #pragma once
 #include "smsm_device.h"
 
+#include <type_traits>
+
 struct Geo {
     int n1, n2, L, Ns, Nc, r, K, nc, e, M, logn1, logn2, logM, B, nband, npairs;
 };
@@ -110,7 +112,7 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
 // and its adjoint unfolds an M-point inverse DFT back to n2 points (the
 // (-1)^(Ns m) factors cancel in the normal operator).
 template <int MODE>
-__global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
+__global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
                       const double2* __restrict__ ST, const double2* __restrict__ theta,
                       const double2* __restrict__ tau, const double2* __restrict__ tw2,
                       const double2* __restrict__ twM, const double2* __restrict__ tw1,
@@ -197,7 +199,7 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
             // unfold and accumulate conj(S) * g[n mod M]
             for (int idx = tid; idx < B * n2; idx += nt) {
                 const int b = idx / n2, n = idx - b * n2, l = b / Ns;
-                ACC[idx] = cadd(ACC[idx], cconjmul(SC[l * n2 + n], F[b * M + (n & (M - 1))]));
+                ACC[idx] = cadd(ACC[idx], cconjmul(SC[l * n2 + n], F[b * M + imod(n, M)]));
             }
             __syncthreads();
         }
@@ -217,7 +219,7 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
             const double2* kr = Kc + (size_t)idx * nc;
             double2 a = cmk(0.0, 0.0);
             for (int d1 = 0; d1 < nc; ++d1) {
-                const int ph = ((d1 - e) * nu1) & (n1 - 1);
+                const int ph = imod((d1 - e) * nu1, n1);
                 a = cfma(kr[d1], tw1[ph], a);
             }
             A[idx] = a;
@@ -232,7 +234,7 @@ __global__ void k_col(Geo g, const double2* __restrict__ h1, double2* __restrict
                 const double2 u = cmulc(U[(l * Ns + i) * n2 + n], tau[i * n2 + n]);
                 const double2* ar = A + ((size_t)(l * Ns + i) * Ns + ip) * nc;
                 double2 kv = cmk(0.0, 0.0);
-                for (int d2 = 0; d2 < nc; ++d2) kv = cfma(ar[d2], TW2[((d2 - e) * nu2) & (n2 - 1)], kv);
+                for (int d2 = 0; d2 < nc; ++d2) kv = cfma(ar[d2], TW2[imod((d2 - e) * nu2, n2)], kv);
                 s = cfma(kv, u, s);
             }
             ACC[idx] = cadd(ACC[idx], s);
@@ -460,22 +462,29 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
         // (wrapped); at most BAND_STAGE entries per thread, all loads issued
         // together (threads past the end reload the last entry)
         const int tot = NS * nr * PP;
-        for (int base = threadIdx.x; base < tot; base += BAND_STAGE * blockDim.x) {
-            double2 v[BAND_STAGE];
+        // the wrap of the staged lines: a mask for power-of-two sizes (the same
+        // for every thread, so the two copies of the loop are a uniform branch)
+        auto stage = [&](auto pow2) {
+            for (int base = threadIdx.x; base < tot; base += BAND_STAGE * blockDim.x) {
+                double2 v[BAND_STAGE];
 #pragma unroll
-            for (int u = 0; u < BAND_STAGE; ++u) {
-                const int i0 = base + u * blockDim.x, idx = i0 < tot ? i0 : tot - 1;
-                const int i = idx / (nr * PP), rem = idx - i * nr * PP;
-                const int rr = rem / PP, pp = rem - rr * PP;
-                const int kx = (lc - e + dl0 + rr) & (n1 - 1), ky = (pos0 - e + pp) & (n2 - 1);
-                v[u] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
-            }
+                for (int u = 0; u < BAND_STAGE; ++u) {
+                    const int i0 = base + u * blockDim.x, idx = i0 < tot ? i0 : tot - 1;
+                    const int i = idx / (nr * PP), rem = idx - i * nr * PP;
+                    const int rr = rem / PP, pp = rem - rr * PP;
+                    const int kx = decltype(pow2)::value ? (lc - e + dl0 + rr) & (n1 - 1) : wrap1(lc - e + dl0 + rr, n1);
+                    const int ky = decltype(pow2)::value ? (pos0 - e + pp) & (n2 - 1) : wrap1(pos0 - e + pp, n2);
+                    v[u] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
+                }
 #pragma unroll
-            for (int u = 0; u < BAND_STAGE; ++u) {
-                const int i0 = base + u * blockDim.x;
-                sm[i0 < tot ? i0 : tot - 1] = v[u];
+                for (int u = 0; u < BAND_STAGE; ++u) {
+                    const int i0 = base + u * blockDim.x;
+                    sm[i0 < tot ? i0 : tot - 1] = v[u];
+                }
             }
-        }
+        };
+        if ((n1 & (n1 - 1)) == 0 && (n2 & (n2 - 1)) == 0) stage(std::true_type{});
+        else stage(std::false_type{});
         const double2* Dsrc = a.Dside + ((size_t)l * 4 * e + side * e + delta) * NS * NC * NC * NS;
         __syncthreads();
         const double2* Pw = sm + (size_t)w * nr * PP + min(lane, npos - 1);
@@ -521,7 +530,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
                     for (int d2 = 0; d2 < NC; ++d2) {
                         const size_t o = dh0 + (((size_t)i * NC + d2) * NS + ip) * n1;
                         dv[u][d2] = TF32 ? c64to128(reinterpret_cast<const float2*>(a.Dhat)[o]) : a.Dhat[o];
-                        pv[u][d2] = pri[(size_t)band_pcol((ky + d2 - e) & (n2 - 1), n2, e) * n1];
+                        pv[u][d2] = pri[(size_t)band_pcol(wrap1(ky + d2 - e, n2), n2, e) * n1];
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -553,7 +562,7 @@ __global__ void __launch_bounds__(64 * NS) k_band_hyb(BandArgs a) {
         for (int it = 0; it < IT; ++it) {
             const int t0 = threadIdx.x + it * TPB, t = t0 < nt ? t0 : nt - 1;
             const int i = t / (NC * NC), d = t - i * NC * NC, d2 = d / NC, d1 = d - d2 * NC;
-            const int kx = (q1 - e + d1) & (n1 - 1), ky = (q2 - e + d2) & (n2 - 1);
+            const int kx = wrap1(q1 - e + d1, n1), ky = wrap1(q2 - e + d2, n2);
             pv[it] = a.pcol[((size_t)(l * NS + i) * 4 * e + band_pcol(kx, n1, e)) * n2 + ky];
 #pragma unroll
             for (int ip = 0; ip < NS; ++ip) {
@@ -621,6 +630,7 @@ inline BandFn band_fn(int nc, int ns, bool tf32 = false) {
 // (side tables 0 and 1).  One workgroup per (l, row, i, d2) with its taps and
 // the kx twiddles in shared memory; thread = x, all i'.
 // f32: written as complex64 (same element index), the mixed-precision form.
+template <bool POW2>
 __global__ void __launch_bounds__(256) k_band_rowhat(Geo g, const double2* __restrict__ Dside,
                                                      const double2* __restrict__ tw1, double2* __restrict__ Dhat,
                                                      int f32) {
@@ -638,7 +648,10 @@ __global__ void __launch_bounds__(256) k_band_rowhat(Geo g, const double2* __res
     for (int x = threadIdx.x; x < n1; x += blockDim.x) {
         for (int ip = 0; ip < Ns; ++ip) {
             double2 s = cmk(0.0, 0.0);
-            for (int d1 = 0; d1 < nc; ++d1) s = cfma(DR[d1 * Ns + ip], T1[((d1 - e) * (x - n1 / 2)) & (n1 - 1)], s);
+            for (int d1 = 0; d1 < nc; ++d1) {
+                const int ph = (d1 - e) * (x - n1 / 2);
+                s = cfma(DR[d1 * Ns + ip], T1[POW2 ? ph & (n1 - 1) : imod(ph, n1)], s);
+            }
             if (f32) reinterpret_cast<float2*>(Dhat)[out0 + (size_t)ip * n1 + x] = make_float2((float)s.x, (float)s.y);
             else Dhat[out0 + (size_t)ip * n1 + x] = s;
         }

@@ -155,6 +155,67 @@ k_rows_fwd_w(Geo g, const double2* __restrict__ in, double2* __restrict__ out, c
 }
 
 // ---------------------------------------------------------------------------
+// Row passes for lengths with an odd factor (n1 = 3 or 7 times a power of
+// two), which the in-wave forms do not take: TR rows of one image per
+// workgroup, staged in shared memory (row stride n1 + 1) and transformed by
+// fft_batch_lds.  Same conventions as k_rows_inv_w / k_rows_fwd_w:
+//   INV:  natural [B][n2][n1] -> hybrid [B][n1][n2], centred unitary inverse DFT along kx;
+//   !INV: hybrid [B][n1][n2] -> natural [B][n2][n1], centred unitary forward DFT along x.
+// grid (n2 / TR, B); TR n1 <= FFT_MIX_PER_THREAD x threads.
+// ---------------------------------------------------------------------------
+template <bool INV>
+__global__ void __launch_bounds__(256)
+k_rows_any(Geo g, const double2* __restrict__ in, double2* __restrict__ out, const double2* __restrict__ tw1,
+           int TR) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, n2 = g.n2, st = n1 + 1;
+    const int b = blockIdx.y, j0 = blockIdx.x * TR;
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        if (INV) {
+            const int jr = idx / n1, c = idx - jr * n1;
+            sm[jr * st + c] = cscale(in[((size_t)b * n2 + j0 + jr) * n1 + c], sgn_pow(c));
+        } else {
+            const int c = idx / TR, jr = idx - c * TR;
+            sm[jr * st + c] = cscale(in[((size_t)b * n1 + c) * n2 + j0 + jr], sgn_pow(c));
+        }
+    }
+    fft_batch_lds(sm, n1, g.logn1, TR, st, tw1, INV);
+    const double sc = 1.0 / sqrt((double)n1);
+    for (int idx = threadIdx.x; idx < TR * n1; idx += blockDim.x) {
+        if (INV) {
+            const int c = idx / TR, jr = idx - c * TR;
+            out[((size_t)b * n1 + c) * n2 + j0 + jr] = cscale(sm[jr * st + c], sc * sgn_pow(c));
+        } else {
+            const int jr = idx / n1, k = idx - jr * n1;
+            out[((size_t)b * n2 + j0 + jr) * n1 + k] = cscale(sm[jr * st + k], sc * sgn_pow(k));
+        }
+    }
+}
+
+// Root-sum-of-squares image (as k_sos_cols) for n2 with an odd factor: the
+// Ns columns of slice l at x inverse-transformed in shared memory ([Ns][n2]
+// and the twiddles), shots added in order.  grid (n1, L).
+__global__ void __launch_bounds__(256) k_sos_any(Geo g, const double2* __restrict__ h,
+                                                 const double2* __restrict__ tw2, double* __restrict__ out) {
+    extern __shared__ double2 sm[];
+    const int n1 = g.n1, n2 = g.n2, Ns = g.Ns;
+    const int x = blockIdx.x, l = blockIdx.y;
+    double2* TW = sm + Ns * n2;
+    for (int k = threadIdx.x; k < n2; k += blockDim.x) TW[k] = tw2[k];
+    for (int idx = threadIdx.x; idx < Ns * n2; idx += blockDim.x) {
+        const int i = idx / n2, k = idx - i * n2;
+        sm[idx] = cscale(h[((size_t)(l * Ns + i) * n1 + x) * n2 + k], sgn_pow(k));
+    }
+    fft_batch_lds(sm, n2, g.logn2, Ns, n2, TW, true);
+    const double sc2 = 1.0 / (double)n2;
+    for (int y = threadIdx.x; y < n2; y += blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < Ns; ++i) s += cabs2(sm[i * n2 + y]);
+        out[((size_t)l * n2 + y) * n1 + x] = sqrt(s * sc2);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Root-sum-of-squares image of each slice (the per-shot images of the forward
 // model combined over shots):
 //   out[l][y][x] = sqrt(sum_i |u_{l,i}[y][x]|^2),

@@ -3,7 +3,8 @@ generic column pass (shot counts without a register-resident instance), the
 band kernel for 1, 2 and 8 shots, the vector pass with fewer than 64 ky per
 row, a coil count that leaves a partial coil group, every instance of the fast
 column pass (folded lengths 16, 32 and 64, two and three slices, odd coil
-counts), and one coil with a 1 x 1 schedule.  Each case checks the normal operator with the
+counts), matrix sizes 3 or 7 times a power of two (96, 112, 192, 224), and one
+coil with a 1 x 1 schedule.  Each case checks the normal operator with the
 oracle's weights and a short IRLS solve against the oracle's."""
 import numpy as np
 import pytest
@@ -58,6 +59,23 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 114),
     "n128_L3_Ns2_r7": (si.Geometry(n=128, n_slices=3, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 115),
+    # matrix sizes with an odd factor (3 or 7 times a power of two): generic column
+    # pass with mixed-length transforms (folded lengths 48, 28, 24, 56, 112), the
+    # row, Gram and image passes for such lengths, vector-pass ky chunks of 16 and 32
+    "n96_L2_Ns2_r3": (si.Geometry(n=96, n_slices=2, n_shots=2, n_coils=3, filt=3, lam=1e-3, n_irls=2, n_cg=3,
+                                  phase_order=2, snr=30.0), 116),
+    "n112_L2_Ns4_r3": (si.Geometry(n=112, n_slices=2, n_shots=4, n_coils=3, filt=3, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=2, snr=30.0), 117),
+    "n192_L2_Ns8_r5": (si.Geometry(n=192, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 118),
+    "n224_L2_Ns4_r7": (si.Geometry(n=224, n_slices=2, n_shots=4, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 119),
+    "n224_L3_Ns2_r7": (si.Geometry(n=224, n_slices=3, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 120),
+    "n224_L2_Ns8_r5": (si.Geometry(n=224, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 121),
+    "n192_L3_Ns4_r7": (si.Geometry(n=192, n_slices=3, n_shots=4, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 122),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
