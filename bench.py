@@ -137,6 +137,15 @@ def batched_measurement(torch, dev, n_streams, reps, directions=30):
                     fn()
                 torch.cuda.synchronize()
                 return (time.perf_counter() - t0) / reps
+            per_group = []
+            for k in range(len(plans)):              # one solve of each group alone
+                pl, y = order[k]
+                pl.solve(y, xs_plain[k])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pl.solve(y, xs_plain[k])
+                torch.cuda.synchronize()
+                per_group.append(round((time.perf_counter() - t0) * 1e3, 2))
             t_plain = timed(plain)
             print(f"[bench] batched: plain {t_plain:.2f} s per pass", file=sys.stderr, flush=True)
             t_graph = timed(batch.launch)
@@ -155,6 +164,7 @@ def batched_measurement(torch, dev, n_streams, reps, directions=30):
             "launch_shapes": ([{"rows_per_workgroup": a, "columns_per_wave": b} for a, b in shapes]
                               if autotuned else "defaults"),
             "reps": reps,
+            "ms_per_solve_by_group": per_group,
             "plain_slice_groups_per_s": round(n / t_plain, 3), "graph_slice_groups_per_s": round(n / t_graph, 3),
             "speedup": round(t_plain / t_graph, 3), "outputs_bitwise_equal_to_plain": equal}
 
