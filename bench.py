@@ -179,40 +179,55 @@ MIXED_SEEDS = 30000          # instances of the mixed-precision comparison: 3000
 STORED_SEEDS = (0, 1000, 1001, 1002, 1003)   # stored FP64 oracle solutions of the 256x256 workload
 
 
+MIXED_FORMS = {
+    "reg_f32": ("SMSM_FLAG_REG_F32", "regulariser tables (image-domain Hankel kernel, band row and corner tables) "
+                                     "stored complex64, widened on load; all arithmetic FP64"),
+    "gram_bf16": ("SMSM_FLAG_GRAM_BF16", "Gram of Eq. 8-9 as a GEMM over the patch anchors on the BF16 matrix cores "
+                                         "(three BF16 parts per real component, six part products, FP32 sums over "
+                                         "2048 anchors, FP64 across); everything else FP64"),
+    "gram_bf16+reg_f32": ("SMSM_FLAG_GRAM_BF16 | SMSM_FLAG_REG_F32", "both of the above"),
+}
+
+
 def mixed_measurement(torch, dev, plan, g, workload, ys, x, reps=10, n_inst=64):
-    """The mixed-precision form (SMSM_FLAG_REG_F32) on the same plan:
-    slice-groups/s over `reps` solves after two warm-up solves; the NRMSE of
-    its solution against the FP64 form's (both complex128) on each of n_inst
-    seeded instances of the workload; and, on the stored FP64 oracle
-    solutions of the workload, the NRMSE of both forms against the oracle."""
+    """The mixed-precision forms on the same plan (created able to take the
+    GEMM-form Gram): slice-groups/s of each over `reps` solves after two
+    warm-up solves; the NRMSE of each form's solution against the FP64
+    form's (both complex128) on each of n_inst seeded instances of the
+    workload; and, on the stored FP64 oracle solutions of the workload, the
+    NRMSE of every form against the oracle."""
     import smsm_inputs as si
     from oracle import smsm_oracle as o
     from paper_1901_01893_amd import smsm
     base = smsm.Params.from_buffer_copy(plan.params)
-    mixed, f64 = with_flags(smsm, base, smsm.SMSM_FLAG_REG_F32), with_flags(smsm, base, smsm.SMSM_FLAG_X_C128)
-    mixed128 = with_flags(smsm, mixed, smsm.SMSM_FLAG_X_C128)
+    flags = {name: sum(getattr(smsm, f) for f in spec.split(" | ")) for name, (spec, _) in MIXED_FORMS.items()}
+    f64 = with_flags(smsm, base, smsm.SMSM_FLAG_X_C128)
     nrmse = lambda a, b: float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+    res = {}
     try:
-        plan.set_params(mixed)
-        for k in range(2):
-            plan.solve(ys[k % len(ys)], x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(reps):
-            plan.solve(ys[k % len(ys)], x)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / reps
+        for name, fl in flags.items():
+            plan.set_params(with_flags(smsm, base, fl))
+            for k in range(2):
+                plan.solve(ys[k % len(ys)], x)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(reps):
+                plan.solve(ys[k % len(ys)], x)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            res[name] = {"flags": MIXED_FORMS[name][0], "form": MIXED_FORMS[name][1],
+                         "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3), "per": []}
         wid = si.WORKLOAD_IDS[workload]
         coils = si.make_case(g, 0, wid)["coils"]
         xa = torch.empty(plan.shape_x, dtype=torch.complex128, device=dev)
         xb = torch.empty_like(xa)
-        per = []
         for y in instances(torch, dev, plan, g, wid, list(range(MIXED_SEEDS, MIXED_SEEDS + n_inst)), coils):
             plan.set_params(f64)
             plan.solve(y, xa)
-            plan.set_params(mixed128)
-            plan.solve(y, xb)
-            per.append(nrmse(xb, xa))
+            for name, fl in flags.items():
+                plan.set_params(with_flags(smsm, f64, fl))
+                plan.solve(y, xb)
+                res[name]["per"].append(nrmse(xb, xa))
         stored = []
         for seed in STORED_SEEDS:
             path = os.path.join(ROOT, "tests", "golden", f"oracle_{workload}_seed{seed}.npy")
@@ -223,19 +238,20 @@ def mixed_measurement(torch, dev, plan, g, workload, ys, x, reps=10, n_inst=64):
             ref = torch.from_numpy(np.load(path).astype(np.complex128)).to(dev)
             plan.set_params(f64)
             plan.solve(yd, xa)
-            plan.set_params(mixed128)
-            plan.solve(yd, xb)
-            stored.append({"seed": seed, "fp64": nrmse(xa, ref), "mixed": nrmse(xb, ref)})
+            row = {"seed": seed, "fp64": nrmse(xa, ref)}
+            for name, fl in flags.items():
+                plan.set_params(with_flags(smsm, f64, fl))
+                plan.solve(yd, xb)
+                row[name] = nrmse(xb, ref)
+            stored.append(row)
     finally:
         plan.set_params(base)
-    return {"form": "regulariser tables (image-domain Hankel kernel, band row and corner tables) stored complex64, "
-                    "widened on load; all arithmetic FP64",
-            "slice_groups_per_s": round(1.0 / t, 3), "ms_per_solve": round(t * 1e3, 3),
-            "instances": n_inst,
-            "per_instance_nrmse_vs_fp64_form": {"seeds": f"{MIXED_SEEDS}..{MIXED_SEEDS + n_inst - 1}",
+    for r in res.values():
+        per = r.pop("per")
+        r["per_instance_nrmse_vs_fp64_form"] = {"seeds": f"{MIXED_SEEDS}..{MIXED_SEEDS + n_inst - 1}",
                                                 "max": max(per), "mean": float(np.mean(per)),
-                                                "all": [float(f"{e:.3e}") for e in per]},
-            "vs_stored_oracle": stored}
+                                                "all": [float(f"{e:.3e}") for e in per]}
+    return {"instances": n_inst, "forms": res, "vs_stored_oracle": stored}
 
 
 def host_truth(g, wid, seed, coils):
@@ -640,8 +656,11 @@ def main():
     case = si.make_case(g, 0, si.WORKLOAD_IDS[args.workload])
     coils = torch.from_numpy(case["coils"]).to(dev)
     params = smsm.make_params(lam=g.lam, n_irls=g.n_irls, n_cg=g.n_cg)
+    # created able to take the GEMM-form Gram (its chunk partials in the
+    # workspace) for the mixed-precision forms; the timed solves run without it
     plan = smsm.Plan(g.n, g.n, g.n_slices, g.n_shots, g.n_coils, g.filt, coils, case["masks"],
-                     case["shifts"], params)
+                     case["shifts"], with_flags(smsm, params, smsm.SMSM_FLAG_GRAM_BF16))
+    plan.set_params(params)
     ys = synth_inputs(torch, dev, plan, g, case, 1 if args.profile_kernel else N_DRAWS)
     y = ys[0]
     x = torch.empty(plan.shape_x, dtype=torch.complex64, device=dev)

@@ -99,6 +99,19 @@ typedef struct {
  * when the weights are next built (each IRLS step, smsm_set_weights); the
  * error against the FP64 oracle is reported per instance by the tests. */
 #define SMSM_FLAG_REG_F32 0x2u
+/* Mixed-precision Gram: G_l = H_l^H H_l is formed as a GEMM over the patch
+ * anchors on the BF16 matrix cores (every entry of H split into three BF16
+ * parts per real component, the six leading part products of each real
+ * product, FP32 sums over chunks of 2048 anchors, FP64 across chunks)
+ * instead of from image-domain correlations in FP64; everything else stays
+ * FP64.  The error against the FP64 oracle is reported per instance by the
+ * tests and the benchmark.  Takes effect in smsm_solve and smsm_gram.  The
+ * plan must be created with it (its workspace then holds the chunk partials,
+ * L * ceil(P/2048) * KB(KB+1)/2 * 64 KiB, P = (n1-r+1)(n2-r+1) anchors, KB =
+ * ceil(K/64));
+ * smsm_plan_set_params returns SMSM_E_UNSUPPORTED when it would turn the
+ * flag on for a plan created without it. */
+#define SMSM_FLAG_GRAM_BF16 0x4u
 
 /*
  * Create a plan for one geometry.  coil_maps_dev: c64 [L][Nc][n2][n1] on

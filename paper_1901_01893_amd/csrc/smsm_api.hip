@@ -9,6 +9,7 @@
 #include "smsm_cnn.h"
 #include "smsm_cnn_mfma.h"
 #include "smsm_al.h"
+#include "smsm_gram_mfma.h"
 #include "smsm.h"
 
 #include <hip/hip_ext.h>
@@ -51,11 +52,23 @@ bool length_ok(int n) {
 constexpr int kRowsAnyTR = 8;         // rows per workgroup of the row passes for lengths with an odd factor
 // ky chunk of the hybrid vector pass: the largest power of two dividing n2, at most 64
 int hyb_ly(const Geo& g) { return std::min(64, g.n2 & -g.n2); }
+// Patch-anchor geometry of the Hankel matrices (the GEMM-form Gram and the
+// augmented-Lagrangian kernels)
+AlGeo anchor_geo(const Geo& g) {
+    AlGeo a{};
+    a.n1 = g.n1; a.n2 = g.n2; a.L = g.L; a.Ns = g.Ns; a.r = g.r; a.K = g.K; a.KP = dense_stride(g.K);
+    a.P1 = g.n1 - g.r + 1; a.P2 = g.n2 - g.r + 1; a.NP = a.P1 * a.P2;
+    a.NPP = (a.NP + AL_PT - 1) / AL_PT * AL_PT;
+    a.KB = (g.K + AL_BK - 1) / AL_BK;
+    return a;
+}
+int gram_bf16_chunks(const AlGeo& a) { return (a.NP + GB_CH - 1) / GB_CH; }
 
 // Offsets (bytes from the workspace base) of the buffers a solve writes.
 struct WsLayout {
     size_t x, b, r, p, q, h1, h2, ytil, G, W, Y0, Y1, Z0, Z1, T, Kc, Khat, Dside, Dx, crow, ccol, ccorner, Dhat,
-        pcol, prow, gpart, gC, grow, gcol, gcor, pr, pq, part0, part1, sigma, eps, wscale, epsin, nsmu, done, cgs;
+        pcol, prow, gpart, gC, grow, gcol, gcor, pr, pq, part0, part1, sigma, eps, wscale, epsin, nsmu, done, cgs,
+        gbpart;
 };
 
 }  // namespace
@@ -94,6 +107,8 @@ struct smsm_plan {
     double2 *x = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     double2 *h1 = nullptr, *h2 = nullptr, *ytil = nullptr;
     double2 *G = nullptr, *W = nullptr, *Y0 = nullptr, *Y1 = nullptr, *Z0 = nullptr, *Z1 = nullptr, *T = nullptr;
+    double2* gbpart = nullptr;   // chunk partials of the GEMM-form Gram
+    bool gram_bf16_ws = false;   // the workspace holds gbpart (created with SMSM_FLAG_GRAM_BF16)
     double2 *Kc = nullptr, *Khat = nullptr, *Dside = nullptr, *Dx = nullptr, *crow = nullptr, *ccol = nullptr, *ccorner = nullptr;
     double2 *Dhat = nullptr, *pcol = nullptr, *prow = nullptr, *fx = nullptr, *finv = nullptr;
     double2 *gpart = nullptr, *gC = nullptr, *grow = nullptr, *gcol = nullptr, *gcor = nullptr;
@@ -447,6 +462,17 @@ smsm_status chain_normal(smsm_plan* P, const double2* v, double2* out, int mode_
 smsm_status chain_gram(smsm_plan* P, const double2* v, const double2* vh, double2* G, hipStream_t st) {
     const Geo& g = P->g;
     smsm_status s = SMSM_OK;
+    if (P->prm.flags & SMSM_FLAG_GRAM_BF16) {
+        // the GEMM form on the BF16 matrix cores (needs the natural v only)
+        const AlGeo a = anchor_geo(g);
+        const int nch = gram_bf16_chunks(a);
+        hipLaunchKernelGGL(k_gram_bf16, dim3(a.KB * (a.KB + 1) / 2, nch, g.L), dim3(kThreads), 0, st, a, v,
+                           P->gbpart);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gram_bf16_sum, dim3(kPadBlocks, g.L), dim3(kThreads), 0, st, a, P->gbpart, nch, G);
+        LAUNCH_CHECK();
+        return SMSM_OK;
+    }
     if (!vh) {
         if ((s = rows_inv(P, v, P->h1, st))) return s;
         vh = P->h1;
@@ -586,6 +612,7 @@ void bind_workspace(smsm_plan* P, void* base) {
     P->nsmu = d1(w.nsmu);
     P->done = c ? (int*)(c + w.done) : nullptr;
     P->cgs = d1(w.cgs);
+    P->gbpart = P->gram_bf16_ws ? d2(w.gbpart) : nullptr;
     // the weight tables of an earlier workspace are not in this one
     P->have_weights = false;
 }
@@ -736,6 +763,11 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     w.epsin = wv.take<double>(L); w.nsmu = wv.take<double>((size_t)P->ns_iters * L);
     w.done = wv.take<int>((size_t)(P->ns_iters + 2) * L);
     w.cgs = wv.take<double>(16);
+    P->gram_bf16_ws = (params->flags & SMSM_FLAG_GRAM_BF16) != 0;
+    if (P->gram_bf16_ws) {   // chunk partials of the GEMM-form Gram, only for plans created with it
+        const AlGeo a = anchor_geo(g);
+        w.gbpart = wv.take<double2>((size_t)L * gram_bf16_chunks(a) * (a.KB * (a.KB + 1) / 2) * 64 * 64);
+    }
     P->ws_bytes = (wv.off + 255) & ~size_t(255);
 
     P->bytes = cv.off;
@@ -866,6 +898,7 @@ smsm_status smsm_plan_set_params(smsm_plan* plan, const smsm_params* params) {
     if (s) return s;
     const int nit = params->ns_max_iter > 0 ? params->ns_max_iter : kNsDefaultIters;
     if (nit > plan->ns_iters) return SMSM_E_UNSUPPORTED;   // done-flag array sized at creation
+    if ((params->flags & SMSM_FLAG_GRAM_BF16) && !plan->gram_bf16_ws) return SMSM_E_UNSUPPORTED;
     plan->prm = *params;
     plan->ns_iters = nit;
     return SMSM_OK;

@@ -27,6 +27,7 @@ SMSM_E_SCRATCH = -7
 NOALLOC_SCRATCH_BYTES = 64 << 20
 SMSM_FLAG_X_C128 = 0x1
 SMSM_FLAG_REG_F32 = 0x2
+SMSM_FLAG_GRAM_BF16 = 0x4
 
 # Every entry point of include/smsm.h.
 ABI_SYMBOLS = (

@@ -1,13 +1,16 @@
-"""Mixed-precision form (SMSM_FLAG_REG_F32: the regulariser's tables stored
-complex64, all arithmetic FP64): NRMSE against the FP64
-oracle per seeded instance of the 64 x 64 workload, and per instance of the
-256 x 256 slice group against the oracle's stored solutions (five seeds),
-beside the FP64 form.  The bar is the solve's NRMSE <= 1e-5."""
+"""Mixed-precision forms: SMSM_FLAG_REG_F32 (the regulariser's tables stored
+complex64, all arithmetic FP64) and SMSM_FLAG_GRAM_BF16 (the Gram of Eq. 8-9
+as a GEMM on the BF16 matrix cores).  The Gram alone against the oracle's,
+entry by entry; whole solves: NRMSE against the FP64 oracle per seeded
+instance of the 64 x 64 workload, and per instance of the 256 x 256 slice
+group against the oracle's stored solutions (five seeds).  The bar is the
+solve's NRMSE <= 1e-5."""
 import os
 
 import numpy as np
 import pytest
 
+import smsm_inputs as si
 from oracle import smsm_oracle as o
 from tests.helpers import case_for, oracle_params
 
@@ -78,4 +81,126 @@ def test_mixed_precision_sg256_against_stored_oracle(torch_dev, seed):
     e_m, e_f = o.nrmse(xm, ref), o.nrmse(xf, ref)
     print(f"[sg256 seed={seed}] NRMSE vs stored oracle: mixed {e_m:.3e}, FP64 {e_f:.3e}", flush=True)
     assert e_f < 1e-7          # FP64 form: the complex64 rounding of the stored reference (~3e-8)
+    assert e_m < SOLVE_TOL
+
+
+# ---- the GEMM-form Gram on the BF16 matrix cores (SMSM_FLAG_GRAM_BF16) ----
+
+GRAM_BF16_TOL = 1e-5   # max |G - G_ref|_ab / sqrt(G_ref_aa G_ref_bb) over the entries
+
+GRAM_GEOMS = {
+    # K = 100: one full 64-column block and a ragged one; 3600 anchors (two chunks, the second ragged)
+    "small": si.WORKLOADS["small"],
+    # K = 196 (four blocks, the last of 4 columns); 3364 anchors
+    "n64_L3_Ns4_r7": si.Geometry(n=64, n_slices=3, n_shots=4, n_coils=8, filt=7, lam=1e-3, n_irls=1, n_cg=1,
+                                 phase_order=2, snr=30.0),
+    # K = 50 (one ragged block), 784 anchors (one partial chunk)
+    "n32_L2_Ns2_r5": si.Geometry(n=32, n_slices=2, n_shots=2, n_coils=4, filt=5, lam=1e-3, n_irls=1, n_cg=1,
+                                 phase_order=2, snr=30.0),
+    # a length of three times a power of two: K = 18, 8836 anchors
+    "n96_L2_Ns2_r3": si.Geometry(n=96, n_slices=2, n_shots=2, n_coils=4, filt=3, lam=1e-3, n_irls=1, n_cg=1,
+                                 phase_order=2, snr=30.0),
+    # eight shots: K = 200 (four blocks, the last of 8 columns)
+    "n64_L2_Ns8_r5": si.Geometry(n=64, n_slices=2, n_shots=8, n_coils=8, filt=5, lam=1e-3, n_irls=1, n_cg=1,
+                                 phase_order=2, snr=30.0),
+}
+
+
+def entry_scaled_error(got, ref):
+    d = np.sqrt(np.abs(np.real(np.diag(ref))))
+    return float(np.max(np.abs(got - ref) / np.maximum(np.outer(d, d), 1e-300)))
+
+
+@pytest.mark.parametrize("name", sorted(GRAM_GEOMS))
+def test_bf16_gram_matches_oracle(torch_dev, name):
+    """smsm_gram of a plan created with SMSM_FLAG_GRAM_BF16 against the
+    oracle's Gram of the Hankel matrix (Eq. 8-9), on the adjoint of simulated
+    data and on random input: every entry within GRAM_BF16_TOL of the
+    Cauchy-Schwarz scale sqrt(G_aa G_bb), exactly Hermitian, and different
+    from the FP64 form (the matrix cores are really used)."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g = GRAM_GEOMS[name]
+    case = si.make_case(g, 5, 300)
+    _, y = o.simulate(case, g.n_slices, g.snr)
+    theta = o.caipi_phase(g.n, case["shifts"])
+    xs = {"adjoint": o.adjoint(y, case["coils"], case["masks"], theta),
+          "random": np.random.default_rng(7).standard_normal((g.n_slices, g.n_shots, g.n, g.n, 2)) @ [1, 1j]}
+    with plan_for(torch, dev, g, case, smsm.SMSM_FLAG_X_C128 | smsm.SMSM_FLAG_GRAM_BF16) as pb, \
+            plan_for(torch, dev, g, case, smsm.SMSM_FLAG_X_C128) as pf:
+        for kind, x in xs.items():
+            xd = torch.from_numpy(np.ascontiguousarray(x, np.complex128)).to(dev)
+            gb = pb.gram(xd).cpu().numpy()
+            gf = pf.gram(xd).cpu().numpy()
+            assert pb.status() == smsm.SMSM_OK
+            errs = []
+            for l in range(g.n_slices):
+                ref = o.gram(x[l], g.filt)
+                errs.append(entry_scaled_error(gb[l], ref))
+                assert np.array_equal(gb[l], gb[l].conj().T)
+            print(f"[bf16 gram {name} {kind}] max scaled entry error {max(errs):.2e} "
+                  f"(FP64 form {max(entry_scaled_error(gf[l], o.gram(x[l], g.filt)) for l in range(g.n_slices)):.1e})",
+                  flush=True)
+            assert max(errs) < GRAM_BF16_TOL
+            assert not np.array_equal(gb, gf)
+
+
+def test_bf16_gram_needs_creation_flag(torch_dev):
+    """The flag cannot be turned on after creation (the workspace has no room
+    for the chunk partials); a plan created with it can turn it off and on."""
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    g, case, _, _ = case_for("small", 100)
+    with plan_for(torch, dev, g, case, smsm.SMSM_FLAG_X_C128) as pf:
+        with pytest.raises(smsm.SmsmError):
+            pf.set_params(smsm.make_params(lam=g.lam, flags=smsm.SMSM_FLAG_X_C128 | smsm.SMSM_FLAG_GRAM_BF16))
+    with plan_for(torch, dev, g, case, smsm.SMSM_FLAG_X_C128 | smsm.SMSM_FLAG_GRAM_BF16) as pb:
+        pb.set_params(smsm.make_params(lam=g.lam, flags=smsm.SMSM_FLAG_X_C128))
+        pb.set_params(smsm.make_params(lam=g.lam, flags=smsm.SMSM_FLAG_X_C128 | smsm.SMSM_FLAG_GRAM_BF16))
+
+
+MIXED_FORMS = {
+    "gram_bf16": "SMSM_FLAG_GRAM_BF16",
+    "gram_bf16+reg_f32": "SMSM_FLAG_GRAM_BF16 | SMSM_FLAG_REG_F32",
+}
+
+
+def form_flags(smsm, form):
+    f = smsm.SMSM_FLAG_X_C128
+    for name in MIXED_FORMS[form].split(" | "):
+        f |= getattr(smsm, name)
+    return f
+
+
+@pytest.mark.parametrize("form", sorted(MIXED_FORMS))
+def test_bf16_gram_solve_per_instance_nrmse(torch_dev, form):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    errs = []
+    for seed in range(N_INSTANCES):
+        g, case, _, y = case_for("small", 100 + seed)
+        ref = o.solve(y.astype(np.complex128), case["coils"], case["masks"], case["shifts"], oracle_params(g))
+        with plan_for(torch, dev, g, case, form_flags(smsm, form)) as pm:
+            xm = pm.solve(torch.from_numpy(y).to(dev)).cpu().numpy()
+            assert pm.status() == smsm.SMSM_OK
+        errs.append(o.nrmse(xm, ref))
+        print(f"[{form} small seed={100 + seed}] NRMSE vs oracle {errs[-1]:.3e}", flush=True)
+        assert errs[-1] < SOLVE_TOL
+    print(f"[{form} small] max NRMSE over {N_INSTANCES} instances = {max(errs):.3e}", flush=True)
+
+
+@pytest.mark.parametrize("seed", SG256_SEEDS)
+def test_bf16_gram_sg256_against_stored_oracle(torch_dev, seed):
+    torch, dev = torch_dev
+    from paper_1901_01893_amd import smsm
+    path = os.path.join(GOLDEN_DIR, f"oracle_sg256_seed{seed}.npy")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle solution not generated")
+    ref = np.load(path).astype(np.complex128)
+    g, case, _, y = case_for("sg256", seed)
+    with plan_for(torch, dev, g, case, form_flags(smsm, "gram_bf16+reg_f32")) as pm:
+        xm = pm.solve(torch.from_numpy(y).to(dev)).cpu().numpy()
+        assert pm.status() == smsm.SMSM_OK
+    e_m = o.nrmse(xm, ref)
+    print(f"[gram_bf16+reg_f32 sg256 seed={seed}] NRMSE vs stored oracle {e_m:.3e}", flush=True)
     assert e_m < SOLVE_TOL
