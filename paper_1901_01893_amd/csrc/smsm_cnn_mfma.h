@@ -28,6 +28,7 @@
 
 typedef __bf16 cm_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float cm_f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned cm_u32x4 __attribute__((ext_vector_type(4)));
 
 #define CM_TR 4                                   // output rows per workgroup (one per wave)
 #define CM_TC 64                                  // output columns per workgroup
@@ -70,19 +71,40 @@ __global__ void k_conv_wpack(int ci, int co, const float* __restrict__ w, int bw
 // BF16 network), and round_out != 0 stores each output rounded to a BF16
 // value (the network's hidden activations).  grid (ceil(H / CM_TR)
 // ceil(W / CM_TC), rows / (16 NOB), N), block 256.
+//
+// Workgroup order: the hardware hands consecutive workgroups to the eight
+// XCDs in turn, so the logical tile of a workgroup is taken XCD-major (when
+// the grid divides by eight): each XCD works through a contiguous run of
+// tiles, whose shared halo rows then meet in that XCD's L2.  The output
+// tile goes out through shared memory (16 channels at a time per wave), so
+// that every store instruction writes whole 128-byte lines.
+#define CM_EST 80    // floats per staged output channel row (64 pixels + 16: the 4 row groups of a write on distinct banks)
 template <int NOB, int PLANES>
 __global__ void __launch_bounds__(256, 3)
 k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__ in,
                const unsigned short* __restrict__ P, const float* __restrict__ bias, float* __restrict__ out,
                int relu, int round_out) {
-    __shared__ __attribute__((aligned(16))) unsigned short xs[PLANES][CM_POS * CM_PSTR];
-    __shared__ __attribute__((aligned(16))) unsigned short wsm[16 * NOB * CM_WSTR];
+    constexpr int XS = CM_POS * CM_PSTR;     // BF16 per staged plane
+    static_assert((PLANES * XS + 16 * NOB * CM_WSTR) * sizeof(unsigned short) >= 4 * 16 * CM_EST * sizeof(float),
+                  "output staging fits the operand buffers");
+    __shared__ __attribute__((aligned(16))) unsigned short sbuf[PLANES * XS + 16 * NOB * CM_WSTR];
+    unsigned short* wsm = sbuf + PLANES * XS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, l16 = lane & 15;
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    {
+        const int nx = gridDim.x, ny = gridDim.y, nb = nx * ny * gridDim.z;
+        if ((nb & 7) == 0) {
+            const int b = bx + nx * (by + ny * bz), lg = (b & 7) * (nb >> 3) + (b >> 3);
+            bx = lg % nx;
+            by = (lg / nx) % ny;
+            bz = lg / (nx * ny);
+        }
+    }
     const int tiles_x = (W + CM_TC - 1) / CM_TC;
-    const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
-    const int r0 = ty * CM_TR, c0 = tx * CM_TC, n = blockIdx.z;
-    const int o0 = blockIdx.y * 16 * NOB;
+    const int ty = bx / tiles_x, tx = bx - ty * tiles_x;
+    const int r0 = ty * CM_TR, c0 = tx * CM_TC, n = bz;
+    const int o0 = by * 16 * NOB;
     const size_t npx = (size_t)H * W;
     const float* src = in + (size_t)n * ci * npx;
     const int half = (g & 1) * 8;               // this lane group's channels within the chunk
@@ -126,13 +148,13 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
     constexpr int NW = (16 * NOB * 9 * 2 + 255) / 256;
     load_chunk(0);
     for (int cc = 0; cc < cols; cc += CM_CK) {
-        uint4 wraw[NW];
+        cm_u32x4 wraw[NW];   // (a native vector: a uint4 struct array is copied as an aggregate and stays in memory)
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int item = tid + 256 * u;
             const int row = item / 18, rem = item - row * 18;
             if (item < 16 * NOB * 18)
-                wraw[u] = *reinterpret_cast<const uint4*>(P + ((size_t)(o0 + row) * 9 + rem / 2) * cols + cc + 8 * (rem & 1));
+                wraw[u] = *reinterpret_cast<const cm_u32x4*>(P + ((size_t)(o0 + row) * 9 + rem / 2) * cols + cc + 8 * (rem & 1));
         }
         __syncthreads();   // the previous chunk's fragments are read
 #pragma unroll
@@ -140,7 +162,7 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
             const int item = tid + 256 * u;
             const int row = item / 18, rem = item - row * 18;
             if (item < 16 * NOB * 18)
-                *reinterpret_cast<uint4*>(&wsm[row * CM_WSTR + (rem / 2) * CM_CK + 8 * (rem & 1)]) = wraw[u];
+                *reinterpret_cast<cm_u32x4*>(&wsm[row * CM_WSTR + (rem / 2) * CM_CK + 8 * (rem & 1)]) = wraw[u];
         }
 #pragma unroll
         for (int u = 0; u < NIT; ++u) {
@@ -159,7 +181,7 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
             }
 #pragma unroll
             for (int pl = 0; pl < PLANES; ++pl)
-                *reinterpret_cast<uint4*>(&xs[pl][s_lds[u]]) = make_uint4(part[pl][0], part[pl][1], part[pl][2], part[pl][3]);
+                *reinterpret_cast<uint4*>(&sbuf[pl * XS + s_lds[u]]) = make_uint4(part[pl][0], part[pl][1], part[pl][2], part[pl][3]);
         }
         __syncthreads();
         if (cc + CM_CK < cols) load_chunk(cc + CM_CK);
@@ -179,7 +201,7 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
                 const int so = ((wave + dy) * (CM_TC + 2) + pb * 16 + l16 + dx) * CM_PSTR + half;
 #pragma unroll
                 for (int pl = 0; pl < PLANES; ++pl) {
-                    const cm_bf16x8 b = *reinterpret_cast<const cm_bf16x8*>(&xs[pl][so]);
+                    const cm_bf16x8 b = *reinterpret_cast<const cm_bf16x8*>(&sbuf[pl * XS + so]);
 #pragma unroll
                     for (int ob = 0; ob < NOB; ++ob)
                         acc[ob][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ob], b, acc[ob][pb], 0, 0, 0);
@@ -187,28 +209,54 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
             }
         }
     }
-    // epilogue: lane holds C[o = ob 16 + 4 g + j][pixel = pb 16 + l16] of tile row `wave`
+    // epilogue: lane holds C[o = ob 16 + 4 g + j][pixel = pb 16 + l16] of tile
+    // row `wave`; per 16-channel block it goes through the wave's staging rows
+    // E[16][CM_EST] and out as 16-byte stores, 16 lanes per channel row of the
+    // tile.  A wave's shared-memory accesses take effect in program order, so
+    // the wave-scope fences between its writes and reads order the lanes.
     const int row = r0 + wave;
-    if (row >= H) return;
+    __syncthreads();   // every wave's last fragment reads are done: the operand buffers become staging
+    float* Eb = reinterpret_cast<float*>(sbuf) + wave * 16 * CM_EST;
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob)
+    for (int ob = 0; ob < NOB; ++ob) {
+        if (ob > 0) {   // the previous block's reads come first
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int o = o0 + ob * 16 + 4 * g + j;
-            if (o >= co) continue;
-            const float bo = bias ? bias[o] : 0.0f;
-            float* dst = out + ((size_t)n * co + o) * npx + (size_t)row * W;
+            const float bo = (bias && o < co) ? bias[o] : 0.0f;
 #pragma unroll
             for (int pb = 0; pb < 4; ++pb) {
-                const int col = c0 + pb * 16 + l16;
-                if (col < W) {
-                    float v = acc[ob][pb][j] + bo;
-                    if (relu && v < 0.0f) v = 0.0f;
-                    if (round_out) v = __uint_as_float(cm_bf16_bits(v) << 16);
-                    dst[col] = v;
+                float v = acc[ob][pb][j] + bo;
+                if (relu && v < 0.0f) v = 0.0f;
+                if (round_out) v = __uint_as_float(cm_bf16_bits(v) << 16);
+                Eb[(4 * g + j) * CM_EST + pb * 16 + l16] = v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row < H) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ch = 4 * q + g, o = o0 + ob * 16 + ch, col = c0 + 4 * l16;
+                if (o >= co) continue;
+                const float4 v = *reinterpret_cast<const float4*>(&Eb[ch * CM_EST + 4 * l16]);
+                float* dst = out + ((size_t)n * co + o) * npx + (size_t)row * W + col;
+                if (col + 3 < W && (W & 3) == 0) {
+                    *reinterpret_cast<float4*>(dst) = v;
+                } else {
+                    if (col < W) dst[0] = v.x;
+                    if (col + 1 < W) dst[1] = v.y;
+                    if (col + 2 < W) dst[2] = v.z;
+                    if (col + 3 < W) dst[3] = v.w;
                 }
             }
         }
+    }
 }
 
 // Weight gradients of one 3 x 3 layer of the BF16 network on the matrix
