@@ -146,9 +146,8 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
     // the chunk's weights: rows o0 .. o0 + 16 NOB - 1, 9 taps x 16 channels
     // each, 16 bytes per item
     constexpr int NW = (16 * NOB * 9 * 2 + 255) / 256;
-    load_chunk(0);
-    for (int cc = 0; cc < cols; cc += CM_CK) {
-        cm_u32x4 wraw[NW];   // (a native vector: a uint4 struct array is copied as an aggregate and stays in memory)
+    cm_u32x4 wraw[NW];   // (a native vector: a uint4 struct array is copied as an aggregate and stays in memory)
+    auto load_weights = [&](int cc) {
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
             const int item = tid + 256 * u;
@@ -156,6 +155,10 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
             if (item < 16 * NOB * 18)
                 wraw[u] = *reinterpret_cast<const cm_u32x4*>(P + ((size_t)(o0 + row) * 9 + rem / 2) * cols + cc + 8 * (rem & 1));
         }
+    };
+    load_chunk(0);
+    load_weights(0);
+    for (int cc = 0; cc < cols; cc += CM_CK) {
         __syncthreads();   // the previous chunk's fragments are read
 #pragma unroll
         for (int u = 0; u < NW; ++u) {
@@ -184,7 +187,10 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
                 *reinterpret_cast<uint4*>(&sbuf[pl * XS + s_lds[u]]) = make_uint4(part[pl][0], part[pl][1], part[pl][2], part[pl][3]);
         }
         __syncthreads();
-        if (cc + CM_CK < cols) load_chunk(cc + CM_CK);
+        if (cc + CM_CK < cols) {   // the next chunk's input and weights, in flight during this chunk's products
+            load_chunk(cc + CM_CK);
+            load_weights(cc + CM_CK);
+        }
 #pragma unroll 1
         for (int st = 0; st < 5; ++st) {
             const int t = 2 * st + (g >> 1);                 // this lane group's tap (9: none)
