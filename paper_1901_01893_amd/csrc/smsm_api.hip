@@ -1687,7 +1687,7 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
                                Lr->cin[k], Lr->cout[k], Lr->H, Lr->W, Lr->act[k], g, Lr->wpart, Lr->wbpart);
             LAUNCH_CHECK();
             const int nout = Lr->cout[k] * Lr->cin[k] * 9 + Lr->cout[k];
-            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + CNN_THREADS - 1) / CNN_THREADS), dim3(CNN_THREADS), 0, st,
+            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + WGS_OUT - 1) / WGS_OUT), dim3(WGS_OUT, WGS_SLICES), 0, st,
                                nchunk, Lr->cin[k], Lr->cout[k], Lr->wpart, Lr->wbpart, Lr->grads + Lr->woff[k],
                                Lr->grads + Lr->boff[k], accumulate);
         } else if (Lr->cin[k] % WG_TILE == 0 && Lr->cout[k] % WG_TILE == 0) {
@@ -1697,7 +1697,7 @@ smsm_status lcnn_backward(smsm_learned* Lr, const float* gout, float* gin, int a
                                Lr->wpart, Lr->wbpart);
             LAUNCH_CHECK();
             const int nout = Lr->cout[k] * Lr->cin[k] * 9 + Lr->cout[k];
-            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + CNN_THREADS - 1) / CNN_THREADS), dim3(CNN_THREADS), 0, st,
+            hipLaunchKernelGGL(k_wgrad_sum, dim3((nout + WGS_OUT - 1) / WGS_OUT), dim3(WGS_OUT, WGS_SLICES), 0, st,
                                nchunk, Lr->cin[k], Lr->cout[k], Lr->wpart, Lr->wbpart, Lr->grads + Lr->woff[k],
                                Lr->grads + Lr->boff[k], accumulate);
         } else {

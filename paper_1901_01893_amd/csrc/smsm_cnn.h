@@ -361,21 +361,35 @@ k_wgrad_part(int ci, int co, int H, int W, const float* __restrict__ in, const f
     }
 }
 
-// gw[o][c][t] (+)= sum over chunks in order of part[chunk][o][c][t];
-// gb[o] (+)= sum of bpart[chunk][o].
-__global__ void k_wgrad_sum(int nchunk, int ci, int co, const float* __restrict__ part,
-                            const float* __restrict__ bpart, float* __restrict__ gw, float* __restrict__ gb,
-                            int accumulate) {
-    const int nw = co * ci * 9;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nw + co; k += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        if (k < nw) {
-            for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * nw + k];
-            gw[k] = accumulate ? gw[k] + s : s;
-        } else {
-            const int o = k - nw;
-            for (int ch = 0; ch < nchunk; ++ch) s += bpart[(size_t)ch * co + o];
-            gb[o] = accumulate ? gb[o] + s : s;
-        }
+// gw[o][c][t] (+)= sum over chunks of part[chunk][o][c][t];
+// gb[o] (+)= sum of bpart[chunk][o].  Block (WGS_OUT, WGS_SLICES): thread
+// (x, y) adds, in chunk order, the chunks of slice y (consecutive runs of
+// ceil(nchunk / WGS_SLICES)) for output blockIdx.x WGS_OUT + x, so that its
+// loads are in flight together; the slice sums are then added in slice
+// order.  The order is fixed, so the result is deterministic.
+#define WGS_OUT 64
+#define WGS_SLICES 16
+__global__ void __launch_bounds__(WGS_OUT * WGS_SLICES)
+k_wgrad_sum(int nchunk, int ci, int co, const float* __restrict__ part, const float* __restrict__ bpart,
+            float* __restrict__ gw, float* __restrict__ gb, int accumulate) {
+    __shared__ float red[WGS_SLICES][WGS_OUT];
+    const int nw = co * ci * 9, x = threadIdx.x, y = threadIdx.y;
+    const int k = blockIdx.x * WGS_OUT + x;
+    const int per = (nchunk + WGS_SLICES - 1) / WGS_SLICES, c0 = y * per, c1 = min(c0 + per, nchunk);
+    float s = 0.0f;
+    if (k < nw) {
+#pragma unroll 16
+        for (int ch = c0; ch < c1; ++ch) s += part[(size_t)ch * nw + k];
+    } else if (k < nw + co) {
+        for (int ch = c0; ch < c1; ++ch) s += bpart[(size_t)ch * co + (k - nw)];
+    }
+    red[y][x] = s;
+    __syncthreads();
+    if (y == 0 && k < nw + co) {
+        float t = red[0][x];
+#pragma unroll
+        for (int j = 1; j < WGS_SLICES; ++j) t += red[j][x];
+        float* dst = k < nw ? gw + k : gb + (k - nw);
+        *dst = accumulate ? *dst + t : t;
     }
 }
