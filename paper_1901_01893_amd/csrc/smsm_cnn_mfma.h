@@ -313,9 +313,24 @@ k_wgrad_mfma(int ci, int co, int H, int W, const float* __restrict__ in, const f
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = cm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;
+    // output gradients of step s of the sub-tile at row y0 (8 pixels of this
+    // lane's row o): loaded one step ahead of their products
+    auto gload = [&](int y0, int s, cm_f32x4& u0, cm_f32x4& u1) __attribute__((always_inline)) {
+        const int y = y0 + (s >> 1), xl = 32 * (s & 1) + 8 * gq;
+        if (o < co && y < H && x0 + xl < W) {
+            const cm_f32x4* gp = reinterpret_cast<const cm_f32x4*>(grow + (size_t)y * W + x0 + xl);
+            u0 = gp[0];
+            u1 = gp[1];
+        } else {
+            u0 = cm_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            u1 = u0;
+        }
+    };
     for (int sr = 0; sr < WGM_ROWS; sr += WGM_SR) {
         const int y0 = yc + sr;
         if (y0 >= H) break;                              // the same for the whole workgroup
+        cm_f32x4 gn0, gn1;
+        gload(y0, 0, gn0, gn1);                          // in flight during the staging
         __syncthreads();                                 // the previous sub-tile's fragments are read
         // items (channel, row, 8-column block), each written as three shifted copies
         for (int it = tid; it < 16 * (WGM_SR + 2) * (WGM_TC / 8); it += 256) {
@@ -332,10 +347,11 @@ k_wgrad_mfma(int ci, int co, int H, int W, const float* __restrict__ in, const f
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {                // copy d holds in[..][x + d - 1]
-                unsigned pk[4];
+                unsigned pk[4];   // the inputs are BF16 values: their upper halves, packed in pairs
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    pk[q] = cm_bf16_bits(v[2 * q + d]) | (cm_bf16_bits(v[2 * q + 1 + d]) << 16);
+                    pk[q] = __builtin_amdgcn_perm(__float_as_uint(v[2 * q + 1 + d]), __float_as_uint(v[2 * q + d]),
+                                                  0x07060302u);
                 *reinterpret_cast<uint4*>(&xs[d][c * WGM_CSTR + r * WGM_TC + 8 * b]) =
                     make_uint4(pk[0], pk[1], pk[2], pk[3]);
             }
@@ -344,29 +360,28 @@ k_wgrad_mfma(int ci, int co, int H, int W, const float* __restrict__ in, const f
 #pragma unroll 1
         for (int s = 0; s < 2 * WGM_SR; ++s) {
             const int ry = s >> 1, xl = 32 * (s & 1) + 8 * gq;   // this lane's 8 pixels: row y0 + ry, columns x0 + xl ..
-            const int y = y0 + ry;
             float gv[8];
-            if (o < co && y < H && x0 + xl < W) {
-                const float4* gp = reinterpret_cast<const float4*>(grow + (size_t)y * W + x0 + xl);
-                const float4 u0 = gp[0], u1 = gp[1];
-                gv[0] = u0.x; gv[1] = u0.y; gv[2] = u0.z; gv[3] = u0.w;
-                gv[4] = u1.x; gv[5] = u1.y; gv[6] = u1.z; gv[7] = u1.w;
-            } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) gv[q] = 0.0f;
+            for (int q = 0; q < 4; ++q) {
+                gv[q] = gn0[q];
+                gv[4 + q] = gn1[q];
             }
+            if (s + 1 < 2 * WGM_SR) gload(y0, s + 1, gn0, gn1);
 #pragma unroll
             for (int q = 0; q < 8; ++q) bsum += gv[q];
+            // g = hi + mid + lo, each part the upper half of what the previous
+            // ones left (a truncation): every subtraction is exact and the
+            // third remainder has at most 8 significant bits, so lo is exact.
             cm_bf16x8 a[3];
 #pragma unroll
             for (int pl = 0; pl < 3; ++pl) {
                 unsigned pk[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const unsigned h0 = cm_bf16_bits(gv[2 * q]), h1 = cm_bf16_bits(gv[2 * q + 1]);
-                    pk[q] = h0 | (h1 << 16);
-                    gv[2 * q] -= __uint_as_float(h0 << 16);        // exact: the remainder of a round to nearest
-                    gv[2 * q + 1] -= __uint_as_float(h1 << 16);
+                    const unsigned b0 = __float_as_uint(gv[2 * q]), b1 = __float_as_uint(gv[2 * q + 1]);
+                    pk[q] = __builtin_amdgcn_perm(b1, b0, 0x07060302u);
+                    gv[2 * q] -= __uint_as_float(b0 & 0xFFFF0000u);
+                    gv[2 * q + 1] -= __uint_as_float(b1 & 0xFFFF0000u);
                 }
                 a[pl] = __builtin_bit_cast(cm_bf16x8, make_uint4(pk[0], pk[1], pk[2], pk[3]));
             }
