@@ -83,7 +83,9 @@ __global__ void k_yrows_fwd(Geo g, const double2* __restrict__ ytil, double2* __
 enum { COL_NORMAL = 0, COL_FWD = 1, COL_ADJ = 2, COL_REG = 3 };
 
 // Shared-memory layout (offsets in double2 units) of k_col; the host sizes
-// the launch with the same function.
+// the launch with the same function.  The coil loop's fold and coil-map
+// buffers (F, SC) and the regulariser's taps (A, filled after the loop's
+// last barrier) share one region.
 struct ColLds {
     int U, ACC, F, SC, TW2, TWM, A, red, total;
 };
@@ -91,12 +93,13 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
     ColLds c;
     c.U = 0;
     c.ACC = c.U + g.B * g.n2;
-    c.F = c.ACC + g.B * g.n2;
-    c.SC = c.F + g.B * g.M;
-    c.TW2 = c.SC + g.L * g.n2;
+    c.TW2 = c.ACC + g.B * g.n2;
     c.TWM = c.TW2 + g.n2;
-    c.A = c.TWM + g.M;
-    c.red = c.A + g.L * g.Ns * g.Ns * g.nc;
+    c.F = c.TWM + g.M;
+    c.SC = c.F + g.B * g.M;
+    c.A = c.F;
+    const int loop = g.B * g.M + g.L * g.n2, taps = g.L * g.Ns * g.Ns * g.nc;
+    c.red = c.F + (loop > taps ? loop : taps);
     c.total = c.red + 16;
     return c;
 }

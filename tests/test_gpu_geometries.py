@@ -76,6 +76,10 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 121),
     "n192_L3_Ns4_r7": (si.Geometry(n=192, n_slices=3, n_shots=4, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 122),
+    # eight shots at 256 ky: the generic column pass at its largest shared-memory
+    # footprint (the coil loop's buffers and the regulariser's taps share one region)
+    "n256_L2_Ns8_r5": (si.Geometry(n=256, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 123),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
