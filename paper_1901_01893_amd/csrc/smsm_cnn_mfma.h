@@ -44,6 +44,13 @@ SMSM_DEV unsigned cm_bf16_bits(float v) {
     const unsigned b = __float_as_uint(v);
     return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
 }
+// The same for two values at once, packed (x in the low half): the gfx950
+// packed conversion, one instruction (equal to cm_bf16_bits for finite values).
+typedef float cm_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 cm_bf16x2 __attribute__((ext_vector_type(2)));
+SMSM_DEV unsigned cm_bf16x2_bits(cm_f32x2 v) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, cm_bf16x2));
+}
 
 // Packed BF16 weights of one layer (w [co][ci][3][3], FP32) for
 //   fwd (bwd = 0): P[o][t][c] = w[o][c][t],      o < rows = co rounded up to 16, c < cols = ci rounded up to 16;
@@ -173,13 +180,15 @@ k_conv3x3_mfma(int ci, int co, int cols, int H, int W, const float* __restrict__
             unsigned part[PLANES][4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                float a0 = raw[u][2 * q], a1 = raw[u][2 * q + 1];
+                cm_f32x2 a = {raw[u][2 * q], raw[u][2 * q + 1]};
 #pragma unroll
                 for (int pl = 0; pl < PLANES; ++pl) {
-                    const unsigned h0 = cm_bf16_bits(a0), h1 = cm_bf16_bits(a1);
-                    part[pl][q] = h0 | (h1 << 16);
-                    a0 -= __uint_as_float(h0 << 16);   // exact: the remainder of a round to nearest
-                    a1 -= __uint_as_float(h1 << 16);
+                    const unsigned h = cm_bf16x2_bits(a);   // both rounded to nearest (even), packed
+                    part[pl][q] = h;
+                    if (pl + 1 < PLANES) {                 // exact: the remainders of a round to nearest
+                        a.x -= __uint_as_float(h << 16);
+                        a.y -= __uint_as_float(h & 0xFFFF0000u);
+                    }
                 }
             }
 #pragma unroll
