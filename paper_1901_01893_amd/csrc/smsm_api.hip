@@ -1584,7 +1584,8 @@ struct smsm_learned {
     float *ga = nullptr, *gbuf = nullptr, *gio = nullptr;   // hidden-gradient ping-pong, nc-channel gradient
     double2 *b = nullptr, *x = nullptr, *z = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr;
     double2 *g = nullptr, *wv = nullptr, *ax = nullptr, *xs = nullptr;
-    double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] rr, [2] alpha, [3] beta, [8] loss num, [9] den
+    double *part = nullptr, *scal = nullptr;   // scal: [0] s, [1] and [4] rr, [2] alpha, [3] beta, [8] loss num, [9] den
+    double* part2 = nullptr;                    // second partials buffer of the fused CG steps
     float *wpart = nullptr, *wbpart = nullptr;  // weight-gradient chunk partials (k_wgrad_part)
     // 0: FP32 weights on the vector ALU; BF16 weights on the matrix cores with
     // 1: exact products (FP32 activations in three BF16 parts), 2: the BF16
@@ -1752,13 +1753,21 @@ smsm_status ldc_cg(smsm_learned* Lr, const double2* rhs, double2* x, hipStream_t
     hipLaunchKernelGGL(k_copy_c128, vec_grid(), dim3(kThreads), 0, st, lvec(Lr), Lr->r, Lr->p);
     LAUNCH_CHECK();
     if ((s = ldot(Lr, Lr->r, Lr->r, st)) || (s = lscalar(Lr, 0, nullptr, 0.0, sc + 1, st))) return s;
+    // each step: q = (A^H A + mu I) p with Re <p, q>; x += alpha p, r -= alpha q
+    // with |r|^2; p = r + beta p.  |r|^2 alternates between scal[1] and scal[4].
+    const long n = lvec(Lr);
     for (int j = 0; j < Lr->n_cg; ++j) {
-        if ((s = lnormal(Lr, Lr->p, Lr->q, st))) return s;
-        if ((s = ldot(Lr, Lr->p, Lr->q, st)) || (s = lscalar(Lr, 1, sc + 1, 0.0, sc + 2, st))) return s;
-        if ((s = laxpy(Lr, x, Lr->p, sc + 2, 1.0, x, st))) return s;              // x += alpha p
-        if ((s = laxpy(Lr, Lr->r, Lr->q, sc + 2, -1.0, Lr->r, st))) return s;     // r -= alpha q
-        if ((s = ldot(Lr, Lr->r, Lr->r, st)) || (s = lscalar(Lr, 2, sc + 1, 0.0, sc + 3, st))) return s;
-        if ((s = laxpy(Lr, Lr->r, Lr->p, sc + 3, 1.0, Lr->p, st))) return s;      // p = r + beta p
+        double* rr_cur = (j & 1) ? sc + 4 : sc + 1;
+        double* rr_next = (j & 1) ? sc + 1 : sc + 4;
+        if ((s = chain_normal(Lr->P, Lr->p, Lr->q, COL_NORMAL, false, st))) return s;
+        hipLaunchKernelGGL(k_dc_qdot, vec_grid(), dim3(kThreads), 0, st, n, Lr->p, Lr->q, Lr->mu, Lr->part);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_dc_xr, vec_grid(), dim3(kThreads), 0, st, n, x, Lr->r, Lr->p, Lr->q, Lr->part,
+                           kVecBlocks, rr_cur, Lr->part2);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_dc_p, vec_grid(), dim3(kThreads), 0, st, n, Lr->r, Lr->p, Lr->part2, kVecBlocks, rr_cur,
+                           rr_next);
+        LAUNCH_CHECK();
     }
     return SMSM_OK;
 }
@@ -1887,6 +1896,7 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     for (int k = 0; k < 9; ++k) ov[k] = cv.take<double2>(n);
     const size_t oax = cv.take<double2>(ny), oxs = cv.take<double2>(n * n_unroll);
     const size_t opart = cv.take<double>(kVecBlocks), oscal = cv.take<double>(16);
+    const size_t opart2 = cv.take<double>(kVecBlocks);
     size_t maxcc = 0, maxco = 0;
     for (int k = 0; k < smsm_learned::kDepth; ++k) {
         maxcc = std::max(maxcc, (size_t)Lr->cin[k] * Lr->cout[k]);
@@ -1921,6 +1931,7 @@ smsm_status smsm_learned_create(smsm_plan* P, int width, int n_unroll, int n_cg,
     Lr->ax = (double2*)(base + oax);
     Lr->xs = (double2*)(base + oxs);
     Lr->part = (double*)(base + opart);
+    Lr->part2 = (double*)(base + opart2);
     Lr->scal = (double*)(base + oscal);
     Lr->wpart = (float*)(base + owp);
     Lr->wbpart = (float*)(base + owb);

@@ -219,6 +219,55 @@ __global__ void k_dc_scalar(int mode, const double* __restrict__ pa, int np, dou
     }
 }
 
+// Fused steps of the data-consistency CG (the same arithmetic, in the same
+// order, as k_dc_axpy / k_dc_dot / k_dc_scalar taken one after another, on
+// the same grid, so the results are the same to the bit):
+// q += mu p (the regularised normal operator) and per-block partials of
+// Re <p, q>.
+__global__ void k_dc_qdot(long n, const double2* __restrict__ p, double2* __restrict__ q, double mu,
+                          double* __restrict__ part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const double2 u = p[k], v = cadd(q[k], cscale(u, mu));
+        q[k] = v;
+        s += u.x * v.x + u.y * v.y;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+// alpha = rr / sum(part_pq) (0 unless both are positive; every block forms it
+// from the partials), x += alpha p, r -= alpha q, per-block partials of |r|^2.
+__global__ void k_dc_xr(long n, double2* __restrict__ x, double2* __restrict__ r, const double2* __restrict__ p,
+                        const double2* __restrict__ q, const double* __restrict__ part_pq, int np,
+                        const double* __restrict__ rr, double* __restrict__ part_rr) {
+    __shared__ double red[16];
+    const double pq = sum_partials(part_pq, np, red), r0 = *rr;
+    const double alpha = (r0 > 0.0 && pq > 0.0) ? r0 / pq : 0.0;
+    double s = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        x[k] = cadd(x[k], cscale(p[k], alpha * 1.0));
+        const double2 v = cadd(r[k], cscale(q[k], alpha * -1.0));
+        r[k] = v;
+        s += v.x * v.x + v.y * v.y;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+// rr_new = sum(part_rr), beta = rr_new / *rr_cur (0 when *rr_cur is 0),
+// p = r + beta p; block 0 stores rr_new in *rr_next (a different slot from
+// rr_cur, which the other blocks still read).
+__global__ void k_dc_p(long n, const double2* __restrict__ r, double2* __restrict__ p,
+                       const double* __restrict__ part_rr, int np, const double* __restrict__ rr_cur,
+                       double* __restrict__ rr_next) {
+    __shared__ double red[16];
+    const double s = sum_partials(part_rr, np, red), r0 = *rr_cur;
+    const double beta = r0 > 0.0 ? s / r0 : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *rr_next = s;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+        p[k] = cadd(r[k], cscale(p[k], beta * 1.0));
+}
+
 // g = 2 g / *den (the loss gradient 2 (x - xt) / ||xt||^2 from g = x - xt).
 __global__ void k_dc_grad0(long n, double2* __restrict__ g, const double* __restrict__ den) {
     const double f = 2.0 / *den;
