@@ -684,6 +684,16 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     while (P->TR & (P->TR - 1)) P->TR &= P->TR - 1;   // a power of two
     P->TRy = std::min(g.M & -g.M, P->TR);              // divides the M folded lines
     P->lds_rows = (size_t)P->TR * (n1 + 1) * sizeof(double2) + 16 * sizeof(double);
+    int max_lds = 0;
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
+    if (max_lds <= 0) max_lds = 65536;
+    // coils per pass of the generic column pass: the most (4, 2, 1) its shared
+    // memory holds, with the transform of a pass (cb B sequences of M) within
+    // the outputs the mixed-length transform keeps in registers
+    g.cb = 4;
+    while (g.cb > 1 && ((size_t)col_lds(g).total * sizeof(double2) > (size_t)max_lds ||
+                        g.cb * g.B * g.M > FFT_MIX_PER_THREAD * kColThreads))
+        g.cb >>= 1;
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);
     P->lds_gram_lines = (size_t)(1 + g.nc) * std::max(n1, n2) * sizeof(double2);
@@ -705,9 +715,6 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         return SMSM_E_UNSUPPORTED;
     }
     P->lds_colfast = (size_t)colfast_lds_total(g) * sizeof(double2);
-    int max_lds = 0;
-    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
-    if (max_lds <= 0) max_lds = 65536;
     if (P->lds_col > (size_t)max_lds || P->lds_gram > (size_t)max_lds || P->lds_gram_lines > (size_t)max_lds ||
         P->lds_band + 16 * sizeof(double) > (size_t)max_lds) {
         delete P;

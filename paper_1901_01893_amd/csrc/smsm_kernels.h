@@ -25,6 +25,7 @@
 
 struct Geo {
     int n1, n2, L, Ns, Nc, r, K, nc, e, M, logn1, logn2, logM, B, nband, npairs;
+    int cb;   // coils per pass of the generic column pass (1, 2 or 4: what its shared memory holds)
 };
 
 // ---------------------------------------------------------------------------
@@ -84,8 +85,8 @@ enum { COL_NORMAL = 0, COL_FWD = 1, COL_ADJ = 2, COL_REG = 3 };
 
 // Shared-memory layout (offsets in double2 units) of k_col; the host sizes
 // the launch with the same function.  The coil loop's fold and coil-map
-// buffers (F, SC) and the regulariser's taps (A, filled after the loop's
-// last barrier) share one region.
+// buffers (F [cb][B][M], SC [cb][L][n2]) and the regulariser's taps (A,
+// filled after the loop's last barrier) share one region.
 struct ColLds {
     int U, ACC, F, SC, TW2, TWM, A, red, total;
 };
@@ -96,9 +97,9 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
     c.TW2 = c.ACC + g.B * g.n2;
     c.TWM = c.TW2 + g.n2;
     c.F = c.TWM + g.M;
-    c.SC = c.F + g.B * g.M;
+    c.SC = c.F + g.cb * g.B * g.M;
     c.A = c.F;
-    const int loop = g.B * g.M + g.L * g.n2, taps = g.L * g.Ns * g.Ns * g.nc;
+    const int loop = g.cb * (g.B * g.M + g.L * g.n2), taps = g.L * g.Ns * g.Ns * g.nc;
     c.red = c.F + (loop > taps ? loop : taps);
     c.total = c.red + 16;
     return c;
@@ -154,55 +155,66 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     __syncthreads();
 
     if (MODE != COL_REG) {
-        for (int c = 0; c < Nc; ++c) {
-            for (int idx = tid; idx < L * n2; idx += nt) {
-                const int l = idx / n2, n = idx - l * n2;
-                SC[idx] = ST[(((size_t)l * Nc + c) * n1 + x1) * n2 + n];
+        // cb coils per pass (the barriers of a pass cover them all); their
+        // corrections reach ACC in coil order, as one coil per pass would
+        const int cb = g.cb;
+        for (int c0 = 0; c0 < Nc; c0 += cb) {
+            const int ncb = min(cb, Nc - c0);
+            for (int idx = tid; idx < ncb * L * n2; idx += nt) {
+                const int cl = idx / n2, n = idx - cl * n2, cc = cl / L, l = cl - cc * L;
+                SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
             }
             if (MODE == COL_ADJ) {
                 __syncthreads();
-                // F[(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
-                for (int idx = tid; idx < B * M; idx += nt) {
-                    const int b = idx / M, m = idx - b * M, l = b / Ns, i = b - l * Ns;
-                    const double2 yv = ytil[(((size_t)i * Nc + c) * n1 + x1) * M + m];
+                // F[c][(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
+                for (int idx = tid; idx < ncb * B * M; idx += nt) {
+                    const int cb_ = idx / M, m = idx - cb_ * M, cc = cb_ / B, b = cb_ - cc * B, l = b / Ns,
+                              i = b - l * Ns;
+                    const double2 yv = ytil[(((size_t)i * Nc + c0 + cc) * n1 + x1) * M + m];
                     F[idx] = cscale(cmulc(yv, theta[l * n2 + i + Ns * m]), sgn_pow(Ns * m));
                 }
             } else {
                 __syncthreads();
-                // fold: F[(l,i)][m] = sum_t S_l[m + M t] * (tau_i u_{l,i})[m + M t]
-                for (int idx = tid; idx < B * M; idx += nt) {
-                    const int b = idx / M, m = idx - b * M, l = b / Ns;
+                // fold: F[c][(l,i)][m] = sum_t S_{l,c}[m + M t] * (tau_i u_{l,i})[m + M t]
+                for (int idx = tid; idx < ncb * B * M; idx += nt) {
+                    const int cb_ = idx / M, m = idx - cb_ * M, cc = cb_ / B, b = cb_ - cc * B, l = b / Ns;
+                    const double2* scl = SC + (cc * L + l) * n2;
                     double2 f = cmk(0.0, 0.0);
                     for (int t = 0; t < Ns; ++t) {
                         const int n = m + M * t;
-                        f = cfma(SC[l * n2 + n], U[b * n2 + n], f);
+                        f = cfma(scl[n], U[b * n2 + n], f);
                     }
                     F[idx] = f;
                 }
-                fft_batch_lds(F, M, g.logM, B, M, TWM, false);
+                fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, false);
                 if (MODE == COL_FWD) {
-                    for (int idx = tid; idx < Ns * M; idx += nt) {
-                        const int i = idx / M, m = idx - i * M, j = i + Ns * m;
+                    for (int idx = tid; idx < ncb * Ns * M; idx += nt) {
+                        const int cim = idx / M, m = idx - cim * M, cc = cim / Ns, i = cim - cc * Ns, j = i + Ns * m;
+                        const double2* fc = F + cc * B * M;
                         double2 z = cmk(0.0, 0.0);
-                        for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], F[(l * Ns + i) * M + m], z);
-                        ytil[(((size_t)i * Nc + c) * n1 + x1) * M + m] = cscale(z, isq2 * sgn_pow(i + Ns * m));
+                        for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], fc[(l * Ns + i) * M + m], z);
+                        ytil[(((size_t)i * Nc + c0 + cc) * n1 + x1) * M + m] = cscale(z, isq2 * sgn_pow(i + Ns * m));
                     }
                     __syncthreads();
                     continue;
                 }
                 // slice sum with CAIPI phase, then back to every slice
-                for (int idx = tid; idx < Ns * M; idx += nt) {
-                    const int i = idx / M, m = idx - i * M, j = i + Ns * m;
+                for (int idx = tid; idx < ncb * Ns * M; idx += nt) {
+                    const int cim = idx / M, m = idx - cim * M, cc = cim / Ns, i = cim - cc * Ns, j = i + Ns * m;
+                    double2* fc = F + cc * B * M;
                     double2 z = cmk(0.0, 0.0);
-                    for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], F[(l * Ns + i) * M + m], z);
-                    for (int l = 0; l < L; ++l) F[(l * Ns + i) * M + m] = cmulc(z, theta[l * n2 + j]);
+                    for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], fc[(l * Ns + i) * M + m], z);
+                    for (int l = 0; l < L; ++l) fc[(l * Ns + i) * M + m] = cmulc(z, theta[l * n2 + j]);
                 }
             }
-            fft_batch_lds(F, M, g.logM, B, M, TWM, true);
-            // unfold and accumulate conj(S) * g[n mod M]
+            fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, true);
+            // unfold and accumulate conj(S) * g[n mod M], coil by coil
             for (int idx = tid; idx < B * n2; idx += nt) {
-                const int b = idx / n2, n = idx - b * n2, l = b / Ns;
-                ACC[idx] = cadd(ACC[idx], cconjmul(SC[l * n2 + n], F[b * M + imod(n, M)]));
+                const int b = idx / n2, n = idx - b * n2, l = b / Ns, nm = imod(n, M);
+                double2 acc = ACC[idx];
+                for (int cc = 0; cc < ncb; ++cc)
+                    acc = cadd(acc, cconjmul(SC[(cc * L + l) * n2 + n], F[(cc * B + b) * M + nm]));
+                ACC[idx] = acc;
             }
             __syncthreads();
         }
