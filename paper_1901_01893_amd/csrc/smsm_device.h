@@ -182,6 +182,16 @@ SMSM_DEV int imod(int v, int n) {
 // formed in registers (at most FFT_MIX_PER_THREAD outputs per thread) and
 // written back.  All threads of the block must call it; it starts and ends
 // with a barrier.
+// Exact division of 0 <= x by a runtime divisor 1 <= d with x d < 2^32 (here
+// both stay below 2^16): q = floor(x m / 2^32) with m = ceil(2^32 / d), whose
+// excess over 2^32 / d is below 1, so x m / 2^32 exceeds x / d by less than
+// 1 / d and the floor is exact.  One high multiply per division.
+struct FastDiv {
+    unsigned d, m;
+    SMSM_DEV explicit FastDiv(int dd) : d((unsigned)dd), m(dd > 1 ? 0xFFFFFFFFu / (unsigned)dd + 1u : 0u) {}
+    SMSM_DEV int div(int x) const { return d > 1 ? (int)__umulhi((unsigned)x, m) : x; }
+};
+
 SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
                             const double2* __restrict__ tw, bool inverse) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -189,8 +199,9 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
     const int q = n >> logn;
     if (q > 1) {
         const int p = 1 << logn, hp = p >> 1;
+        const FastDiv fn(n), fq(q), fqh(q * hp);   // nb n stays below 2^16 (the register bound above)
         for (int idx = tid; idx < nb * n; idx += nt) {
-            const int b = idx / n, jj = idx - b * n, m = jj / q, r = jj - m * q;
+            const int b = fn.div(idx), jj = idx - b * n, m = fq.div(jj), r = jj - m * q;
             const int rm = logn ? (int)(__brev((unsigned)m) >> (32 - logn)) : 0;
             if (m < rm) {
                 double2* s = buf + b * stride;
@@ -203,7 +214,7 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
         for (int st = 0; st < logn; ++st) {
             const int half = 1 << st;
             for (int idx = tid; idx < nb * q * hp; idx += nt) {
-                const int b = idx / (q * hp), rem = idx - b * q * hp, r = rem / hp, k = rem - r * hp;
+                const int b = fqh.div(idx), rem = idx - b * q * hp, r = rem >> (logn - 1), k = rem & (hp - 1);
                 const int pos = k & (half - 1);
                 const int i0 = ((k >> st) << (st + 1)) + pos, i1 = i0 + half;
                 double2 w = tw[(pos << (logn - 1 - st)) * q];   // w_p^(.) = w_n^(q .)
@@ -221,7 +232,7 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
         for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
             const int idx = tid + u * nt;
             if (idx < nb * n) {
-                const int b = idx / n, k = idx - b * n, km = k & (p - 1);
+                const int b = fn.div(idx), k = idx - b * n, km = k & (p - 1);
                 const double2* base = buf + b * stride + q * km;
                 double2 acc = base[0];
                 int ph = 0;                                   // r k mod n
@@ -240,7 +251,7 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
         for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
             const int idx = tid + u * nt;
             if (idx < nb * n) {
-                const int b = idx / n, k = idx - b * n;
+                const int b = fn.div(idx), k = idx - b * n;
                 buf[b * stride + k] = out[u];
             }
         }
@@ -263,7 +274,7 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
     for (int s = 0; s < logn; ++s) {
         const int half = 1 << s;
         for (int idx = tid; idx < nb * hn; idx += nt) {
-            const int b = idx / hn, k = idx - b * hn;
+            const int b = idx >> (logn - 1), k = idx & (hn - 1);
             const int pos = k & (half - 1);
             const int i0 = ((k >> s) << (s + 1)) + pos;
             const int i1 = i0 + half;

@@ -134,6 +134,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     double2* TWM = sm + lay.TWM;
     double2* A = sm + lay.A;
     const double isq2 = 1.0 / sqrt((double)n2);
+    const FastDiv dn2(n2), dM(M), dB(B), dNs(Ns), dL(L);   // index arithmetic (operands below 2^16)
 
     for (int k = tid; k < n2; k += nt) TW2[k] = tw2[k];
     for (int k = tid; k < M; k += nt) TWM[k] = twM[k];
@@ -141,12 +142,12 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     if (MODE != COL_ADJ) {
         // image column u = centred inverse DFT along ky; stored as tau_i * u
         for (int idx = tid; idx < B * n2; idx += nt) {
-            const int b = idx / n2, j = idx - b * n2;
+            const int b = dn2.div(idx), j = idx - b * n2;
             U[idx] = cscale(h1[((size_t)b * n1 + x1) * n2 + j], sgn_pow(j));
         }
         fft_batch_lds(U, n2, g.logn2, B, n2, TW2, true);
         for (int idx = tid; idx < B * n2; idx += nt) {
-            const int b = idx / n2, n = idx - b * n2, i = b % Ns;
+            const int b = dn2.div(idx), n = idx - b * n2, i = b - dNs.div(b) * Ns;
             U[idx] = cmul(tau[i * n2 + n], cscale(U[idx], isq2 * sgn_pow(n)));
         }
     }
@@ -161,14 +162,14 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
         for (int c0 = 0; c0 < Nc; c0 += cb) {
             const int ncb = min(cb, Nc - c0);
             for (int idx = tid; idx < ncb * L * n2; idx += nt) {
-                const int cl = idx / n2, n = idx - cl * n2, cc = cl / L, l = cl - cc * L;
+                const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
                 SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
             }
             if (MODE == COL_ADJ) {
                 __syncthreads();
                 // F[c][(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
                 for (int idx = tid; idx < ncb * B * M; idx += nt) {
-                    const int cb_ = idx / M, m = idx - cb_ * M, cc = cb_ / B, b = cb_ - cc * B, l = b / Ns,
+                    const int cb_ = dM.div(idx), m = idx - cb_ * M, cc = dB.div(cb_), b = cb_ - cc * B, l = dNs.div(b),
                               i = b - l * Ns;
                     const double2 yv = ytil[(((size_t)i * Nc + c0 + cc) * n1 + x1) * M + m];
                     F[idx] = cscale(cmulc(yv, theta[l * n2 + i + Ns * m]), sgn_pow(Ns * m));
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                 __syncthreads();
                 // fold: F[c][(l,i)][m] = sum_t S_{l,c}[m + M t] * (tau_i u_{l,i})[m + M t]
                 for (int idx = tid; idx < ncb * B * M; idx += nt) {
-                    const int cb_ = idx / M, m = idx - cb_ * M, cc = cb_ / B, b = cb_ - cc * B, l = b / Ns;
+                    const int cb_ = dM.div(idx), m = idx - cb_ * M, cc = dB.div(cb_), b = cb_ - cc * B, l = dNs.div(b);
                     const double2* scl = SC + (cc * L + l) * n2;
                     double2 f = cmk(0.0, 0.0);
                     for (int t = 0; t < Ns; ++t) {
@@ -189,7 +190,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                 fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, false);
                 if (MODE == COL_FWD) {
                     for (int idx = tid; idx < ncb * Ns * M; idx += nt) {
-                        const int cim = idx / M, m = idx - cim * M, cc = cim / Ns, i = cim - cc * Ns, j = i + Ns * m;
+                        const int cim = dM.div(idx), m = idx - cim * M, cc = dNs.div(cim), i = cim - cc * Ns, j = i + Ns * m;
                         const double2* fc = F + cc * B * M;
                         double2 z = cmk(0.0, 0.0);
                         for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], fc[(l * Ns + i) * M + m], z);
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                 }
                 // slice sum with CAIPI phase, then back to every slice
                 for (int idx = tid; idx < ncb * Ns * M; idx += nt) {
-                    const int cim = idx / M, m = idx - cim * M, cc = cim / Ns, i = cim - cc * Ns, j = i + Ns * m;
+                    const int cim = dM.div(idx), m = idx - cim * M, cc = dNs.div(cim), i = cim - cc * Ns, j = i + Ns * m;
                     double2* fc = F + cc * B * M;
                     double2 z = cmk(0.0, 0.0);
                     for (int l = 0; l < L; ++l) z = cfma(theta[l * n2 + j], fc[(l * Ns + i) * M + m], z);
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
             fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, true);
             // unfold and accumulate conj(S) * g[n mod M], coil by coil
             for (int idx = tid; idx < B * n2; idx += nt) {
-                const int b = idx / n2, n = idx - b * n2, l = b / Ns, nm = imod(n, M);
+                const int b = dn2.div(idx), n = idx - b * n2, l = dNs.div(b), nm = n - dM.div(n) * M;
                 double2 acc = ACC[idx];
                 for (int cc = 0; cc < ncb; ++cc)
                     acc = cadd(acc, cconjmul(SC[(cc * L + l) * n2 + n], F[(cc * B + b) * M + nm]));
@@ -221,7 +222,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
         if (MODE == COL_FWD) return;
         // normal: conj(tau_i[n]) / n2 ; adjoint: (-1)^i conj(tau_i[n]) / sqrt(n2)
         for (int idx = tid; idx < B * n2; idx += nt) {
-            const int b = idx / n2, n = idx - b * n2, i = b % Ns;
+            const int b = dn2.div(idx), n = idx - b * n2, i = b - dNs.div(b) * Ns;
             const double s = (MODE == COL_ADJ) ? isq2 * sgn_pow(i) : 1.0 / (double)n2;
             ACC[idx] = cscale(cmulc(ACC[idx], tau[i * n2 + n]), s);
         }
@@ -230,26 +231,37 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     if (MODE != COL_ADJ && use_reg) {
         // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}
         const int nc = g.nc, e = g.e, nu1 = x1 - n1 / 2;
+        // the phase (d1 - e) nu1 mod n1 advances by nu1 mod n1 per tap
+        const int ph1 = imod(-e * nu1, n1), st1 = imod(nu1, n1);
         for (int idx = tid; idx < L * Ns * Ns * nc; idx += nt) {
             const double2* kr = Kc + (size_t)idx * nc;
             double2 a = cmk(0.0, 0.0);
+            int ph = ph1;
             for (int d1 = 0; d1 < nc; ++d1) {
-                const int ph = imod((d1 - e) * nu1, n1);
                 a = cfma(kr[d1], tw1[ph], a);
+                ph += st1;
+                if (ph >= n1) ph -= n1;
             }
             A[idx] = a;
         }
         __syncthreads();
         // ACC[(l,i')][n] += sum_i sum_d2 A[l][i][i'][d2] e^{-2 pi i d2 (n - n2/2)/n2} u_{l,i}[n]
         for (int idx = tid; idx < B * n2; idx += nt) {
-            const int b = idx / n2, n = idx - b * n2, l = b / Ns, ip = b - l * Ns;
+            const int b = dn2.div(idx), n = idx - b * n2, l = dNs.div(b), ip = b - l * Ns;
             const int nu2 = n - n2 / 2;
+            // the phase (d2 - e) nu2 mod n2 advances by nu2 mod n2 per tap
+            const int ph2 = imod(-e * nu2, n2), st2 = imod(nu2, n2);
             double2 s = cmk(0.0, 0.0);
             for (int i = 0; i < Ns; ++i) {
                 const double2 u = cmulc(U[(l * Ns + i) * n2 + n], tau[i * n2 + n]);
                 const double2* ar = A + ((size_t)(l * Ns + i) * Ns + ip) * nc;
                 double2 kv = cmk(0.0, 0.0);
-                for (int d2 = 0; d2 < nc; ++d2) kv = cfma(ar[d2], TW2[imod((d2 - e) * nu2, n2)], kv);
+                int ph = ph2;
+                for (int d2 = 0; d2 < nc; ++d2) {
+                    kv = cfma(ar[d2], TW2[ph], kv);
+                    ph += st2;
+                    if (ph >= n2) ph -= n2;
+                }
                 s = cfma(kv, u, s);
             }
             ACC[idx] = cadd(ACC[idx], s);
@@ -263,7 +275,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     }
     fft_batch_lds(ACC, n2, g.logn2, B, n2, TW2, false);
     for (int idx = tid; idx < B * n2; idx += nt) {
-        const int b = idx / n2, j = idx - b * n2;
+        const int b = dn2.div(idx), j = idx - b * n2;
         h2[((size_t)b * n1 + x1) * n2 + j] = cscale(ACC[idx], isq2 * sgn_pow(j));
     }
 }
