@@ -115,6 +115,26 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
 //  (F_y v)[i + Ns m] = (-1)^(i + Ns m)/sqrt(n2) * DFT_M( sum_t tau_i v [m + M t] )[m]
 // and its adjoint unfolds an M-point inverse DFT back to n2 points (the
 // (-1)^(Ns m) factors cancel in the normal operator).
+// Coil maps of one pass of k_col (coils c0 .. c0 + ncb - 1, every slice, the
+// column x1), [coil][s][n], at most KCOL_SCR per thread (the host keeps
+// cb L n2 within KCOL_SCR x threads); held as native two-double vectors so
+// that they stay in registers.
+#define KCOL_SCR 8
+typedef double kcol_v2 __attribute__((ext_vector_type(2)));
+SMSM_DEV void kcol_sc_load(kcol_v2 (&scr)[KCOL_SCR], const double2* __restrict__ ST, const Geo& g,
+                           int c0, int ncb, int x1, const FastDiv& dn2, const FastDiv& dL) {
+    const kcol_v2* src = reinterpret_cast<const kcol_v2*>(ST);
+    const int tid = threadIdx.x, nt = blockDim.x, n2 = g.n2, L = g.L;
+#pragma unroll
+    for (int u = 0; u < KCOL_SCR; ++u) {
+        const int idx = tid + u * nt;
+        if (idx < ncb * L * n2) {
+            const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
+            scr[u] = src[(((size_t)l * g.Nc + c0 + cc) * g.n1 + x1) * n2 + n];
+        }
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
                       const double2* __restrict__ ST, const double2* __restrict__ theta,
@@ -158,15 +178,29 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
     if (MODE != COL_REG) {
         // cb coils per pass (the barriers of a pass cover them all); their
         // corrections reach ACC in coil order, as one coil per pass would
+        // the next pass's coil maps are loaded into registers during this one
+        // (when a pass's maps fit them; otherwise each pass loads its own)
         const int cb = g.cb;
+        const bool pre = cb * L * n2 <= KCOL_SCR * nt;
+        kcol_v2 scr[KCOL_SCR];
+        if (pre) kcol_sc_load(scr, ST, g, 0, min(cb, Nc), x1, dn2, dL);
         for (int c0 = 0; c0 < Nc; c0 += cb) {
             const int ncb = min(cb, Nc - c0);
-            for (int idx = tid; idx < ncb * L * n2; idx += nt) {
-                const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
-                SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
+            if (pre) {
+#pragma unroll
+                for (int u = 0; u < KCOL_SCR; ++u) {
+                    const int idx = tid + u * nt;
+                    if (idx < ncb * L * n2) SC[idx] = make_double2(scr[u].x, scr[u].y);
+                }
+            } else {
+                for (int idx = tid; idx < ncb * L * n2; idx += nt) {
+                    const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
+                    SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
+                }
             }
+            __syncthreads();
+            if (pre && c0 + cb < Nc) kcol_sc_load(scr, ST, g, c0 + cb, min(cb, Nc - c0 - cb), x1, dn2, dL);
             if (MODE == COL_ADJ) {
-                __syncthreads();
                 // F[c][(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
                 for (int idx = tid; idx < ncb * B * M; idx += nt) {
                     const int cb_ = dM.div(idx), m = idx - cb_ * M, cc = dB.div(cb_), b = cb_ - cc * B, l = dNs.div(b),
@@ -175,7 +209,6 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                     F[idx] = cscale(cmulc(yv, theta[l * n2 + i + Ns * m]), sgn_pow(Ns * m));
                 }
             } else {
-                __syncthreads();
                 // fold: F[c][(l,i)][m] = sum_t S_{l,c}[m + M t] * (tau_i u_{l,i})[m + M t]
                 for (int idx = tid; idx < ncb * B * M; idx += nt) {
                     const int cb_ = dM.div(idx), m = idx - cb_ * M, cc = dB.div(cb_), b = cb_ - cc * B, l = dNs.div(b);
