@@ -251,29 +251,33 @@ struct ColFastInst {
     const void* fn;
     const void* fn_f32;   // the instance reading Khat as complex64
 };
-#define COLFAST(M_, L_) {M_, L_, 4, (const void*)&k_col_fast<M_, L_, 4, 2>, (const void*)&k_col_fast<M_, L_, 4, 2, true>}
-const ColFastInst kColFast[] = {COLFAST(16, 2), COLFAST(16, 3), COLFAST(32, 2),
-                                COLFAST(32, 3), COLFAST(64, 2), COLFAST(64, 3)};
+// Instances: 4 shots with two coil groups (8 waves), 8 shots with one (8
+// waves, two or four coils per wave); the folded length M = n2 / Ns.
+#define COLFAST(M_, L_, NS_, CG_) \
+    {M_, L_, NS_, (const void*)&k_col_fast<M_, L_, NS_, CG_>, (const void*)&k_col_fast<M_, L_, NS_, CG_, true>}
+const ColFastInst kColFast[] = {COLFAST(16, 2, 4, 2), COLFAST(16, 3, 4, 2), COLFAST(32, 2, 4, 2),
+                                COLFAST(32, 3, 4, 2), COLFAST(64, 2, 4, 2), COLFAST(64, 3, 4, 2),
+                                COLFAST(32, 2, 8, 1), COLFAST(16, 2, 8, 1)};   // (three slices at 8 shots spill)
 #undef COLFAST
 
-template <int M_, int L_, bool KF32>
+template <int M_, int L_, int NS_, int CG_, bool KF32>
 void launch_colfast_k(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
     if (P->kt_n < P->kt_cap && P->kt_seen++ % P->kt_stride == 0) {
         const int n = P->kt_n++;
-        hipExtLaunchKernelGGL((k_col_fast<M_, L_, 4, 2, KF32>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st,
-                              P->kt_ev[2 * n], P->kt_ev[2 * n + 1], 0, g, in, out, P->ST, P->theta, P->tw2,
+        hipExtLaunchKernelGGL((k_col_fast<M_, L_, NS_, CG_, KF32>), dim3(g.n1), dim3(64 * NS_ * CG_), P->lds_colfast,
+                              st, P->kt_ev[2 * n], P->kt_ev[2 * n + 1], 0, g, in, out, P->ST, P->theta, P->tw2,
                               P->twM, P->Khat, use_reg, pc, P->prow);
     } else {
-        hipLaunchKernelGGL((k_col_fast<M_, L_, 4, 2, KF32>), dim3(g.n1), dim3(64 * 4 * 2), P->lds_colfast, st, g, in,
-                           out, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
+        hipLaunchKernelGGL((k_col_fast<M_, L_, NS_, CG_, KF32>), dim3(g.n1), dim3(64 * NS_ * CG_), P->lds_colfast, st,
+                           g, in, out, P->ST, P->theta, P->tw2, P->twM, P->Khat, use_reg, pc, P->prow);
     }
 }
-template <int M_, int L_>
+template <int M_, int L_, int NS_ = 4, int CG_ = 2>
 void launch_colfast(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     // the complex64 table only matters where the regulariser term is applied
-    if (use_reg && P->khat_f32) launch_colfast_k<M_, L_, true>(P, in, out, use_reg, pc, st);
-    else launch_colfast_k<M_, L_, false>(P, in, out, use_reg, pc, st);
+    if (use_reg && P->khat_f32) launch_colfast_k<M_, L_, NS_, CG_, true>(P, in, out, use_reg, pc, st);
+    else launch_colfast_k<M_, L_, NS_, CG_, false>(P, in, out, use_reg, pc, st);
 }
 
 // Column pass (hybrid in -> hybrid out).  For MODE == COL_NORMAL, `pc` may
@@ -289,7 +293,9 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
             case 2: launch_colfast<32, 2>(P, in, out, use_reg, pc, st); break;
             case 3: launch_colfast<32, 3>(P, in, out, use_reg, pc, st); break;
             case 4: launch_colfast<64, 2>(P, in, out, use_reg, pc, st); break;
-            default: launch_colfast<64, 3>(P, in, out, use_reg, pc, st); break;
+            case 5: launch_colfast<64, 3>(P, in, out, use_reg, pc, st); break;
+            case 6: launch_colfast<32, 2, 8, 1>(P, in, out, use_reg, pc, st); break;
+            default: launch_colfast<16, 2, 8, 1>(P, in, out, use_reg, pc, st); break;
         }
         LAUNCH_CHECK();
         return SMSM_OK;

@@ -42,7 +42,7 @@ GEOMS = {
                                   phase_order=2, snr=30.0), 108),
     # the batched bench's instances: band kernel <13, 2> with the generic column
     # pass at 256 ky and 2 shots, and at 128 ky; band kernel <9, 8> with the
-    # generic column pass at 128 ky and 8 shots (few coils, short schedules)
+    # fast column pass <16, 2, 8 shots, 1 coil group> at 128 ky (few coils, short schedules)
     "n256_L2_Ns2_r7": (si.Geometry(n=256, n_slices=2, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 109),
     "n128_L2_Ns2_r7": (si.Geometry(n=128, n_slices=2, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
@@ -76,8 +76,10 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 121),
     "n192_L3_Ns4_r7": (si.Geometry(n=192, n_slices=3, n_shots=4, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 122),
-    # eight shots at 256 ky: the generic column pass at its largest shared-memory
-    # footprint (the coil loop's buffers and the regulariser's taps share one region)
+    # eight shots at 256 ky: the fast column pass <32, 2, 8 shots, 1 coil group> for
+    # the normal operator, and the generic one (forward, adjoint and regulariser
+    # modes) at its largest shared-memory footprint (the coil loop's buffers and
+    # the regulariser's taps share one region)
     "n256_L2_Ns8_r5": (si.Geometry(n=256, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 123),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
