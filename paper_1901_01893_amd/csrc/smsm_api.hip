@@ -252,12 +252,15 @@ struct ColFastInst {
     const void* fn_f32;   // the instance reading Khat as complex64
 };
 // Instances: 4 shots with two coil groups (8 waves), 8 shots with one (8
-// waves, two or four coils per wave); the folded length M = n2 / Ns.
+// waves, two or four coils per wave), 2 shots with four (8 waves; at folded
+// length 128 two points per lane); the folded length M = n2 / Ns.
 #define COLFAST(M_, L_, NS_, CG_) \
     {M_, L_, NS_, (const void*)&k_col_fast<M_, L_, NS_, CG_>, (const void*)&k_col_fast<M_, L_, NS_, CG_, true>}
-const ColFastInst kColFast[] = {COLFAST(16, 2, 4, 2), COLFAST(16, 3, 4, 2), COLFAST(32, 2, 4, 2),
-                                COLFAST(32, 3, 4, 2), COLFAST(64, 2, 4, 2), COLFAST(64, 3, 4, 2),
-                                COLFAST(32, 2, 8, 1), COLFAST(16, 2, 8, 1)};   // (three slices at 8 shots spill)
+const ColFastInst kColFast[] = {COLFAST(16, 2, 4, 2),  COLFAST(16, 3, 4, 2),  COLFAST(32, 2, 4, 2),
+                                COLFAST(32, 3, 4, 2),  COLFAST(64, 2, 4, 2),  COLFAST(64, 3, 4, 2),
+                                COLFAST(32, 2, 8, 1),  COLFAST(16, 2, 8, 1),  // (three slices at 8 shots spill)
+                                COLFAST(128, 2, 2, 4), COLFAST(128, 3, 2, 4), COLFAST(64, 2, 2, 4),
+                                COLFAST(64, 3, 2, 4)};
 #undef COLFAST
 
 template <int M_, int L_, int NS_, int CG_, bool KF32>
@@ -295,7 +298,11 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
             case 4: launch_colfast<64, 2>(P, in, out, use_reg, pc, st); break;
             case 5: launch_colfast<64, 3>(P, in, out, use_reg, pc, st); break;
             case 6: launch_colfast<32, 2, 8, 1>(P, in, out, use_reg, pc, st); break;
-            default: launch_colfast<16, 2, 8, 1>(P, in, out, use_reg, pc, st); break;
+            case 7: launch_colfast<16, 2, 8, 1>(P, in, out, use_reg, pc, st); break;
+            case 8: launch_colfast<128, 2, 2, 4>(P, in, out, use_reg, pc, st); break;
+            case 9: launch_colfast<128, 3, 2, 4>(P, in, out, use_reg, pc, st); break;
+            case 10: launch_colfast<64, 2, 2, 4>(P, in, out, use_reg, pc, st); break;
+            default: launch_colfast<64, 3, 2, 4>(P, in, out, use_reg, pc, st); break;
         }
         LAUNCH_CHECK();
         return SMSM_OK;

@@ -187,18 +187,23 @@ struct ColCg {
 // Normal operator column pass; same input/output contract as k_col<COL_NORMAL>.
 // Also writes prow[b][j][x] (the input's rows within 2e of the ky edges, j as
 // in k_band_extract) for the band kernel.
-// Template: M = n2/Ns (folded length), L slices, NS shots, CG coil groups
-// (waves per shot), KF32: Khat stored complex64 (the mixed-precision form).
-// blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
+// Template: M = n2/Ns (folded length, 8 to 128), L slices, NS shots, CG coil
+// groups (waves per shot), KF32: Khat stored complex64 (the mixed-precision
+// form).  blockDim.x = 64 * NS * CG.  n2 = M * NS >= 64.
 template <int M, int L, int NS, int CG, bool KF32 = false>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
            const double2* __restrict__ theta, const double2* __restrict__ tw2, const double2* __restrict__ twM,
            const double2* __restrict__ Khat, int use_reg, ColCg pc, double2* __restrict__ prow) {
-    constexpr int T = NS;          // n2 = M * NS
     constexpr int N2 = M * NS;
-    constexpr int G = 64 / M;      // coils processed side by side in one wave
-    constexpr int LOGM = (M == 8) ? 3 : (M == 16) ? 4 : (M == 32) ? 5 : 6;
+    // M <= 64: a folded sequence spans ML = M lanes (G = 64 / M coils side by
+    // side); M = 128: each lane holds MR = 2 of its points (m and m + 64), the
+    // first transform stage is in registers and the rest spans the 64 lanes.
+    constexpr int MR = M > 64 ? M / 64 : 1, ML = M / MR;
+    static_assert(MR == 1 || MR == 2, "folded lengths up to 128");
+    constexpr int TQ = NS * MR;    // positions per lane: n = m + ML q, q < TQ
+    constexpr int G = 64 / ML;     // coils processed side by side in one wave
+    constexpr int LOGM = (ML == 8) ? 3 : (ML == 16) ? 4 : (ML == 32) ? 5 : 6;
     constexpr int B = L * NS, NW = NS * CG;
     using FC = WaveFft<N2>;
     constexpr int RC = FC::R;
@@ -208,7 +213,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int i = wave % NS, cg = wave / NS;
-    const int grp = lane / M, m = lane % M;
+    const int grp = lane / ML, m = lane % ML;
     double2* U = sm;
     double2* ACC = sm + B * N2;
     double2* TW2 = sm + 2 * B * N2;
@@ -264,12 +269,12 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
     }
     __syncthreads();
 
-    // ---- per-lane constants (tau_i u stays in shared memory: U[(s,i)][m + M t])
-    double2 acc[L][T];
+    // ---- per-lane constants (tau_i u stays in shared memory: U[(s,i)][m + ML q])
+    double2 acc[L][TQ];
 #pragma unroll
     for (int s = 0; s < L; ++s)
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[s][t] = cmk(0.0, 0.0);
+        for (int q = 0; q < TQ; ++q) acc[s][q] = cmk(0.0, 0.0);
     const double2* Ui = U + i * N2 + m;
     double2 w[8];
     double sg[8];
@@ -280,10 +285,13 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         sg[st] = upper ? 1.0 : -1.0;
         w[st] = upper ? cmk(1.0, 0.0) : twM[(m & (h - 1)) * (M / (2 * h))];
     }
-    const int kb = (int)(__brev((unsigned)m) >> (32 - LOGM));   // this lane's DFT bin after DIF
-    double2 th[L];
+    const double2 wr = MR == 2 ? twM[m] : cmk(1.0, 0.0);        // the in-register stage's twiddle w_M^m
+    const int kb = (int)(__brev((unsigned)m) >> (32 - LOGM));   // this lane's bin of the lane transform
+    double2 th[L][MR];                                          // CAIPI phase of register j's bin MR kb + j
 #pragma unroll
-    for (int s = 0; s < L; ++s) th[s] = theta[s * N2 + i + NS * kb];
+    for (int s = 0; s < L; ++s)
+#pragma unroll
+        for (int j = 0; j < MR; ++j) th[s][j] = theta[s * N2 + i + NS * (MR * kb + j)];
 
     // ---- coil loop (indices past Nc are clamped and their fold is zeroed)
     const int per_iter = CG * G;
@@ -295,52 +303,74 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
         const int c = (it * CG + cg) * G + grp;
         const double live = (c < Nc) ? 1.0 : 0.0;
         const int cbase = lane_off + min(c, Nc - 1) * coil_stride;
-        double2 sc[L][T];
+        double2 sc[L][TQ];
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < T; ++t) sc[s][t] = ST[cbase + s * slice_stride + M * t];
-        double2 f[L];
+            for (int q = 0; q < TQ; ++q) sc[s][q] = ST[cbase + s * slice_stride + ML * q];
+        // fold: f[s][j] = sum over the positions q = j (mod MR) of S u
+        double2 f[L * MR];
 #pragma unroll
-        for (int s = 0; s < L; ++s) {
-            double2 a = cmk(0.0, 0.0);
+        for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < T; ++t) a = cfma(sc[s][t], Ui[s * NS * N2 + M * t], a);
-            f[s] = cscale(a, live);
+            for (int j = 0; j < MR; ++j) {
+                double2 a = cmk(0.0, 0.0);
+#pragma unroll
+                for (int q = j; q < TQ; q += MR) a = cfma(sc[s][q], Ui[s * NS * N2 + ML * q], a);
+                f[s * MR + j] = cscale(a, live);
+            }
+        if constexpr (MR == 2) {   // first decimation-in-frequency stage, in registers
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double2 a = f[2 * s], b = f[2 * s + 1];
+                f[2 * s] = cadd(a, b);
+                f[2 * s + 1] = cmul(csub(a, b), wr);
+            }
         }
-        fft_dif<M, L>(f, w, sg);
-        double2 z = cmk(0.0, 0.0);
+        fft_dif<ML, L * MR>(f, w, sg);
 #pragma unroll
-        for (int s = 0; s < L; ++s) z = cfma(th[s], f[s], z);
+        for (int j = 0; j < MR; ++j) {
+            double2 z = cmk(0.0, 0.0);
 #pragma unroll
-        for (int s = 0; s < L; ++s) f[s] = cmulc(z, th[s]);
-        fft_dit_inv<M, L>(f, w, sg);
+            for (int s = 0; s < L; ++s) z = cfma(th[s][j], f[s * MR + j], z);
+#pragma unroll
+            for (int s = 0; s < L; ++s) f[s * MR + j] = cmulc(z, th[s][j]);
+        }
+        fft_dit_inv<ML, L * MR>(f, w, sg);
+        if constexpr (MR == 2) {   // last decimation-in-time stage of the inverse, in registers
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double2 a = f[2 * s], b = cmulc(f[2 * s + 1], wr);   // conj(w_M^m) B
+                f[2 * s] = cadd(a, b);
+                f[2 * s + 1] = csub(a, b);
+            }
+        }
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < T; ++t) acc[s][t] = cadd(acc[s][t], cconjmul(sc[s][t], f[s]));
+            for (int q = 0; q < TQ; ++q) acc[s][q] = cadd(acc[s][q], cconjmul(sc[s][q], f[s * MR + q % MR]));
     }
 
     // ---- reduce the coil-group members of the wave
 #pragma unroll
     for (int s = 0; s < L; ++s)
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            if constexpr (G >= 4) acc[s][t] = cadd(acc[s][t], lane_xor2<16>(acc[s][t]));
-            if constexpr (G >= 2) acc[s][t] = cadd(acc[s][t], lane_xor2<32>(acc[s][t]));
+        for (int q = 0; q < TQ; ++q) {
+            if constexpr (G >= 4) acc[s][q] = cadd(acc[s][q], lane_xor2<16>(acc[s][q]));
+            if constexpr (G >= 2) acc[s][q] = cadd(acc[s][q], lane_xor2<32>(acc[s][q]));
         }
     // ---- normal-operator scaling conj(tau_i[n]) / n2, then the circular Hankel
-    // term for the positions t = cg (mod CG) of this wave (output shot i):
+    // term for the positions q = cg (mod CG) of this wave (output shot i):
     //   sum_j Khat[s][j][i][x][n] u_{s,j}[n]   (stored pairs j <= i; conjugate for j > i)
     const bool writer = (grp == 0);
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int n = m + M * t;
+    for (int q = 0; q < TQ; ++q) {
+        const int n = m + ML * q;
         const double2 tai = cscale(TW2[(i * n) & (N2 - 1)], sgn_pow(n));
-        const bool mine = use_reg && writer && (t % CG == cg);
+        const bool mine = use_reg && writer && (q % CG == cg);
 #pragma unroll
         for (int s = 0; s < L; ++s) {
-            acc[s][t] = cscale(cmulc(acc[s][t], tai), 1.0 / (double)N2);
+            acc[s][q] = cscale(cmulc(acc[s][q], tai), 1.0 / (double)N2);
             if (mine) {
                 double2 rg = cmk(0.0, 0.0);
 #pragma unroll
@@ -352,7 +382,7 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
                     const double2 taj = cscale(TW2[(j * n) & (N2 - 1)], sgn_pow(n));
                     rg = cfma(kv, cmulc(U[(s * NS + j) * N2 + n], taj), rg);
                 }
-                acc[s][t] = cadd(acc[s][t], rg);
+                acc[s][q] = cadd(acc[s][q], rg);
             }
         }
     }
@@ -362,9 +392,9 @@ k_col_fast(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, cons
 #pragma unroll
             for (int s = 0; s < L; ++s)
 #pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const int o = (s * NS + i) * N2 + m + M * t;
-                    ACC[o] = (k == 0) ? acc[s][t] : cadd(ACC[o], acc[s][t]);
+                for (int q = 0; q < TQ; ++q) {
+                    const int o = (s * NS + i) * N2 + m + ML * q;
+                    ACC[o] = (k == 0) ? acc[s][q] : cadd(ACC[o], acc[s][q]);
                 }
         }
         __syncthreads();

@@ -40,8 +40,9 @@ GEOMS = {
                                    phase_order=2, snr=30.0), 107),
     "n64_L3_Ns4_r3": (si.Geometry(n=64, n_slices=3, n_shots=4, n_coils=3, filt=3, lam=1e-3, n_irls=2, n_cg=3,
                                   phase_order=2, snr=30.0), 108),
-    # the batched bench's instances: band kernel <13, 2> with the generic column
-    # pass at 256 ky and 2 shots, and at 128 ky; band kernel <9, 8> with the
+    # the batched bench's instances: band kernel <13, 2> with the fast column
+    # pass at 2 shots, folded length 128 (two points per lane) at 256 ky and 64
+    # at 128 ky; band kernel <9, 8> with the
     # fast column pass <16, 2, 8 shots, 1 coil group> at 128 ky (few coils, short schedules)
     "n256_L2_Ns2_r7": (si.Geometry(n=256, n_slices=2, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 109),
