@@ -700,14 +700,18 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     int max_lds = 0;
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->dev);
     if (max_lds <= 0) max_lds = 65536;
-    // coils per pass of the generic column pass: the most (4, 2, 1) its shared
-    // memory holds, with the transform of a pass (cb B sequences of M) within
-    // the outputs the mixed-length transform keeps in registers and the pass's
-    // coil maps within the registers that prefetch them
+    // the generic column pass: its coil loop accumulates in registers (B n2 <=
+    // KCOL_ACC x threads; a larger accumulator would not fit its shared memory
+    // either); coils per pass, the most (4, 2, 1) its shared memory holds with
+    // the transform of a pass (cb B sequences of M) within the outputs the
+    // loop's mixed-length transforms keep in registers
+    if (g.B * n2 > KCOL_ACC * kColThreads) {
+        delete P;
+        return SMSM_E_UNSUPPORTED;
+    }
     g.cb = 4;
     while (g.cb > 1 && ((size_t)col_lds(g).total * sizeof(double2) > (size_t)max_lds ||
-                        g.cb * g.B * g.M > FFT_MIX_PER_THREAD * kColThreads ||
-                        g.cb * g.L * n2 > KCOL_SCR * kColThreads))
+                        g.cb * g.B * g.M > KCOL_FOUT * kColThreads))
         g.cb >>= 1;
     P->lds_col = (size_t)col_lds(g).total * sizeof(double2);
     P->lds_gram = (size_t)(g.B * n2 + n2) * sizeof(double2);

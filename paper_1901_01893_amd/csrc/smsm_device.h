@@ -192,6 +192,7 @@ struct FastDiv {
     SMSM_DEV int div(int x) const { return d > 1 ? (int)__umulhi((unsigned)x, m) : x; }
 };
 
+template <int NOUT = FFT_MIX_PER_THREAD>   // outputs per thread of the odd-factor step (nb n <= NOUT x threads)
 SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
                             const double2* __restrict__ tw, bool inverse) {
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -227,9 +228,9 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
             }
             __syncthreads();
         }
-        double2 out[FFT_MIX_PER_THREAD];
+        double2 out[NOUT];
 #pragma unroll
-        for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
+        for (int u = 0; u < NOUT; ++u) {
             const int idx = tid + u * nt;
             if (idx < nb * n) {
                 const int b = fn.div(idx), k = idx - b * n, km = k & (p - 1);
@@ -248,7 +249,7 @@ SMSM_DEV void fft_batch_lds(double2* buf, int n, int logn, int nb, int stride,
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < FFT_MIX_PER_THREAD; ++u) {
+        for (int u = 0; u < NOUT; ++u) {
             const int idx = tid + u * nt;
             if (idx < nb * n) {
                 const int b = fn.div(idx), k = idx - b * n;

@@ -85,22 +85,25 @@ enum { COL_NORMAL = 0, COL_FWD = 1, COL_ADJ = 2, COL_REG = 3 };
 
 // Shared-memory layout (offsets in double2 units) of k_col; the host sizes
 // the launch with the same function.  The coil loop's fold and coil-map
-// buffers (F [cb][B][M], SC [cb][L][n2]) and the regulariser's taps (A,
-// filled after the loop's last barrier) share one region.
+// buffers (F [cb][B][M], SC [cb][L][n2]) share one region with what follows
+// the loop's last barrier: the accumulator ACC [B][n2] (kept in registers
+// during the loop) and the regulariser's taps A.
+#define KCOL_ACC 10  // accumulator elements per thread (B n2 <= KCOL_ACC x threads; larger does not fit anyway)
+#define KCOL_FOUT 8  // outputs per thread of the coil loop's transforms' odd-factor step (cb B M <= 8 x threads)
 struct ColLds {
     int U, ACC, F, SC, TW2, TWM, A, red, total;
 };
 __host__ __device__ inline ColLds col_lds(const Geo& g) {
     ColLds c;
+    const int bn = g.B * g.n2, loop = g.cb * (g.B * g.M + g.L * g.n2), taps = g.L * g.Ns * g.Ns * g.nc;
     c.U = 0;
-    c.ACC = c.U + g.B * g.n2;
-    c.TW2 = c.ACC + g.B * g.n2;
+    c.TW2 = c.U + bn;
     c.TWM = c.TW2 + g.n2;
     c.F = c.TWM + g.M;
     c.SC = c.F + g.cb * g.B * g.M;
-    c.A = c.F;
-    const int loop = g.cb * (g.B * g.M + g.L * g.n2), taps = g.L * g.Ns * g.Ns * g.nc;
-    c.red = c.F + (loop > taps ? loop : taps);
+    c.ACC = c.F;
+    c.A = c.F + bn;
+    c.red = c.F + (loop > bn + taps ? loop : bn + taps);
     c.total = c.red + 16;
     return c;
 }
@@ -115,26 +118,6 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
 //  (F_y v)[i + Ns m] = (-1)^(i + Ns m)/sqrt(n2) * DFT_M( sum_t tau_i v [m + M t] )[m]
 // and its adjoint unfolds an M-point inverse DFT back to n2 points (the
 // (-1)^(Ns m) factors cancel in the normal operator).
-// Coil maps of one pass of k_col (coils c0 .. c0 + ncb - 1, every slice, the
-// column x1), [coil][s][n], at most KCOL_SCR per thread (the host keeps
-// cb L n2 within KCOL_SCR x threads); held as native two-double vectors so
-// that they stay in registers.
-#define KCOL_SCR 8
-typedef double kcol_v2 __attribute__((ext_vector_type(2)));
-SMSM_DEV void kcol_sc_load(kcol_v2 (&scr)[KCOL_SCR], const double2* __restrict__ ST, const Geo& g,
-                           int c0, int ncb, int x1, const FastDiv& dn2, const FastDiv& dL) {
-    const kcol_v2* src = reinterpret_cast<const kcol_v2*>(ST);
-    const int tid = threadIdx.x, nt = blockDim.x, n2 = g.n2, L = g.L;
-#pragma unroll
-    for (int u = 0; u < KCOL_SCR; ++u) {
-        const int idx = tid + u * nt;
-        if (idx < ncb * L * n2) {
-            const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
-            scr[u] = src[(((size_t)l * g.Nc + c0 + cc) * g.n1 + x1) * n2 + n];
-        }
-    }
-}
-
 template <int MODE>
 __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2,
                       const double2* __restrict__ ST, const double2* __restrict__ theta,
@@ -171,35 +154,27 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
             U[idx] = cmul(tau[i * n2 + n], cscale(U[idx], isq2 * sgn_pow(n)));
         }
     }
-    if (MODE != COL_FWD)
+    // the coil loop's accumulator: each thread's elements tid + k nt, in
+    // registers (ACC shares the loop's buffers); the regulariser alone starts
+    // from zero in ACC
+    double2 accv[KCOL_ACC];
+#pragma unroll
+    for (int k = 0; k < KCOL_ACC; ++k) accv[k] = cmk(0.0, 0.0);
+    if (MODE == COL_REG)
         for (int idx = tid; idx < B * n2; idx += nt) ACC[idx] = cmk(0.0, 0.0);
     __syncthreads();
 
     if (MODE != COL_REG) {
         // cb coils per pass (the barriers of a pass cover them all); their
         // corrections reach ACC in coil order, as one coil per pass would
-        // the next pass's coil maps are loaded into registers during this one
-        // (when a pass's maps fit them; otherwise each pass loads its own)
         const int cb = g.cb;
-        const bool pre = cb * L * n2 <= KCOL_SCR * nt;
-        kcol_v2 scr[KCOL_SCR];
-        if (pre) kcol_sc_load(scr, ST, g, 0, min(cb, Nc), x1, dn2, dL);
         for (int c0 = 0; c0 < Nc; c0 += cb) {
             const int ncb = min(cb, Nc - c0);
-            if (pre) {
-#pragma unroll
-                for (int u = 0; u < KCOL_SCR; ++u) {
-                    const int idx = tid + u * nt;
-                    if (idx < ncb * L * n2) SC[idx] = make_double2(scr[u].x, scr[u].y);
-                }
-            } else {
-                for (int idx = tid; idx < ncb * L * n2; idx += nt) {
-                    const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
-                    SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
-                }
+            for (int idx = tid; idx < ncb * L * n2; idx += nt) {
+                const int cl = dn2.div(idx), n = idx - cl * n2, cc = dL.div(cl), l = cl - cc * L;
+                SC[idx] = ST[(((size_t)l * Nc + c0 + cc) * n1 + x1) * n2 + n];
             }
             __syncthreads();
-            if (pre && c0 + cb < Nc) kcol_sc_load(scr, ST, g, c0 + cb, min(cb, Nc - c0 - cb), x1, dn2, dL);
             if (MODE == COL_ADJ) {
                 // F[c][(l,i)][m] = conj(theta_l[i + Ns m]) * ytil[i][c][x][m]
                 for (int idx = tid; idx < ncb * B * M; idx += nt) {
@@ -220,7 +195,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                     }
                     F[idx] = f;
                 }
-                fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, false);
+                fft_batch_lds<KCOL_FOUT>(F, M, g.logM, ncb * B, M, TWM, false);
                 if (MODE == COL_FWD) {
                     for (int idx = tid; idx < ncb * Ns * M; idx += nt) {
                         const int cim = dM.div(idx), m = idx - cim * M, cc = dNs.div(cim), i = cim - cc * Ns, j = i + Ns * m;
@@ -241,18 +216,30 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
                     for (int l = 0; l < L; ++l) fc[(l * Ns + i) * M + m] = cmulc(z, theta[l * n2 + j]);
                 }
             }
-            fft_batch_lds(F, M, g.logM, ncb * B, M, TWM, true);
+            fft_batch_lds<KCOL_FOUT>(F, M, g.logM, ncb * B, M, TWM, true);
             // unfold and accumulate conj(S) * g[n mod M], coil by coil
-            for (int idx = tid; idx < B * n2; idx += nt) {
-                const int b = dn2.div(idx), n = idx - b * n2, l = dNs.div(b), nm = n - dM.div(n) * M;
-                double2 acc = ACC[idx];
-                for (int cc = 0; cc < ncb; ++cc)
-                    acc = cadd(acc, cconjmul(SC[(cc * L + l) * n2 + n], F[(cc * B + b) * M + nm]));
-                ACC[idx] = acc;
+#pragma unroll
+            for (int k = 0; k < KCOL_ACC; ++k) {
+                const int idx = tid + k * nt;
+                if (idx < B * n2) {
+                    const int b = dn2.div(idx), n = idx - b * n2, l = dNs.div(b), nm = n - dM.div(n) * M;
+                    double2 acc = accv[k];
+                    for (int cc = 0; cc < ncb; ++cc)
+                        acc = cadd(acc, cconjmul(SC[(cc * L + l) * n2 + n], F[(cc * B + b) * M + nm]));
+                    accv[k] = acc;
+                }
             }
             __syncthreads();
         }
         if (MODE == COL_FWD) return;
+        // the accumulator into ACC, over the loop's buffers (the last pass
+        // ended with a barrier); each thread reads back only its own elements
+        // below, so no barrier is needed before that
+#pragma unroll
+        for (int k = 0; k < KCOL_ACC; ++k) {
+            const int idx = tid + k * nt;
+            if (idx < B * n2) ACC[idx] = accv[k];
+        }
         // normal: conj(tau_i[n]) / n2 ; adjoint: (-1)^i conj(tau_i[n]) / sqrt(n2)
         for (int idx = tid; idx < B * n2; idx += nt) {
             const int b = dn2.div(idx), n = idx - b * n2, i = b - dNs.div(b) * Ns;
