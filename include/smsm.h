@@ -119,8 +119,11 @@ typedef struct {
  * the call synchronises before returning.  shot_mask: host uint8 [Ns][n2],
  * 1 where shot i acquires ky line j2; this build supports the interleaved
  * pattern of Eq. 2 only (j2 % Ns == i) and returns SMSM_E_UNSUPPORTED for
- * any other.  caipi_shift: host [L] shift of each slice as a fraction of
- * the FOV (NULL = l/L).  The plan's own device memory (coil maps widened to
+ * any other.  Geometries whose column pass does not fit one workgroup's
+ * shared memory (at most 5120 = L Ns n2 image points per column, fewer
+ * with large filters) also return SMSM_E_UNSUPPORTED.  caipi_shift: host
+ * [L] shift of each slice as a fraction of the FOV (NULL = l/L).  The plan's
+ * own device memory (coil maps widened to
  * complex128, transform and phase tables: smsm_plan_device_bytes) is
  * allocated here and released by smsm_plan_destroy; the plan has no
  * workspace until smsm_set_workspace binds one.  On failure *out is NULL.
