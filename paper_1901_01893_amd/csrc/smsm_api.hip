@@ -2,6 +2,7 @@
 // and the kernel sequences behind every C-ABI entry point of smsm.h.
 #include "smsm_kernels.h"
 #include "smsm_col_fast.h"
+#include "smsm_col_mix.h"
 #include "smsm_wavefft.h"
 #include "smsm_dense.h"
 #include "smsm_gram.h"
@@ -119,6 +120,8 @@ struct smsm_plan {
 
     int ns_iters = kNsDefaultIters;
     int col_fast = -1;        // instance of k_col_fast for this geometry (-1: generic k_col)
+    int col_mix = -1;         // instance of k_col_mix (odd-factor folded lengths) for the normal pass, or -1
+    size_t lds_colmix = 0;
     // per-launch timing of the fast column pass (diagnostic, off by default):
     // start/stop event pairs recorded with the dispatches
     std::vector<hipEvent_t> kt_ev;
@@ -263,6 +266,16 @@ const ColFastInst kColFast[] = {COLFAST(16, 2, 4, 2),  COLFAST(16, 3, 4, 2),  CO
                                 COLFAST(64, 3, 2, 4)};
 #undef COLFAST
 
+// Normal-pass instances for folded lengths with an odd factor (8 waves).
+struct ColMixInst {
+    int M, L, Ns, CG;
+    const void* fn;
+};
+#define COLMIX(M_, L_, NS_, CG_) {M_, L_, NS_, CG_, (const void*)&k_col_mix<M_, L_, NS_, CG_>}
+const ColMixInst kColMix[] = {COLMIX(56, 3, 4, 2), COLMIX(56, 2, 4, 2), COLMIX(48, 3, 4, 2), COLMIX(48, 2, 4, 2),
+                              COLMIX(28, 2, 8, 1), COLMIX(24, 2, 8, 1), COLMIX(28, 2, 4, 2)};
+#undef COLMIX
+
 template <int M_, int L_, int NS_, int CG_, bool KF32>
 void launch_colfast_k(smsm_plan* P, const double2* in, double2* out, int use_reg, const ColCg& pc, hipStream_t st) {
     const Geo& g = P->g;
@@ -314,8 +327,24 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
         LAUNCH_CHECK();
         in = pc.p;
     }
-    hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, in, out,
-                       P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
+    if (MODE == COL_NORMAL && P->col_mix >= 0) {
+#define COLMIX_LAUNCH(M_, L_, NS_, CG_)                                                                          \
+    hipLaunchKernelGGL((k_col_mix<M_, L_, NS_, CG_>), dim3(g.n1), dim3(64 * NS_ * CG_), P->lds_colmix, st, g, in, \
+                       out, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg)
+        switch (P->col_mix) {
+            case 0: COLMIX_LAUNCH(56, 3, 4, 2); break;
+            case 1: COLMIX_LAUNCH(56, 2, 4, 2); break;
+            case 2: COLMIX_LAUNCH(48, 3, 4, 2); break;
+            case 3: COLMIX_LAUNCH(48, 2, 4, 2); break;
+            case 4: COLMIX_LAUNCH(28, 2, 8, 1); break;
+            case 5: COLMIX_LAUNCH(24, 2, 8, 1); break;
+            default: COLMIX_LAUNCH(28, 2, 4, 2); break;
+        }
+#undef COLMIX_LAUNCH
+    } else {
+        hipLaunchKernelGGL(k_col<MODE>, dim3(g.n1), dim3(kColThreads), P->lds_col, st, g, in, out,
+                           P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
+    }
     LAUNCH_CHECK();
     if (pc.mode != 0) {
         hipLaunchKernelGGL(k_hyb_dot, vec_grid(), dim3(kThreads), 0, st, nvec, pc.p, out, pc.pq);
@@ -743,6 +772,15 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         if (kColFast[k].M == g.M && kColFast[k].L == L && kColFast[k].Ns == Ns && is_pow2(n1) && is_pow2(n2) &&
             P->lds_colfast <= (size_t)max_lds)
             P->col_fast = k;
+    if (P->col_fast < 0)
+        for (int k = 0; k < (int)(sizeof(kColMix) / sizeof(kColMix[0])); ++k) {
+            const ColMixInst& c = kColMix[k];
+            const size_t bytes = (size_t)colmix_lds_total(g, colmix_wb(c.M, c.L, c.Ns, c.CG)) * sizeof(double2);
+            if (c.M == g.M && c.L == L && c.Ns == Ns && 64 * c.Ns * c.CG == kColThreads && bytes <= (size_t)max_lds) {
+                P->col_mix = k;
+                P->lds_colmix = bytes;
+            }
+        }
 
     // device memory: the plan arena holds what creation derives; every buffer
     // a solve or operator chain writes lives in the caller's workspace
@@ -884,6 +922,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
                                  hipFuncSetAttribute(kColFast[P->col_fast].fn_f32,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)P->lds_colfast) != hipSuccess))
+            ok = false;
+        if (P->col_mix >= 0 && hipFuncSetAttribute(kColMix[P->col_mix].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)P->lds_colmix) != hipSuccess)
             ok = false;
     }
     ok = ok && hipStreamSynchronize(st) == hipSuccess;

@@ -83,6 +83,12 @@ GEOMS = {
     # the regulariser's taps share one region)
     "n256_L2_Ns8_r5": (si.Geometry(n=256, n_slices=2, n_shots=8, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 123),
+    # the odd-length register-resident column pass <56, 3 slices, 4 shots> (the
+    # batch's 224x224 MB3 group) and <48, 2 slices, 4 shots>
+    "n224_L3_Ns4_r7": (si.Geometry(n=224, n_slices=3, n_shots=4, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 125),
+    "n192_L2_Ns4_r5": (si.Geometry(n=192, n_slices=2, n_shots=4, n_coils=5, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 126),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
