@@ -213,43 +213,7 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
         ACC[idx] = cscale(cmulc(ACC[idx], tau[ib * N2 + n]), 1.0 / (double)N2);
     }
 
-    if (use_reg) {
-        // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}
-        const int nu1 = x1 - n1 / 2;
-        const int ph1 = imod(-e * nu1, n1), st1 = imod(nu1, n1);
-        for (int idx = tid; idx < L * NS * NS * nc; idx += nt) {
-            const double2* kr = Kc + (size_t)idx * nc;
-            double2 a = cmk(0.0, 0.0);
-            int ph = ph1;
-            for (int d1 = 0; d1 < nc; ++d1) {
-                a = cfma(kr[d1], tw1[ph], a);
-                ph += st1;
-                if (ph >= n1) ph -= n1;
-            }
-            A[idx] = a;
-        }
-        __syncthreads();
-        // ACC[(l,i')][n] += sum_i sum_d2 A[l][i][i'][d2] e^{-2 pi i d2 (n - n2/2)/n2} u_{l,i}[n]
-        for (int idx = tid; idx < B * N2; idx += nt) {
-            const int b = dn2.div(idx), n = idx - b * N2, l = b / NS, ip = b - l * NS;
-            const int nu2 = n - N2 / 2;
-            const int ph2 = imod(-e * nu2, N2), st2 = imod(nu2, N2);
-            double2 s = cmk(0.0, 0.0);
-            for (int ii = 0; ii < NS; ++ii) {
-                const double2 u = cmulc(U[(l * NS + ii) * N2 + n], tau[ii * N2 + n]);
-                const double2* ar = A + ((size_t)(l * NS + ii) * NS + ip) * nc;
-                double2 kv = cmk(0.0, 0.0);
-                int ph = ph2;
-                for (int d2 = 0; d2 < nc; ++d2) {
-                    kv = cfma(ar[d2], TW2[ph], kv);
-                    ph += st2;
-                    if (ph >= N2) ph -= N2;
-                }
-                s = cfma(kv, u, s);
-            }
-            ACC[idx] = cadd(ACC[idx], s);
-        }
-    }
+    if (use_reg) hankel_image_term(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
     __syncthreads();
     // centred forward DFT along ky
     for (int idx = tid; idx < B * N2; idx += nt) {

@@ -108,6 +108,85 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
     return c;
 }
 
+#define BAND_MAX_NC 17   // taps per filter dimension (2 r - 1) the kernels take
+
+// Image-domain circular Hankel term of the normal operator (Eq. 8-9) for
+// image column x1, added to ACC[(l, i')][n] (hybrid, before the final ky DFT):
+//   ACC += sum_d2 w2^(d2 - e) sum_i A[l][i][i'][d2] u_{l,i}[n] conj(tau_i[n]),
+//   A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] w1^(d1 - e),
+// w1 = e^{-2 pi i (x1 - n1/2)/n1}, w2 = e^{-2 pi i (n - n2/2)/n2} (tw1, TW2 hold
+// e^{-2 pi i k/n}), U = tau u, tau_i[n] = (-1)^n TW2[i n mod n2].  Both tap
+// sums run by Horner's rule in w1, w2 (one table lookup per sum instead of one
+// per tap): an element costs Ns (nc + 1) complex multiply-adds.  A wave takes
+// whole output rows (l, i') and a lane the ky points lane + 64 r, so a row's
+// taps are wave-uniform and each is read once for up to four points.
+// nc <= BAND_MAX_NC, n2 <= 256.  A holds
+// L Ns Ns nc entries of shared memory.  The callers' ACC writes before the
+// call are ordered by the barrier after the table build; they order the
+// writes here before their next use of ACC.
+SMSM_DEV void hankel_image_term(const Geo& g, int x1, const double2* U, const double2* __restrict__ tw1,
+                                const double2* TW2, const double2* __restrict__ Kc, double2* A, double2* ACC,
+                                const FastDiv& dn2, const FastDiv& dNs) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e;
+    const int nu1 = x1 - n1 / 2;
+    const double2 w1 = tw1[imod(nu1, n1)], w1e = tw1[imod(-e * nu1, n1)];
+    for (int idx = tid; idx < g.L * Ns * Ns * nc; idx += nt) {
+        // every workgroup reads the same Kc rows at once: issue a row's loads
+        // together rather than one dependent load per tap
+        const double2* kr = Kc + (size_t)idx * nc;
+        double2 kv[BAND_MAX_NC];
+#pragma unroll
+        for (int d1 = 0; d1 < BAND_MAX_NC; ++d1)
+            if (d1 < nc) kv[d1] = kr[d1];
+        double2 p = cmk(0.0, 0.0);
+#pragma unroll
+        for (int d1 = BAND_MAX_NC - 1; d1 >= 0; --d1)
+            if (d1 < nc) p = cfma(p, w1, kv[d1]);
+        A[idx] = cmul(p, w1e);
+    }
+    __syncthreads();
+    const int lane = tid & 63, nw = nt >> 6, R = (n2 + 63) >> 6;
+    for (int b = tid >> 6; b < g.B; b += nw) {
+        const int l = dNs.div(b), ip = b - l * Ns;
+        double2 w2[4], acc[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = min(lane + 64 * r, n2 - 1);   // lanes past n2 compute, never store
+            w2[r] = TW2[imod(n - n2 / 2, n2)];
+            acc[r] = cmk(0.0, 0.0);
+        }
+        for (int i = 0; i < Ns; ++i) {
+            const double2* ar = A + (size_t)((l * Ns + i) * Ns + ip) * nc;
+            double2 p[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) p[r] = cmk(0.0, 0.0);
+            for (int d2 = nc - 1; d2 >= 0; --d2) {
+                const double2 a = ar[d2];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < R) p[r] = cfma(p[r], w2[r], a);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < R) {
+                    const int n = min(lane + 64 * r, n2 - 1);
+                    const int k = i * n - n2 * dn2.div(i * n);
+                    const double2 u = cmulc(U[(l * Ns + i) * n2 + n], cscale(TW2[k], sgn_pow(n)));
+                    acc[r] = cfma(p[r], u, acc[r]);
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = lane + 64 * r;
+            if (r < R && n < n2) {
+                const double2 w2e = TW2[imod(-e * (n - n2 / 2), n2)];
+                ACC[b * n2 + n] = cadd(ACC[b * n2 + n], cmul(acc[r], w2e));
+            }
+        }
+    }
+}
+
 // One workgroup per image column x (blockIdx.x).
 //  COL_NORMAL  h2 = F_y[ sum_c S^H F_y^-1 M theta^H theta M F_y S u + (reg) ] for
 //              u = F_y^-1 h1 (h1, h2 hybrid [B][n1][n2]);
@@ -248,45 +327,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
         }
     }
 
-    if (MODE != COL_ADJ && use_reg) {
-        // A[l][i][i'][d2] = sum_d1 Kc[l][i][i'][d2][d1] e^{-2 pi i d1 (x - n1/2)/n1}
-        const int nc = g.nc, e = g.e, nu1 = x1 - n1 / 2;
-        // the phase (d1 - e) nu1 mod n1 advances by nu1 mod n1 per tap
-        const int ph1 = imod(-e * nu1, n1), st1 = imod(nu1, n1);
-        for (int idx = tid; idx < L * Ns * Ns * nc; idx += nt) {
-            const double2* kr = Kc + (size_t)idx * nc;
-            double2 a = cmk(0.0, 0.0);
-            int ph = ph1;
-            for (int d1 = 0; d1 < nc; ++d1) {
-                a = cfma(kr[d1], tw1[ph], a);
-                ph += st1;
-                if (ph >= n1) ph -= n1;
-            }
-            A[idx] = a;
-        }
-        __syncthreads();
-        // ACC[(l,i')][n] += sum_i sum_d2 A[l][i][i'][d2] e^{-2 pi i d2 (n - n2/2)/n2} u_{l,i}[n]
-        for (int idx = tid; idx < B * n2; idx += nt) {
-            const int b = dn2.div(idx), n = idx - b * n2, l = dNs.div(b), ip = b - l * Ns;
-            const int nu2 = n - n2 / 2;
-            // the phase (d2 - e) nu2 mod n2 advances by nu2 mod n2 per tap
-            const int ph2 = imod(-e * nu2, n2), st2 = imod(nu2, n2);
-            double2 s = cmk(0.0, 0.0);
-            for (int i = 0; i < Ns; ++i) {
-                const double2 u = cmulc(U[(l * Ns + i) * n2 + n], tau[i * n2 + n]);
-                const double2* ar = A + ((size_t)(l * Ns + i) * Ns + ip) * nc;
-                double2 kv = cmk(0.0, 0.0);
-                int ph = ph2;
-                for (int d2 = 0; d2 < nc; ++d2) {
-                    kv = cfma(ar[d2], TW2[ph], kv);
-                    ph += st2;
-                    if (ph >= n2) ph -= n2;
-                }
-                s = cfma(kv, u, s);
-            }
-            ACC[idx] = cadd(ACC[idx], s);
-        }
-    }
+    if (MODE != COL_ADJ && use_reg) hankel_image_term(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, dNs);
     __syncthreads();
     // centred forward DFT along ky
     for (int idx = tid; idx < B * n2; idx += nt) {
@@ -408,7 +449,6 @@ __global__ void k_band_tables(Geo g, const double2* __restrict__ W, double half_
 // Every workgroup also writes its share of Re <p, correction> (the band part
 // of Re <p, N p>) to part[blockIdx.y * gridDim.x + blockIdx.x].
 #define BAND_SEG 64
-#define BAND_MAX_NC 17
 #define BAND_MAX_DS 4
 #define BAND_STAGE 8      // staged patch entries per thread and pass
 __host__ __device__ inline int band_segs(int len) { return (len + BAND_SEG - 1) / BAND_SEG; }
