@@ -4,14 +4,13 @@
 // circular Hankel term from the tap table Kc).  The column image and the
 // final ky transform are block-wide, as in k_col; the coil loop is
 // register-resident, as in k_col_fast: wave w takes shot i = w % NS and the
-// coils of coil group w / NS, lane l = grp M + m coil group member grp and
-// folded point m (G = 64 / M members side by side, the remaining lanes idle).
+// coils of coil group w / NS; lane l = grp M + a P + j is coil group member
+// grp (G = 64 / M members side by side, the remaining lanes idle), group a < Q
+// and place j < P of the folded length, and holds folded point Q j + a.
 // Per coil: fold, M-point DFT, CAIPI sum and split, inverse DFT, unfold into
-// the lane's accumulators.  The M-point transforms run through a buffer of
-// the wave's own in shared memory (no block barrier), as a two-factor
-// decomposition (see wave_dft).
+// the lane's accumulators (see mix_dft for the transforms).
 #pragma once
-#include "smsm_kernels.h"
+#include "smsm_col_fast.h"
 
 // Shared memory (double2 units): U [B][n2], ACC [B][n2], ky twiddles [n2],
 // folded twiddles [M], the waves' transform buffers [NS CG][G][L][M], the
@@ -27,63 +26,89 @@ SMSM_DEV void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Unnormalised DFT of length M = P Q (forward e^{-2 pi i jk/M}, INV e^{+...})
-// of NV sequences held one point per lane (lane m holds point m of each),
-// through the wave's buffer buf [NV][M] (this coil group's part):
-//   X[k1 + P k2] = sum_{n2<Q} w^{P n2 k2} w^{n2 k1} sum_{n1<P} x[Q n1 + n2] w^{Q n1 k1}
-// (n Q-major in, k P-minor out; w^{nk} splits because w^{M n1 k2} = 1).  Lane
-// m forms the inner sum for (n2, k1) = (m / P, m % P) and stores it at m,
-// then the outer for (k1, k2) = (m % P, m / P): output X[m], natural order.
-// The powers of each sum's base are formed by repeated products from the
-// table twm[k] = e^{-2 pi i k / M}.  Inactive lanes read but never write.
+// Per-lane constants of the M = P Q point transforms (twm[k] = e^{-2 pi i k/M}):
+// the radix-2 stage twiddles and signs of the P-point transform across the P
+// lanes of a group, the inter-factor twiddle w_M^(a brev(j)) and the base
+// w_Q^a of the Q-point sums.  Built from the shared-memory table at each
+// transform (a few independent reads), so they hold no registers across the
+// coil loop.
+template <int M, int Q>
+struct MixLane {
+    static constexpr int P = M / Q;
+    static constexpr int LOGP = P == 16 ? 4 : P == 8 ? 3 : 2;
+    static_assert(P * Q == M && (P == 4 || P == 8 || P == 16), "M = P Q with P = 4, 8 or 16");
+    double2 w[8];
+    double sg[8];
+    double2 tf, tq;
+    int j;
+    SMSM_DEV void setup(const double2* twm, int m) {
+        const int a = m / P;
+        j = m % P;
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int h = 1 << st;
+            const bool upper = (j & h) == 0;
+            sg[st] = upper ? 1.0 : -1.0;
+            w[st] = (st >= LOGP || upper) ? cmk(1.0, 0.0) : twm[(j & (h - 1)) * (M / (2 * h))];
+        }
+        const int bj = (int)(__brev((unsigned)j) >> (32 - LOGP));
+        tf = twm[a * bj];
+        tq = twm[P * a];
+    }
+};
+
+// Q-point sums through the wave's buffer buf [NV][M] (this member's part):
+// lane (a, j) stores its value at a P + j, then forms
+//   sum_{a' < Q} buf[a' P + j] (w_Q^{+-a})^{a'}
+// (the powers of the base by repeated products).  Inactive lanes read but
+// never write.
 template <int M, int Q, int NV, bool INV>
-SMSM_DEV void wave_dft(double2 (&f)[NV], double2* buf, const double2* twm, int m, bool active) {
+SMSM_DEV void mix_qsum(double2 (&f)[NV], double2* buf, const MixLane<M, Q>& c, int m, bool active) {
     constexpr int P = M / Q;
-    static_assert(P * Q == M && (P & (P - 1)) == 0, "M = P Q with P a power of two");
-    auto tw = [&](int k) {
-        const double2 w = twm[k];
-        return INV ? cconj(w) : w;
-    };
     if (active) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) buf[v * M + m] = f[v];
     }
     wave_fence();
-    const int a = m / P, k1 = m % P;   // inner: n2 = a; outer: k2 = a
-    double2 z[NV];
-    {
-        const double2 base = tw((Q * k1) % M), tz = tw((a * k1) % M);
+    const double2 base = INV ? cconj(c.tq) : c.tq;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) z[v] = cmk(0.0, 0.0);
-        double2 wc = cmk(1.0, 0.0);   // w^{Q n1 k1}, shared by the NV sequences
-#pragma unroll 4
-        for (int n1 = 0; n1 < P; ++n1) {
+    for (int v = 0; v < NV; ++v) f[v] = cmk(0.0, 0.0);
+    double2 wc = cmk(1.0, 0.0);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) z[v] = cfma(buf[v * M + Q * n1 + a], wc, z[v]);
-            wc = cmul(wc, base);
-        }
+    for (int q = 0; q < Q; ++q) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) z[v] = cmul(z[v], tz);
+        for (int v = 0; v < NV; ++v) f[v] = cfma(buf[v * M + q * P + c.j], wc, f[v]);
+        wc = cmul(wc, base);
     }
     wave_fence();
-    if (active) {
+}
+
+// Unnormalised M-point DFT (forward e^{-2 pi i nk/M}, INV e^{+...}) of NV
+// sequences, M = P Q, n = Q n1 + a, k = k1 + P k2:
+//   X[k1 + P k2] = sum_a w_Q^(a k2) w_M^(a k1) sum_{n1 < P} x[Q n1 + a] w_P^(n1 k1)
+// (w_M^(nk) splits because w_M^(Q n1 P k2) = 1).  Forward: lane (a, j) holds
+// x[Q j + a]; the P-point transform runs across the lanes of group a
+// (decimation in frequency, leaving k1 = brev(j)), then the twiddle, then the
+// Q-point sum of mix_qsum leaves X[brev(j) + P a] at lane (a, j).  The inverse
+// is the conjugate transpose: Q-point sums, conjugate twiddle, decimation in
+// time across the group (bit-reversed in, natural out), back to the lane's
+// point Q j + a.
+template <int M, int Q, int NV, bool INV>
+SMSM_DEV void mix_dft(double2 (&f)[NV], double2* buf, const double2* twm, int m, bool active) {
+    constexpr int P = M / Q;
+    MixLane<M, Q> c;
+    c.setup(twm, m);
+    if constexpr (!INV) {
+        fft_dif<P, NV>(f, c.w, c.sg);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) buf[v * M + m] = z[v];
+        for (int v = 0; v < NV; ++v) f[v] = cmul(f[v], c.tf);
+        mix_qsum<M, Q, NV, false>(f, buf, c, m, active);
+    } else {
+        mix_qsum<M, Q, NV, true>(f, buf, c, m, active);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = cmulc(f[v], c.tf);
+        fft_dit_inv<P, NV>(f, c.w, c.sg);
     }
-    wave_fence();
-    {
-        const double2 base = tw((P * a) % M);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) f[v] = cmk(0.0, 0.0);
-        double2 wc = cmk(1.0, 0.0);   // w^{P n2 k2}
-#pragma unroll
-        for (int n2 = 0; n2 < Q; ++n2) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) f[v] = cfma(buf[v * M + n2 * P + k1], wc, f[v]);
-            wc = cmul(wc, base);
-        }
-    }
-    wave_fence();
 }
 
 // grid (n1), block 64 NS CG (= 512).  n2 = M NS.
@@ -102,6 +127,8 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
     const int lane = tid & 63, wave = tid >> 6;
     const int i = wave % NS, cg = wave / NS;
     const int grp0 = lane / M, m = lane % M;
+    constexpr int P = M / Q;
+    const int tpos = Q * (m % P) + m / P;   // the lane's folded point
     const bool active = grp0 < G;
     const int grp = active ? grp0 : G - 1;
     double2* U = sm;
@@ -127,20 +154,22 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
     }
     __syncthreads();
 
-    // ---- coil loop: lane accumulators of positions n = m + M t, t < NS
+    // ---- coil loop: lane accumulators of positions n = tpos + M t, t < NS
     double2 acc[L][NS];
 #pragma unroll
     for (int s = 0; s < L; ++s)
 #pragma unroll
         for (int t = 0; t < NS; ++t) acc[s][t] = cmk(0.0, 0.0);
-    const double2* Ui = U + i * N2 + m;
-    double2 th[L];   // CAIPI phase of this lane's bin m (natural order)
+    const double2* Ui = U + i * N2 + tpos;
+    // CAIPI phase of this lane's bin after the forward transform
+    const int bin = (int)(__brev((unsigned)(m % P)) >> (32 - MixLane<M, Q>::LOGP)) + P * (m / P);
+    double2 th[L];
 #pragma unroll
-    for (int s = 0; s < L; ++s) th[s] = theta[s * N2 + i + NS * m];
+    for (int s = 0; s < L; ++s) th[s] = theta[s * N2 + i + NS * bin];
     double2* buf = WB + (wave * G + grp) * L * M;
     const int per_iter = CG * G;
     const int iters = (Nc + per_iter - 1) / per_iter;
-    const size_t lane_off = (size_t)x1 * N2 + m;
+    const size_t lane_off = (size_t)x1 * N2 + tpos;
     const size_t slice_stride = (size_t)Nc * n1 * N2, coil_stride = (size_t)n1 * N2;
 #pragma unroll 1
     for (int it = 0; it < iters; ++it) {
@@ -160,13 +189,13 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
             for (int t = 0; t < NS; ++t) a = cfma(sc[s][t], Ui[s * NS * N2 + M * t], a);
             f[s] = cscale(a, live);
         }
-        wave_dft<M, Q, L, false>(f, buf, TWM, m, active);
+        mix_dft<M, Q, L, false>(f, buf, TWM, m, active);
         double2 z = cmk(0.0, 0.0);
 #pragma unroll
         for (int s = 0; s < L; ++s) z = cfma(th[s], f[s], z);
 #pragma unroll
         for (int s = 0; s < L; ++s) f[s] = cmulc(z, th[s]);
-        wave_dft<M, Q, L, true>(f, buf, TWM, m, active);
+        mix_dft<M, Q, L, true>(f, buf, TWM, m, active);
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
@@ -201,7 +230,7 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
             for (int s = 0; s < L; ++s)
 #pragma unroll
                 for (int t = 0; t < NS; ++t) {
-                    const int o = (s * NS + i) * N2 + m + M * t;
+                    const int o = (s * NS + i) * N2 + tpos + M * t;
                     ACC[o] = (k == 0) ? acc[s][t] : cadd(ACC[o], acc[s][t]);
                 }
         }
