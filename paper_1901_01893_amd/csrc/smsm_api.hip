@@ -272,8 +272,9 @@ struct ColMixInst {
     const void* fn;
 };
 #define COLMIX(M_, L_, NS_, CG_) {M_, L_, NS_, CG_, (const void*)&k_col_mix<M_, L_, NS_, CG_>}
-const ColMixInst kColMix[] = {COLMIX(56, 3, 4, 2), COLMIX(56, 2, 4, 2), COLMIX(48, 3, 4, 2), COLMIX(48, 2, 4, 2),
-                              COLMIX(28, 2, 8, 1), COLMIX(24, 2, 8, 1), COLMIX(28, 2, 4, 2)};
+const ColMixInst kColMix[] = {COLMIX(56, 3, 4, 2),  COLMIX(56, 2, 4, 2),  COLMIX(48, 3, 4, 2),  COLMIX(48, 2, 4, 2),
+                              COLMIX(28, 2, 8, 1),  COLMIX(24, 2, 8, 1),  COLMIX(28, 2, 4, 2),  COLMIX(112, 2, 2, 4),
+                              COLMIX(96, 3, 2, 4),  COLMIX(96, 2, 2, 4)};
 #undef COLMIX
 
 template <int M_, int L_, int NS_, int CG_, bool KF32>
@@ -338,7 +339,10 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
             case 3: COLMIX_LAUNCH(48, 2, 4, 2); break;
             case 4: COLMIX_LAUNCH(28, 2, 8, 1); break;
             case 5: COLMIX_LAUNCH(24, 2, 8, 1); break;
-            default: COLMIX_LAUNCH(28, 2, 4, 2); break;
+            case 6: COLMIX_LAUNCH(28, 2, 4, 2); break;
+            case 7: COLMIX_LAUNCH(112, 2, 2, 4); break;
+            case 8: COLMIX_LAUNCH(96, 3, 2, 4); break;
+            default: COLMIX_LAUNCH(96, 2, 2, 4); break;
         }
 #undef COLMIX_LAUNCH
     } else {

@@ -1,12 +1,14 @@
 // Normal-operator column pass for folded lengths with an odd factor
-// (M = P Q, Q = 3 or 7, P a power of two: 24, 28, 48, 56 at n2 = 192, 224),
-// with the contract of k_col<COL_NORMAL> (hybrid in -> hybrid out, the
-// circular Hankel term from the tap table Kc).  The column image and the
-// final ky transform are block-wide, as in k_col; the coil loop is
+// (M = P Q, Q = 3 or 7, P a power of two: 24, 28, 48, 56, 96, 112 at
+// n2 = 192, 224), with the contract of k_col<COL_NORMAL> (hybrid in -> hybrid
+// out, the circular Hankel term from the tap table Kc).  The column image and
+// the final ky transform are block-wide, as in k_col; the coil loop is
 // register-resident, as in k_col_fast: wave w takes shot i = w % NS and the
-// coils of coil group w / NS; lane l = grp M + a P + j is coil group member
-// grp (G = 64 / M members side by side, the remaining lanes idle), group a < Q
-// and place j < P of the folded length, and holds folded point Q j + a.
+// coils of coil group w / NS.  M <= 64: lane l = grp M + a P + j is coil group
+// member grp (G = 64 / M members side by side, the remaining lanes idle),
+// group a < Q and place j < P, and holds folded point Q j + a.  M > 64: one
+// member, two points per lane: lane a' P + j holds groups a = a' + (64 / P) r
+// in its registers r = 0, 1 (the slots with a >= Q idle).
 // Per coil: fold, M-point DFT, CAIPI sum and split, inverse DFT, unfold into
 // the lane's accumulators (see mix_dft for the transforms).
 #pragma once
@@ -15,7 +17,9 @@
 // Shared memory (double2 units): U [B][n2], ACC [B][n2], ky twiddles [n2],
 // folded twiddles [M], the waves' transform buffers [NS CG][G][L][M], the
 // regulariser's taps [L][Ns][Ns][nc], 16 for reductions.
-__host__ __device__ inline int colmix_wb(int M, int L, int NS, int CG) { return NS * CG * (64 / M) * L * M; }
+__host__ __device__ inline int colmix_wb(int M, int L, int NS, int CG) {
+    return NS * CG * (M > 64 ? 1 : 64 / M) * L * M;
+}
 __host__ __device__ inline int colmix_lds_total(const Geo& g, int wb) {
     return 2 * g.B * g.n2 + g.n2 + g.M + wb + g.L * g.Ns * g.Ns * g.nc + 16;
 }
@@ -28,22 +32,19 @@ SMSM_DEV void wave_fence() {
 
 // Per-lane constants of the M = P Q point transforms (twm[k] = e^{-2 pi i k/M}):
 // the radix-2 stage twiddles and signs of the P-point transform across the P
-// lanes of a group, the inter-factor twiddle w_M^(a brev(j)) and the base
-// w_Q^a of the Q-point sums.  Built from the shared-memory table at each
-// transform (a few independent reads), so they hold no registers across the
-// coil loop.
-template <int M, int Q>
+// lanes of a group, and per register r the inter-factor twiddle
+// w_M^(a_r brev(j)) and the base w_Q^(a_r) of the Q-point sums.  Built from
+// the shared-memory table at each transform (a few independent reads), so
+// they hold no registers across the coil loop.
+template <int M, int Q, int MR>
 struct MixLane {
     static constexpr int P = M / Q;
-    static constexpr int LOGP = P == 16 ? 4 : P == 8 ? 3 : 2;
-    static_assert(P * Q == M && (P == 4 || P == 8 || P == 16), "M = P Q with P = 4, 8 or 16");
+    static constexpr int LOGP = P == 32 ? 5 : P == 16 ? 4 : P == 8 ? 3 : 2;
+    static_assert(P * Q == M && (P == 4 || P == 8 || P == 16 || P == 32), "M = P Q with P = 4 .. 32");
     double2 w[8];
     double sg[8];
-    double2 tf, tq;
-    int j;
-    SMSM_DEV void setup(const double2* twm, int m) {
-        const int a = m / P;
-        j = m % P;
+    double2 tf[MR], tq[MR];
+    SMSM_DEV void setup(const double2* twm, int j, const int (&a)[MR]) {
 #pragma unroll
         for (int st = 0; st < 8; ++st) {
             const int h = 1 << st;
@@ -52,62 +53,82 @@ struct MixLane {
             w[st] = (st >= LOGP || upper) ? cmk(1.0, 0.0) : twm[(j & (h - 1)) * (M / (2 * h))];
         }
         const int bj = (int)(__brev((unsigned)j) >> (32 - LOGP));
-        tf = twm[a * bj];
-        tq = twm[P * a];
+#pragma unroll
+        for (int r = 0; r < MR; ++r) {
+            tf[r] = twm[a[r] * bj];
+            tq[r] = twm[P * a[r]];
+        }
     }
 };
 
-// Q-point sums through the wave's buffer buf [NV][M] (this member's part):
-// lane (a, j) stores its value at a P + j, then forms
+// Q-point sums through the wave's buffer buf [L][M] (this member's part):
+// slot (a, j) stores its value at a P + j, then forms
 //   sum_{a' < Q} buf[a' P + j] (w_Q^{+-a})^{a'}
-// (the powers of the base by repeated products).  Inactive lanes read but
-// never write.
-template <int M, int Q, int NV, bool INV>
-SMSM_DEV void mix_qsum(double2 (&f)[NV], double2* buf, const MixLane<M, Q>& c, int m, bool active) {
+// (the powers of the base by repeated products).  Idle slots read but never
+// write.
+template <int M, int Q, int L, int MR, bool INV>
+SMSM_DEV void mix_qsum(double2 (&f)[L * MR], double2* buf, const MixLane<M, Q, MR>& c, int j,
+                       const int (&a)[MR], const bool (&ok)[MR]) {
     constexpr int P = M / Q;
-    if (active) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) buf[v * M + m] = f[v];
-    }
+    for (int r = 0; r < MR; ++r)
+        if (ok[r]) {
+#pragma unroll
+            for (int s = 0; s < L; ++s) buf[s * M + a[r] * P + j] = f[s * MR + r];
+        }
     wave_fence();
-    const double2 base = INV ? cconj(c.tq) : c.tq;
+    double2 base[MR], wc[MR];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) f[v] = cmk(0.0, 0.0);
-    double2 wc = cmk(1.0, 0.0);
+    for (int r = 0; r < MR; ++r) {
+        base[r] = INV ? cconj(c.tq[r]) : c.tq[r];
+        wc[r] = cmk(1.0, 0.0);
+    }
+#pragma unroll
+    for (int v = 0; v < L * MR; ++v) f[v] = cmk(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) f[v] = cfma(buf[v * M + q * P + c.j], wc, f[v]);
-        wc = cmul(wc, base);
+        for (int s = 0; s < L; ++s) {
+            const double2 x = buf[s * M + q * P + j];
+#pragma unroll
+            for (int r = 0; r < MR; ++r) f[s * MR + r] = cfma(x, wc[r], f[s * MR + r]);
+        }
+#pragma unroll
+        for (int r = 0; r < MR; ++r) wc[r] = cmul(wc[r], base[r]);
     }
     wave_fence();
 }
 
-// Unnormalised M-point DFT (forward e^{-2 pi i nk/M}, INV e^{+...}) of NV
-// sequences, M = P Q, n = Q n1 + a, k = k1 + P k2:
+// Unnormalised M-point DFT (forward e^{-2 pi i nk/M}, INV e^{+...}) of L
+// sequences (MR slots each), M = P Q, n = Q n1 + a, k = k1 + P k2:
 //   X[k1 + P k2] = sum_a w_Q^(a k2) w_M^(a k1) sum_{n1 < P} x[Q n1 + a] w_P^(n1 k1)
-// (w_M^(nk) splits because w_M^(Q n1 P k2) = 1).  Forward: lane (a, j) holds
+// (w_M^(nk) splits because w_M^(Q n1 P k2) = 1).  Forward: slot (a, j) holds
 // x[Q j + a]; the P-point transform runs across the lanes of group a
 // (decimation in frequency, leaving k1 = brev(j)), then the twiddle, then the
-// Q-point sum of mix_qsum leaves X[brev(j) + P a] at lane (a, j).  The inverse
+// Q-point sum of mix_qsum leaves X[brev(j) + P a] in slot (a, j).  The inverse
 // is the conjugate transpose: Q-point sums, conjugate twiddle, decimation in
-// time across the group (bit-reversed in, natural out), back to the lane's
+// time across the group (bit-reversed in, natural out), back to the slot's
 // point Q j + a.
-template <int M, int Q, int NV, bool INV>
-SMSM_DEV void mix_dft(double2 (&f)[NV], double2* buf, const double2* twm, int m, bool active) {
+template <int M, int Q, int L, int MR, bool INV>
+SMSM_DEV void mix_dft(double2 (&f)[L * MR], double2* buf, const double2* twm, int j, const int (&a)[MR],
+                      const bool (&ok)[MR]) {
     constexpr int P = M / Q;
-    MixLane<M, Q> c;
-    c.setup(twm, m);
+    MixLane<M, Q, MR> c;
+    c.setup(twm, j, a);
     if constexpr (!INV) {
-        fft_dif<P, NV>(f, c.w, c.sg);
+        fft_dif<P, L * MR>(f, c.w, c.sg);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) f[v] = cmul(f[v], c.tf);
-        mix_qsum<M, Q, NV, false>(f, buf, c, m, active);
+        for (int s = 0; s < L; ++s)
+#pragma unroll
+            for (int r = 0; r < MR; ++r) f[s * MR + r] = cmul(f[s * MR + r], c.tf[r]);
+        mix_qsum<M, Q, L, MR, false>(f, buf, c, j, a, ok);
     } else {
-        mix_qsum<M, Q, NV, true>(f, buf, c, m, active);
+        mix_qsum<M, Q, L, MR, true>(f, buf, c, j, a, ok);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) f[v] = cmulc(f[v], c.tf);
-        fft_dit_inv<P, NV>(f, c.w, c.sg);
+        for (int s = 0; s < L; ++s)
+#pragma unroll
+            for (int r = 0; r < MR; ++r) f[s * MR + r] = cmulc(f[s * MR + r], c.tf[r]);
+        fft_dit_inv<P, L * MR>(f, c.w, c.sg);
     }
 }
 
@@ -118,19 +139,32 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
           const double2* __restrict__ theta, const double2* __restrict__ tau, const double2* __restrict__ tw2,
           const double2* __restrict__ twM, const double2* __restrict__ tw1, const double2* __restrict__ Kc,
           int use_reg) {
-    constexpr int Q = (M % 7 == 0) ? 7 : 3;
-    constexpr int G = 64 / M, B = L * NS, NW = NS * CG, N2 = M * NS;
+    constexpr int Q = (M % 7 == 0) ? 7 : 3, P = M / Q;
+    constexpr int MR = M > 64 ? 2 : 1;          // folded points per lane
+    constexpr int G = M > 64 ? 1 : 64 / M;      // coil-group members per wave
+    constexpr int GL = 64 / P;                  // lane groups per register (MR = 2)
+    constexpr int B = L * NS, NW = NS * CG, N2 = M * NS;
+    static_assert(MR == 1 || Q <= 2 * GL, "two slots per lane cover the Q groups");
     extern __shared__ double2 sm[];
     const int n1 = g.n1, Nc = g.Nc, nc = g.nc, e = g.e;
     const int x1 = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int i = wave % NS, cg = wave / NS;
-    const int grp0 = lane / M, m = lane % M;
-    constexpr int P = M / Q;
-    const int tpos = Q * (m % P) + m / P;   // the lane's folded point
+    const int grp0 = MR == 1 ? lane / M : 0;
+    const int m = MR == 1 ? lane % M : lane;   // lane within its member
+    const int j = m % P;
     const bool active = grp0 < G;
     const int grp = active ? grp0 : G - 1;
+    int a[MR], tpos[MR];   // each slot's group and folded point
+    bool ok[MR];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) {
+        const int ar = m / P + GL * r;
+        ok[r] = active && ar < Q;
+        a[r] = min(ar, Q - 1);
+        tpos[r] = Q * j + a[r];
+    }
     double2* U = sm;
     double2* ACC = sm + B * N2;
     double2* TW2 = sm + 2 * B * N2;
@@ -154,52 +188,67 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
     }
     __syncthreads();
 
-    // ---- coil loop: lane accumulators of positions n = tpos + M t, t < NS
-    double2 acc[L][NS];
+    // ---- coil loop: slot accumulators of positions n = tpos + M t, t < NS
+    double2 acc[L][NS][MR];
 #pragma unroll
     for (int s = 0; s < L; ++s)
 #pragma unroll
-        for (int t = 0; t < NS; ++t) acc[s][t] = cmk(0.0, 0.0);
-    const double2* Ui = U + i * N2 + tpos;
-    // CAIPI phase of this lane's bin after the forward transform
-    const int bin = (int)(__brev((unsigned)(m % P)) >> (32 - MixLane<M, Q>::LOGP)) + P * (m / P);
-    double2 th[L];
+        for (int t = 0; t < NS; ++t)
 #pragma unroll
-    for (int s = 0; s < L; ++s) th[s] = theta[s * N2 + i + NS * bin];
+            for (int r = 0; r < MR; ++r) acc[s][t][r] = cmk(0.0, 0.0);
+    const double2* Ui = U + i * N2;
+    // CAIPI phase of each slot's bin after the forward transform
+    const int bj = (int)(__brev((unsigned)j) >> (32 - MixLane<M, Q, MR>::LOGP));
+    double2 th[L][MR];
+#pragma unroll
+    for (int s = 0; s < L; ++s)
+#pragma unroll
+        for (int r = 0; r < MR; ++r) th[s][r] = theta[s * N2 + i + NS * (bj + P * a[r])];
     double2* buf = WB + (wave * G + grp) * L * M;
     const int per_iter = CG * G;
     const int iters = (Nc + per_iter - 1) / per_iter;
-    const size_t lane_off = (size_t)x1 * N2 + tpos;
+    const size_t col_off = (size_t)x1 * N2;
     const size_t slice_stride = (size_t)Nc * n1 * N2, coil_stride = (size_t)n1 * N2;
 #pragma unroll 1
     for (int it = 0; it < iters; ++it) {
         const int c = (it * CG + cg) * G + grp0;
-        const double live = (active && c < Nc) ? 1.0 : 0.0;
-        const size_t cbase = lane_off + (size_t)min(c, Nc - 1) * coil_stride;
-        double2 sc[L][NS];
+        const size_t cbase = col_off + (size_t)min(c, Nc - 1) * coil_stride;
+        double2 sc[L][NS][MR];
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < NS; ++t) sc[s][t] = ST[cbase + s * slice_stride + M * t];
-        double2 f[L];
+            for (int t = 0; t < NS; ++t)
 #pragma unroll
-        for (int s = 0; s < L; ++s) {
-            double2 a = cmk(0.0, 0.0);
+                for (int r = 0; r < MR; ++r) sc[s][t][r] = ST[cbase + s * slice_stride + tpos[r] + M * t];
+        double2 f[L * MR];
 #pragma unroll
-            for (int t = 0; t < NS; ++t) a = cfma(sc[s][t], Ui[s * NS * N2 + M * t], a);
-            f[s] = cscale(a, live);
+        for (int r = 0; r < MR; ++r) {
+            const double live = (ok[r] && c < Nc) ? 1.0 : 0.0;
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                double2 v = cmk(0.0, 0.0);
+#pragma unroll
+                for (int t = 0; t < NS; ++t) v = cfma(sc[s][t][r], Ui[s * NS * N2 + tpos[r] + M * t], v);
+                f[s * MR + r] = cscale(v, live);
+            }
         }
-        mix_dft<M, Q, L, false>(f, buf, TWM, m, active);
-        double2 z = cmk(0.0, 0.0);
+        mix_dft<M, Q, L, MR, false>(f, buf, TWM, j, a, ok);
 #pragma unroll
-        for (int s = 0; s < L; ++s) z = cfma(th[s], f[s], z);
+        for (int r = 0; r < MR; ++r) {
+            double2 z = cmk(0.0, 0.0);
 #pragma unroll
-        for (int s = 0; s < L; ++s) f[s] = cmulc(z, th[s]);
-        mix_dft<M, Q, L, true>(f, buf, TWM, m, active);
+            for (int s = 0; s < L; ++s) z = cfma(th[s][r], f[s * MR + r], z);
+#pragma unroll
+            for (int s = 0; s < L; ++s) f[s * MR + r] = cmulc(z, th[s][r]);
+        }
+        mix_dft<M, Q, L, MR, true>(f, buf, TWM, j, a, ok);
 #pragma unroll
         for (int s = 0; s < L; ++s)
 #pragma unroll
-            for (int t = 0; t < NS; ++t) acc[s][t] = cadd(acc[s][t], cconjmul(sc[s][t], f[s]));
+            for (int t = 0; t < NS; ++t)
+#pragma unroll
+                for (int r = 0; r < MR; ++r)
+                    acc[s][t][r] = cadd(acc[s][t][r], cconjmul(sc[s][t][r], f[s * MR + r]));
     }
 
     // ---- coil-group members of a wave: member g > 0 hands its sums to member 0
@@ -212,12 +261,12 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
             for (int gg = 1; gg < G; ++gg) {
                 if (grp0 == gg) {
 #pragma unroll
-                    for (int s = 0; s < L; ++s) b0[s * M + m] = acc[s][t];
+                    for (int s = 0; s < L; ++s) b0[s * M + m] = acc[s][t][0];
                 }
                 wave_fence();
                 if (grp0 == 0) {
 #pragma unroll
-                    for (int s = 0; s < L; ++s) acc[s][t] = cadd(acc[s][t], b0[s * M + m]);
+                    for (int s = 0; s < L; ++s) acc[s][t][0] = cadd(acc[s][t][0], b0[s * M + m]);
                 }
                 wave_fence();
             }
@@ -227,11 +276,15 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
     for (int k = 0; k < CG; ++k) {
         if (cg == k && grp0 == 0) {
 #pragma unroll
-            for (int s = 0; s < L; ++s)
+            for (int r = 0; r < MR; ++r)
+                if (ok[r]) {
 #pragma unroll
-                for (int t = 0; t < NS; ++t) {
-                    const int o = (s * NS + i) * N2 + tpos + M * t;
-                    ACC[o] = (k == 0) ? acc[s][t] : cadd(ACC[o], acc[s][t]);
+                    for (int s = 0; s < L; ++s)
+#pragma unroll
+                        for (int t = 0; t < NS; ++t) {
+                            const int o = (s * NS + i) * N2 + tpos[r] + M * t;
+                            ACC[o] = (k == 0) ? acc[s][t][r] : cadd(ACC[o], acc[s][t][r]);
+                        }
                 }
         }
         __syncthreads();

@@ -89,6 +89,15 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 125),
     "n192_L2_Ns4_r5": (si.Geometry(n=192, n_slices=2, n_shots=4, n_coils=5, filt=5, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 126),
+    # the odd-length pass with two folded points per lane: <112, 2 slices,
+    # 2 shots> (the batch's 224x224 MB2 two-shot group), <96, 3 slices> (a
+    # partial second coil pass: 5 coils over 4 coil groups) and <96, 2 slices>
+    "n224_L2_Ns2_r7": (si.Geometry(n=224, n_slices=2, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 127),
+    "n192_L3_Ns2_r7": (si.Geometry(n=192, n_slices=3, n_shots=2, n_coils=5, filt=7, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 128),
+    "n192_L2_Ns2_r5": (si.Geometry(n=192, n_slices=2, n_shots=2, n_coils=3, filt=5, lam=1e-3, n_irls=2, n_cg=3,
+                                   phase_order=3, snr=20.0), 129),
     # degenerate: one coil (three of the four coil slots of the fast column pass <16, 2>
     # clamped and zero-weighted) and the smallest schedule, 1 IRLS x 1 CG
     "n64_L2_Ns4_r3_c1": (si.Geometry(n=64, n_slices=2, n_shots=4, n_coils=1, filt=3, lam=1e-3, n_irls=1, n_cg=1,
