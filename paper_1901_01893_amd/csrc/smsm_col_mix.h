@@ -295,7 +295,7 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
         ACC[idx] = cscale(cmulc(ACC[idx], tau[ib * N2 + n]), 1.0 / (double)N2);
     }
 
-    if (use_reg) hankel_image_term(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
+    if (use_reg) hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
     __syncthreads();
     // centred forward DFT along ky
     for (int idx = tid; idx < B * N2; idx += nt) {
