@@ -132,6 +132,52 @@ SMSM_DEV void mix_dft(double2 (&f)[L * MR], double2* buf, const double2* twm, in
     }
 }
 
+// In-wave ky DFT of rows of length N2 = RQ RL (RQ = 3 or 7, RL = 16, 32 or 64
+// lanes per row, 64 / RL rows per wave): lane j of a row holds x[j + RL t],
+// t < RQ.  With n = j + RL t and k = k1 + RQ k2,
+//   X[k1 + RQ k2] = sum_j w_RL^(j k2) w_N2^(j k1) sum_t x[j + RL t] w_RQ^(t k1),
+// so the RQ-point DFT of the lane's own values, the twiddle w_N2^(j k1) and
+// the RL-point transform across the row's lanes (decimation in frequency)
+// leave X[k1 + RQ brev(j)] in register k1 (unnormalised; INV: the conjugate
+// transform).  TW2[k] = e^{-2 pi i k / N2} (shared memory).
+template <int N2>
+struct KyRow {
+    static constexpr int RQ = N2 % 7 == 0 ? 7 : 3, RL = N2 / RQ;
+    static constexpr int LOGL = RL == 64 ? 6 : RL == 32 ? 5 : RL == 16 ? 4 : 3;
+    static_assert(RQ * RL == N2 && (RL & (RL - 1)) == 0 && RL >= 8 && RL <= 64, "n2 = RQ 2^a, 8 <= 2^a <= 64");
+};
+
+template <bool INV>
+SMSM_DEV double2 tw_at(const double2* TW2, int k) {
+    const double2 w = TW2[k];
+    return INV ? cconj(w) : w;
+}
+
+template <int N2, bool INV>
+SMSM_DEV void ky_row_dft(double2 (&x)[KyRow<N2>::RQ], const double2* TW2, int j) {
+    constexpr int RQ = KyRow<N2>::RQ, RL = KyRow<N2>::RL, LOGL = KyRow<N2>::LOGL;
+    double2 y[RQ];
+#pragma unroll
+    for (int k1 = 0; k1 < RQ; ++k1) {
+        double2 sum = x[0];
+#pragma unroll
+        for (int t = 1; t < RQ; ++t) sum = cfma(x[t], tw_at<INV>(TW2, ((t * k1) % RQ) * RL), sum);
+        y[k1] = k1 == 0 ? sum : cmul(sum, tw_at<INV>(TW2, j * k1));
+    }
+    double2 w[8];
+    double sg[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        const int h = 1 << st;
+        const bool upper = (j & h) == 0;
+        sg[st] = upper ? 1.0 : -1.0;
+        w[st] = (st >= LOGL || upper) ? cmk(1.0, 0.0) : tw_at<INV>(TW2, (j & (h - 1)) * (N2 / (2 * h)));
+    }
+    fft_dif<RL, RQ>(y, w, sg);
+#pragma unroll
+    for (int k1 = 0; k1 < RQ; ++k1) x[k1] = y[k1];
+}
+
 // grid (n1), block 64 NS CG (= 512).  n2 = M NS.
 template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
@@ -176,15 +222,28 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
 
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
     for (int k = tid; k < M; k += nt) TWM[k] = twM[k];
-    // image column u = centred inverse DFT along ky; stored as tau_i * u
-    for (int idx = tid; idx < B * N2; idx += nt) {
-        const int b = dn2.div(idx), j = idx - b * N2;
-        U[idx] = cscale(h1[((size_t)b * n1 + x1) * N2 + j], sgn_pow(j));
-    }
-    fft_batch_lds(U, N2, g.logn2, B, N2, TW2, true);
-    for (int idx = tid; idx < B * N2; idx += nt) {
-        const int b = dn2.div(idx), n = idx - b * N2, ib = b % NS;
-        U[idx] = cmul(tau[ib * N2 + n], cscale(U[idx], isq2 * sgn_pow(n)));
+    __syncthreads();
+    // ky rows in-wave: wave w takes rows w RG + lane / RL, + NW RG per step
+    constexpr int RQ = KyRow<N2>::RQ, RL = KyRow<N2>::RL, RG = 64 / RL;
+    // image column u = centred inverse DFT along ky; stored as tau_i * u,
+    // tau_i[n] = (-1)^n w_n2^(i n) (bitwise the host table)
+    for (int b0 = wave * RG; b0 < B; b0 += NW * RG) {
+        const int b = b0 + lane / RL, bc = min(b, B - 1), jr = lane % RL;
+        double2 x[RQ];
+#pragma unroll
+        for (int t = 0; t < RQ; ++t) {
+            const int n = jr + RL * t;
+            x[t] = cscale(h1[((size_t)bc * n1 + x1) * N2 + n], sgn_pow(n));
+        }
+        ky_row_dft<N2, true>(x, TW2, jr);
+        if (b < B) {
+            const int ib = b % NS, bjr = (int)(__brev((unsigned)jr) >> (32 - KyRow<N2>::LOGL));
+#pragma unroll
+            for (int k1 = 0; k1 < RQ; ++k1) {
+                const int n = k1 + RQ * bjr, k = ib * n - N2 * dn2.div(ib * n);
+                U[b * N2 + n] = cmul(cscale(TW2[k], sgn_pow(n)), cscale(x[k1], isq2 * sgn_pow(n)));
+            }
+        }
     }
     __syncthreads();
 
@@ -297,14 +356,33 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
 
     if (use_reg) hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
     __syncthreads();
-    // centred forward DFT along ky
-    for (int idx = tid; idx < B * N2; idx += nt) {
-        const int n = idx - dn2.div(idx) * N2;
-        ACC[idx] = cscale(ACC[idx], sgn_pow(n));
-    }
-    fft_batch_lds(ACC, N2, g.logn2, B, N2, TW2, false);
-    for (int idx = tid; idx < B * N2; idx += nt) {
-        const int b = dn2.div(idx), j = idx - b * N2;
-        h2[((size_t)b * n1 + x1) * N2 + j] = cscale(ACC[idx], isq2 * sgn_pow(j));
+    // centred forward DFT along ky, in-wave by rows; a wave reorders its own
+    // rows through ACC for a coalesced store
+    for (int b0 = wave * RG; b0 < B; b0 += NW * RG) {
+        const int b = b0 + lane / RL, bc = min(b, B - 1), jr = lane % RL;
+        double2 x[RQ];
+#pragma unroll
+        for (int t = 0; t < RQ; ++t) {
+            const int n = jr + RL * t;
+            x[t] = cscale(ACC[bc * N2 + n], sgn_pow(n));
+        }
+        ky_row_dft<N2, false>(x, TW2, jr);
+        wave_fence();
+        if (b < B) {
+            const int bjr = (int)(__brev((unsigned)jr) >> (32 - KyRow<N2>::LOGL));
+#pragma unroll
+            for (int k1 = 0; k1 < RQ; ++k1) {
+                const int n = k1 + RQ * bjr;
+                ACC[b * N2 + n] = cscale(x[k1], isq2 * sgn_pow(n));
+            }
+        }
+        wave_fence();
+        if (b < B) {
+#pragma unroll
+            for (int t = 0; t < RQ; ++t) {
+                const int n = jr + RL * t;
+                h2[((size_t)b * n1 + x1) * N2 + n] = ACC[b * N2 + n];
+            }
+        }
     }
 }
