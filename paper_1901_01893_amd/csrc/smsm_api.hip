@@ -274,7 +274,7 @@ struct ColMixInst {
 #define COLMIX(M_, L_, NS_, CG_) {M_, L_, NS_, CG_, (const void*)&k_col_mix<M_, L_, NS_, CG_>}
 const ColMixInst kColMix[] = {COLMIX(56, 3, 4, 2),  COLMIX(56, 2, 4, 2),  COLMIX(48, 3, 4, 2),  COLMIX(48, 2, 4, 2),
                               COLMIX(28, 2, 8, 1),  COLMIX(24, 2, 8, 1),  COLMIX(28, 2, 4, 2),  COLMIX(112, 2, 2, 4),
-                              COLMIX(96, 3, 2, 4),  COLMIX(96, 2, 2, 4)};
+                              COLMIX(96, 3, 2, 4),  COLMIX(96, 2, 2, 4),  COLMIX(112, 3, 2, 4)};
 #undef COLMIX
 
 template <int M_, int L_, int NS_, int CG_, bool KF32>
@@ -342,7 +342,8 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
             case 6: COLMIX_LAUNCH(28, 2, 4, 2); break;
             case 7: COLMIX_LAUNCH(112, 2, 2, 4); break;
             case 8: COLMIX_LAUNCH(96, 3, 2, 4); break;
-            default: COLMIX_LAUNCH(96, 2, 2, 4); break;
+            case 9: COLMIX_LAUNCH(96, 2, 2, 4); break;
+            default: COLMIX_LAUNCH(112, 3, 2, 4); break;
         }
 #undef COLMIX_LAUNCH
     } else {
