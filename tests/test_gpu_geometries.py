@@ -60,8 +60,9 @@ GEOMS = {
                                    phase_order=3, snr=20.0), 114),
     "n128_L3_Ns2_r7": (si.Geometry(n=128, n_slices=3, n_shots=2, n_coils=3, filt=7, lam=1e-3, n_irls=2, n_cg=3,
                                    phase_order=3, snr=20.0), 115),
-    # matrix sizes with an odd factor (3 or 7 times a power of two): generic column
-    # pass with mixed-length transforms (folded lengths 48, 28, 24, 56, 112), the
+    # matrix sizes with an odd factor (3 or 7 times a power of two): the generic
+    # column pass with mixed-length transforms (96x96, folded length 48 at 2 shots),
+    # the odd-length register-resident pass (folded lengths 28, 24, 56, 112), the
     # row, Gram and image passes for such lengths, vector-pass ky chunks of 16 and 32
     "n96_L2_Ns2_r3": (si.Geometry(n=96, n_slices=2, n_shots=2, n_coils=3, filt=3, lam=1e-3, n_irls=2, n_cg=3,
                                   phase_order=2, snr=30.0), 116),
