@@ -322,16 +322,18 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
         return SMSM_OK;
     }
     const long nvec = (long)g.B * g.n1 * g.n2;
-    if (pc.mode != 0) {
+    // the odd-length pass takes the direction update and the Re <p, out> partials itself
+    const bool fused = MODE == COL_NORMAL && P->col_mix >= 0;
+    if (pc.mode != 0 && !fused) {
         hipLaunchKernelGGL(k_hyb_pupdate, vec_grid(), dim3(kThreads), 0, st, nvec, pc.r, pc.p_old, pc.p, pc.x,
                            pc.alpha_prev, pc.rr_new, pc.nrr, pc.rr_old, pc.rr_out, pc.mode == 1 ? 1 : 0);
         LAUNCH_CHECK();
         in = pc.p;
     }
-    if (MODE == COL_NORMAL && P->col_mix >= 0) {
+    if (fused) {
 #define COLMIX_LAUNCH(M_, L_, NS_, CG_)                                                                          \
     hipLaunchKernelGGL((k_col_mix<M_, L_, NS_, CG_>), dim3(g.n1), dim3(64 * NS_ * CG_), P->lds_colmix, st, g, in, \
-                       out, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg)
+                       out, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, pc)
         switch (P->col_mix) {
             case 0: COLMIX_LAUNCH(56, 3, 4, 2); break;
             case 1: COLMIX_LAUNCH(56, 2, 4, 2); break;
@@ -351,7 +353,7 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
                            P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, P->ytil);
     }
     LAUNCH_CHECK();
-    if (pc.mode != 0) {
+    if (pc.mode != 0 && !fused) {
         hipLaunchKernelGGL(k_hyb_dot, vec_grid(), dim3(kThreads), 0, st, nvec, pc.p, out, pc.pq);
         LAUNCH_CHECK();
     }
@@ -801,7 +803,7 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
     const size_t oth = cv.take<double2>((size_t)L * n2), otau = cv.take<double2>((size_t)Ns * n2);
     const size_t ofx = cv.take<double2>((size_t)n1 * P->np_band), ofinv = cv.take<double2>((size_t)n1 * HYB_MAX_E2);
     const size_t oflags = cv.take<int>(4);
-    P->npc = P->col_fast >= 0 ? n1 : kVecBlocks;
+    P->npc = (P->col_fast >= 0 || P->col_mix >= 0) ? n1 : kVecBlocks;
     Carver wv;
     WsLayout& w = P->wo;
     w.x = wv.take<double2>(nvec); w.b = wv.take<double2>(nvec); w.r = wv.take<double2>(nvec);

@@ -178,13 +178,17 @@ SMSM_DEV void ky_row_dft(double2 (&x)[KyRow<N2>::RQ], const double2* TW2, int j)
     for (int k1 = 0; k1 < RQ; ++k1) x[k1] = y[k1];
 }
 
-// grid (n1), block 64 NS CG (= 512).  n2 = M NS.
+// grid (n1), block 64 NS CG (= 512).  n2 = M NS.  With pc.mode != 0 the pass
+// also takes the CG direction update of its column (p = r, or x += alpha p_old
+// and p = r + beta p_old with beta from the |r|^2 partials) as it loads the
+// rows, and writes its column's Re <p, output> partial to pc.pq[blockIdx.x],
+// formed in the image domain (the ky transforms are unitary).
 template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
           const double2* __restrict__ theta, const double2* __restrict__ tau, const double2* __restrict__ tw2,
           const double2* __restrict__ twM, const double2* __restrict__ tw1, const double2* __restrict__ Kc,
-          int use_reg) {
+          int use_reg, ColCg pc) {
     constexpr int Q = (M % 7 == 0) ? 7 : 3, P = M / Q;
     constexpr int MR = M > 64 ? 2 : 1;          // folded points per lane
     constexpr int G = M > 64 ? 1 : 64 / M;      // coil-group members per wave
@@ -220,8 +224,19 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
     const double isq2 = 1.0 / sqrt((double)N2);
     const FastDiv dn2(N2);
 
+    double* red = (double*)(sm + colmix_lds_total(g, colmix_wb(M, L, NS, CG)) - 16);
     for (int k = tid; k < N2; k += nt) TW2[k] = tw2[k];
     for (int k = tid; k < M; k += nt) TWM[k] = twM[k];
+    double beta = 0.0;
+    const double alpha_prev = (pc.mode == 2 && pc.x) ? *pc.alpha_prev : 0.0;
+    if (pc.mode != 0) {
+        const double rn = sum_partials(pc.rr_new, pc.nrr, red);
+        if (pc.mode == 2) {
+            const double ro = *pc.rr_old;
+            beta = ro > 0.0 ? rn / ro : 0.0;
+        }
+        if (x1 == 0 && tid == 0) *pc.rr_out = rn;
+    }
     __syncthreads();
     // ky rows in-wave: wave w takes rows w RG + lane / RL, + NW RG per step
     constexpr int RQ = KyRow<N2>::RQ, RL = KyRow<N2>::RL, RG = 64 / RL;
@@ -233,7 +248,21 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
 #pragma unroll
         for (int t = 0; t < RQ; ++t) {
             const int n = jr + RL * t;
-            x[t] = cscale(h1[((size_t)bc * n1 + x1) * N2 + n], sgn_pow(n));
+            const size_t k0 = ((size_t)bc * n1 + x1) * N2 + n;
+            double2 val;
+            if (pc.mode == 0) {
+                val = h1[k0];
+            } else {
+                // rows past B (clamped) read only; their results are dropped
+                val = pc.r[k0];
+                if (pc.mode == 2) {
+                    const double2 po = pc.p_old[k0];
+                    if (pc.x && b < B) pc.x[k0] = cadd(pc.x[k0], cscale(po, alpha_prev));
+                    val = cadd(val, cscale(po, beta));
+                }
+                if (b < B) pc.p[k0] = val;
+            }
+            x[t] = cscale(val, sgn_pow(n));
         }
         ky_row_dft<N2, true>(x, TW2, jr);
         if (b < B) {
@@ -356,6 +385,19 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
 
     if (use_reg) hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
     __syncthreads();
+    // Re <p, output> = Re <u, ACC> with u = conj(tau) U (unitary ky transforms)
+    if (pc.mode != 0) {
+        double dot = 0.0;
+        for (int idx = tid; idx < B * N2; idx += nt) {
+            const int b = dn2.div(idx), n = idx - b * N2, ib = b % NS;
+            const int k = ib * n - N2 * dn2.div(ib * n);
+            const double2 cu = cmul(cscale(TW2[k], sgn_pow(n)), cconj(U[idx]));   // conj(u)
+            const double2 a = ACC[idx];
+            dot += cu.x * a.x - cu.y * a.y;
+        }
+        dot = block_sum(dot, red);
+        if (tid == 0) pc.pq[blockIdx.x] = dot;
+    }
     // centred forward DFT along ky, in-wave by rows; a wave reorders its own
     // rows through ACC for a coalesced store
     for (int b0 = wave * RG; b0 < B; b0 += NW * RG) {
