@@ -2,7 +2,10 @@
 // (M = P Q, Q = 3 or 7, P a power of two: 24, 28, 48, 56, 96, 112 at
 // n2 = 192, 224), with the contract of k_col<COL_NORMAL> (hybrid in -> hybrid
 // out, the circular Hankel term from the tap table Kc).  The column image and
-// the final ky transform are block-wide, as in k_col; the coil loop is
+// the final ky transform run in-wave by rows (ky_row_dft), the image-domain
+// Hankel term is that of k_col, and with pc.mode != 0 the pass also takes the
+// CG direction update and the Re <p, Np> partial of its column, as
+// k_col_fast does.  The coil loop is
 // register-resident, as in k_col_fast: wave w takes shot i = w % NS and the
 // coils of coil group w / NS.  M <= 64: lane l = grp M + a P + j is coil group
 // member grp (G = 64 / M members side by side, the remaining lanes idle),
