@@ -181,6 +181,66 @@ SMSM_DEV void ky_row_dft(double2 (&x)[KyRow<N2>::RQ], const double2* TW2, int j)
     for (int k1 = 0; k1 < RQ; ++k1) x[k1] = y[k1];
 }
 
+// Image-domain Hankel term (as hankel_image_term) by points, each shot pair
+// once: W is Hermitian, so Kc[l][i][j][d] = conj(Kc[l][j][i][2e - d]) and the
+// evaluated kernel K[l][i][j](x, n) = conj(K[l][j][i](x, n)).  A thread takes
+// a point (l, n), evaluates K[l][i][j] for i <= j by Horner's rule and adds
+// K u_i to output shot j and conj(K) u_j to output shot i: NS (NS + 1) / 2
+// tap sums per point instead of NS^2.  Only the i <= j part of the tap table
+// A is built.
+template <int NS>
+SMSM_DEV void hankel_image_pairs(const Geo& g, int x1, const double2* U, const double2* __restrict__ tw1,
+                                 const double2* TW2, const double2* __restrict__ Kc, double2* A, double2* ACC,
+                                 const FastDiv& dn2) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n1 = g.n1, n2 = g.n2, nc = g.nc, e = g.e;
+    const int nu1 = x1 - n1 / 2;
+    const double2 w1 = tw1[imod(nu1, n1)], w1e = tw1[imod(-e * nu1, n1)];
+    const FastDiv dnc(nc), dns(NS);
+    for (int idx = tid; idx < g.L * NS * NS * nc; idx += nt) {
+        const int q = dnc.div(idx), ip = q - NS * dns.div(q), i = dns.div(q) - NS * dns.div(dns.div(q));
+        if (i > ip) continue;
+        const double2* kr = Kc + (size_t)idx * nc;
+        double2 kv[BAND_MAX_NC];
+#pragma unroll
+        for (int d1 = 0; d1 < BAND_MAX_NC; ++d1)
+            if (d1 < nc) kv[d1] = kr[d1];
+        double2 p = cmk(0.0, 0.0);
+#pragma unroll
+        for (int d1 = BAND_MAX_NC - 1; d1 >= 0; --d1)
+            if (d1 < nc) p = cfma(p, w1, kv[d1]);
+        A[idx] = cmul(p, w1e);
+    }
+    __syncthreads();
+    for (int item = tid; item < g.L * n2; item += nt) {
+        const int l = dn2.div(item), n = item - l * n2;
+        const double2 w2 = TW2[imod(n - n2 / 2, n2)], w2e = TW2[imod(-e * (n - n2 / 2), n2)];
+        double2 u[NS], acc[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int k = i * n - n2 * dn2.div(i * n);
+            u[i] = cmulc(U[(l * NS + i) * n2 + n], cscale(TW2[k], sgn_pow(n)));
+            acc[i] = cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int j = i; j < NS; ++j) {
+                const double2* ar = A + (size_t)((l * NS + i) * NS + j) * nc;
+                double2 p = cmk(0.0, 0.0);
+                for (int d2 = nc - 1; d2 >= 0; --d2) p = cfma(p, w2, ar[d2]);
+                const double2 kij = cmul(p, w2e);
+                acc[j] = cfma(kij, u[i], acc[j]);
+                if (j != i) acc[i] = cfma(cconj(kij), u[j], acc[i]);
+            }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int o = (l * NS + j) * n2 + n;
+            ACC[o] = cadd(ACC[o], acc[j]);
+        }
+    }
+}
+
 // grid (n1), block 64 NS CG (= 512).  n2 = M NS.  With pc.mode != 0 the pass
 // also takes the CG direction update of its column (p = r, or x += alpha p_old
 // and p = r + beta p_old with beta from the |r|^2 partials) as it loads the
@@ -386,7 +446,10 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
         ACC[idx] = cscale(cmulc(ACC[idx], tau[ib * N2 + n]), 1.0 / (double)N2);
     }
 
-    if (use_reg) hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
+    if (use_reg) {
+        if constexpr (NS == 8) hankel_image_pairs<NS>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2);
+        else hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
+    }
     __syncthreads();
     // Re <p, output> = Re <u, ACC> with u = conj(tau) U (unitary ky transforms)
     if (pc.mode != 0) {
