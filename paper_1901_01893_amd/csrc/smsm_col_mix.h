@@ -3,7 +3,8 @@
 // n2 = 192, 224), with the contract of k_col<COL_NORMAL> (hybrid in -> hybrid
 // out, the circular Hankel term from the tap table Kc).  The column image and
 // the final ky transform run in-wave by rows (ky_row_dft), the image-domain
-// Hankel term is that of k_col, and with pc.mode != 0 the pass also takes the
+// Hankel term runs over Hermitian shot pairs (hankel_image_pairs), and with
+// pc.mode != 0 the pass also takes the
 // CG direction update and the Re <p, Np> partial of its column, as
 // k_col_fast does.  The coil loop is
 // register-resident, as in k_col_fast: wave w takes shot i = w % NS and the
@@ -181,7 +182,7 @@ SMSM_DEV void ky_row_dft(double2 (&x)[KyRow<N2>::RQ], const double2* TW2, int j)
     for (int k1 = 0; k1 < RQ; ++k1) x[k1] = y[k1];
 }
 
-// Image-domain Hankel term (as hankel_image_term) by points, each shot pair
+// Image-domain Hankel term (that of hankel_image_term) by points, each shot pair
 // once: W is Hermitian, so Kc[l][i][j][d] = conj(Kc[l][j][i][2e - d]) and the
 // evaluated kernel K[l][i][j](x, n) = conj(K[l][j][i](x, n)).  A thread takes
 // a point (l, n), evaluates K[l][i][j] for i <= j by Horner's rule and adds
@@ -446,10 +447,7 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
         ACC[idx] = cscale(cmulc(ACC[idx], tau[ib * N2 + n]), 1.0 / (double)N2);
     }
 
-    if (use_reg) {
-        if constexpr (NS == 8) hankel_image_pairs<NS>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2);
-        else hankel_image_term<NS, (N2 + 63) / 64>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, FastDiv(NS));
-    }
+    if (use_reg) hankel_image_pairs<NS>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2);
     __syncthreads();
     // Re <p, output> = Re <u, ACC> with u = conj(tau) U (unitary ky transforms)
     if (pc.mode != 0) {

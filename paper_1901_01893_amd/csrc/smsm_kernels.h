@@ -119,19 +119,16 @@ __host__ __device__ inline ColLds col_lds(const Geo& g) {
 // sums run by Horner's rule in w1, w2 (one table lookup per sum instead of one
 // per tap): an element costs Ns (nc + 1) complex multiply-adds.  A wave takes
 // whole output rows (l, i') and a lane the ky points lane + 64 r, so a row's
-// taps are wave-uniform and each is read once for up to four points.  NSC and
-// RC fix the shot count and the points per lane at compile time (the odd-length
-// pass), which removes the per-point guards from the tap loop.
+// taps are wave-uniform and each is read once for up to four points.
 // nc <= BAND_MAX_NC, n2 <= 256.  A holds
 // L Ns Ns nc entries of shared memory.  The callers' ACC writes before the
 // call are ordered by the barrier after the table build; they order the
 // writes here before their next use of ACC.
-template <int NSC, int RC>   // shots and ky points per lane when known at compile time (0: from g)
 SMSM_DEV void hankel_image_term(const Geo& g, int x1, const double2* U, const double2* __restrict__ tw1,
                                 const double2* TW2, const double2* __restrict__ Kc, double2* A, double2* ACC,
                                 const FastDiv& dn2, const FastDiv& dNs) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int n1 = g.n1, n2 = g.n2, Ns = NSC > 0 ? NSC : g.Ns, nc = g.nc, e = g.e;
+    const int n1 = g.n1, n2 = g.n2, Ns = g.Ns, nc = g.nc, e = g.e;
     const int nu1 = x1 - n1 / 2;
     const double2 w1 = tw1[imod(nu1, n1)], w1e = tw1[imod(-e * nu1, n1)];
     for (int idx = tid; idx < g.L * Ns * Ns * nc; idx += nt) {
@@ -149,7 +146,7 @@ SMSM_DEV void hankel_image_term(const Geo& g, int x1, const double2* U, const do
         A[idx] = cmul(p, w1e);
     }
     __syncthreads();
-    const int lane = tid & 63, nw = nt >> 6, R = RC > 0 ? RC : (n2 + 63) >> 6;
+    const int lane = tid & 63, nw = nt >> 6, R = (n2 + 63) >> 6;
     for (int b = tid >> 6; b < g.B; b += nw) {
         const int l = dNs.div(b), ip = b - l * Ns;
         double2 w2[4], acc[4];
@@ -332,7 +329,7 @@ __global__ void __launch_bounds__(512) k_col(Geo g, const double2* __restrict__ 
         }
     }
 
-    if (MODE != COL_ADJ && use_reg) hankel_image_term<0, 0>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, dNs);
+    if (MODE != COL_ADJ && use_reg) hankel_image_term(g, x1, U, tw1, TW2, Kc, A, ACC, dn2, dNs);
     __syncthreads();
     // centred forward DFT along ky
     for (int idx = tid; idx < B * n2; idx += nt) {
