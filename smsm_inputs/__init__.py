@@ -62,8 +62,12 @@ WORKLOADS = {
                       n_irls=10, n_cg=10, phase_order=2, snr=30.0),
     "sg256": Geometry(n=256, n_slices=3, n_shots=4, n_coils=32, filt=7, lam=1e-3,
                       n_irls=15, n_cg=15, phase_order=3, snr=20.0),
+    # an odd-factor matrix size (224 = 7 x 32) at the same multiband and shot
+    # counts, for profiling the odd-length column pass
+    "sg224": Geometry(n=224, n_slices=3, n_shots=4, n_coils=32, filt=7, lam=1e-3,
+                      n_irls=15, n_cg=15, phase_order=3, snr=20.0),
 }
-WORKLOAD_IDS = {"small": 1, "sg256": 2}
+WORKLOAD_IDS = {"small": 1, "sg256": 2, "sg224": 3}
 
 
 def _coords(n):
