@@ -333,7 +333,7 @@ smsm_status col(smsm_plan* P, const double2* in, double2* out, int use_reg, cons
     if (fused) {
 #define COLMIX_LAUNCH(M_, L_, NS_, CG_)                                                                          \
     hipLaunchKernelGGL((k_col_mix<M_, L_, NS_, CG_>), dim3(g.n1), dim3(64 * NS_ * CG_), P->lds_colmix, st, g, in, \
-                       out, P->ST, P->theta, P->tau, P->tw2, P->twM, P->tw1, P->Kc, use_reg, pc)
+                       out, P->ST, P->theta, P->tau, P->tw2, P->twM, P->Khat, use_reg, pc)
         switch (P->col_mix) {
             case 0: COLMIX_LAUNCH(56, 3, 4, 2); break;
             case 1: COLMIX_LAUNCH(56, 2, 4, 2); break;
@@ -477,6 +477,11 @@ smsm_status band_tables(smsm_plan* P, hipStream_t st) {
         hipLaunchKernelGGL(k_band_rowhat<false>, dim3(g.L * 2 * g.e * g.Ns * g.nc), dim3(kThreads), 0, st, g,
                            P->Dside, P->tw1, P->Dhat, P->khat_f32 ? 1 : 0);
     LAUNCH_CHECK();
+    if (P->col_mix >= 0) {
+        // the odd-length pass's per-column tap table lives in the (otherwise unused) Khat region
+        hipLaunchKernelGGL(k_colmix_taps, dim3(g.n1), dim3(256), 0, st, g, P->Kc, P->tw1, P->Khat);
+        LAUNCH_CHECK();
+    }
     if (P->col_fast >= 0) {
         hipLaunchKernelGGL(k_hankel_image, dim3(g.n1, g.L * g.Ns * (g.Ns + 1) / 2), dim3(kThreads), 0, st, g, P->Kc, P->tw1,
                            P->tw2, P->Khat, P->khat_f32 ? 1 : 0);
@@ -783,7 +788,9 @@ smsm_status smsm_plan_create(const smsm_geometry* geom, const smsm_params* param
         for (int k = 0; k < (int)(sizeof(kColMix) / sizeof(kColMix[0])); ++k) {
             const ColMixInst& c = kColMix[k];
             const size_t bytes = (size_t)colmix_lds_total(g, colmix_wb(c.M, c.L, c.Ns, c.CG)) * sizeof(double2);
-            if (c.M == g.M && c.L == L && c.Ns == Ns && 64 * c.Ns * c.CG == kColThreads && bytes <= (size_t)max_lds) {
+            const bool taps_fit = (size_t)n1 * L * Ns * Ns * g.nc <= (size_t)L * Ns * (Ns + 1) / 2 * n1 * n2;
+            if (c.M == g.M && c.L == L && c.Ns == Ns && 64 * c.Ns * c.CG == kColThreads && bytes <= (size_t)max_lds &&
+                taps_fit) {
                 P->col_mix = k;
                 P->lds_colmix = bytes;
             }

@@ -1,8 +1,9 @@
 // Normal-operator column pass for folded lengths with an odd factor
 // (M = P Q, Q = 3 or 7, P a power of two: 24, 28, 48, 56, 96, 112 at
 // n2 = 192, 224), with the contract of k_col<COL_NORMAL> (hybrid in -> hybrid
-// out, the circular Hankel term from the tap table Kc).  The column image and
-// the final ky transform run in-wave by rows (ky_row_dft), the image-domain
+// out, the circular Hankel term from the per-column tap table of
+// k_colmix_taps).  The column image and the final ky transform run in-wave
+// by rows (ky_row_dft), the image-domain
 // Hankel term runs over Hermitian shot pairs (hankel_image_pairs), and with
 // pc.mode != 0 the pass also takes the
 // CG direction update and the Re <p, Np> partial of its column, as
@@ -182,25 +183,18 @@ SMSM_DEV void ky_row_dft(double2 (&x)[KyRow<N2>::RQ], const double2* TW2, int j)
     for (int k1 = 0; k1 < RQ; ++k1) x[k1] = y[k1];
 }
 
-// Image-domain Hankel term (that of hankel_image_term) by points, each shot pair
-// once: W is Hermitian, so Kc[l][i][j][d] = conj(Kc[l][j][i][2e - d]) and the
-// evaluated kernel K[l][i][j](x, n) = conj(K[l][j][i](x, n)).  A thread takes
-// a point (l, n), evaluates K[l][i][j] for i <= j by Horner's rule and adds
-// K u_i to output shot j and conj(K) u_j to output shot i: NS (NS + 1) / 2
-// tap sums per point instead of NS^2.  Only the i <= j part of the tap table
-// A is built.
-template <int NS>
-SMSM_DEV void hankel_image_pairs(const Geo& g, int x1, const double2* U, const double2* __restrict__ tw1,
-                                 const double2* TW2, const double2* __restrict__ Kc, double2* A, double2* ACC,
-                                 const FastDiv& dn2) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int n1 = g.n1, n2 = g.n2, nc = g.nc, e = g.e;
+// Per-column tap table of the image-domain Hankel term, built once per weight
+// update (grid n1): At[x1][l][i][j][d2] = sum_d1 Kc[l][i][j][d2][d1] w1^(d1 - e),
+// w1 = e^{-2 pi i (x1 - n1/2)/n1}, by Horner's rule in w1 (the arithmetic of
+// hankel_image_term's table), so that the column pass copies its column's
+// L Ns Ns nc entries instead of every workgroup re-reading all of Kc.
+__global__ void __launch_bounds__(256) k_colmix_taps(Geo g, const double2* __restrict__ Kc,
+                                                     const double2* __restrict__ tw1, double2* __restrict__ At) {
+    const int x1 = blockIdx.x, n1 = g.n1, nc = g.nc, e = g.e;
+    const int ntap = g.L * g.Ns * g.Ns * nc;
     const int nu1 = x1 - n1 / 2;
     const double2 w1 = tw1[imod(nu1, n1)], w1e = tw1[imod(-e * nu1, n1)];
-    const FastDiv dnc(nc), dns(NS);
-    for (int idx = tid; idx < g.L * NS * NS * nc; idx += nt) {
-        const int q = dnc.div(idx), ip = q - NS * dns.div(q), i = dns.div(q) - NS * dns.div(dns.div(q));
-        if (i > ip) continue;
+    for (int idx = threadIdx.x; idx < ntap; idx += blockDim.x) {
         const double2* kr = Kc + (size_t)idx * nc;
         double2 kv[BAND_MAX_NC];
 #pragma unroll
@@ -210,8 +204,25 @@ SMSM_DEV void hankel_image_pairs(const Geo& g, int x1, const double2* U, const d
 #pragma unroll
         for (int d1 = BAND_MAX_NC - 1; d1 >= 0; --d1)
             if (d1 < nc) p = cfma(p, w1, kv[d1]);
-        A[idx] = cmul(p, w1e);
+        At[(size_t)x1 * ntap + idx] = cmul(p, w1e);
     }
+}
+
+// Image-domain Hankel term (that of hankel_image_term) by points, each shot pair
+// once: W is Hermitian, so Kc[l][i][j][d] = conj(Kc[l][j][i][2e - d]) and the
+// evaluated kernel K[l][i][j](x, n) = conj(K[l][j][i](x, n)).  A thread takes
+// a point (l, n), evaluates K[l][i][j] for i <= j by Horner's rule and adds
+// K u_i to output shot j and conj(K) u_j to output shot i: NS (NS + 1) / 2
+// tap sums per point instead of NS^2.  The column's taps come from the table
+// of k_colmix_taps (At).
+template <int NS>
+SMSM_DEV void hankel_image_pairs(const Geo& g, int x1, const double2* U, const double2* __restrict__ At,
+                                 const double2* TW2, double2* A, double2* ACC, const FastDiv& dn2) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n2 = g.n2, nc = g.nc, e = g.e;
+    const int ntap = g.L * NS * NS * nc;
+    const double2* Ac = At + (size_t)x1 * ntap;
+    for (int idx = tid; idx < ntap; idx += nt) A[idx] = Ac[idx];
     __syncthreads();
     for (int item = tid; item < g.L * n2; item += nt) {
         const int l = dn2.div(item), n = item - l * n2;
@@ -251,8 +262,7 @@ template <int M, int L, int NS, int CG>
 __global__ void __launch_bounds__(64 * NS * CG)
 k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const double2* __restrict__ ST,
           const double2* __restrict__ theta, const double2* __restrict__ tau, const double2* __restrict__ tw2,
-          const double2* __restrict__ twM, const double2* __restrict__ tw1, const double2* __restrict__ Kc,
-          int use_reg, ColCg pc) {
+          const double2* __restrict__ twM, const double2* __restrict__ At, int use_reg, ColCg pc) {
     constexpr int Q = (M % 7 == 0) ? 7 : 3, P = M / Q;
     constexpr int MR = M > 64 ? 2 : 1;          // folded points per lane
     constexpr int G = M > 64 ? 1 : 64 / M;      // coil-group members per wave
@@ -447,7 +457,7 @@ k_col_mix(Geo g, const double2* __restrict__ h1, double2* __restrict__ h2, const
         ACC[idx] = cscale(cmulc(ACC[idx], tau[ib * N2 + n]), 1.0 / (double)N2);
     }
 
-    if (use_reg) hankel_image_pairs<NS>(g, x1, U, tw1, TW2, Kc, A, ACC, dn2);
+    if (use_reg) hankel_image_pairs<NS>(g, x1, U, At, TW2, A, ACC, dn2);
     __syncthreads();
     // Re <p, output> = Re <u, ACC> with u = conj(tau) U (unitary ky transforms)
     if (pc.mode != 0) {
